@@ -1,0 +1,218 @@
+/*
+ * qsim -- state-vector (Schroedinger-type) quantum circuit simulation on one
+ * AMD Instinct MI355X (gfx950).  Plain C ABI: plain pointers and sizes, no
+ * C++ or PyTorch types.
+ *
+ * The problem (paper, Sec. I.A "Background"; Sec. II "Methods"): the state of
+ * n qubits is a vector of 2^n complex amplitudes held all at once; every gate
+ * of a circuit acts on it as a 2^n x 2^n matrix, so simulation is a chain of
+ * matrix-vector products whose cost grows linearly with the number of gates.
+ * A k-qubit gate is its 2^k x 2^k matrix applied to every group of 2^k
+ * amplitudes whose indices agree outside the target bits.
+ *
+ * Conventions (the paper leaves them open):
+ *   - amplitude index x = sum_q bit_q * 2^q: qubit q is bit q (little-endian);
+ *   - for a gate on targets[0..k-1], targets[b] is bit b of the gate matrix's
+ *     row/column index;
+ *   - matrices are row-major, complex128 as interleaved (re, im) doubles;
+ *   - state memory is 2^n interleaved complex numbers, complex64 (2 x float)
+ *     or complex128 (2 x double), contiguous, at least 256-byte aligned.
+ *
+ * Errors: every call returns a qsim_status.  Arguments are validated before
+ * any device work; on a validation error the state is left unchanged and
+ * qsim_last_error() describes the problem.  A failed HIP call returns
+ * QSIM_ERR_DEVICE and marks the state invalid; every later call on that state
+ * except qsim_free returns QSIM_ERR_STATE.
+ *
+ * Streams and synchronisation: each state carries a HIP stream (the null
+ * stream by default).  Gate and circuit calls are stream-ordered and return
+ * without waiting for the device; calls that deliver a value to host memory
+ * (qsim_copy_to_host, qsim_expectation) synchronise the state's stream.
+ *
+ * Threads: calls on different states may run concurrently from different host
+ * threads; calls on one state must be serialised by the caller.
+ */
+#ifndef QSIM_H
+#define QSIM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    QSIM_OK = 0,
+    QSIM_ERR_ARG = -1,          /* invalid argument; nothing was done */
+    QSIM_ERR_OOM = -2,          /* device memory could not be allocated */
+    QSIM_ERR_DEVICE = -3,       /* a HIP call failed; the state is now invalid */
+    QSIM_ERR_UNSUPPORTED = -4,  /* valid request this build does not support */
+    QSIM_ERR_STATE = -5         /* the state handle is invalid */
+} qsim_status;
+
+typedef enum {
+    QSIM_C64 = 1,   /* complex64: 8 bytes per amplitude */
+    QSIM_C128 = 2   /* complex128: 16 bytes per amplitude */
+} qsim_dtype;
+
+/* Gate kinds.  Named gates follow the textbook / OpenQASM 2 definitions:
+ *   H = [[1,1],[1,-1]]/sqrt2; X, Y, Z Pauli; S = diag(1,i); T = diag(1,e^{i pi/4});
+ *   SDG, TDG their inverses; RX/RY/RZ(t) = exp(-i t P/2) for P = X/Y/Z;
+ *   U3(t,p,l) = [[cos t/2, -e^{il} sin t/2], [e^{ip} sin t/2, e^{i(p+l)} cos t/2]];
+ *   CX(control, target); CZ; CP(p) = diag(1,1,1,e^{ip}); SWAP;
+ *   CCX(c1, c2, target); CCZ = diag(1,...,1,-1).
+ * QSIM_GATE_MATRIX applies a dense 2^k x 2^k matrix from the circuit's pool;
+ * it is not required to be unitary. */
+typedef enum {
+    QSIM_GATE_MATRIX = 0,
+    QSIM_GATE_H, QSIM_GATE_X, QSIM_GATE_Y, QSIM_GATE_Z,
+    QSIM_GATE_S, QSIM_GATE_SDG, QSIM_GATE_T, QSIM_GATE_TDG,
+    QSIM_GATE_RX, QSIM_GATE_RY, QSIM_GATE_RZ, QSIM_GATE_U3,
+    QSIM_GATE_CX, QSIM_GATE_CZ, QSIM_GATE_CP, QSIM_GATE_SWAP,
+    QSIM_GATE_CCX, QSIM_GATE_CCZ,
+    QSIM_GATE_COUNT_
+} qsim_gate_kind;
+
+#define QSIM_MAX_K 6           /* largest gate / fused block, in qubits */
+#define QSIM_MAX_QUBITS_C64 35 /* 256 GiB of complex64 */
+#define QSIM_MAX_QUBITS_C128 34
+
+/* One circuit operation.  `k` must equal the gate's arity for named gates
+ * and lie in [1, QSIM_MAX_K] for QSIM_GATE_MATRIX.  Parametric gates (RX, RY,
+ * RZ, CP: one angle; U3: three) read their angles from params[param ...] when
+ * param >= 0, otherwise from `angles`.  For QSIM_GATE_MATRIX, `mat_off` is the
+ * offset, in complex entries, of the row-major 2^k x 2^k matrix in the
+ * circuit's pool. */
+typedef struct {
+    int32_t kind;
+    int32_t k;
+    int32_t targets[QSIM_MAX_K];
+    int32_t param;
+    int32_t reserved_;
+    double angles[3];
+    int64_t mat_off;
+} qsim_op;
+
+typedef struct {
+    int32_t n;             /* circuit width in qubits */
+    int32_t nops;
+    const qsim_op *ops;    /* host array of nops ops */
+    const double *mats;    /* host complex128 pool (interleaved), may be NULL */
+    int64_t nmats;         /* complex entries in mats */
+} qsim_circuit;
+
+/* H = sum_t coeff_t * P_t with P_t = i^{|x & z|} X^x Z^z: bit q of xmask
+ * (zmask) puts an X (Z) on qubit q, both bits a Y. */
+typedef struct {
+    double coeff;
+    uint64_t xmask;
+    uint64_t zmask;
+} qsim_pauli_term;
+
+typedef struct {
+    int32_t nterms;
+    const qsim_pauli_term *terms;   /* host array */
+} qsim_pauli_sum;
+
+/* Execution options.  Zero-initialised options select automatic choices.
+ *   fuse_k:  1 = no gate fusion; 2..6 = merge runs of gates into dense blocks
+ *            on at most fuse_k qubits (products formed in double precision and
+ *            rounded once); 0 = automatic.
+ *   tile_m:  -1 = every gate / block is its own sweep over the state;
+ *            m in [4, 13] (c64) / [4, 12] (c128) = group gates into passes
+ *            that hold 2^m-amplitude tiles in LDS; 0 = automatic.
+ *   use_mfma: -1 never, 1 whenever a fused block has k >= 4, 0 automatic. */
+typedef struct {
+    int32_t fuse_k;
+    int32_t tile_m;
+    int32_t use_mfma;
+    int32_t reserved_;
+} qsim_options;
+
+typedef struct qsim_state_s *qsim_state;
+
+/* Allocates a state of n qubits on the current HIP device, owned by the
+ * library, initialised to |0...0>.  1 <= n <= 35 (c64) or 34 (c128).
+ * QSIM_ERR_OOM if the device memory cannot be allocated. */
+qsim_status qsim_alloc(int n, qsim_dtype dtype, qsim_state *out);
+
+/* Wraps caller-owned device memory (e.g. a PyTorch tensor) holding 2^n
+ * amplitudes of `dtype`, 256-byte aligned, without copying or initialising
+ * it.  `hip_stream` (a hipStream_t, may be NULL) becomes the state's stream.
+ * The caller keeps ownership and must keep the memory alive until qsim_free. */
+qsim_status qsim_wrap(void *dev_ptr, int n, qsim_dtype dtype, void *hip_stream, qsim_state *out);
+
+/* Releases the handle and, for qsim_alloc'd states, the device memory (after
+ * synchronising the state's stream).  NULL is accepted. */
+qsim_status qsim_free(qsim_state s);
+
+qsim_status qsim_set_stream(qsim_state s, void *hip_stream);
+
+/* Reports the width, dtype and device address of a state (any out pointer
+ * may be NULL). */
+qsim_status qsim_state_info(qsim_state s, int *n, int *dtype, void **dev_ptr);
+
+/* Sets the state to the basis state |index> (index < 2^n). Stream-ordered. */
+qsim_status qsim_set_basis(qsim_state s, uint64_t index);
+
+/* Copies the whole state to / from host memory; `bytes` must equal
+ * 2^n * bytes-per-amplitude.  Synchronous with respect to the host. */
+qsim_status qsim_copy_to_host(qsim_state s, void *host, size_t bytes);
+qsim_status qsim_copy_from_host(qsim_state s, const void *host, size_t bytes);
+
+/* Applies the 2^k x 2^k complex128 row-major host matrix U on `targets`
+ * (k in [1, QSIM_MAX_K], distinct qubits < n, any order).  The matrix is
+ * copied before returning and rounded once to the state's precision.
+ * (paper, Sec. I.A and Sec. II: one gate = one matrix-vector product.) */
+qsim_status qsim_apply_gate(qsim_state s, const int *targets, int k, const double *U);
+
+/* Applies a circuit's ops in order (paper, Sec. I.A: the state advanced by
+ * each moment's matrix).  `params` (host array of `nparams` doubles; may be
+ * NULL with nparams = 0 when no op is parametric) supplies parametric angles;
+ * `opts` may be NULL (automatic).
+ * The circuit width must equal the state's.  Every op is validated before any
+ * device work.  Plans (fusion, pass grouping, uploaded matrices) are cached
+ * per state for circuits with no parametric op. */
+qsim_status qsim_apply_circuit(qsim_state s, const qsim_circuit *c, const double *params,
+                               int64_t nparams, const qsim_options *opts);
+
+/* Writes <psi|H|psi> (no renormalisation) to *out_host, accumulated in double
+ * precision with a fixed-order reduction (bitwise reproducible run to run).
+ * Synchronises the state's stream.  Qubit masks must lie below 2^n. */
+qsim_status qsim_expectation(qsim_state s, const qsim_pauli_sum *H, double *out_host);
+
+/* Plans a circuit for an n-qubit state of `dtype` without touching any
+ * device (host-only): validates the ops as qsim_apply_circuit does and
+ * reports how many passes of each kind (QSIM_KCLASS_*, `counts` has
+ * QSIM_KCLASS_COUNT_ entries) the circuit would take and the algorithmic HBM
+ * bytes they move in total.  Any out pointer may be NULL. */
+qsim_status qsim_plan_summary(int n, qsim_dtype dtype, const qsim_circuit *c, const double *params,
+                              int64_t nparams, const qsim_options *opts, int64_t *counts, double *bytes);
+
+/* Thread-local description of the last error on this thread ("" if none). */
+const char *qsim_last_error(void);
+
+/* Per-kernel-class timing of this library's launches on a state, measured
+ * with HIP events recorded on the state's stream around every launch while
+ * enabled.  qsim_profile_enable(s, 1) clears and starts; 0 stops.
+ * qsim_profile_read synchronises the stream and reports, for class `cls`
+ * (QSIM_KCLASS_*), the number of launches, their summed duration in
+ * milliseconds and the summed algorithmic bytes they move. */
+typedef enum {
+    QSIM_KCLASS_SWEEP_DENSE = 0,  /* dense / controlled gate sweeps over HBM */
+    QSIM_KCLASS_SWEEP_DIAG = 1,   /* diagonal-gate sweeps */
+    QSIM_KCLASS_TILE = 2,         /* LDS tile passes */
+    QSIM_KCLASS_MFMA = 3,         /* MFMA fused-block passes */
+    QSIM_KCLASS_EXPECT = 4,       /* expectation passes */
+    QSIM_KCLASS_COUNT_ = 5
+} qsim_kernel_class;
+
+qsim_status qsim_profile_enable(qsim_state s, int on);
+qsim_status qsim_profile_read(qsim_state s, int cls, int64_t *launches, double *ms, double *bytes);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* QSIM_H */

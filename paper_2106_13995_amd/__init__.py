@@ -1,0 +1,323 @@
+"""Python binding of the qsim HIP library (gfx950).
+
+A thin ctypes layer over ``libqsim.so``: it marshals arguments into the C ABI
+declared in ``include/qsim.h`` and nothing else -- every step of gate
+application, fusion planning and reduction runs in the library.  PyTorch
+supplies device memory (state tensors) and streams.
+
+The functions named ``qsim_*`` mirror the C entry points one to one;
+:class:`State` wraps them around a torch-owned state tensor.
+
+The library must be built (``python -m paper_2106_13995_amd.build`` or
+``__graft_entry__.build()``); importing this module raises if it is missing.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Dict, Optional, Sequence, Tuple
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libqsim.so")
+
+QSIM_OK = 0
+QSIM_ERR_ARG = -1
+QSIM_ERR_OOM = -2
+QSIM_ERR_DEVICE = -3
+QSIM_ERR_UNSUPPORTED = -4
+QSIM_ERR_STATE = -5
+
+QSIM_C64 = 1
+QSIM_C128 = 2
+DTYPES = {"c64": QSIM_C64, "c128": QSIM_C128, "complex64": QSIM_C64, "complex128": QSIM_C128}
+
+GATE_CODES: Dict[str, int] = {
+    "matrix": 0, "h": 1, "x": 2, "y": 3, "z": 4, "s": 5, "sdg": 6, "t": 7, "tdg": 8,
+    "rx": 9, "ry": 10, "rz": 11, "u3": 12, "cx": 13, "cz": 14, "cp": 15, "swap": 16,
+    "ccx": 17, "ccz": 18,
+}
+
+KCLASS = {"sweep_dense": 0, "sweep_diag": 1, "tile": 2, "mfma": 3, "expect": 4}
+
+MAX_K = 6
+
+# Every symbol include/qsim.h declares.
+EXPORTS = (
+    "qsim_alloc", "qsim_wrap", "qsim_free", "qsim_set_stream", "qsim_state_info",
+    "qsim_set_basis", "qsim_copy_to_host", "qsim_copy_from_host", "qsim_apply_gate",
+    "qsim_apply_circuit", "qsim_expectation", "qsim_last_error", "qsim_profile_enable",
+    "qsim_profile_read", "qsim_plan_summary",
+)
+
+
+class QsimError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"qsim status {status}: {msg}")
+        self.status = status
+
+
+class QsimOp(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32), ("k", ctypes.c_int32), ("targets", ctypes.c_int32 * MAX_K),
+                ("param", ctypes.c_int32), ("reserved_", ctypes.c_int32), ("angles", ctypes.c_double * 3),
+                ("mat_off", ctypes.c_int64)]
+
+
+class QsimCircuit(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int32), ("nops", ctypes.c_int32), ("ops", ctypes.POINTER(QsimOp)),
+                ("mats", ctypes.POINTER(ctypes.c_double)), ("nmats", ctypes.c_int64)]
+
+
+class QsimPauliTerm(ctypes.Structure):
+    _fields_ = [("coeff", ctypes.c_double), ("xmask", ctypes.c_uint64), ("zmask", ctypes.c_uint64)]
+
+
+class QsimPauliSum(ctypes.Structure):
+    _fields_ = [("nterms", ctypes.c_int32), ("terms", ctypes.POINTER(QsimPauliTerm))]
+
+
+class QsimOptions(ctypes.Structure):
+    _fields_ = [("fuse_k", ctypes.c_int32), ("tile_m", ctypes.c_int32), ("use_mfma", ctypes.c_int32),
+                ("reserved_", ctypes.c_int32)]
+
+
+def _load() -> ctypes.CDLL:
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is not built; run __graft_entry__.build() first")
+    lib = ctypes.CDLL(LIB_PATH)
+    P, i32, i64, u64 = ctypes.c_void_p, ctypes.c_int, ctypes.c_int64, ctypes.c_uint64
+    S = ctypes.c_int
+    sig = {
+        "qsim_alloc": ([i32, i32, ctypes.POINTER(P)], S),
+        "qsim_wrap": ([P, i32, i32, P, ctypes.POINTER(P)], S),
+        "qsim_free": ([P], S),
+        "qsim_set_stream": ([P, P], S),
+        "qsim_state_info": ([P, ctypes.POINTER(i32), ctypes.POINTER(i32), ctypes.POINTER(P)], S),
+        "qsim_set_basis": ([P, u64], S),
+        "qsim_copy_to_host": ([P, P, ctypes.c_size_t], S),
+        "qsim_copy_from_host": ([P, P, ctypes.c_size_t], S),
+        "qsim_apply_gate": ([P, ctypes.POINTER(i32), i32, ctypes.POINTER(ctypes.c_double)], S),
+        "qsim_apply_circuit": ([P, ctypes.POINTER(QsimCircuit), ctypes.POINTER(ctypes.c_double), i64,
+                                ctypes.POINTER(QsimOptions)], S),
+        "qsim_expectation": ([P, ctypes.POINTER(QsimPauliSum), ctypes.POINTER(ctypes.c_double)], S),
+        "qsim_last_error": ([], ctypes.c_char_p),
+        "qsim_plan_summary": ([i32, i32, ctypes.POINTER(QsimCircuit), ctypes.POINTER(ctypes.c_double), i64,
+                               ctypes.POINTER(QsimOptions), ctypes.POINTER(i64), ctypes.POINTER(ctypes.c_double)], S),
+        "qsim_profile_enable": ([P, i32], S),
+        "qsim_profile_read": ([P, i32, ctypes.POINTER(i64), ctypes.POINTER(ctypes.c_double),
+                               ctypes.POINTER(ctypes.c_double)], S),
+    }
+    for name, (args, res) in sig.items():
+        fn = getattr(lib, name)
+        fn.argtypes = args
+        fn.restype = res
+    return lib
+
+
+_lib = _load()
+
+
+def _check(status: int) -> None:
+    if status != QSIM_OK:
+        raise QsimError(status, _lib.qsim_last_error().decode())
+
+
+def _dptr(a: Optional[np.ndarray]):
+    if a is None:
+        return None
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+# ------------------------------------------------------------ raw entry points
+
+def qsim_alloc(n: int, dtype: int) -> int:
+    h = ctypes.c_void_p()
+    _check(_lib.qsim_alloc(n, dtype, ctypes.byref(h)))
+    return h.value
+
+
+def qsim_wrap(dev_ptr: int, n: int, dtype: int, stream: int = 0) -> int:
+    h = ctypes.c_void_p()
+    _check(_lib.qsim_wrap(ctypes.c_void_p(dev_ptr), n, dtype, ctypes.c_void_p(stream or None), ctypes.byref(h)))
+    return h.value
+
+
+def qsim_free(h: int) -> None:
+    _check(_lib.qsim_free(ctypes.c_void_p(h)))
+
+
+def qsim_set_stream(h: int, stream: int) -> None:
+    _check(_lib.qsim_set_stream(ctypes.c_void_p(h), ctypes.c_void_p(stream or None)))
+
+
+def qsim_state_info(h: int) -> Tuple[int, int, int]:
+    n, dt, p = ctypes.c_int(), ctypes.c_int(), ctypes.c_void_p()
+    _check(_lib.qsim_state_info(ctypes.c_void_p(h), ctypes.byref(n), ctypes.byref(dt), ctypes.byref(p)))
+    return n.value, dt.value, p.value or 0
+
+
+def qsim_set_basis(h: int, index: int) -> None:
+    _check(_lib.qsim_set_basis(ctypes.c_void_p(h), index))
+
+
+def qsim_copy_to_host(h: int, out: np.ndarray) -> None:
+    _check(_lib.qsim_copy_to_host(ctypes.c_void_p(h), out.ctypes.data_as(ctypes.c_void_p), out.nbytes))
+
+
+def qsim_copy_from_host(h: int, src: np.ndarray) -> None:
+    src = np.ascontiguousarray(src)
+    _check(_lib.qsim_copy_from_host(ctypes.c_void_p(h), src.ctypes.data_as(ctypes.c_void_p), src.nbytes))
+
+
+def qsim_apply_gate(h: int, targets: Sequence[int], U: np.ndarray) -> None:
+    t = (ctypes.c_int * len(targets))(*[int(x) for x in targets])
+    U = np.ascontiguousarray(U, dtype=np.complex128)
+    _check(_lib.qsim_apply_gate(ctypes.c_void_p(h), t, len(targets), _dptr(U.view(np.float64))))
+
+
+class PackedCircuit:
+    """A circuit marshalled into the C structs (kept alive with its arrays)."""
+
+    def __init__(self, circ):
+        ops = (QsimOp * max(1, len(circ.ops)))()
+        mats = []
+        pos = 0
+        for i, o in enumerate(circ.ops):
+            op = ops[i]
+            op.kind = GATE_CODES[o.kind]
+            op.k = len(o.targets)
+            for b, t in enumerate(o.targets):
+                op.targets[b] = int(t)
+            op.param = int(o.param)
+            for a, v in enumerate(o.angles):
+                op.angles[a] = float(v)
+            if o.kind == "matrix":
+                op.mat_off = pos
+                mats.append(np.ascontiguousarray(o.matrix, dtype=np.complex128).reshape(-1))
+                pos += o.matrix.size
+        self.ops = ops
+        self.mats = np.ascontiguousarray(np.concatenate(mats)) if mats else np.zeros(1, dtype=np.complex128)
+        self.c = QsimCircuit(circ.n, len(circ.ops), ops,
+                             self.mats.view(np.float64).ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                             pos)
+        self.n = circ.n
+        self.nops = len(circ.ops)
+
+
+def make_options(fuse_k: int = 0, tile_m: int = 0, use_mfma: int = 0) -> QsimOptions:
+    return QsimOptions(fuse_k, tile_m, use_mfma, 0)
+
+
+def qsim_apply_circuit(h: int, packed: PackedCircuit, params: Optional[np.ndarray] = None,
+                       opts: Optional[QsimOptions] = None) -> None:
+    p = None if params is None else np.ascontiguousarray(params, dtype=np.float64)
+    _check(_lib.qsim_apply_circuit(ctypes.c_void_p(h), ctypes.byref(packed.c), _dptr(p),
+                                   0 if p is None else p.size, ctypes.byref(opts) if opts is not None else None))
+
+
+class PackedPauliSum:
+    def __init__(self, H):
+        terms = (QsimPauliTerm * max(1, len(H.coeffs)))()
+        for i, (c, x, z) in enumerate(zip(H.coeffs, H.xmasks, H.zmasks)):
+            terms[i] = QsimPauliTerm(float(c), int(x), int(z))
+        self.terms = terms
+        self.h = QsimPauliSum(len(H.coeffs), terms)
+
+
+def qsim_expectation(h: int, packedH: PackedPauliSum) -> float:
+    out = ctypes.c_double()
+    _check(_lib.qsim_expectation(ctypes.c_void_p(h), ctypes.byref(packedH.h), ctypes.byref(out)))
+    return out.value
+
+
+def qsim_plan_summary(n: int, dtype: int, circ, params: Optional[np.ndarray] = None,
+                      opts: Optional[QsimOptions] = None) -> Tuple[Dict[str, int], float]:
+    """Host-only planning: passes per kernel class and algorithmic bytes."""
+    pc = circ if isinstance(circ, PackedCircuit) else PackedCircuit(circ)
+    p = None if params is None else np.ascontiguousarray(params, dtype=np.float64)
+    counts = (ctypes.c_int64 * len(KCLASS))()
+    by = ctypes.c_double()
+    _check(_lib.qsim_plan_summary(n, dtype, ctypes.byref(pc.c), _dptr(p), 0 if p is None else p.size,
+                                  ctypes.byref(opts) if opts is not None else None, counts, ctypes.byref(by)))
+    return {name: counts[i] for name, i in KCLASS.items()}, by.value
+
+
+def qsim_profile_enable(h: int, on: bool) -> None:
+    _check(_lib.qsim_profile_enable(ctypes.c_void_p(h), 1 if on else 0))
+
+
+def qsim_profile_read(h: int, cls: int) -> Tuple[int, float, float]:
+    n, ms, by = ctypes.c_int64(), ctypes.c_double(), ctypes.c_double()
+    _check(_lib.qsim_profile_read(ctypes.c_void_p(h), cls, ctypes.byref(n), ctypes.byref(ms), ctypes.byref(by)))
+    return n.value, ms.value, by.value
+
+
+# ------------------------------------------------------------ torch-backed state
+
+class State:
+    """A state vector in a torch CUDA tensor, driven through the C ABI on
+    torch's current stream."""
+
+    def __init__(self, n: int, dtype: str = "c64", device: str = "cuda:0", init: bool = True):
+        import torch
+        self.n = n
+        self.dtype = DTYPES[dtype]
+        real = torch.float32 if self.dtype == QSIM_C64 else torch.float64
+        self.tensor = torch.empty(2 << n, dtype=real, device=device)
+        self.stream = torch.cuda.current_stream(self.tensor.device).cuda_stream
+        self.handle = qsim_wrap(self.tensor.data_ptr(), n, self.dtype, self.stream)
+        self._packed: Dict[int, PackedCircuit] = {}
+        if init:
+            self.set_basis(0)
+
+    def close(self) -> None:
+        if getattr(self, "handle", None):
+            qsim_free(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def nbytes(self) -> int:
+        return self.tensor.numel() * self.tensor.element_size()
+
+    def set_basis(self, index: int = 0) -> None:
+        qsim_set_basis(self.handle, index)
+
+    def apply_gate(self, targets: Sequence[int], U: np.ndarray) -> None:
+        qsim_apply_gate(self.handle, targets, U)
+
+    def packed(self, circ) -> PackedCircuit:
+        key = id(circ)
+        pc = self._packed.get(key)
+        if pc is None or pc.nops != len(circ.ops):
+            pc = PackedCircuit(circ)
+            self._packed[key] = pc
+        return pc
+
+    def apply_circuit(self, circ, params: Optional[np.ndarray] = None, fuse_k: int = 0, tile_m: int = 0,
+                      use_mfma: int = 0) -> None:
+        qsim_apply_circuit(self.handle, self.packed(circ), params, make_options(fuse_k, tile_m, use_mfma))
+
+    def expectation(self, H) -> float:
+        return qsim_expectation(self.handle, PackedPauliSum(H))
+
+    def to_numpy(self) -> np.ndarray:
+        out = np.empty(1 << self.n, dtype=np.complex64 if self.dtype == QSIM_C64 else np.complex128)
+        qsim_copy_to_host(self.handle, out)
+        return out
+
+    def from_numpy(self, v: np.ndarray) -> None:
+        v = np.ascontiguousarray(v, dtype=np.complex64 if self.dtype == QSIM_C64 else np.complex128)
+        qsim_copy_from_host(self.handle, v)
+
+    def profile(self, on: bool) -> None:
+        qsim_profile_enable(self.handle, on)
+
+    def profile_read(self, cls: str) -> Tuple[int, float, float]:
+        return qsim_profile_read(self.handle, KCLASS[cls])

@@ -1,0 +1,642 @@
+// C ABI of the qsim library: argument validation, state lifetime, plan cache
+// and dispatch of passes to the HIP kernels.
+#include <algorithm>
+#include <cstring>
+#include <map>
+#include <new>
+
+#include "qsim_internal.h"
+
+namespace qsim {
+
+static thread_local std::string g_last_error;
+
+qsim_status set_error(qsim_status st, const std::string &msg) {
+    g_last_error = msg;
+    return st;
+}
+
+void clear_error() { g_last_error.clear(); }
+
+static qsim_status device_error(qsim_state s, hipError_t e, const char *what) {
+    if (s) s->valid = false;
+    return set_error(QSIM_ERR_DEVICE, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+#define QSIM_HIP(s, call, what)                                   \
+    do {                                                          \
+        hipError_t e_ = (call);                                   \
+        if (e_ != hipSuccess) return device_error((s), e_, what); \
+    } while (0)
+
+static qsim_status check_state(qsim_state s) {
+    if (!s) return set_error(QSIM_ERR_ARG, "state handle is NULL");
+    if (!s->valid) return set_error(QSIM_ERR_STATE, "state is invalid after an earlier device error");
+    clear_error();
+    return QSIM_OK;
+}
+
+static int max_qubits(int dtype) { return dtype == QSIM_C128 ? QSIM_MAX_QUBITS_C128 : QSIM_MAX_QUBITS_C64; }
+
+static bool valid_dtype(int dtype) { return dtype == QSIM_C64 || dtype == QSIM_C128; }
+
+// ------------------------------------------------------------ profiling
+
+void prof_begin(qsim_state s, int cls, double bytes) {
+    if (!s->prof.on) return;
+    Profile::Rec r;
+    r.cls = cls;
+    r.bytes = bytes;
+    for (hipEvent_t *e : {&r.a, &r.b}) {
+        if (!s->prof.pool.empty()) {
+            *e = s->prof.pool.back();
+            s->prof.pool.pop_back();
+        } else if (hipEventCreate(e) != hipSuccess) {
+            *e = nullptr;
+        }
+    }
+    if (r.a) (void)hipEventRecord(r.a, s->stream);
+    s->prof.recs.push_back(r);
+}
+
+void prof_end(qsim_state s) {
+    if (!s->prof.on || s->prof.recs.empty()) return;
+    Profile::Rec &r = s->prof.recs.back();
+    if (r.b) (void)hipEventRecord(r.b, s->stream);
+}
+
+static void prof_clear(qsim_state s) {
+    for (auto &r : s->prof.recs) {
+        if (r.a) s->prof.pool.push_back(r.a);
+        if (r.b) s->prof.pool.push_back(r.b);
+    }
+    s->prof.recs.clear();
+}
+
+// ------------------------------------------------------------ device buffers
+
+static qsim_status ensure_scratch(qsim_state s, size_t bytes) {
+    if (s->scratch_bytes >= bytes) return QSIM_OK;
+    QSIM_HIP(s, hipStreamSynchronize(s->stream), "hipStreamSynchronize");
+    if (s->scratch) (void)hipFree(s->scratch);
+    s->scratch = nullptr;
+    s->scratch_bytes = 0;
+    const size_t cap = std::max<size_t>(bytes, 1 << 20);
+    if (hipMalloc(&s->scratch, cap) != hipSuccess) {
+        (void)hipGetLastError();
+        return set_error(QSIM_ERR_OOM, "cannot allocate scratch memory");
+    }
+    s->scratch_bytes = cap;
+    return QSIM_OK;
+}
+
+// Host staging buffer (pinned) for stream-ordered uploads.  Waits for the
+// previous upload from it to finish before handing it out again.
+static qsim_status ensure_pinned(qsim_state s, size_t bytes) {
+    if (s->pinned_ev_pending) {
+        QSIM_HIP(s, hipEventSynchronize(s->pinned_ev), "hipEventSynchronize");
+        s->pinned_ev_pending = false;
+    }
+    if (s->pinned_bytes >= bytes) return QSIM_OK;
+    if (s->pinned) (void)hipHostFree(s->pinned);
+    s->pinned = nullptr;
+    s->pinned_bytes = 0;
+    const size_t cap = std::max<size_t>(bytes, 1 << 16);
+    if (hipHostMalloc(&s->pinned, cap, hipHostMallocDefault) != hipSuccess) {
+        (void)hipGetLastError();
+        return set_error(QSIM_ERR_OOM, "cannot allocate pinned host memory");
+    }
+    s->pinned_bytes = cap;
+    return QSIM_OK;
+}
+
+static qsim_status upload_staged(qsim_state s, void *dst, size_t bytes) {
+    QSIM_HIP(s, hipMemcpyAsync(dst, s->pinned, bytes, hipMemcpyHostToDevice, s->stream), "hipMemcpyAsync");
+    if (!s->pinned_ev) QSIM_HIP(s, hipEventCreateWithFlags(&s->pinned_ev, hipEventDisableTiming), "hipEventCreate");
+    QSIM_HIP(s, hipEventRecord(s->pinned_ev, s->stream), "hipEventRecord");
+    s->pinned_ev_pending = true;
+    return QSIM_OK;
+}
+
+// ------------------------------------------------------------ plans
+
+template <typename T>
+static void pack_pool(const std::vector<cd> &pool, void *dst) {
+    T *p = static_cast<T *>(dst);
+    for (size_t i = 0; i < pool.size(); ++i) {
+        p[2 * i] = T(pool[i].real());
+        p[2 * i + 1] = T(pool[i].imag());
+    }
+}
+
+static qsim_status upload_plan(qsim_state s, Plan &plan) {
+    if (plan.uploaded) return QSIM_OK;
+    const size_t ops_bytes = plan.tile_ops.size() * sizeof(TileOp);
+    plan.pool_dev_off = (ops_bytes + 255) & ~size_t(255);
+    const size_t total = plan.pool_dev_off + plan.tile_pool.size() * amp_bytes(plan.dtype);
+    if (total == plan.pool_dev_off && ops_bytes == 0) {
+        plan.uploaded = true;
+        return QSIM_OK;
+    }
+    if (hipMalloc(&plan.dev, total) != hipSuccess) {
+        (void)hipGetLastError();
+        plan.dev = nullptr;
+        return set_error(QSIM_ERR_OOM, "cannot allocate device memory for the plan");
+    }
+    if (hipHostMalloc(&plan.host_pinned, total, hipHostMallocDefault) != hipSuccess) {
+        (void)hipGetLastError();
+        plan.host_pinned = nullptr;
+        return set_error(QSIM_ERR_OOM, "cannot allocate pinned memory for the plan");
+    }
+    char *h = static_cast<char *>(plan.host_pinned);
+    if (ops_bytes) std::memcpy(h, plan.tile_ops.data(), ops_bytes);
+    if (plan.dtype == QSIM_C64)
+        pack_pool<float>(plan.tile_pool, h + plan.pool_dev_off);
+    else
+        pack_pool<double>(plan.tile_pool, h + plan.pool_dev_off);
+    QSIM_HIP(s, hipMemcpyAsync(plan.dev, plan.host_pinned, total, hipMemcpyHostToDevice, s->stream),
+             "hipMemcpyAsync(plan)");
+    plan.dev_bytes = total;
+    plan.uploaded = true;
+    return QSIM_OK;
+}
+
+static qsim_status run_plan(qsim_state s, Plan &plan) {
+    qsim_status st = upload_plan(s, plan);
+    if (st != QSIM_OK) return st;
+    for (const Pass &p : plan.passes) {
+        hipError_t e = hipSuccess;
+        switch (p.kind) {
+            case PASS_DENSE:
+                prof_begin(s, QSIM_KCLASS_SWEEP_DENSE, p.bytes);
+                e = launch_dense_sweep(s, p);
+                break;
+            case PASS_DIAG:
+                prof_begin(s, QSIM_KCLASS_SWEEP_DIAG, p.bytes);
+                e = launch_diag_sweep(s, p);
+                break;
+            case PASS_TILE:
+                prof_begin(s, QSIM_KCLASS_TILE, p.bytes);
+                e = launch_tile_pass(s, plan, p);
+                break;
+            default:
+                return set_error(QSIM_ERR_UNSUPPORTED, "pass kind not supported");
+        }
+        prof_end(s);
+        if (e != hipSuccess) return device_error(s, e, "kernel launch");
+    }
+    return QSIM_OK;
+}
+
+// Validates one op and returns its normalised gate.
+static qsim_status make_gate(const qsim_circuit *c, int i, const double *params, int64_t nparams, HostGate &g) {
+    const qsim_op &op = c->ops[i];
+    const int n = c->n;
+    char buf[160];
+    int k = op.k;
+    if (op.kind == QSIM_GATE_MATRIX) {
+        if (k < 1 || k > QSIM_MAX_K) {
+            snprintf(buf, sizeof buf, "op %d: matrix gate with k=%d outside [1, %d]", i, k, QSIM_MAX_K);
+            return set_error(QSIM_ERR_ARG, buf);
+        }
+    } else {
+        const int ar = named_gate_arity(op.kind);
+        if (ar < 0) {
+            snprintf(buf, sizeof buf, "op %d: unknown gate kind %d", i, op.kind);
+            return set_error(QSIM_ERR_ARG, buf);
+        }
+        if (k != ar) {
+            snprintf(buf, sizeof buf, "op %d: gate kind %d acts on %d qubits, op says k=%d", i, op.kind, ar, k);
+            return set_error(QSIM_ERR_ARG, buf);
+        }
+    }
+    if (k > n) {
+        snprintf(buf, sizeof buf, "op %d: k=%d exceeds the %d-qubit register", i, k, n);
+        return set_error(QSIM_ERR_ARG, buf);
+    }
+    uint64_t seen = 0;
+    for (int b = 0; b < k; ++b) {
+        const int t = op.targets[b];
+        if (t < 0 || t >= n) {
+            snprintf(buf, sizeof buf, "op %d: target %d outside [0, %d)", i, t, n);
+            return set_error(QSIM_ERR_ARG, buf);
+        }
+        if (seen & (1ull << t)) {
+            snprintf(buf, sizeof buf, "op %d: target %d repeated", i, t);
+            return set_error(QSIM_ERR_ARG, buf);
+        }
+        seen |= 1ull << t;
+        g.targets[b] = t;
+    }
+    g.k = k;
+    g.src_op = i;
+    const int d = 1 << k;
+    g.M.resize(size_t(d) * d);
+    if (op.kind == QSIM_GATE_MATRIX) {
+        if (!c->mats || op.mat_off < 0 || op.mat_off + int64_t(d) * d > c->nmats) {
+            snprintf(buf, sizeof buf, "op %d: matrix at offset %lld does not fit the %lld-entry pool", i,
+                     (long long)op.mat_off, (long long)c->nmats);
+            return set_error(QSIM_ERR_ARG, buf);
+        }
+        const double *m = c->mats + 2 * op.mat_off;
+        for (int e = 0; e < d * d; ++e) g.M[e] = cd(m[2 * e], m[2 * e + 1]);
+        return QSIM_OK;
+    }
+    double ang[3] = {op.angles[0], op.angles[1], op.angles[2]};
+    if (op.param >= 0) {
+        const int na = op.kind == QSIM_GATE_U3 ? 3
+                       : (op.kind == QSIM_GATE_RX || op.kind == QSIM_GATE_RY || op.kind == QSIM_GATE_RZ ||
+                          op.kind == QSIM_GATE_CP)
+                           ? 1
+                           : 0;
+        if (na == 0) {
+            snprintf(buf, sizeof buf, "op %d: gate kind %d takes no parameter", i, op.kind);
+            return set_error(QSIM_ERR_ARG, buf);
+        }
+        if (!params || int64_t(op.param) + na > nparams) {
+            snprintf(buf, sizeof buf, "op %d: parameter index %d outside the %lld supplied", i, op.param,
+                     (long long)nparams);
+            return set_error(QSIM_ERR_ARG, buf);
+        }
+        for (int a = 0; a < na; ++a) ang[a] = params[op.param + a];
+    }
+    named_gate_matrix(op.kind, ang, g.M.data());
+    return QSIM_OK;
+}
+
+// Exact cache key: options, width, dtype, ops, referenced matrices and parameters.
+static std::string plan_key(qsim_state s, const qsim_circuit *c, const double *params, int64_t nparams,
+                            const PlanOptions &po) {
+    std::string key;
+    auto put = [&key](const void *p, size_t n) { key.append(static_cast<const char *>(p), n); };
+    put(&po, sizeof po);
+    put(&s->n, sizeof s->n);
+    put(&s->dtype, sizeof s->dtype);
+    put(c->ops, sizeof(qsim_op) * size_t(c->nops));
+    if (c->mats && c->nmats > 0) put(c->mats, sizeof(double) * 2 * size_t(c->nmats));
+    if (params && nparams > 0) put(params, sizeof(double) * size_t(nparams));
+    return key;
+}
+
+static const size_t kMaxCachedPlans = 16;
+
+static qsim_status get_plan(qsim_state s, const qsim_circuit *c, const double *params, int64_t nparams,
+                            const qsim_options *opts, Plan **out, bool cache = true) {
+    const PlanOptions po = resolve_options(opts, s->n, s->dtype);
+    std::string key;
+    if (cache) {
+        key = plan_key(s, c, params, nparams, po);
+        for (auto &cp : s->plans)
+            if (cp.key == key) {
+                cp.last_use = ++s->use_clock;
+                *out = cp.plan.get();
+                return QSIM_OK;
+            }
+    }
+    std::vector<HostGate> gates(size_t(c->nops));
+    for (int i = 0; i < c->nops; ++i) {
+        qsim_status st = make_gate(c, i, params, nparams, gates[size_t(i)]);
+        if (st != QSIM_OK) return st;
+    }
+    std::unique_ptr<Plan> plan(new (std::nothrow) Plan());
+    if (!plan) return set_error(QSIM_ERR_OOM, "host allocation failed");
+    plan->n = s->n;
+    plan->dtype = s->dtype;
+    build_plan(*plan, gates, po);
+    if (!cache) {
+        // one transient plan per state; its device buffer may still be read
+        // by queued kernels, so wait before replacing one that has it
+        if (s->transient && s->transient->dev)
+            QSIM_HIP(s, hipStreamSynchronize(s->stream), "hipStreamSynchronize");
+        s->transient = std::move(plan);
+        *out = s->transient.get();
+        return QSIM_OK;
+    }
+    if (s->plans.size() >= kMaxCachedPlans) {
+        auto lru = std::min_element(s->plans.begin(), s->plans.end(),
+                                    [](const CachedPlan &a, const CachedPlan &b) { return a.last_use < b.last_use; });
+        QSIM_HIP(s, hipStreamSynchronize(s->stream), "hipStreamSynchronize");
+        s->plans.erase(lru);
+    }
+    CachedPlan cp;
+    cp.key = std::move(key);
+    cp.plan = std::move(plan);
+    cp.last_use = ++s->use_clock;
+    s->plans.push_back(std::move(cp));
+    *out = s->plans.back().plan.get();
+    return QSIM_OK;
+}
+
+}  // namespace qsim
+
+using namespace qsim;
+
+extern "C" {
+
+const char *qsim_last_error(void) { return g_last_error.c_str(); }
+
+qsim_status qsim_wrap(void *dev_ptr, int n, qsim_dtype dtype, void *hip_stream, qsim_state *out) {
+    clear_error();
+    if (!out) return set_error(QSIM_ERR_ARG, "out is NULL");
+    *out = nullptr;
+    if (!valid_dtype(dtype)) return set_error(QSIM_ERR_ARG, "dtype must be QSIM_C64 or QSIM_C128");
+    if (n < 1 || n > max_qubits(dtype)) return set_error(QSIM_ERR_ARG, "n outside the supported range");
+    if (!dev_ptr) return set_error(QSIM_ERR_ARG, "device pointer is NULL");
+    if (reinterpret_cast<uintptr_t>(dev_ptr) % 256 != 0)
+        return set_error(QSIM_ERR_ARG, "device pointer must be 256-byte aligned");
+    qsim_state s = new (std::nothrow) qsim_state_s();
+    if (!s) return set_error(QSIM_ERR_OOM, "host allocation failed");
+    s->n = n;
+    s->dtype = dtype;
+    s->data = dev_ptr;
+    s->owned = false;
+    s->stream = static_cast<hipStream_t>(hip_stream);
+    (void)hipGetDevice(&s->device);
+    *out = s;
+    return QSIM_OK;
+}
+
+qsim_status qsim_alloc(int n, qsim_dtype dtype, qsim_state *out) {
+    clear_error();
+    if (!out) return set_error(QSIM_ERR_ARG, "out is NULL");
+    *out = nullptr;
+    if (!valid_dtype(dtype)) return set_error(QSIM_ERR_ARG, "dtype must be QSIM_C64 or QSIM_C128");
+    if (n < 1 || n > max_qubits(dtype)) return set_error(QSIM_ERR_ARG, "n outside the supported range");
+    void *p = nullptr;
+    const size_t bytes = amp_bytes(dtype) << n;
+    if (hipMalloc(&p, bytes) != hipSuccess) {
+        (void)hipGetLastError();
+        return set_error(QSIM_ERR_OOM, "cannot allocate " + std::to_string(bytes) + " bytes of device memory");
+    }
+    qsim_state s = new (std::nothrow) qsim_state_s();
+    if (!s) {
+        (void)hipFree(p);
+        return set_error(QSIM_ERR_OOM, "host allocation failed");
+    }
+    s->n = n;
+    s->dtype = dtype;
+    s->data = p;
+    s->owned = true;
+    (void)hipGetDevice(&s->device);
+    hipError_t e = launch_set_basis(s, 0);
+    if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
+    if (e != hipSuccess) {
+        (void)hipFree(p);
+        delete s;
+        return set_error(QSIM_ERR_DEVICE, std::string("initialising the state: ") + hipGetErrorString(e));
+    }
+    *out = s;
+    return QSIM_OK;
+}
+
+qsim_status qsim_free(qsim_state s) {
+    clear_error();
+    if (!s) return QSIM_OK;
+    (void)hipStreamSynchronize(s->stream);
+    s->plans.clear();
+    s->transient.reset();
+    prof_clear(s);
+    for (hipEvent_t e : s->prof.pool) (void)hipEventDestroy(e);
+    if (s->pinned_ev) (void)hipEventDestroy(s->pinned_ev);
+    if (s->scratch) (void)hipFree(s->scratch);
+    if (s->pinned) (void)hipHostFree(s->pinned);
+    if (s->owned && s->data) (void)hipFree(s->data);
+    delete s;
+    return QSIM_OK;
+}
+
+qsim_status qsim_set_stream(qsim_state s, void *hip_stream) {
+    qsim_status st = check_state(s);
+    if (st != QSIM_OK) return st;
+    // order the new stream after everything queued so far on the old one
+    QSIM_HIP(s, hipStreamSynchronize(s->stream), "hipStreamSynchronize");
+    s->stream = static_cast<hipStream_t>(hip_stream);
+    return QSIM_OK;
+}
+
+qsim_status qsim_state_info(qsim_state s, int *n, int *dtype, void **dev_ptr) {
+    if (!s) return set_error(QSIM_ERR_ARG, "state handle is NULL");
+    clear_error();
+    if (n) *n = s->n;
+    if (dtype) *dtype = s->dtype;
+    if (dev_ptr) *dev_ptr = s->data;
+    return QSIM_OK;
+}
+
+qsim_status qsim_set_basis(qsim_state s, uint64_t index) {
+    qsim_status st = check_state(s);
+    if (st != QSIM_OK) return st;
+    if (index >= (1ull << s->n)) return set_error(QSIM_ERR_ARG, "basis index outside [0, 2^n)");
+    QSIM_HIP(s, launch_set_basis(s, index), "set_basis launch");
+    return QSIM_OK;
+}
+
+qsim_status qsim_copy_to_host(qsim_state s, void *host, size_t bytes) {
+    qsim_status st = check_state(s);
+    if (st != QSIM_OK) return st;
+    if (!host) return set_error(QSIM_ERR_ARG, "host pointer is NULL");
+    if (bytes != (amp_bytes(s->dtype) << s->n)) return set_error(QSIM_ERR_ARG, "byte count does not match the state");
+    QSIM_HIP(s, hipMemcpyAsync(host, s->data, bytes, hipMemcpyDeviceToHost, s->stream), "hipMemcpyAsync");
+    QSIM_HIP(s, hipStreamSynchronize(s->stream), "hipStreamSynchronize");
+    return QSIM_OK;
+}
+
+qsim_status qsim_copy_from_host(qsim_state s, const void *host, size_t bytes) {
+    qsim_status st = check_state(s);
+    if (st != QSIM_OK) return st;
+    if (!host) return set_error(QSIM_ERR_ARG, "host pointer is NULL");
+    if (bytes != (amp_bytes(s->dtype) << s->n)) return set_error(QSIM_ERR_ARG, "byte count does not match the state");
+    QSIM_HIP(s, hipMemcpyAsync(s->data, host, bytes, hipMemcpyHostToDevice, s->stream), "hipMemcpyAsync");
+    QSIM_HIP(s, hipStreamSynchronize(s->stream), "hipStreamSynchronize");
+    return QSIM_OK;
+}
+
+qsim_status qsim_apply_gate(qsim_state s, const int *targets, int k, const double *U) {
+    qsim_status st = check_state(s);
+    if (st != QSIM_OK) return st;
+    if (!targets || !U) return set_error(QSIM_ERR_ARG, "targets or U is NULL");
+    if (k < 1 || k > QSIM_MAX_K) return set_error(QSIM_ERR_ARG, "k outside [1, 6]");
+    qsim_op op{};
+    op.kind = QSIM_GATE_MATRIX;
+    op.k = k;
+    for (int b = 0; b < k; ++b) op.targets[b] = targets[b];
+    op.param = -1;
+    op.mat_off = 0;
+    qsim_circuit c{};
+    c.n = s->n;
+    c.nops = 1;
+    c.ops = &op;
+    c.mats = U;
+    c.nmats = int64_t(1) << (2 * k);
+    HostGate g;
+    st = make_gate(&c, 0, nullptr, 0, g);
+    if (st != QSIM_OK) return st;
+    qsim_options o{};
+    o.fuse_k = 1;
+    o.tile_m = -1;
+    Plan *plan = nullptr;
+    st = get_plan(s, &c, nullptr, 0, &o, &plan, /*cache=*/false);
+    if (st != QSIM_OK) return st;
+    return run_plan(s, *plan);
+}
+
+qsim_status qsim_apply_circuit(qsim_state s, const qsim_circuit *c, const double *params, int64_t nparams,
+                               const qsim_options *opts) {
+    qsim_status st = check_state(s);
+    if (st != QSIM_OK) return st;
+    if (!c) return set_error(QSIM_ERR_ARG, "circuit is NULL");
+    if (c->n != s->n) return set_error(QSIM_ERR_ARG, "circuit width does not match the state");
+    if (c->nops < 0 || (c->nops > 0 && !c->ops)) return set_error(QSIM_ERR_ARG, "bad op array");
+    if (nparams < 0) return set_error(QSIM_ERR_ARG, "nparams is negative");
+    if (opts) {
+        if (opts->fuse_k < 0 || opts->fuse_k > QSIM_MAX_K) return set_error(QSIM_ERR_ARG, "fuse_k outside [0, 6]");
+        if (opts->tile_m > 0 && opts->tile_m < 7)
+            return set_error(QSIM_ERR_ARG, "tile_m must be -1, 0 or at least 7");
+    }
+    if (c->nops == 0) return QSIM_OK;
+    Plan *plan = nullptr;
+    st = get_plan(s, c, params, nparams, opts, &plan);
+    if (st != QSIM_OK) return st;
+    return run_plan(s, *plan);
+}
+
+qsim_status qsim_expectation(qsim_state s, const qsim_pauli_sum *H, double *out_host) {
+    qsim_status st = check_state(s);
+    if (st != QSIM_OK) return st;
+    if (!H || !out_host || (H->nterms > 0 && !H->terms)) return set_error(QSIM_ERR_ARG, "NULL argument");
+    if (H->nterms < 0) return set_error(QSIM_ERR_ARG, "negative term count");
+    const uint64_t lim = (s->n >= 64) ? ~0ull : ((1ull << s->n) - 1);
+    for (int t = 0; t < H->nterms; ++t)
+        if ((H->terms[t].xmask & ~lim) || (H->terms[t].zmask & ~lim))
+            return set_error(QSIM_ERR_ARG, "Pauli mask has a bit at or above n");
+    // group terms by X mask
+    std::map<uint64_t, std::vector<int>> groups;
+    for (int t = 0; t < H->nterms; ++t) groups[H->terms[t].xmask].push_back(t);
+    struct DevTerm {
+        double wr, wi;
+        uint64_t z, pad;
+    };
+    const int maxp = 2048;
+    const size_t ngroups = groups.size();
+    const size_t terms_off = ngroups * maxp * sizeof(double) + 256;
+    const size_t terms_bytes = sizeof(DevTerm) * size_t(std::max(H->nterms, 1));
+    const size_t out_off = (terms_off + terms_bytes + 255) & ~size_t(255);
+    st = ensure_scratch(s, out_off + 256);
+    if (st != QSIM_OK) return st;
+    st = ensure_pinned(s, std::max(terms_bytes, size_t(64)));
+    if (st != QSIM_OK) return st;
+    DevTerm *ht = static_cast<DevTerm *>(s->pinned);
+    std::vector<std::pair<uint64_t, int>> spans;   // (x, first term slot)
+    int slot = 0;
+    for (auto &kv : groups) {
+        spans.push_back({kv.first, slot});
+        for (int t : kv.second) {
+            const qsim_pauli_term &pt = H->terms[t];
+            const int ny = __builtin_popcountll(pt.xmask & pt.zmask) & 3;
+            // coeff * i^ny
+            const double re[4] = {1, 0, -1, 0}, im[4] = {0, 1, 0, -1};
+            ht[slot].wr = pt.coeff * re[ny];
+            ht[slot].wi = pt.coeff * im[ny];
+            ht[slot].z = pt.zmask;
+            ht[slot].pad = 0;
+            ++slot;
+        }
+    }
+    char *scr = static_cast<char *>(s->scratch);
+    double *partials = reinterpret_cast<double *>(scr);
+    DevTerm *dterms = reinterpret_cast<DevTerm *>(scr + terms_off);
+    double *dout = reinterpret_cast<double *>(scr + out_off);
+    if (H->nterms > 0) {
+        st = upload_staged(s, dterms, terms_bytes);
+        if (st != QSIM_OK) return st;
+    }
+    int total = 0;
+    for (size_t gi = 0; gi < spans.size(); ++gi) {
+        const int first = spans[gi].second;
+        const int cnt = (gi + 1 < spans.size() ? spans[gi + 1].second : slot) - first;
+        int wrote = 0;
+        const double bytes = double(amp_bytes(s->dtype) << s->n) * (spans[gi].first ? 2.0 : 1.0);
+        prof_begin(s, QSIM_KCLASS_EXPECT, bytes);
+        hipError_t e = launch_expect_group(s, spans[gi].first, dterms + first, cnt, partials + total, &wrote);
+        prof_end(s);
+        if (e != hipSuccess) return device_error(s, e, "expectation launch");
+        total += wrote;
+    }
+    if (total == 0) {
+        *out_host = 0.0;
+        return QSIM_OK;
+    }
+    QSIM_HIP(s, launch_reduce(s, partials, total, dout), "reduce launch");
+    double *hout = static_cast<double *>(s->pinned) + (terms_bytes + 7) / 8;
+    (void)hout;
+    QSIM_HIP(s, hipMemcpyAsync(out_host, dout, sizeof(double), hipMemcpyDeviceToHost, s->stream), "hipMemcpyAsync");
+    QSIM_HIP(s, hipStreamSynchronize(s->stream), "hipStreamSynchronize");
+    s->pinned_ev_pending = false;
+    return QSIM_OK;
+}
+
+qsim_status qsim_plan_summary(int n, qsim_dtype dtype, const qsim_circuit *c, const double *params,
+                              int64_t nparams, const qsim_options *opts, int64_t *counts, double *bytes) {
+    clear_error();
+    if (!valid_dtype(dtype)) return set_error(QSIM_ERR_ARG, "dtype must be QSIM_C64 or QSIM_C128");
+    if (n < 1 || n > max_qubits(dtype)) return set_error(QSIM_ERR_ARG, "n outside the supported range");
+    if (!c || c->n != n) return set_error(QSIM_ERR_ARG, "circuit is NULL or its width is not n");
+    if (c->nops < 0 || (c->nops > 0 && !c->ops)) return set_error(QSIM_ERR_ARG, "bad op array");
+    std::vector<HostGate> gates(size_t(c->nops));
+    for (int i = 0; i < c->nops; ++i) {
+        qsim_status st = make_gate(c, i, params, nparams, gates[size_t(i)]);
+        if (st != QSIM_OK) return st;
+    }
+    Plan plan;
+    plan.n = n;
+    plan.dtype = dtype;
+    build_plan(plan, gates, resolve_options(opts, n, dtype));
+    int64_t cnt[QSIM_KCLASS_COUNT_] = {0};
+    double by = 0.0;
+    for (const Pass &p : plan.passes) {
+        const int cls = p.kind == PASS_DENSE ? QSIM_KCLASS_SWEEP_DENSE
+                        : p.kind == PASS_DIAG ? QSIM_KCLASS_SWEEP_DIAG
+                        : p.kind == PASS_TILE ? QSIM_KCLASS_TILE
+                                              : QSIM_KCLASS_MFMA;
+        ++cnt[cls];
+        by += p.bytes;
+    }
+    if (counts)
+        for (int i = 0; i < QSIM_KCLASS_COUNT_; ++i) counts[i] = cnt[i];
+    if (bytes) *bytes = by;
+    return QSIM_OK;
+}
+
+qsim_status qsim_profile_enable(qsim_state s, int on) {
+    qsim_status st = check_state(s);
+    if (st != QSIM_OK) return st;
+    if (on) {
+        QSIM_HIP(s, hipStreamSynchronize(s->stream), "hipStreamSynchronize");
+        prof_clear(s);
+    }
+    s->prof.on = on != 0;
+    return QSIM_OK;
+}
+
+qsim_status qsim_profile_read(qsim_state s, int cls, int64_t *launches, double *ms, double *bytes) {
+    qsim_status st = check_state(s);
+    if (st != QSIM_OK) return st;
+    if (cls < 0 || cls >= QSIM_KCLASS_COUNT_) return set_error(QSIM_ERR_ARG, "unknown kernel class");
+    QSIM_HIP(s, hipStreamSynchronize(s->stream), "hipStreamSynchronize");
+    int64_t cnt = 0;
+    double tot = 0.0, by = 0.0;
+    for (auto &r : s->prof.recs) {
+        if (r.cls != cls || !r.a || !r.b) continue;
+        float t = 0.f;
+        QSIM_HIP(s, hipEventElapsedTime(&t, r.a, r.b), "hipEventElapsedTime");
+        ++cnt;
+        tot += t;
+        by += r.bytes;
+    }
+    if (launches) *launches = cnt;
+    if (ms) *ms = tot;
+    if (bytes) *bytes = by;
+    return QSIM_OK;
+}
+
+}  // extern "C"

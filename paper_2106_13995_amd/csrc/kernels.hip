@@ -1,0 +1,523 @@
+// HIP kernels for gfx950 (CDNA4, 64-wide wavefronts): gate sweeps over HBM,
+// LDS tile passes, basis-state initialisation and expectation values.
+//
+// Amplitudes are interleaved complex (float2 for complex64, double2 for
+// complex128).  Index arithmetic is 64-bit: a state holds up to 2^35
+// amplitudes.
+#include <hip/hip_runtime.h>
+
+#include "qsim_internal.h"
+
+namespace qsim {
+
+// ------------------------------------------------------------ complex helpers
+
+template <typename T> struct C2;
+template <> struct C2<float> { using type = float2; using vec2 = float4; };
+template <> struct C2<double> { using type = double2; using vec2 = double4; };
+
+template <typename T> using c2_t = typename C2<T>::type;
+
+template <typename T>
+__device__ __forceinline__ void cfma(T &accr, T &acci, T ur, T ui, T vr, T vi) {
+    accr = fma(ur, vr, accr);
+    accr = fma(-ui, vi, accr);
+    acci = fma(ur, vi, acci);
+    acci = fma(ui, vr, acci);
+}
+
+// Inserts a zero bit at each of the ascending positions pos[0..np-1].
+__device__ __forceinline__ uint64_t insert_zeros(uint64_t x, const int *pos, int np) {
+    for (int i = 0; i < np; ++i) {
+        const uint64_t lo = x & ((1ull << pos[i]) - 1ull);
+        x = ((x - lo) << 1) | lo;
+    }
+    return x;
+}
+
+// ------------------------------------------------------------ dense sweep
+
+constexpr int kSweepThreads = 256;
+
+template <typename T, int K>
+struct DenseArgs {
+    T re[1 << (2 * K)];
+    T im[1 << (2 * K)];
+    uint64_t cmask;           // control bits (all must be 1)
+    uint64_t toff[1 << K];    // offset of local index j
+    int npos;                 // targets + controls, ascending
+    int pos[QSIM_MAX_K];
+};
+
+// One thread applies the gate to V consecutive groups (V = 2 moves two
+// complex64 amplitudes per 16-byte access; needs the lowest inserted
+// position >= 1 so that the two groups are adjacent in memory).
+template <typename T, int K, int V>
+__global__ void __launch_bounds__(kSweepThreads)
+k_dense_sweep(c2_t<T> *__restrict__ psi, const DenseArgs<T, K> a, uint64_t nthreads) {
+    const uint64_t tid = uint64_t(blockIdx.x) * kSweepThreads + threadIdx.x;
+    if (tid >= nthreads) return;
+    constexpr int D = 1 << K;
+    const uint64_t x = insert_zeros(tid * V, a.pos, a.npos) | a.cmask;
+    T vr[D][V], vi[D][V];
+#pragma unroll
+    for (int j = 0; j < D; ++j) {
+        if constexpr (V == 2) {
+            const float4 w = *reinterpret_cast<const float4 *>(psi + x + a.toff[j]);
+            vr[j][0] = w.x; vi[j][0] = w.y; vr[j][1] = w.z; vi[j][1] = w.w;
+        } else {
+            const c2_t<T> w = psi[x + a.toff[j]];
+            vr[j][0] = w.x; vi[j][0] = w.y;
+        }
+    }
+#pragma unroll
+    for (int r = 0; r < D; ++r) {
+        T orr[V], oi[V];
+#pragma unroll
+        for (int v = 0; v < V; ++v) { orr[v] = T(0); oi[v] = T(0); }
+#pragma unroll
+        for (int c = 0; c < D; ++c) {
+            const T ur = a.re[r * D + c], ui = a.im[r * D + c];
+#pragma unroll
+            for (int v = 0; v < V; ++v) cfma(orr[v], oi[v], ur, ui, vr[c][v], vi[c][v]);
+        }
+        if constexpr (V == 2) {
+            *reinterpret_cast<float4 *>(psi + x + a.toff[r]) = make_float4(orr[0], oi[0], orr[1], oi[1]);
+        } else {
+            c2_t<T> w;
+            w.x = orr[0]; w.y = oi[0];
+            psi[x + a.toff[r]] = w;
+        }
+    }
+}
+
+template <typename T, int K>
+static hipError_t dense_sweep_t(qsim_state s, const Pass &p) {
+    DenseArgs<T, K> a{};
+    constexpr int D = 1 << K;
+    for (int i = 0; i < D * D; ++i) {
+        a.re[i] = T(p.M[i].real());
+        a.im[i] = T(p.M[i].imag());
+    }
+    int all[QSIM_MAX_K];
+    int np = 0;
+    a.cmask = 0;
+    for (int b = 0; b < p.k; ++b) all[np++] = p.targets[b];
+    for (int c = 0; c < p.nctrl; ++c) {
+        all[np++] = p.ctrls[c];
+        a.cmask |= 1ull << p.ctrls[c];
+    }
+    std::sort(all, all + np);
+    a.npos = np;
+    for (int i = 0; i < np; ++i) a.pos[i] = all[i];
+    for (int j = 0; j < D; ++j) {
+        uint64_t o = 0;
+        for (int b = 0; b < K; ++b)
+            if ((j >> b) & 1) o |= 1ull << p.targets[b];
+        a.toff[j] = o;
+    }
+    const uint64_t groups = 1ull << (s->n - np);
+    auto *psi = static_cast<c2_t<T> *>(s->data);
+    if (std::is_same<T, float>::value && all[0] >= 1 && groups >= 2) {
+        const uint64_t nt = groups / 2;
+        const dim3 grid(unsigned((nt + kSweepThreads - 1) / kSweepThreads));
+        hipLaunchKernelGGL((k_dense_sweep<T, K, 2>), grid, dim3(kSweepThreads), 0, s->stream, psi, a, nt);
+    } else {
+        const dim3 grid(unsigned((groups + kSweepThreads - 1) / kSweepThreads));
+        hipLaunchKernelGGL((k_dense_sweep<T, K, 1>), grid, dim3(kSweepThreads), 0, s->stream, psi, a, groups);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_dense_sweep(qsim_state s, const Pass &p) {
+    const bool f = s->dtype == QSIM_C64;
+    switch (p.k) {
+        case 1: return f ? dense_sweep_t<float, 1>(s, p) : dense_sweep_t<double, 1>(s, p);
+        case 2: return f ? dense_sweep_t<float, 2>(s, p) : dense_sweep_t<double, 2>(s, p);
+        case 3: return f ? dense_sweep_t<float, 3>(s, p) : dense_sweep_t<double, 3>(s, p);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+// ------------------------------------------------------------ diagonal sweep
+
+template <typename T>
+struct DiagArgs {
+    T dre[64];
+    T dim[64];
+    uint64_t joff[64];
+    int nj;                   // non-unit diagonal entries
+    int npos;
+    int pos[QSIM_MAX_K];
+};
+
+template <typename T, int V>
+__global__ void __launch_bounds__(kSweepThreads)
+k_diag_sweep(c2_t<T> *__restrict__ psi, const DiagArgs<T> a, uint64_t nthreads) {
+    const uint64_t tid = uint64_t(blockIdx.x) * kSweepThreads + threadIdx.x;
+    if (tid >= nthreads) return;
+    const uint64_t x = insert_zeros(tid * V, a.pos, a.npos);
+    for (int i = 0; i < a.nj; ++i) {
+        const T dr = a.dre[i], di = a.dim[i];
+        c2_t<T> *p = psi + x + a.joff[i];
+        if constexpr (V == 2) {
+            float4 w = *reinterpret_cast<const float4 *>(p);
+            float4 o;
+            o.x = dr * w.x - di * w.y; o.y = dr * w.y + di * w.x;
+            o.z = dr * w.z - di * w.w; o.w = dr * w.w + di * w.z;
+            *reinterpret_cast<float4 *>(p) = o;
+        } else {
+            const c2_t<T> w = *p;
+            c2_t<T> o;
+            o.x = dr * w.x - di * w.y;
+            o.y = dr * w.y + di * w.x;
+            *p = o;
+        }
+    }
+}
+
+template <typename T>
+static hipError_t diag_sweep_t(qsim_state s, const Pass &p) {
+    DiagArgs<T> a{};
+    const int D = 1 << p.k;
+    a.nj = 0;
+    for (int j = 0; j < D; ++j) {
+        if (p.M[j] == cd(1.0)) continue;
+        uint64_t o = 0;
+        for (int b = 0; b < p.k; ++b)
+            if ((j >> b) & 1) o |= 1ull << p.targets[b];
+        a.dre[a.nj] = T(p.M[j].real());
+        a.dim[a.nj] = T(p.M[j].imag());
+        a.joff[a.nj] = o;
+        ++a.nj;
+    }
+    if (a.nj == 0) return hipSuccess;
+    a.npos = p.k;
+    for (int b = 0; b < p.k; ++b) a.pos[b] = p.targets[b];
+    const uint64_t groups = 1ull << (s->n - p.k);
+    auto *psi = static_cast<c2_t<T> *>(s->data);
+    if (std::is_same<T, float>::value && p.targets[0] >= 1 && groups >= 2) {
+        const uint64_t nt = groups / 2;
+        hipLaunchKernelGGL((k_diag_sweep<T, 2>), dim3(unsigned((nt + kSweepThreads - 1) / kSweepThreads)),
+                           dim3(kSweepThreads), 0, s->stream, psi, a, nt);
+    } else {
+        hipLaunchKernelGGL((k_diag_sweep<T, 1>), dim3(unsigned((groups + kSweepThreads - 1) / kSweepThreads)),
+                           dim3(kSweepThreads), 0, s->stream, psi, a, groups);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_diag_sweep(qsim_state s, const Pass &p) {
+    return s->dtype == QSIM_C64 ? diag_sweep_t<float>(s, p) : diag_sweep_t<double>(s, p);
+}
+
+// ------------------------------------------------------------ LDS tile pass
+
+constexpr int kTileThreads = 256;
+constexpr int kMaxTileHigh = 16;
+
+template <typename T>
+struct TileArgs {
+    c2_t<T> *psi;
+    const TileOp *ops;
+    const c2_t<T> *pool;
+    int nops;
+    int m, L, H;
+    int hpos[kMaxTileHigh];
+};
+
+// Global index offset of tile-local index l: low L bits stay, bit L+i of l
+// moves to hpos[i].
+template <typename T>
+__device__ __forceinline__ uint64_t tile_scatter(const TileArgs<T> &a, uint32_t l) {
+    uint64_t g = l & ((1u << a.L) - 1u);
+    uint32_t h = l >> a.L;
+    for (int i = 0; i < a.H; ++i) g |= uint64_t((h >> i) & 1u) << a.hpos[i];
+    return g;
+}
+
+template <typename T, int K>
+__device__ __forceinline__ void tile_dense_small(c2_t<T> *lds, const TileOp &op, const c2_t<T> *U, uint32_t M) {
+    constexpr int D = 1 << K;
+    const uint32_t ngroups = M >> K;
+    int pos[K];
+#pragma unroll
+    for (int b = 0; b < K; ++b) pos[b] = op.pos[b];
+    uint32_t off[D];
+#pragma unroll
+    for (int j = 0; j < D; ++j) {
+        uint32_t o = 0;
+#pragma unroll
+        for (int b = 0; b < K; ++b)
+            if ((j >> b) & 1) o |= 1u << pos[b];
+        off[j] = o;
+    }
+    for (uint32_t g = threadIdx.x; g < ngroups; g += kTileThreads) {
+        uint32_t x = g;
+#pragma unroll
+        for (int b = 0; b < K; ++b) {
+            const uint32_t lo = x & ((1u << pos[b]) - 1u);
+            x = ((x - lo) << 1) | lo;
+        }
+        T vr[D], vi[D];
+#pragma unroll
+        for (int j = 0; j < D; ++j) {
+            const c2_t<T> w = lds[x + off[j]];
+            vr[j] = w.x; vi[j] = w.y;
+        }
+#pragma unroll
+        for (int r = 0; r < D; ++r) {
+            T orr = T(0), oi = T(0);
+#pragma unroll
+            for (int c = 0; c < D; ++c) {
+                const c2_t<T> u = U[r * D + c];
+                cfma(orr, oi, u.x, u.y, vr[c], vi[c]);
+            }
+            c2_t<T> w;
+            w.x = orr; w.y = oi;
+            lds[x + off[r]] = w;
+        }
+    }
+}
+
+// Wide dense op (k = 4..6) inside a tile: all outputs of the tile's groups
+// are computed into registers from LDS, then written after a barrier.
+template <typename T, int K>
+__device__ __forceinline__ void tile_dense_wide(c2_t<T> *lds, const TileOp &op, const c2_t<T> *U, uint32_t M) {
+    constexpr int D = 1 << K;
+    const uint32_t ngroups = M >> K;
+    int pos[K];
+#pragma unroll
+    for (int b = 0; b < K; ++b) pos[b] = op.pos[b];
+    // each thread owns outputs (g, r) with index e = threadIdx.x + i * kTileThreads
+    constexpr int kMaxPer = (1 << 13) / kTileThreads;   // M <= 2^13
+    T orr[kMaxPer], oi[kMaxPer];
+    const uint32_t per = (M + kTileThreads - 1) / kTileThreads;
+    for (uint32_t i = 0; i < per; ++i) {
+        const uint32_t e = threadIdx.x + i * kTileThreads;
+        if (e >= M) break;
+        const uint32_t r = e % D, g = e / D;
+        (void)ngroups;
+        uint32_t x = g;
+#pragma unroll
+        for (int b = 0; b < K; ++b) {
+            const uint32_t lo = x & ((1u << pos[b]) - 1u);
+            x = ((x - lo) << 1) | lo;
+        }
+        T ar = T(0), ai = T(0);
+        for (int c = 0; c < D; ++c) {
+            uint32_t o = 0;
+#pragma unroll
+            for (int b = 0; b < K; ++b)
+                if ((c >> b) & 1) o |= 1u << pos[b];
+            const c2_t<T> v = lds[x + o];
+            const c2_t<T> u = U[r * D + c];
+            cfma(ar, ai, u.x, u.y, v.x, v.y);
+        }
+        orr[i] = ar;
+        oi[i] = ai;
+    }
+    __syncthreads();
+    for (uint32_t i = 0; i < per; ++i) {
+        const uint32_t e = threadIdx.x + i * kTileThreads;
+        if (e >= M) break;
+        const uint32_t r = e % D, g = e / D;
+        uint32_t x = g;
+#pragma unroll
+        for (int b = 0; b < K; ++b) {
+            const uint32_t lo = x & ((1u << pos[b]) - 1u);
+            x = ((x - lo) << 1) | lo;
+        }
+        uint32_t o = 0;
+#pragma unroll
+        for (int b = 0; b < K; ++b)
+            if ((r >> b) & 1) o |= 1u << pos[b];
+        c2_t<T> w;
+        w.x = orr[i]; w.y = oi[i];
+        lds[x + o] = w;
+    }
+}
+
+template <typename T>
+__device__ __forceinline__ void tile_diag(c2_t<T> *lds, const TileArgs<T> &a, const TileOp &op,
+                                          const c2_t<T> *Dg, uint64_t base, uint32_t M) {
+    for (uint32_t l = threadIdx.x; l < M; l += kTileThreads) {
+        const uint64_t gidx = base | tile_scatter(a, l);
+        int j = 0;
+        for (int b = 0; b < op.k; ++b) j |= int((gidx >> op.pos[b]) & 1ull) << b;
+        const c2_t<T> d = Dg[j];
+        if (d.x == T(1) && d.y == T(0)) continue;
+        const c2_t<T> w = lds[l];
+        c2_t<T> o;
+        o.x = d.x * w.x - d.y * w.y;
+        o.y = d.x * w.y + d.y * w.x;
+        lds[l] = o;
+    }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kTileThreads) k_tile_pass(const TileArgs<T> a) {
+    extern __shared__ char lds_raw[];
+    c2_t<T> *lds = reinterpret_cast<c2_t<T> *>(lds_raw);
+    const uint32_t M = 1u << a.m;
+    // tile base: the block index with zeros inserted at every tile position
+    uint64_t base = uint64_t(blockIdx.x) << a.L;
+    for (int i = 0; i < a.H; ++i) {
+        const uint64_t lo = base & ((1ull << a.hpos[i]) - 1ull);
+        base = ((base - lo) << 1) | lo;
+    }
+    for (uint32_t l = threadIdx.x; l < M; l += kTileThreads) lds[l] = a.psi[base | tile_scatter(a, l)];
+    __syncthreads();
+    for (int o = 0; o < a.nops; ++o) {
+        const TileOp op = a.ops[o];
+        const c2_t<T> *U = a.pool + op.moff;
+        if (op.type == 1) {
+            tile_diag<T>(lds, a, op, U, base, M);
+        } else {
+            switch (op.k) {
+                case 1: tile_dense_small<T, 1>(lds, op, U, M); break;
+                case 2: tile_dense_small<T, 2>(lds, op, U, M); break;
+                case 3: tile_dense_small<T, 3>(lds, op, U, M); break;
+                case 4: tile_dense_wide<T, 4>(lds, op, U, M); break;
+                case 5: tile_dense_wide<T, 5>(lds, op, U, M); break;
+                case 6: tile_dense_wide<T, 6>(lds, op, U, M); break;
+                default: break;
+            }
+        }
+        __syncthreads();
+    }
+    for (uint32_t l = threadIdx.x; l < M; l += kTileThreads) a.psi[base | tile_scatter(a, l)] = lds[l];
+}
+
+template <typename T>
+static hipError_t tile_pass_t(qsim_state s, const Plan &plan, const Pass &p) {
+    TileArgs<T> a{};
+    a.psi = static_cast<c2_t<T> *>(s->data);
+    a.ops = reinterpret_cast<const TileOp *>(plan.dev) + p.op_begin;
+    a.pool = reinterpret_cast<const c2_t<T> *>(static_cast<const char *>(plan.dev) + plan.pool_dev_off);
+    a.nops = p.op_end - p.op_begin;
+    a.m = p.m;
+    a.L = p.L;
+    a.H = int(p.hpos.size());
+    if (a.H > kMaxTileHigh || a.L + a.H != a.m) return hipErrorInvalidValue;
+    for (int i = 0; i < a.H; ++i) a.hpos[i] = p.hpos[i];
+    const uint64_t ntiles = 1ull << (s->n - p.m);
+    const size_t lds = sizeof(c2_t<T>) << p.m;
+    hipLaunchKernelGGL((k_tile_pass<T>), dim3(unsigned(ntiles)), dim3(kTileThreads), lds, s->stream, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_tile_pass(qsim_state s, const Plan &plan, const Pass &p) {
+    return s->dtype == QSIM_C64 ? tile_pass_t<float>(s, plan, p) : tile_pass_t<double>(s, plan, p);
+}
+
+// ------------------------------------------------------------ basis state
+
+template <typename T>
+__global__ void __launch_bounds__(256) k_set_basis(c2_t<T> *psi, uint64_t N, uint64_t index) {
+    for (uint64_t i = uint64_t(blockIdx.x) * 256 + threadIdx.x; i < N; i += uint64_t(gridDim.x) * 256) {
+        c2_t<T> w;
+        w.x = (i == index) ? T(1) : T(0);
+        w.y = T(0);
+        psi[i] = w;
+    }
+}
+
+hipError_t launch_set_basis(qsim_state s, uint64_t index) {
+    const uint64_t N = 1ull << s->n;
+    const unsigned grid = unsigned(std::min<uint64_t>((N + 255) / 256, 65536));
+    if (s->dtype == QSIM_C64)
+        hipLaunchKernelGGL((k_set_basis<float>), dim3(grid), dim3(256), 0, s->stream,
+                           static_cast<float2 *>(s->data), N, index);
+    else
+        hipLaunchKernelGGL((k_set_basis<double>), dim3(grid), dim3(256), 0, s->stream,
+                           static_cast<double2 *>(s->data), N, index);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------ expectation
+
+// Device form of one Pauli term inside a group sharing the X mask:
+// weight w = coeff * i^{|x & z|} (complex), sign mask z.
+struct ExpTerm {
+    double wr, wi;
+    uint64_t z;
+    uint64_t pad_;
+};
+
+constexpr int kExpThreads = 256;
+
+__device__ __forceinline__ double block_sum(double v) {
+    __shared__ double red[kExpThreads / 64];
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    const int w = threadIdx.x / 64, lane = threadIdx.x % 64;
+    if (lane == 0) red[w] = v;
+    __syncthreads();
+    double t = 0.0;
+    if (threadIdx.x == 0)
+        for (int i = 0; i < kExpThreads / 64; ++i) t += red[i];
+    return t;
+}
+
+// Sum over y of Re[w_t (-1)^{|(y^x) & z_t|} conj(psi_y) psi_{y^x}] for every
+// term of the group, accumulated in double.
+template <typename T>
+__global__ void __launch_bounds__(kExpThreads)
+k_expect(const c2_t<T> *__restrict__ psi, uint64_t N, uint64_t x, const ExpTerm *__restrict__ terms, int nterms,
+         double *__restrict__ partials) {
+    double acc = 0.0;
+    for (uint64_t y = uint64_t(blockIdx.x) * kExpThreads + threadIdx.x; y < N;
+         y += uint64_t(gridDim.x) * kExpThreads) {
+        const c2_t<T> a = psi[y];
+        const c2_t<T> b = x ? psi[y ^ x] : a;
+        // conj(a) * b
+        const double pr = double(a.x) * double(b.x) + double(a.y) * double(b.y);
+        const double pi = double(a.x) * double(b.y) - double(a.y) * double(b.x);
+        const uint64_t src = y ^ x;
+        double s = 0.0;
+        for (int t = 0; t < nterms; ++t) {
+            const ExpTerm e = terms[t];
+            const double v = e.wr * pr - e.wi * pi;
+            s += (__popcll(src & e.z) & 1) ? -v : v;
+        }
+        acc += s;
+    }
+    const double tot = block_sum(acc);
+    if (threadIdx.x == 0) partials[blockIdx.x] = tot;
+}
+
+static int expect_grid(uint64_t N) {
+    const uint64_t want = (N + kExpThreads * 8 - 1) / (kExpThreads * 8);
+    return int(std::max<uint64_t>(1, std::min<uint64_t>(want, 2048)));
+}
+
+hipError_t launch_expect_group(qsim_state s, uint64_t xmask, const void *dev_terms, int nterms,
+                               double *partials, int *nwritten) {
+    const uint64_t N = 1ull << s->n;
+    const int grid = expect_grid(N);
+    const ExpTerm *terms = static_cast<const ExpTerm *>(dev_terms);
+    if (s->dtype == QSIM_C64)
+        hipLaunchKernelGGL((k_expect<float>), dim3(grid), dim3(kExpThreads), 0, s->stream,
+                           static_cast<const float2 *>(s->data), N, xmask, terms, nterms, partials);
+    else
+        hipLaunchKernelGGL((k_expect<double>), dim3(grid), dim3(kExpThreads), 0, s->stream,
+                           static_cast<const double2 *>(s->data), N, xmask, terms, nterms, partials);
+    *nwritten = grid;
+    return hipGetLastError();
+}
+
+__global__ void __launch_bounds__(kExpThreads) k_reduce(const double *__restrict__ partials, int count, double *out) {
+    double acc = 0.0;
+    for (int i = threadIdx.x; i < count; i += kExpThreads) acc += partials[i];
+    const double tot = block_sum(acc);
+    if (threadIdx.x == 0) out[0] = tot;
+}
+
+hipError_t launch_reduce(qsim_state s, const double *partials, int count, double *out) {
+    hipLaunchKernelGGL(k_reduce, dim3(1), dim3(kExpThreads), 0, s->stream, partials, count, out);
+    return hipGetLastError();
+}
+
+int expect_partials_max() { return 2048; }
+
+}  // namespace qsim

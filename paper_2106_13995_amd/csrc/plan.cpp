@@ -1,0 +1,247 @@
+// Host planner: gate fusion and grouping of gates into device passes.
+//
+// A pass is one sweep over the state in HBM:
+//   PASS_DENSE  one gate on <= 3 targets (plus exact control bits, which
+//               restrict the sweep to the amplitudes whose controls are 1);
+//   PASS_DIAG   one diagonal gate, touching only amplitudes whose diagonal
+//               entry differs from 1;
+//   PASS_TILE   a run of gates applied to 2^m-amplitude tiles held in LDS:
+//               every dense gate of the run acts inside the tile's qubit set,
+//               diagonal gates may act anywhere (bits outside the tile are
+//               constant across a tile).
+#include <algorithm>
+#include <cstring>
+#include <set>
+
+#include "qsim_internal.h"
+
+namespace qsim {
+
+size_t amp_bytes(int dtype) { return dtype == QSIM_C128 ? 16 : 8; }
+
+static int max_tile_m(int dtype) { return dtype == QSIM_C128 ? 12 : 13; }
+static int default_tile_m(int dtype) { return dtype == QSIM_C128 ? 11 : 12; }
+static int low_tile_qubits(int dtype) { return dtype == QSIM_C128 ? 4 : 5; }
+
+PlanOptions resolve_options(const qsim_options *o, int n, int dtype) {
+    PlanOptions po;
+    qsim_options z{};
+    if (!o) o = &z;
+    po.fuse_k = o->fuse_k == 0 ? 1 : o->fuse_k;
+    if (o->tile_m == 0)
+        po.tile_m = std::min(n, default_tile_m(dtype));
+    else if (o->tile_m < 0)
+        po.tile_m = -1;
+    else
+        po.tile_m = std::min(n, std::min(o->tile_m, max_tile_m(dtype)));
+    po.use_mfma = o->use_mfma;
+    return po;
+}
+
+Plan::~Plan() {
+    if (dev) (void)hipFree(dev);
+    if (host_pinned) (void)hipHostFree(host_pinned);
+}
+
+// ------------------------------------------------------------ fusion
+
+static uint64_t qmask(const HostGate &g) {
+    uint64_t m = 0;
+    for (int b = 0; b < g.k; ++b) m |= 1ull << g.targets[b];
+    return m;
+}
+
+std::vector<HostGate> fuse_gates(const std::vector<HostGate> &gates, int fuse_k) {
+    if (fuse_k <= 1) return gates;
+    // Blocks in execution order.  A gate joins the last block that shares a
+    // qubit with it when the union stays within fuse_k qubits; otherwise it
+    // may join any later block (it commutes with those, as they share no
+    // qubit with it); otherwise it opens a new block.
+    std::vector<HostGate> blocks;
+    std::vector<uint64_t> masks;
+    for (const HostGate &g : gates) {
+        const uint64_t gm = qmask(g);
+        int last = -1;
+        for (int i = int(blocks.size()) - 1; i >= 0; --i)
+            if (masks[i] & gm) { last = i; break; }
+        int best = -1, best_size = 1 << 30;
+        for (int i = std::max(last, 0); i < int(blocks.size()); ++i) {
+            if (i < last) continue;
+            const int u = __builtin_popcountll(masks[i] | gm);
+            if (u > fuse_k) continue;
+            // prefer the dependency block, then the smallest union
+            const int score = (i == last ? -100 : 0) + u;
+            if (score < best_size) { best_size = score; best = i; }
+        }
+        if (best < 0) {
+            blocks.push_back(g);
+            blocks.back().src_op = -1;
+            masks.push_back(gm);
+        } else {
+            blocks[best] = fuse_pair(blocks[best], g);
+            blocks[best].src_op = -1;
+            masks[best] |= gm;
+        }
+    }
+    return blocks;
+}
+
+// ------------------------------------------------------------ passes
+
+static double diag_bytes(const HostGate &g, int n, int dtype) {
+    int nonunit = 0;
+    const int d = 1 << g.k;
+    for (int j = 0; j < d; ++j)
+        if (g.M[j * d + j] != cd(1.0)) ++nonunit;
+    return 2.0 * double(nonunit) * std::ldexp(1.0, n - g.k) * double(amp_bytes(dtype));
+}
+
+static Pass sweep_pass(const HostGate &g, int n, int dtype) {
+    Pass p;
+    if (is_diagonal(g)) {
+        HostGate s = sorted_targets(g);
+        p.kind = PASS_DIAG;
+        p.k = s.k;
+        for (int b = 0; b < s.k; ++b) p.targets[b] = s.targets[b];
+        const int d = 1 << s.k;
+        p.M.resize(d);
+        for (int j = 0; j < d; ++j) p.M[j] = s.M[j * d + j];
+        p.bytes = diag_bytes(s, n, dtype);
+        return p;
+    }
+    HostGate red;
+    int ctrls[QSIM_MAX_K];
+    const int nc = extract_controls(g, red, ctrls);
+    HostGate s = sorted_targets(red);
+    p.kind = PASS_DENSE;
+    p.k = s.k;
+    for (int b = 0; b < s.k; ++b) p.targets[b] = s.targets[b];
+    p.nctrl = nc;
+    std::sort(ctrls, ctrls + nc);
+    for (int i = 0; i < nc; ++i) p.ctrls[i] = ctrls[i];
+    p.M = s.M;
+    p.bytes = 2.0 * std::ldexp(1.0, n - nc) * double(amp_bytes(dtype));
+    return p;
+}
+
+struct TileBuilder {
+    int n, dtype, m, L;
+    Plan &plan;
+    TileBuilder(Plan &p, int n_, int dt, int m_) : n(n_), dtype(dt), m(m_), L(0), plan(p) {
+        L = std::min(m, low_tile_qubits(dt));
+    }
+
+    // Adds a tile pass over qubit set `q` (must contain the low L qubits)
+    // holding the given gates, in order.
+    void emit(uint64_t q, const std::vector<const HostGate *> &gs) {
+        Pass p;
+        p.kind = PASS_TILE;
+        p.m = m;
+        p.L = L;
+        // pad the tile with the lowest unused qubits (longer contiguous runs)
+        for (int b = 0; b < n && __builtin_popcountll(q) < m; ++b) q |= 1ull << b;
+        int local_of[64];
+        int nl = 0;
+        for (int b = 0; b < L; ++b) local_of[b] = nl++;
+        for (int b = L; b < n; ++b)
+            if ((q >> b) & 1) {
+                p.hpos.push_back(b);
+                local_of[b] = nl++;
+            }
+        p.op_begin = int(plan.tile_ops.size());
+        for (const HostGate *g : gs) {
+            TileOp op{};
+            if (is_diagonal(*g)) {
+                HostGate s = sorted_targets(*g);
+                op.type = 1;
+                op.k = s.k;
+                for (int b = 0; b < s.k; ++b) op.pos[b] = s.targets[b];
+                op.moff = int(plan.tile_pool.size());
+                const int d = 1 << s.k;
+                for (int j = 0; j < d; ++j) plan.tile_pool.push_back(s.M[j * d + j]);
+            } else {
+                HostGate s = sorted_targets(*g);
+                op.type = 0;
+                op.k = s.k;
+                for (int b = 0; b < s.k; ++b) op.pos[b] = local_of[s.targets[b]];
+                op.moff = int(plan.tile_pool.size());
+                plan.tile_pool.insert(plan.tile_pool.end(), s.M.begin(), s.M.end());
+            }
+            plan.tile_ops.push_back(op);
+            p.logical_gates += 1;
+        }
+        p.op_end = int(plan.tile_ops.size());
+        p.bytes = 2.0 * std::ldexp(1.0, n) * double(amp_bytes(dtype));
+        plan.passes.push_back(std::move(p));
+    }
+};
+
+void build_plan(Plan &plan, const std::vector<HostGate> &gates_in, const PlanOptions &po) {
+    const int n = plan.n, dtype = plan.dtype;
+    std::vector<HostGate> gates = fuse_gates(gates_in, po.fuse_k);
+    const int per_block = int(gates_in.size());
+    (void)per_block;
+
+    if (po.tile_m < 0) {
+        for (const HostGate &g : gates) {
+            HostGate red;
+            int ctrls[QSIM_MAX_K];
+            const bool diag = is_diagonal(g);
+            const int nc = diag ? 0 : extract_controls(g, red, ctrls);
+            if (diag || g.k - nc <= 3) {
+                plan.passes.push_back(sweep_pass(g, n, dtype));
+            } else {
+                // wide dense block: a one-gate tile pass over its qubits
+                TileBuilder tb(plan, n, dtype, std::min(n, max_tile_m(dtype)));
+                uint64_t q = (1ull << tb.L) - 1;
+                q |= qmask(g);
+                tb.emit(q, {&g});
+            }
+        }
+    } else {
+        TileBuilder tb(plan, n, dtype, po.tile_m);
+        const uint64_t low = (1ull << tb.L) - 1;
+        std::vector<char> done(gates.size(), 0);
+        size_t remaining = gates.size();
+        size_t first = 0;
+        while (remaining) {
+            while (done[first]) ++first;
+            uint64_t q = low;
+            uint64_t blocked = 0;
+            std::vector<const HostGate *> chosen;
+            for (size_t i = first; i < gates.size(); ++i) {
+                if (done[i]) continue;
+                const HostGate &g = gates[i];
+                const uint64_t gm = qmask(g);
+                if (gm & blocked) {
+                    blocked |= gm;
+                    continue;
+                }
+                if (is_diagonal(g)) {
+                    chosen.push_back(&g);
+                    done[i] = 1;
+                    --remaining;
+                    continue;
+                }
+                if (__builtin_popcountll(q | gm) <= tb.m) {
+                    q |= gm;
+                    chosen.push_back(&g);
+                    done[i] = 1;
+                    --remaining;
+                } else {
+                    blocked |= gm;
+                }
+            }
+            if (chosen.empty()) {
+                // a gate wider than the tile: cannot happen for k <= 6 < m
+                break;
+            }
+            tb.emit(q, chosen);
+        }
+    }
+    // logical gate counts for sweep passes
+    for (Pass &p : plan.passes)
+        if (p.kind != PASS_TILE) p.logical_gates = 1;
+}
+
+}  // namespace qsim

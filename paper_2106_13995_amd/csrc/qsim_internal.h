@@ -1,0 +1,181 @@
+// Internal declarations of the qsim HIP library (gfx950).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <complex>
+#include <cstdint>
+#include <memory>
+#include <string>
+#include <unordered_map>
+#include <vector>
+
+#include "../../include/qsim.h"
+
+namespace qsim {
+
+using cd = std::complex<double>;
+
+// ------------------------------------------------------------ errors
+
+struct Error {
+    qsim_status status;
+    std::string msg;
+};
+
+qsim_status set_error(qsim_status st, const std::string &msg);
+void clear_error();
+
+// ------------------------------------------------------------ host gate model
+
+// A gate in normalised form: a 2^k x 2^k row-major matrix on `targets`
+// (targets[b] is bit b of the matrix index).
+struct HostGate {
+    int k = 0;
+    int targets[QSIM_MAX_K] = {0, 0, 0, 0, 0, 0};
+    std::vector<cd> M;
+    int src_op = -1;   // index of the circuit op it came from (-1 for fused blocks)
+};
+
+// Builds the matrix of a named gate; returns its arity, or -1 for an unknown kind.
+int named_gate_matrix(int kind, const double *angles, cd *U);
+int named_gate_arity(int kind);
+
+// True when every off-diagonal entry of M is exactly zero.
+bool is_diagonal(const HostGate &g);
+
+// Splits a gate into exact controls (bits on which it acts as the identity
+// unless the bit is 1) and the reduced gate on the remaining targets.
+// Returns the number of controls written to `controls` (global qubit ids).
+int extract_controls(const HostGate &g, HostGate &reduced, int *controls);
+
+// Re-expresses a gate with its targets sorted ascending (matrix permuted).
+HostGate sorted_targets(const HostGate &g);
+
+// Product B * A of two gates as one gate on the union of their qubits
+// (A applied first), formed in double precision.
+HostGate fuse_pair(const HostGate &first, const HostGate &second);
+
+// ------------------------------------------------------------ plan
+
+enum PassKind : int { PASS_DENSE = 0, PASS_DIAG = 1, PASS_TILE = 2, PASS_MFMA = 3 };
+
+// Device-side op of a tile pass.
+struct TileOp {
+    int32_t type;      // 0 dense on tile-local positions, 1 diagonal on global positions
+    int32_t k;
+    int32_t pos[QSIM_MAX_K];  // dense: local positions, ascending; diag: global qubits
+    int32_t moff;      // offset of the matrix / diagonal in the pass pool (complex entries)
+    int32_t pad_;
+};
+
+struct Pass {
+    PassKind kind;
+    // sweep passes
+    int k = 0;                        // targets of the (reduced) gate
+    int targets[QSIM_MAX_K] = {};     // ascending
+    int nctrl = 0;
+    int ctrls[QSIM_MAX_K] = {};
+    std::vector<cd> M;                // dense: 2^k x 2^k on sorted targets; diag: 2^k entries
+    // tile passes
+    int m = 0;                        // tile qubits
+    int L = 0;                        // low qubits always in the tile
+    std::vector<int> hpos;            // global positions of the other m - L tile qubits, ascending
+    int op_begin = 0, op_end = 0;     // range in Plan::tile_ops
+    // accounting
+    int logical_gates = 0;
+    double bytes = 0;                 // algorithmic HBM bytes
+};
+
+struct Plan {
+    int n = 0;
+    int dtype = 0;
+    std::vector<Pass> passes;
+    std::vector<TileOp> tile_ops;
+    std::vector<cd> tile_pool;        // matrices / diagonals of tile ops
+    // device copies (tile ops + pool rounded to the state precision)
+    void *dev = nullptr;
+    size_t dev_bytes = 0;
+    size_t pool_dev_off = 0;          // byte offset of the pool inside dev
+    void *host_pinned = nullptr;
+    bool uploaded = false;
+    ~Plan();
+};
+
+struct PlanOptions {
+    int fuse_k = 1;
+    int tile_m = -1;
+    int use_mfma = -1;
+};
+
+PlanOptions resolve_options(const qsim_options *o, int n, int dtype);
+
+// Builds passes from normalised gates.
+void build_plan(Plan &plan, const std::vector<HostGate> &gates, const PlanOptions &po);
+
+// Fusion: greedy merge into blocks of at most fuse_k qubits.
+std::vector<HostGate> fuse_gates(const std::vector<HostGate> &gates, int fuse_k);
+
+// ------------------------------------------------------------ state
+
+struct Profile {
+    bool on = false;
+    struct Rec {
+        int cls;
+        hipEvent_t a, b;
+        double bytes;
+    };
+    std::vector<Rec> recs;
+    std::vector<hipEvent_t> pool;
+};
+
+struct CachedPlan {
+    std::string key;
+    std::unique_ptr<Plan> plan;
+    uint64_t last_use = 0;
+};
+
+}  // namespace qsim
+
+struct qsim_state_s {
+    int n = 0;
+    int dtype = 0;
+    void *data = nullptr;
+    bool owned = false;
+    bool valid = true;
+    int device = 0;
+    hipStream_t stream = nullptr;
+    // scratch for reductions and per-call uploads
+    void *scratch = nullptr;
+    size_t scratch_bytes = 0;
+    void *pinned = nullptr;
+    size_t pinned_bytes = 0;
+    hipEvent_t pinned_ev = nullptr;   // last upload from `pinned`
+    bool pinned_ev_pending = false;
+    qsim::Profile prof;
+    std::vector<qsim::CachedPlan> plans;
+    std::unique_ptr<qsim::Plan> transient;   // last uncached plan (single gates)
+    uint64_t use_clock = 0;
+};
+
+namespace qsim {
+
+size_t amp_bytes(int dtype);
+
+// Launchers (kernels_*.hip).  All return hipSuccess or the launch error.
+hipError_t launch_dense_sweep(qsim_state s, const Pass &p);
+hipError_t launch_diag_sweep(qsim_state s, const Pass &p);
+hipError_t launch_tile_pass(qsim_state s, const Plan &plan, const Pass &p);
+hipError_t launch_set_basis(qsim_state s, uint64_t index);
+
+// Expectation: writes partial sums to `partials` (double) and returns the
+// number written; the final reduction runs in launch_reduce.
+hipError_t launch_expect_group(qsim_state s, uint64_t xmask, const void *dev_terms, int nterms,
+                               double *partials, int *nwritten);
+hipError_t launch_reduce(qsim_state s, const double *partials, int count, double *out);
+
+// Profiling hooks around launches.
+void prof_begin(qsim_state s, int cls, double bytes);
+void prof_end(qsim_state s);
+
+}  // namespace qsim

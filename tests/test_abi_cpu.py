@@ -1,0 +1,143 @@
+"""CPU-side checks of the C-ABI library: it loads, exports every symbol the
+header declares, and rejects invalid arguments before any device work.
+
+No kernel runs here: states are wrapped around a placeholder address that is
+never dereferenced, and every call below fails validation first.
+"""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import workloads as W
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "qsim.h")
+
+q = pytest.importorskip("paper_2106_13995_amd")
+
+FAKE_PTR = 1 << 40   # 256-byte aligned placeholder, never dereferenced
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(qsim_[a-z_]+)\s*\(", text)))
+
+
+def test_header_declarations_all_exported():
+    decl = declared_functions()
+    assert set(decl) == set(q.EXPORTS)
+    lib = ctypes.CDLL(q.LIB_PATH)
+    for name in decl:
+        assert hasattr(lib, name), name
+
+
+def test_struct_layouts_match_header_sizes():
+    # qsim_op: 2 + 6 + 2 int32, 3 doubles, 1 int64 = 72 bytes
+    assert ctypes.sizeof(q.QsimOp) == 72
+    assert ctypes.sizeof(q.QsimPauliTerm) == 24
+    assert ctypes.sizeof(q.QsimOptions) == 16
+
+
+def test_wrap_validation():
+    with pytest.raises(q.QsimError) as e:
+        q.qsim_wrap(FAKE_PTR, 0, q.QSIM_C64)
+    assert e.value.status == q.QSIM_ERR_ARG
+    with pytest.raises(q.QsimError):
+        q.qsim_wrap(FAKE_PTR, 36, q.QSIM_C64)
+    with pytest.raises(q.QsimError):
+        q.qsim_wrap(FAKE_PTR, 35, q.QSIM_C128)
+    with pytest.raises(q.QsimError):
+        q.qsim_wrap(FAKE_PTR + 8, 10, q.QSIM_C64)
+    with pytest.raises(q.QsimError):
+        q.qsim_wrap(FAKE_PTR, 10, 7)
+    with pytest.raises(q.QsimError):
+        q.qsim_wrap(0, 10, q.QSIM_C64)
+
+
+@pytest.fixture
+def fake_state():
+    h = q.qsim_wrap(FAKE_PTR, 8, q.QSIM_C64)
+    yield h
+    q.qsim_free(h)
+
+
+def test_state_info(fake_state):
+    assert q.qsim_state_info(fake_state) == (8, q.QSIM_C64, FAKE_PTR)
+
+
+@pytest.mark.parametrize("targets,k", [([8], 1), ([-1], 1), ([1, 1], 2), ([0, 1, 2, 3, 4, 5, 6], 7)])
+def test_apply_gate_rejects_bad_targets(fake_state, targets, k):
+    U = np.eye(1 << min(k, 6), dtype=np.complex128)
+    t = (ctypes.c_int * len(targets))(*targets)
+    st = q._lib.qsim_apply_gate(ctypes.c_void_p(fake_state), t, k, U.view(np.float64).ctypes.data_as(
+        ctypes.POINTER(ctypes.c_double)))
+    assert st == q.QSIM_ERR_ARG
+    assert q._lib.qsim_last_error().decode()
+
+
+def _circuit_status(h, circ, params=None, opts=None):
+    pc = q.PackedCircuit(circ)
+    p = None if params is None else np.ascontiguousarray(params, dtype=np.float64)
+    return q._lib.qsim_apply_circuit(ctypes.c_void_p(h), ctypes.byref(pc.c), q._dptr(p),
+                                     0 if p is None else p.size,
+                                     ctypes.byref(opts) if opts is not None else None)
+
+
+def test_apply_circuit_validation(fake_state):
+    # width mismatch
+    assert _circuit_status(fake_state, W.ghz_circuit(5)) == q.QSIM_ERR_ARG
+    # duplicate / out-of-range targets are caught in op validation
+    bad = W.Circuit(8, [W.Op("cx", (3, 3))])
+    assert _circuit_status(fake_state, bad) == q.QSIM_ERR_ARG
+    bad = W.Circuit(8, [W.Op("h", (9,))])
+    assert _circuit_status(fake_state, bad) == q.QSIM_ERR_ARG
+    # parametric op without parameters
+    par = W.Circuit(8, [W.op("ry", 0, param=0)], 1)
+    assert _circuit_status(fake_state, par) == q.QSIM_ERR_ARG
+    assert _circuit_status(fake_state, par, params=np.zeros(0)) == q.QSIM_ERR_ARG
+    # parametric index past the end
+    par2 = W.Circuit(8, [W.op("u3", 0, param=1)], 3)
+    assert _circuit_status(fake_state, par2, params=np.zeros(3)) == q.QSIM_ERR_ARG
+    # arity mismatch
+    bad = W.Circuit(8, [W.Op("ccx", (0, 1))])
+    assert _circuit_status(fake_state, bad) == q.QSIM_ERR_ARG
+    # bad options
+    assert _circuit_status(fake_state, W.ghz_circuit(8), opts=q.make_options(fuse_k=7)) == q.QSIM_ERR_ARG
+    assert _circuit_status(fake_state, W.ghz_circuit(8), opts=q.make_options(tile_m=3)) == q.QSIM_ERR_ARG
+
+
+def test_matrix_pool_bounds(fake_state):
+    op = q.QsimOp()
+    op.kind = 0
+    op.k = 2
+    op.targets[0], op.targets[1] = 0, 1
+    op.param = -1
+    op.mat_off = 4          # 16 entries needed from offset 4: pool of 16 is too short
+    mats = np.zeros(16, dtype=np.complex128)
+    c = q.QsimCircuit(8, 1, ctypes.pointer(op), mats.view(np.float64).ctypes.data_as(
+        ctypes.POINTER(ctypes.c_double)), 16)
+    st = q._lib.qsim_apply_circuit(ctypes.c_void_p(fake_state), ctypes.byref(c), None, 0, None)
+    assert st == q.QSIM_ERR_ARG
+    assert "pool" in q._lib.qsim_last_error().decode()
+
+
+def test_expectation_mask_validation(fake_state):
+    H = W.PauliSum(9, [1.0], [0], [1 << 8])
+    out = ctypes.c_double()
+    st = q._lib.qsim_expectation(ctypes.c_void_p(fake_state), ctypes.byref(q.PackedPauliSum(H).h),
+                                 ctypes.byref(out))
+    assert st == q.QSIM_ERR_ARG
+
+
+def test_set_basis_validation(fake_state):
+    with pytest.raises(q.QsimError):
+        q.qsim_set_basis(fake_state, 256)
+
+
+def test_null_handles():
+    assert q._lib.qsim_set_basis(None, 0) == q.QSIM_ERR_ARG
+    assert q._lib.qsim_free(None) == q.QSIM_OK

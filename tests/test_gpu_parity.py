@@ -1,0 +1,275 @@
+"""GPU parity: the HIP path, called through the C ABI, against the CPU oracle.
+
+Bars (amplitudes, relative L2 against the complex128 oracle):
+complex128 <= 1e-12, complex64 <= 2e-5.  Permutation-only circuits on basis
+inputs are compared bit for bit.
+"""
+import numpy as np
+import pytest
+
+import oracle as O
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+TOL = {"c64": 2e-5, "c128": 1e-12}
+MODES = {
+    "sweep": dict(fuse_k=1, tile_m=-1),
+    "tile": dict(fuse_k=1, tile_m=0),
+    "tile9": dict(fuse_k=1, tile_m=9),
+    "fuse2": dict(fuse_k=2, tile_m=-1),
+    "fuse3": dict(fuse_k=3, tile_m=-1),
+    "fuse4": dict(fuse_k=4, tile_m=-1),
+    "fuse5": dict(fuse_k=5, tile_m=-1),
+    "fuse6": dict(fuse_k=6, tile_m=-1),
+    "fuse3_tile": dict(fuse_k=3, tile_m=0),
+    "fuse5_tile": dict(fuse_k=5, tile_m=0),
+}
+
+
+@pytest.fixture(scope="module")
+def qs():
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2106_13995_amd as q
+    return q
+
+
+def _state(q, n, dtype, psi0=None):
+    s = q.State(n, dtype)
+    if psi0 is not None:
+        s.from_numpy(psi0)
+    return s
+
+
+def _rounded(psi, dtype):
+    """The input as the device holds it, back in complex128."""
+    return psi.astype(np.complex64).astype(np.complex128) if dtype == "c64" else psi.copy()
+
+
+# ------------------------------------------------------------ single gates
+
+@pytest.mark.parametrize("dtype", ["c64", "c128"])
+def test_one_qubit_gate_every_target(qs, dtype):
+    n = 14
+    rng = np.random.default_rng(101)
+    psi0 = _rounded(W.random_state(n, rng), dtype)
+    s = _state(qs, n, dtype, psi0)
+    ref = psi0.copy()
+    for t in range(n):
+        U = W.random_unitary(1, rng)
+        s.apply_gate([t], U)
+        O.apply_matrix(ref, [t], U)
+    assert O.rel_l2(s.to_numpy(), ref) <= TOL[dtype]
+
+
+@pytest.mark.parametrize("dtype", ["c64", "c128"])
+def test_two_qubit_gate_all_ordered_pairs(qs, dtype):
+    n = 10
+    rng = np.random.default_rng(102)
+    psi0 = _rounded(W.random_state(n, rng), dtype)
+    s = _state(qs, n, dtype, psi0)
+    ref = psi0.copy()
+    for a in range(n):
+        for b in range(n):
+            if a == b:
+                continue
+            U = W.random_unitary(2, rng)
+            s.apply_gate([a, b], U)
+            O.apply_matrix(ref, [a, b], U)
+    assert O.rel_l2(s.to_numpy(), ref) <= TOL[dtype]
+
+
+@pytest.mark.parametrize("dtype", ["c64", "c128"])
+@pytest.mark.parametrize("k", [3, 4, 5, 6])
+def test_dense_k_qubit_gates_sampled_targets(qs, dtype, k):
+    n = 15
+    rng = np.random.default_rng(103 + k)
+    psi0 = _rounded(W.random_state(n, rng), dtype)
+    s = _state(qs, n, dtype, psi0)
+    ref = psi0.copy()
+    target_sets = [list(range(k)), list(range(n - k, n))[::-1]]
+    target_sets += [[int(t) for t in rng.choice(n, size=k, replace=False)] for _ in range(6)]
+    for tg in target_sets:
+        U = W.random_unitary(k, rng)
+        s.apply_gate(tg, U)
+        O.apply_matrix(ref, tg, U)
+    assert O.rel_l2(s.to_numpy(), ref) <= TOL[dtype]
+
+
+@pytest.mark.parametrize("dtype", ["c64", "c128"])
+def test_non_unitary_matrix(qs, dtype):
+    # the ABI applies any matrix (a projector-like random matrix here)
+    n = 12
+    rng = np.random.default_rng(104)
+    psi0 = _rounded(W.random_state(n, rng), dtype)
+    s = _state(qs, n, dtype, psi0)
+    ref = psi0.copy()
+    for tg in ([0], [11, 3], [5, 9, 1]):
+        M = W.random_matrix(len(tg), rng) * 0.5
+        s.apply_gate(tg, M)
+        O.apply_matrix(ref, tg, M)
+    assert O.rel_l2(s.to_numpy(), ref) <= TOL[dtype]
+
+
+# ------------------------------------------------------------ circuits
+
+@pytest.mark.parametrize("mode", sorted(MODES))
+def test_line12_c128_depth20(qs, mode):
+    """12-qubit random circuit, complex128, depth 20 from |0...0>."""
+    circ = W.random_line_circuit(12, 20, seed=1)
+    ref = O.apply_circuit(circ)
+    s = _state(qs, 12, "c128")
+    s.apply_circuit(circ, **MODES[mode])
+    assert O.rel_l2(s.to_numpy(), ref) <= TOL["c128"]
+
+
+@pytest.mark.parametrize("dtype", ["c64", "c128"])
+@pytest.mark.parametrize("mode", sorted(MODES))
+def test_random_mixed_circuit(qs, dtype, mode):
+    n = 14
+    rng = np.random.default_rng(105)
+    circ = W.random_circuit(n, 120, rng, max_matrix_k=4)
+    psi0 = _rounded(W.random_state(n, rng), dtype)
+    ref = O.apply_circuit(circ, psi0)
+    s = _state(qs, n, dtype, psi0)
+    s.apply_circuit(circ, **MODES[mode])
+    assert O.rel_l2(s.to_numpy(), ref) <= TOL[dtype]
+
+
+@pytest.mark.parametrize("dtype", ["c64", "c128"])
+@pytest.mark.parametrize("mode", ["sweep", "tile", "fuse4", "fuse5_tile"])
+def test_grid_circuit_16q(qs, dtype, mode):
+    circ = W.random_grid_circuit(4, 4, depth=12, seed=2)
+    ref = O.apply_circuit(circ)
+    s = _state(qs, 16, dtype)
+    s.apply_circuit(circ, **MODES[mode])
+    assert O.rel_l2(s.to_numpy(), ref) <= TOL[dtype]
+
+
+@pytest.mark.parametrize("n", [1, 2, 3, 5, 7])
+@pytest.mark.parametrize("mode", ["sweep", "tile", "fuse3", "fuse3_tile"])
+def test_small_registers(qs, n, mode):
+    rng = np.random.default_rng(106 + n)
+    circ = W.random_circuit(n, 30, rng, max_matrix_k=min(n, 3))
+    psi0 = W.random_state(n, rng)
+    ref = O.apply_circuit(circ, psi0)
+    s = _state(qs, n, "c128", psi0)
+    s.apply_circuit(circ, **MODES[mode])
+    assert O.rel_l2(s.to_numpy(), ref) <= TOL["c128"]
+
+
+def test_repeated_calls_use_cached_plan(qs):
+    circ = W.random_line_circuit(13, 6, seed=8)
+    s = _state(qs, 13, "c128")
+    for _ in range(3):
+        s.apply_circuit(circ, fuse_k=3, tile_m=0)
+    ref = O.basis_state(13)
+    for _ in range(3):
+        ref = O.apply_circuit(circ, ref)
+    assert O.rel_l2(s.to_numpy(), ref) <= TOL["c128"]
+
+
+@pytest.mark.parametrize("mode", ["sweep", "tile", "fuse3"])
+def test_parametric_circuit(qs, mode):
+    n, L = 10, 3
+    circ = W.ansatz_circuit(n, L)
+    p = W.ansatz_params(n, L, seed=4)
+    ref = O.apply_circuit(circ, params=p)
+    s = _state(qs, n, "c128")
+    s.apply_circuit(circ, params=p, **MODES[mode])
+    assert O.rel_l2(s.to_numpy(), ref) <= TOL["c128"]
+    # a second parameter vector on a fresh state
+    p2 = p + 0.37
+    s.set_basis(0)
+    s.apply_circuit(circ, params=p2, **MODES[mode])
+    assert O.rel_l2(s.to_numpy(), O.apply_circuit(circ, params=p2)) <= TOL["c128"]
+
+
+# ------------------------------------------------------------ closed forms through the oracle
+
+@pytest.mark.parametrize("mode", ["sweep", "tile", "fuse4"])
+def test_ghz_and_qft(qs, mode):
+    n = 16
+    s = _state(qs, n, "c128")
+    s.apply_circuit(W.ghz_circuit(n), **MODES[mode])
+    assert O.rel_l2(s.to_numpy(), O.apply_circuit(W.ghz_circuit(n))) <= TOL["c128"]
+    x = 12345
+    s.set_basis(x)
+    s.apply_circuit(W.qft_circuit(n), **MODES[mode])
+    ref = O.apply_circuit(W.qft_circuit(n), O.basis_state(n, x))
+    assert O.rel_l2(s.to_numpy(), ref) <= TOL["c128"]
+
+
+@pytest.mark.parametrize("mode", ["sweep", "tile", "fuse3", "fuse6"])
+def test_multiplier_basis_inputs_bit_exact(qs, mode):
+    bits = 3
+    L = W.MultiplierLayout(bits)
+    rng = np.random.default_rng(107)
+    for a, b in rng.integers(0, 1 << bits, size=(4, 2)):
+        circ = W.multiplier_circuit(int(a), int(b), bits)
+        s = _state(qs, L.n, "c64")
+        s.apply_circuit(circ, **MODES[mode])
+        got = s.to_numpy()
+        expect_index = int(O.classical_run(circ, [0])[0])
+        assert expect_index == L.basis_index(int(a), int(b), int(a * b))
+        ref = np.zeros(1 << L.n, dtype=np.complex64)
+        ref[expect_index] = 1.0
+        np.testing.assert_array_equal(got, ref)
+
+
+@pytest.mark.parametrize("dtype", ["c64", "c128"])
+def test_multiplier_superposition(qs, dtype):
+    bits = 3
+    circ = W.multiplier_circuit(0, 5, bits, superpose_a=True)
+    ref = O.apply_circuit(circ)
+    s = _state(qs, W.MultiplierLayout(bits).n, dtype)
+    s.apply_circuit(circ, fuse_k=1, tile_m=-1)
+    assert O.rel_l2(s.to_numpy(), ref) <= TOL[dtype]
+
+
+# ------------------------------------------------------------ expectation
+
+@pytest.mark.parametrize("dtype", ["c64", "c128"])
+@pytest.mark.parametrize("n", [1, 4, 11, 17])
+def test_expectation_random_pauli_sums(qs, dtype, n):
+    rng = np.random.default_rng(108 + n)
+    H = W.random_pauli_sum(n, 25, rng)
+    psi = _rounded(W.random_state(n, rng), dtype)
+    s = _state(qs, n, dtype, psi)
+    got = s.expectation(H)
+    ref = O.expectation(psi, H)
+    scale = sum(abs(c) for c in H.coeffs)
+    assert abs(got - ref) <= 1e-12 * scale
+    # deterministic reduction: bitwise identical on repeat
+    assert s.expectation(H) == got
+
+
+def test_expectation_chain_observable_after_circuit(qs):
+    n = 14
+    circ = W.random_line_circuit(n, 8, seed=9)
+    s = _state(qs, n, "c128")
+    s.apply_circuit(circ, tile_m=0)
+    H = W.chain_observable(n)
+    ref = O.expectation(O.apply_circuit(circ), H)
+    assert abs(s.expectation(H) - ref) < 1e-11
+
+
+def test_expectation_empty_sum(qs):
+    s = _state(qs, 5, "c64")
+    assert s.expectation(W.PauliSum(5, [], [], [])) == 0.0
+
+
+# ------------------------------------------------------------ error handling on a live state
+
+def test_invalid_gate_leaves_state_unchanged(qs):
+    n = 9
+    rng = np.random.default_rng(110)
+    psi0 = W.random_state(n, rng)
+    s = _state(qs, n, "c128", psi0)
+    with pytest.raises(qs.QsimError):
+        s.apply_gate([3, 3], np.eye(4))
+    with pytest.raises(qs.QsimError):
+        s.apply_circuit(W.Circuit(n, [W.op("h", 1), W.Op("cx", (2, 9))]))
+    np.testing.assert_array_equal(s.to_numpy(), psi0)
