@@ -82,10 +82,25 @@ class QsimOptions(ctypes.Structure):
                 ("reserved_", ctypes.c_int32)]
 
 
+def _hip_runtimes() -> set:
+    try:
+        with open("/proc/self/maps") as f:
+            return {ln.split()[-1] for ln in f if "libamdhip64" in ln}
+    except OSError:
+        return set()
+
+
 def _load() -> ctypes.CDLL:
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} is not built; run __graft_entry__.build() first")
+    # torch provides device memory and streams, so the library must bind to
+    # the HIP runtime torch already loaded (same soname) rather than a second
+    # copy: import torch first, then check that only one runtime is mapped.
+    import torch  # noqa: F401
     lib = ctypes.CDLL(LIB_PATH)
+    rts = _hip_runtimes()
+    if len(rts) > 1:
+        raise ImportError(f"more than one HIP runtime is loaded: {sorted(rts)}")
     P, i32, i64, u64 = ctypes.c_void_p, ctypes.c_int, ctypes.c_int64, ctypes.c_uint64
     S = ctypes.c_int
     sig = {

@@ -219,23 +219,34 @@ constexpr int kMaxTileHigh = 16;
 template <typename T>
 struct TileArgs {
     c2_t<T> *psi;
-    const TileOp *ops;
-    const c2_t<T> *pool;
+    const TileOp *ops;          // this pass's ops (global memory)
+    const c2_t<T> *pool;        // this pass's matrices / diagonals (global memory)
     int nops;
+    int npool;                  // complex entries in the pool
     int m, L, H;
     int hpos[kMaxTileHigh];
 };
 
-// Global index offset of tile-local index l: low L bits stay, bit L+i of l
-// moves to hpos[i].
+// Global index offset of tile-local index l: the low L bits stay, bit L+i of
+// l moves to hpos[i].
 template <typename T>
 __device__ __forceinline__ uint64_t tile_scatter(const TileArgs<T> &a, uint32_t l) {
     uint64_t g = l & ((1u << a.L) - 1u);
-    uint32_t h = l >> a.L;
+    const uint32_t h = l >> a.L;
     for (int i = 0; i < a.H; ++i) g |= uint64_t((h >> i) & 1u) << a.hpos[i];
     return g;
 }
 
+__device__ __forceinline__ uint32_t insert_zeros32(uint32_t x, const int *pos, int np) {
+    for (int i = 0; i < np; ++i) {
+        const uint32_t lo = x & ((1u << pos[i]) - 1u);
+        x = ((x - lo) << 1) | lo;
+    }
+    return x;
+}
+
+// Dense op on k <= 3 local positions: one thread per group of 2^k amplitudes.
+// The matrix is read from LDS (the same address in every lane).
 template <typename T, int K>
 __device__ __forceinline__ void tile_dense_small(c2_t<T> *lds, const TileOp &op, const c2_t<T> *U, uint32_t M) {
     constexpr int D = 1 << K;
@@ -251,6 +262,12 @@ __device__ __forceinline__ void tile_dense_small(c2_t<T> *lds, const TileOp &op,
         for (int b = 0; b < K; ++b)
             if ((j >> b) & 1) o |= 1u << pos[b];
         off[j] = o;
+    }
+    // small matrices live in registers for the whole op
+    T ur[K <= 2 ? D * D : 1], ui[K <= 2 ? D * D : 1];
+    if constexpr (K <= 2) {
+#pragma unroll
+        for (int e = 0; e < D * D; ++e) { ur[e] = U[e].x; ui[e] = U[e].y; }
     }
     for (uint32_t g = threadIdx.x; g < ngroups; g += kTileThreads) {
         uint32_t x = g;
@@ -270,8 +287,12 @@ __device__ __forceinline__ void tile_dense_small(c2_t<T> *lds, const TileOp &op,
             T orr = T(0), oi = T(0);
 #pragma unroll
             for (int c = 0; c < D; ++c) {
-                const c2_t<T> u = U[r * D + c];
-                cfma(orr, oi, u.x, u.y, vr[c], vi[c]);
+                if constexpr (K <= 2) {
+                    cfma(orr, oi, ur[r * D + c], ui[r * D + c], vr[c], vi[c]);
+                } else {
+                    const c2_t<T> u = U[r * D + c];
+                    cfma(orr, oi, u.x, u.y, vr[c], vi[c]);
+                }
             }
             c2_t<T> w;
             w.x = orr; w.y = oi;
@@ -280,47 +301,49 @@ __device__ __forceinline__ void tile_dense_small(c2_t<T> *lds, const TileOp &op,
     }
 }
 
-// Wide dense op (k = 4..6) inside a tile: all outputs of the tile's groups
-// are computed into registers from LDS, then written after a barrier.
+// Dense op on k = 4..6 local positions: every output (group, row) is
+// computed into registers from LDS, then written after a barrier.
 template <typename T, int K>
 __device__ __forceinline__ void tile_dense_wide(c2_t<T> *lds, const TileOp &op, const c2_t<T> *U, uint32_t M) {
     constexpr int D = 1 << K;
-    const uint32_t ngroups = M >> K;
     int pos[K];
 #pragma unroll
     for (int b = 0; b < K; ++b) pos[b] = op.pos[b];
-    // each thread owns outputs (g, r) with index e = threadIdx.x + i * kTileThreads
+    auto offset = [&pos](uint32_t j) {
+        uint32_t o = 0;
+#pragma unroll
+        for (int b = 0; b < K; ++b) o |= ((j >> b) & 1u) << pos[b];
+        return o;
+    };
     constexpr int kMaxPer = (1 << 13) / kTileThreads;   // M <= 2^13
     T orr[kMaxPer], oi[kMaxPer];
     const uint32_t per = (M + kTileThreads - 1) / kTileThreads;
-    for (uint32_t i = 0; i < per; ++i) {
-        const uint32_t e = threadIdx.x + i * kTileThreads;
-        if (e >= M) break;
-        const uint32_t r = e % D, g = e / D;
-        (void)ngroups;
-        uint32_t x = g;
 #pragma unroll
-        for (int b = 0; b < K; ++b) {
-            const uint32_t lo = x & ((1u << pos[b]) - 1u);
-            x = ((x - lo) << 1) | lo;
-        }
+    for (int i = 0; i < kMaxPer; ++i) {
+        const uint32_t e = threadIdx.x + uint32_t(i) * kTileThreads;
         T ar = T(0), ai = T(0);
-        for (int c = 0; c < D; ++c) {
-            uint32_t o = 0;
+        if (uint32_t(i) < per && e < M) {
+            const uint32_t r = e % D, g = e / D;
+            uint32_t x = g;
 #pragma unroll
-            for (int b = 0; b < K; ++b)
-                if ((c >> b) & 1) o |= 1u << pos[b];
-            const c2_t<T> v = lds[x + o];
-            const c2_t<T> u = U[r * D + c];
-            cfma(ar, ai, u.x, u.y, v.x, v.y);
+            for (int b = 0; b < K; ++b) {
+                const uint32_t lo = x & ((1u << pos[b]) - 1u);
+                x = ((x - lo) << 1) | lo;
+            }
+            for (int c = 0; c < D; ++c) {
+                const c2_t<T> v = lds[x + offset(uint32_t(c))];
+                const c2_t<T> u = U[r * D + c];
+                cfma(ar, ai, u.x, u.y, v.x, v.y);
+            }
         }
         orr[i] = ar;
         oi[i] = ai;
     }
     __syncthreads();
-    for (uint32_t i = 0; i < per; ++i) {
-        const uint32_t e = threadIdx.x + i * kTileThreads;
-        if (e >= M) break;
+#pragma unroll
+    for (int i = 0; i < kMaxPer; ++i) {
+        const uint32_t e = threadIdx.x + uint32_t(i) * kTileThreads;
+        if (uint32_t(i) >= per || e >= M) continue;
         const uint32_t r = e % D, g = e / D;
         uint32_t x = g;
 #pragma unroll
@@ -328,38 +351,60 @@ __device__ __forceinline__ void tile_dense_wide(c2_t<T> *lds, const TileOp &op, 
             const uint32_t lo = x & ((1u << pos[b]) - 1u);
             x = ((x - lo) << 1) | lo;
         }
-        uint32_t o = 0;
-#pragma unroll
-        for (int b = 0; b < K; ++b)
-            if ((r >> b) & 1) o |= 1u << pos[b];
         c2_t<T> w;
         w.x = orr[i]; w.y = oi[i];
-        lds[x + o] = w;
+        lds[x + offset(r)] = w;
     }
 }
 
+// Diagonal op: the bits of targets outside the tile are fixed for the whole
+// tile (taken from its base index); the loop runs over the groups of the
+// in-tile targets and skips diagonal entries equal to 1 (a branch that is
+// uniform across the workgroup).
 template <typename T>
-__device__ __forceinline__ void tile_diag(c2_t<T> *lds, const TileArgs<T> &a, const TileOp &op,
-                                          const c2_t<T> *Dg, uint64_t base, uint32_t M) {
-    for (uint32_t l = threadIdx.x; l < M; l += kTileThreads) {
-        const uint64_t gidx = base | tile_scatter(a, l);
-        int j = 0;
-        for (int b = 0; b < op.k; ++b) j |= int((gidx >> op.pos[b]) & 1ull) << b;
+__device__ __forceinline__ void tile_diag(c2_t<T> *lds, const TileOp &op, const c2_t<T> *Dg, uint64_t base,
+                                          uint32_t M) {
+    int jfix = 0;
+    for (int i = 0; i < op.k - op.kin; ++i) jfix |= int((base >> op.gpos[i]) & 1ull) << op.gbit[i];
+    const int kin = op.kin;
+    const uint32_t ngroups = M >> kin;
+    for (int c = 0; c < (1 << kin); ++c) {
+        int j = jfix;
+        uint32_t off = 0;
+        for (int i = 0; i < kin; ++i)
+            if ((c >> i) & 1) {
+                j |= 1 << op.jbit[i];
+                off |= 1u << op.pos[i];
+            }
         const c2_t<T> d = Dg[j];
         if (d.x == T(1) && d.y == T(0)) continue;
-        const c2_t<T> w = lds[l];
-        c2_t<T> o;
-        o.x = d.x * w.x - d.y * w.y;
-        o.y = d.x * w.y + d.y * w.x;
-        lds[l] = o;
+        for (uint32_t g = threadIdx.x; g < ngroups; g += kTileThreads) {
+            const uint32_t x = insert_zeros32(g, op.pos, kin) + off;
+            const c2_t<T> w = lds[x];
+            c2_t<T> o;
+            o.x = d.x * w.x - d.y * w.y;
+            o.y = d.x * w.y + d.y * w.x;
+            lds[x] = o;
+        }
     }
 }
 
-template <typename T>
+// LDS layout: [tile: 2^m amplitudes][ops][pool].
+template <typename T, int KMAX>
 __global__ void __launch_bounds__(kTileThreads) k_tile_pass(const TileArgs<T> a) {
     extern __shared__ char lds_raw[];
     c2_t<T> *lds = reinterpret_cast<c2_t<T> *>(lds_raw);
     const uint32_t M = 1u << a.m;
+    TileOp *sops = reinterpret_cast<TileOp *>(lds + M);
+    c2_t<T> *spool = reinterpret_cast<c2_t<T> *>(sops + a.nops);
+    // stage the op list and the matrices in LDS
+    {
+        const int *src = reinterpret_cast<const int *>(a.ops);
+        int *dst = reinterpret_cast<int *>(sops);
+        const int nwords = a.nops * int(sizeof(TileOp) / sizeof(int));
+        for (int w = threadIdx.x; w < nwords; w += kTileThreads) dst[w] = src[w];
+        for (int e = threadIdx.x; e < a.npool; e += kTileThreads) spool[e] = a.pool[e];
+    }
     // tile base: the block index with zeros inserted at every tile position
     uint64_t base = uint64_t(blockIdx.x) << a.L;
     for (int i = 0; i < a.H; ++i) {
@@ -369,19 +414,25 @@ __global__ void __launch_bounds__(kTileThreads) k_tile_pass(const TileArgs<T> a)
     for (uint32_t l = threadIdx.x; l < M; l += kTileThreads) lds[l] = a.psi[base | tile_scatter(a, l)];
     __syncthreads();
     for (int o = 0; o < a.nops; ++o) {
-        const TileOp op = a.ops[o];
-        const c2_t<T> *U = a.pool + op.moff;
+        const TileOp &op = sops[o];
+        const c2_t<T> *U = spool + op.moff;
         if (op.type == 1) {
-            tile_diag<T>(lds, a, op, U, base, M);
+            tile_diag<T>(lds, op, U, base, M);
         } else {
             switch (op.k) {
                 case 1: tile_dense_small<T, 1>(lds, op, U, M); break;
                 case 2: tile_dense_small<T, 2>(lds, op, U, M); break;
                 case 3: tile_dense_small<T, 3>(lds, op, U, M); break;
-                case 4: tile_dense_wide<T, 4>(lds, op, U, M); break;
-                case 5: tile_dense_wide<T, 5>(lds, op, U, M); break;
-                case 6: tile_dense_wide<T, 6>(lds, op, U, M); break;
-                default: break;
+                default:
+                    if constexpr (KMAX > 3) {
+                        switch (op.k) {
+                            case 4: tile_dense_wide<T, 4>(lds, op, U, M); break;
+                            case 5: tile_dense_wide<T, 5>(lds, op, U, M); break;
+                            case 6: tile_dense_wide<T, 6>(lds, op, U, M); break;
+                            default: break;
+                        }
+                    }
+                    break;
             }
         }
         __syncthreads();
@@ -394,16 +445,32 @@ static hipError_t tile_pass_t(qsim_state s, const Plan &plan, const Pass &p) {
     TileArgs<T> a{};
     a.psi = static_cast<c2_t<T> *>(s->data);
     a.ops = reinterpret_cast<const TileOp *>(plan.dev) + p.op_begin;
-    a.pool = reinterpret_cast<const c2_t<T> *>(static_cast<const char *>(plan.dev) + plan.pool_dev_off);
+    a.pool = reinterpret_cast<const c2_t<T> *>(static_cast<const char *>(plan.dev) + plan.pool_dev_off) +
+             p.pool_begin;
     a.nops = p.op_end - p.op_begin;
+    a.npool = p.pool_end - p.pool_begin;
     a.m = p.m;
     a.L = p.L;
     a.H = int(p.hpos.size());
     if (a.H > kMaxTileHigh || a.L + a.H != a.m) return hipErrorInvalidValue;
     for (int i = 0; i < a.H; ++i) a.hpos[i] = p.hpos[i];
     const uint64_t ntiles = 1ull << (s->n - p.m);
-    const size_t lds = sizeof(c2_t<T>) << p.m;
-    hipLaunchKernelGGL((k_tile_pass<T>), dim3(unsigned(ntiles)), dim3(kTileThreads), lds, s->stream, a);
+    const size_t lds = (sizeof(c2_t<T>) << p.m) + sizeof(TileOp) * size_t(a.nops) + sizeof(c2_t<T>) * size_t(a.npool);
+    int kmax = 1;
+    for (int o = p.op_begin; o < p.op_end; ++o)
+        if (plan.tile_ops[size_t(o)].type == 0) kmax = std::max(kmax, int(plan.tile_ops[size_t(o)].k));
+    const void *fn = kmax <= 3 ? reinterpret_cast<const void *>(&k_tile_pass<T, 3>)
+                               : reinterpret_cast<const void *>(&k_tile_pass<T, 6>);
+    if (lds > 65536) {
+        // beyond the default limit: raise it (gfx950 has 160 KiB of LDS per CU)
+        if (lds > 160 * 1024) return hipErrorInvalidValue;
+        hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, int(lds));
+        if (e != hipSuccess) return e;
+    }
+    if (kmax <= 3)
+        hipLaunchKernelGGL((k_tile_pass<T, 3>), dim3(unsigned(ntiles)), dim3(kTileThreads), lds, s->stream, a);
+    else
+        hipLaunchKernelGGL((k_tile_pass<T, 6>), dim3(unsigned(ntiles)), dim3(kTileThreads), lds, s->stream, a);
     return hipGetLastError();
 }
 

@@ -149,28 +149,42 @@ struct TileBuilder {
                 local_of[b] = nl++;
             }
         p.op_begin = int(plan.tile_ops.size());
+        p.pool_begin = int(plan.tile_pool.size());
         for (const HostGate *g : gs) {
             TileOp op{};
-            if (is_diagonal(*g)) {
-                HostGate s = sorted_targets(*g);
+            HostGate s = sorted_targets(*g);
+            op.k = s.k;
+            op.moff = int(plan.tile_pool.size()) - p.pool_begin;
+            const int d = 1 << s.k;
+            if (is_diagonal(s)) {
                 op.type = 1;
-                op.k = s.k;
-                for (int b = 0; b < s.k; ++b) op.pos[b] = s.targets[b];
-                op.moff = int(plan.tile_pool.size());
-                const int d = 1 << s.k;
+                int nin = 0, nout = 0;
+                // targets are ascending globally, hence ascending locally too
+                for (int b = 0; b < s.k; ++b) {
+                    const int t = s.targets[b];
+                    if ((q >> t) & 1) {
+                        op.pos[nin] = local_of[t];
+                        op.jbit[nin] = b;
+                        ++nin;
+                    } else {
+                        op.gpos[nout] = t;
+                        op.gbit[nout] = b;
+                        ++nout;
+                    }
+                }
+                op.kin = nin;
                 for (int j = 0; j < d; ++j) plan.tile_pool.push_back(s.M[j * d + j]);
             } else {
-                HostGate s = sorted_targets(*g);
                 op.type = 0;
-                op.k = s.k;
+                op.kin = s.k;
                 for (int b = 0; b < s.k; ++b) op.pos[b] = local_of[s.targets[b]];
-                op.moff = int(plan.tile_pool.size());
                 plan.tile_pool.insert(plan.tile_pool.end(), s.M.begin(), s.M.end());
             }
             plan.tile_ops.push_back(op);
             p.logical_gates += 1;
         }
         p.op_end = int(plan.tile_ops.size());
+        p.pool_end = int(plan.tile_pool.size());
         p.bytes = 2.0 * std::ldexp(1.0, n) * double(amp_bytes(dtype));
         plan.passes.push_back(std::move(p));
     }

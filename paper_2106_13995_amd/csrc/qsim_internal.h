@@ -61,12 +61,21 @@ HostGate fuse_pair(const HostGate &first, const HostGate &second);
 enum PassKind : int { PASS_DENSE = 0, PASS_DIAG = 1, PASS_TILE = 2, PASS_MFMA = 3 };
 
 // Device-side op of a tile pass.
+//   dense (type 0): 2^k x 2^k matrix on tile-local positions pos[0..k-1]
+//     (ascending; matrix index bit b <-> pos[b]);
+//   diagonal (type 1): 2^k entries; kin targets lie inside the tile at local
+//     positions pos[0..kin-1] (ascending) and give bit jbit[i] of the
+//     diagonal index; the other k - kin lie outside, at global positions
+//     gpos[i], giving bit gbit[i] (constant across a tile).
 struct TileOp {
-    int32_t type;      // 0 dense on tile-local positions, 1 diagonal on global positions
+    int32_t type;
     int32_t k;
-    int32_t pos[QSIM_MAX_K];  // dense: local positions, ascending; diag: global qubits
+    int32_t kin;
     int32_t moff;      // offset of the matrix / diagonal in the pass pool (complex entries)
-    int32_t pad_;
+    int32_t pos[QSIM_MAX_K];
+    int32_t jbit[QSIM_MAX_K];
+    int32_t gpos[QSIM_MAX_K];
+    int32_t gbit[QSIM_MAX_K];
 };
 
 struct Pass {
@@ -82,6 +91,7 @@ struct Pass {
     int L = 0;                        // low qubits always in the tile
     std::vector<int> hpos;            // global positions of the other m - L tile qubits, ascending
     int op_begin = 0, op_end = 0;     // range in Plan::tile_ops
+    int pool_begin = 0, pool_end = 0; // range in Plan::tile_pool
     // accounting
     int logical_gates = 0;
     double bytes = 0;                 // algorithmic HBM bytes
