@@ -7,10 +7,12 @@ complex64 (8 GiB state).  One step applies the whole circuit to the state,
 which stays resident in HBM.  Prints one JSON line.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--fuse-k F] [--tile-m M]
+    python bench.py --calib-copy      # plain 8 GiB device copy (counter calibration)
 """
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -21,6 +23,16 @@ sys.path.insert(0, ROOT)
 
 METRIC = "gate-apps/s + HBM GB/s (30q c64); adjoint grads/s and batched circuits/s"
 HBM_PEAK_GBS = 8000.0
+# Vector ALU ceiling without packed-FP32 instructions (this build keeps them
+# off): 256 CUs x 4 SIMDs x 16 lanes x 2 flop per FMA x 2.4 GHz.  The same
+# figure is the FP64 vector peak.
+ALU_PEAK_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
+KERNEL_SOURCES = {
+    "tile": ["kernels_reg.hip", "kernels.hip"],
+    "sweep_dense": ["kernels.hip"],
+    "sweep_diag": ["kernels.hip"],
+}
+PMC_SUMMARY = os.path.join(ROOT, "profiles", "pmc_traffic.json")
 
 
 def parse():
@@ -35,13 +47,34 @@ def parse():
     ap.add_argument("--modes", default="", help="comma list of extra fuse_k:tile_m variants to time")
     ap.add_argument("--cpu-gates", type=int, default=4, help="gates of the circuit the oracle times")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--calib-copy", action="store_true", help="run a plain device copy of the state size")
     return ap.parse_args()
+
+
+def kernel_hash(cls: str) -> str:
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES.get(cls, []):
+        with open(os.path.join(ROOT, "paper_2106_13995_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(cls: str, config_key: str):
+    """HBM bytes per launch from the committed counter summary, if it was taken
+    on the current kernel source for this workload; else None."""
+    try:
+        with open(PMC_SUMMARY) as f:
+            rec = json.load(f).get(config_key, {}).get(cls)
+    except (OSError, ValueError):
+        return None
+    if not rec or rec.get("source_hash") != kernel_hash(cls):
+        return None
+    return rec.get("bytes_per_launch")
 
 
 def cpu_baseline(circ, ngates: int):
     """The CPU oracle (complex128, one thread) on the first `ngates` gates of
     the same circuit at full width."""
-    import numpy as np
     import oracle as O
     import workloads as W
     sub = W.Circuit(circ.n, circ.ops[:ngates], 0, circ.name + f"_first{ngates}")
@@ -50,12 +83,12 @@ def cpu_baseline(circ, ngates: int):
     O.apply_circuit(sub, psi)
     dt = time.perf_counter() - t0
     del psi
-    return {"value": ngates / dt, "unit": "gate-apps/s", "cores": 1, "kind": "oracle",
-            "sample": f"first {ngates} gates of the {circ.n}-qubit circuit, complex128, 1 thread, "
-                      f"{dt:.1f} s"}
+    return {"value": round(ngates / dt, 4), "unit": "gate-apps/s", "cores": 1, "kind": "oracle",
+            "sample": f"first {ngates} gates (U3) of the same {circ.n}-qubit circuit, complex128 oracle, "
+                      f"1 thread, {dt:.1f} s (includes one copy of the 2^{circ.n}-amplitude input)"}
 
 
-def time_mode(q, torch, s, circ, steps, warmup, fuse_k, tile_m):
+def time_mode(torch, s, circ, steps, warmup, fuse_k, tile_m):
     for _ in range(warmup):
         s.apply_circuit(circ, fuse_k=fuse_k, tile_m=tile_m)
     torch.cuda.synchronize()
@@ -73,11 +106,27 @@ def time_mode(q, torch, s, circ, steps, warmup, fuse_k, tile_m):
     ev_ms = start.elapsed_time(stop)
     stats = {}
     for cls in ("sweep_dense", "sweep_diag", "tile", "mfma"):
-        n, ms, by = s.profile_read(cls)
+        n, ms, by, fl = s.profile_read(cls)
         if n:
-            stats[cls] = (n, ms, by)
+            stats[cls] = (n, ms, by, fl)
     s.profile(False)
     return wall, ev_ms, stats
+
+
+def calib_copy(torch, n: int, dtype: str):
+    real = torch.float32 if dtype == "c64" else torch.float64
+    a = torch.ones(2 << n, dtype=real, device="cuda")
+    b = torch.empty_like(a)
+    torch.cuda.synchronize()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev0.record()
+    b.copy_(a)
+    ev1.record()
+    torch.cuda.synchronize()
+    nbytes = a.numel() * a.element_size()
+    ms = ev0.elapsed_time(ev1)
+    print(json.dumps({"calib_copy_bytes_read": nbytes, "calib_copy_bytes_written": nbytes, "ms": round(ms, 3),
+                      "gbs": round(2 * nbytes / ms / 1e6, 1)}))
 
 
 def main():
@@ -86,6 +135,9 @@ def main():
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
         sys.exit(2)
     import torch
+    if a.calib_copy:
+        calib_copy(torch, a.n, a.dtype)
+        return
     import paper_2106_13995_amd as q
     import workloads as W
 
@@ -95,31 +147,45 @@ def main():
     ngates = len(circ.ops)
     s = q.State(circ.n, a.dtype)
 
-    wall, ev_ms, stats = time_mode(q, torch, s, circ, a.steps, a.warmup, a.fuse_k, a.tile_m)
+    wall, ev_ms, stats = time_mode(torch, s, circ, a.steps, a.warmup, a.fuse_k, a.tile_m)
     ms_per_step = ev_ms / a.steps
     value = ngates * a.steps / (ev_ms / 1e3)
 
-    # dominant kernel class by total time
-    dom = max(stats.items(), key=lambda kv: kv[1][1])
-    dname, (dn, dms, dby) = dom
-    achieved = dby / (dms / 1e3) / 1e9
-    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-                "kernel": dname, "launches": dn, "avg_launch_ms": round(dms / dn, 4),
-                "bytes_per_launch": dby / dn}
+    # dominant kernel class by total time, and what bounds it
+    dname, (dn, dms, dby, dfl) = max(stats.items(), key=lambda kv: kv[1][1])
+    sec = dms / 1e3
+    hbm_gbs = dby / sec / 1e9
+    alu_tfs = dfl / sec / 1e12
+    t_hbm = dby / (HBM_PEAK_GBS * 1e9)
+    t_alu = dfl / (ALU_PEAK_TFLOPS * 1e12)
+    config_key = f"grid{rows}x{cols}_d20_{a.dtype}_fuse{a.fuse_k}_tile{a.tile_m}"
+    traffic = measured_traffic(dname, config_key)
+    if t_alu > t_hbm:
+        roofline = {"bound": "alu", "achieved": round(alu_tfs, 2), "peak": round(ALU_PEAK_TFLOPS, 1),
+                    "unit": "TFLOP/s", "frac": round(alu_tfs / ALU_PEAK_TFLOPS, 4)}
+    else:
+        roofline = {"bound": "hbm", "achieved": round(hbm_gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                    "frac": round(hbm_gbs / HBM_PEAK_GBS, 4)}
+    roofline.update({
+        "traffic": traffic,
+        "kernel": dname, "launches": dn, "avg_launch_ms": round(dms / dn, 4),
+        "bytes_per_launch": dby / dn, "flops_per_launch": dfl / dn,
+        "hbm_gbs": round(hbm_gbs, 1), "hbm_frac": round(hbm_gbs / HBM_PEAK_GBS, 4),
+        "alu_tflops": round(alu_tfs, 2), "alu_frac": round(alu_tfs / ALU_PEAK_TFLOPS, 4),
+    })
     total_bytes = sum(v[2] for v in stats.values())
 
-    # norm check: <psi|psi> (unitary circuit from |0>)
+    # <psi|psi> after the timed steps (unitary circuit from |0...0>)
     norm = s.expectation(W.PauliSum(circ.n, [1.0], [0], [0]))
 
     extra = {}
     for m in [x for x in a.modes.split(",") if x]:
         fk, tm = (int(v) for v in m.split(":"))
         s.set_basis(0)
-        w2, e2, st2 = time_mode(q, torch, s, circ, max(1, a.steps // 2), 1, fk, tm)
-        extra[m] = {"ms_per_step": round(e2 / max(1, a.steps // 2), 3),
-                    "gate_apps_per_s": round(ngates * max(1, a.steps // 2) / (e2 / 1e3), 1),
-                    "passes_per_step": sum(v[0] for v in st2.values()) // max(1, a.steps // 2)}
+        k = max(1, a.steps // 2)
+        w2, e2, st2 = time_mode(torch, s, circ, k, 1, fk, tm)
+        extra[m] = {"ms_per_step": round(e2 / k, 3), "gate_apps_per_s": round(ngates * k / (e2 / 1e3), 1),
+                    "passes_per_step": sum(v[0] for v in st2.values()) // k}
 
     s.close()
     del s

@@ -185,10 +185,13 @@ qsim_status qsim_expectation(qsim_state s, const qsim_pauli_sum *H, double *out_
 /* Plans a circuit for an n-qubit state of `dtype` without touching any
  * device (host-only): validates the ops as qsim_apply_circuit does and
  * reports how many passes of each kind (QSIM_KCLASS_*, `counts` has
- * QSIM_KCLASS_COUNT_ entries) the circuit would take and the algorithmic HBM
- * bytes they move in total.  Any out pointer may be NULL. */
+ * QSIM_KCLASS_COUNT_ entries) the circuit would take, the algorithmic HBM
+ * bytes they move and the floating-point operations their gate arithmetic
+ * takes (8 * 2^k per amplitude a dense k-qubit gate changes, 6 per amplitude
+ * a diagonal entry other than 1 multiplies).  Any out pointer may be NULL. */
 qsim_status qsim_plan_summary(int n, qsim_dtype dtype, const qsim_circuit *c, const double *params,
-                              int64_t nparams, const qsim_options *opts, int64_t *counts, double *bytes);
+                              int64_t nparams, const qsim_options *opts, int64_t *counts, double *bytes,
+                              double *flops);
 
 /* Thread-local description of the last error on this thread ("" if none). */
 const char *qsim_last_error(void);
@@ -198,7 +201,8 @@ const char *qsim_last_error(void);
  * enabled.  qsim_profile_enable(s, 1) clears and starts; 0 stops.
  * qsim_profile_read synchronises the stream and reports, for class `cls`
  * (QSIM_KCLASS_*), the number of launches, their summed duration in
- * milliseconds and the summed algorithmic bytes they move. */
+ * milliseconds, the summed algorithmic bytes they move and the summed
+ * floating-point operations of their gate arithmetic (as qsim_plan_summary). */
 typedef enum {
     QSIM_KCLASS_SWEEP_DENSE = 0,  /* dense / controlled gate sweeps over HBM */
     QSIM_KCLASS_SWEEP_DIAG = 1,   /* diagonal-gate sweeps */
@@ -209,7 +213,8 @@ typedef enum {
 } qsim_kernel_class;
 
 qsim_status qsim_profile_enable(qsim_state s, int on);
-qsim_status qsim_profile_read(qsim_state s, int cls, int64_t *launches, double *ms, double *bytes);
+qsim_status qsim_profile_read(qsim_state s, int cls, int64_t *launches, double *ms, double *bytes,
+                              double *flops);
 
 #ifdef __cplusplus
 }

@@ -118,10 +118,11 @@ def _load() -> ctypes.CDLL:
         "qsim_expectation": ([P, ctypes.POINTER(QsimPauliSum), ctypes.POINTER(ctypes.c_double)], S),
         "qsim_last_error": ([], ctypes.c_char_p),
         "qsim_plan_summary": ([i32, i32, ctypes.POINTER(QsimCircuit), ctypes.POINTER(ctypes.c_double), i64,
-                               ctypes.POINTER(QsimOptions), ctypes.POINTER(i64), ctypes.POINTER(ctypes.c_double)], S),
+                               ctypes.POINTER(QsimOptions), ctypes.POINTER(i64), ctypes.POINTER(ctypes.c_double),
+                               ctypes.POINTER(ctypes.c_double)], S),
         "qsim_profile_enable": ([P, i32], S),
         "qsim_profile_read": ([P, i32, ctypes.POINTER(i64), ctypes.POINTER(ctypes.c_double),
-                               ctypes.POINTER(ctypes.c_double)], S),
+                               ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)], S),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)
@@ -247,25 +248,28 @@ def qsim_expectation(h: int, packedH: PackedPauliSum) -> float:
 
 
 def qsim_plan_summary(n: int, dtype: int, circ, params: Optional[np.ndarray] = None,
-                      opts: Optional[QsimOptions] = None) -> Tuple[Dict[str, int], float]:
-    """Host-only planning: passes per kernel class and algorithmic bytes."""
+                      opts: Optional[QsimOptions] = None) -> Tuple[Dict[str, int], float, float]:
+    """Host-only planning: passes per kernel class, algorithmic bytes and flops."""
     pc = circ if isinstance(circ, PackedCircuit) else PackedCircuit(circ)
     p = None if params is None else np.ascontiguousarray(params, dtype=np.float64)
     counts = (ctypes.c_int64 * len(KCLASS))()
-    by = ctypes.c_double()
+    by, fl = ctypes.c_double(), ctypes.c_double()
     _check(_lib.qsim_plan_summary(n, dtype, ctypes.byref(pc.c), _dptr(p), 0 if p is None else p.size,
-                                  ctypes.byref(opts) if opts is not None else None, counts, ctypes.byref(by)))
-    return {name: counts[i] for name, i in KCLASS.items()}, by.value
+                                  ctypes.byref(opts) if opts is not None else None, counts, ctypes.byref(by),
+                                  ctypes.byref(fl)))
+    return {name: counts[i] for name, i in KCLASS.items()}, by.value, fl.value
 
 
 def qsim_profile_enable(h: int, on: bool) -> None:
     _check(_lib.qsim_profile_enable(ctypes.c_void_p(h), 1 if on else 0))
 
 
-def qsim_profile_read(h: int, cls: int) -> Tuple[int, float, float]:
-    n, ms, by = ctypes.c_int64(), ctypes.c_double(), ctypes.c_double()
-    _check(_lib.qsim_profile_read(ctypes.c_void_p(h), cls, ctypes.byref(n), ctypes.byref(ms), ctypes.byref(by)))
-    return n.value, ms.value, by.value
+def qsim_profile_read(h: int, cls: int) -> Tuple[int, float, float, float]:
+    """(launches, total ms, algorithmic bytes, algorithmic flops) of one kernel class."""
+    n, ms, by, fl = ctypes.c_int64(), ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
+    _check(_lib.qsim_profile_read(ctypes.c_void_p(h), cls, ctypes.byref(n), ctypes.byref(ms), ctypes.byref(by),
+                                  ctypes.byref(fl)))
+    return n.value, ms.value, by.value, fl.value
 
 
 # ------------------------------------------------------------ torch-backed state
@@ -334,5 +338,5 @@ class State:
     def profile(self, on: bool) -> None:
         qsim_profile_enable(self.handle, on)
 
-    def profile_read(self, cls: str) -> Tuple[int, float, float]:
+    def profile_read(self, cls: str) -> Tuple[int, float, float, float]:
         return qsim_profile_read(self.handle, KCLASS[cls])

@@ -42,11 +42,12 @@ static bool valid_dtype(int dtype) { return dtype == QSIM_C64 || dtype == QSIM_C
 
 // ------------------------------------------------------------ profiling
 
-void prof_begin(qsim_state s, int cls, double bytes) {
+void prof_begin(qsim_state s, int cls, double bytes, double flops) {
     if (!s->prof.on) return;
     Profile::Rec r;
     r.cls = cls;
     r.bytes = bytes;
+    r.flops = flops;
     for (hipEvent_t *e : {&r.a, &r.b}) {
         if (!s->prof.pool.empty()) {
             *e = s->prof.pool.back();
@@ -131,10 +132,15 @@ static void pack_pool(const std::vector<cd> &pool, void *dst) {
 
 static qsim_status upload_plan(qsim_state s, Plan &plan) {
     if (plan.uploaded) return QSIM_OK;
+    auto align = [](size_t v) { return (v + 255) & ~size_t(255); };
     const size_t ops_bytes = plan.tile_ops.size() * sizeof(TileOp);
-    plan.pool_dev_off = (ops_bytes + 255) & ~size_t(255);
+    plan.reg_stages_dev_off = align(ops_bytes);
+    const size_t st_bytes = plan.reg_stages.size() * sizeof(RegStage);
+    plan.reg_ops_dev_off = align(plan.reg_stages_dev_off + st_bytes);
+    const size_t rop_bytes = plan.reg_ops.size() * sizeof(RegOp);
+    plan.pool_dev_off = align(plan.reg_ops_dev_off + rop_bytes);
     const size_t total = plan.pool_dev_off + plan.tile_pool.size() * amp_bytes(plan.dtype);
-    if (total == plan.pool_dev_off && ops_bytes == 0) {
+    if (ops_bytes == 0 && st_bytes == 0 && rop_bytes == 0 && plan.tile_pool.empty()) {
         plan.uploaded = true;
         return QSIM_OK;
     }
@@ -150,6 +156,8 @@ static qsim_status upload_plan(qsim_state s, Plan &plan) {
     }
     char *h = static_cast<char *>(plan.host_pinned);
     if (ops_bytes) std::memcpy(h, plan.tile_ops.data(), ops_bytes);
+    if (st_bytes) std::memcpy(h + plan.reg_stages_dev_off, plan.reg_stages.data(), st_bytes);
+    if (rop_bytes) std::memcpy(h + plan.reg_ops_dev_off, plan.reg_ops.data(), rop_bytes);
     if (plan.dtype == QSIM_C64)
         pack_pool<float>(plan.tile_pool, h + plan.pool_dev_off);
     else
@@ -168,16 +176,16 @@ static qsim_status run_plan(qsim_state s, Plan &plan) {
         hipError_t e = hipSuccess;
         switch (p.kind) {
             case PASS_DENSE:
-                prof_begin(s, QSIM_KCLASS_SWEEP_DENSE, p.bytes);
+                prof_begin(s, QSIM_KCLASS_SWEEP_DENSE, p.bytes, p.flops);
                 e = launch_dense_sweep(s, p);
                 break;
             case PASS_DIAG:
-                prof_begin(s, QSIM_KCLASS_SWEEP_DIAG, p.bytes);
+                prof_begin(s, QSIM_KCLASS_SWEEP_DIAG, p.bytes, p.flops);
                 e = launch_diag_sweep(s, p);
                 break;
             case PASS_TILE:
-                prof_begin(s, QSIM_KCLASS_TILE, p.bytes);
-                e = launch_tile_pass(s, plan, p);
+                prof_begin(s, QSIM_KCLASS_TILE, p.bytes, p.flops);
+                e = p.reg_r > 0 ? launch_tile_reg_pass(s, plan, p) : launch_tile_pass(s, plan, p);
                 break;
             default:
                 return set_error(QSIM_ERR_UNSUPPORTED, "pass kind not supported");
@@ -576,7 +584,8 @@ qsim_status qsim_expectation(qsim_state s, const qsim_pauli_sum *H, double *out_
 }
 
 qsim_status qsim_plan_summary(int n, qsim_dtype dtype, const qsim_circuit *c, const double *params,
-                              int64_t nparams, const qsim_options *opts, int64_t *counts, double *bytes) {
+                              int64_t nparams, const qsim_options *opts, int64_t *counts, double *bytes,
+                              double *flops) {
     clear_error();
     if (!valid_dtype(dtype)) return set_error(QSIM_ERR_ARG, "dtype must be QSIM_C64 or QSIM_C128");
     if (n < 1 || n > max_qubits(dtype)) return set_error(QSIM_ERR_ARG, "n outside the supported range");
@@ -592,7 +601,7 @@ qsim_status qsim_plan_summary(int n, qsim_dtype dtype, const qsim_circuit *c, co
     plan.dtype = dtype;
     build_plan(plan, gates, resolve_options(opts, n, dtype));
     int64_t cnt[QSIM_KCLASS_COUNT_] = {0};
-    double by = 0.0;
+    double by = 0.0, fl = 0.0;
     for (const Pass &p : plan.passes) {
         const int cls = p.kind == PASS_DENSE ? QSIM_KCLASS_SWEEP_DENSE
                         : p.kind == PASS_DIAG ? QSIM_KCLASS_SWEEP_DIAG
@@ -600,10 +609,12 @@ qsim_status qsim_plan_summary(int n, qsim_dtype dtype, const qsim_circuit *c, co
                                               : QSIM_KCLASS_MFMA;
         ++cnt[cls];
         by += p.bytes;
+        fl += p.flops;
     }
     if (counts)
         for (int i = 0; i < QSIM_KCLASS_COUNT_; ++i) counts[i] = cnt[i];
     if (bytes) *bytes = by;
+    if (flops) *flops = fl;
     return QSIM_OK;
 }
 
@@ -618,13 +629,14 @@ qsim_status qsim_profile_enable(qsim_state s, int on) {
     return QSIM_OK;
 }
 
-qsim_status qsim_profile_read(qsim_state s, int cls, int64_t *launches, double *ms, double *bytes) {
+qsim_status qsim_profile_read(qsim_state s, int cls, int64_t *launches, double *ms, double *bytes,
+                              double *flops) {
     qsim_status st = check_state(s);
     if (st != QSIM_OK) return st;
     if (cls < 0 || cls >= QSIM_KCLASS_COUNT_) return set_error(QSIM_ERR_ARG, "unknown kernel class");
     QSIM_HIP(s, hipStreamSynchronize(s->stream), "hipStreamSynchronize");
     int64_t cnt = 0;
-    double tot = 0.0, by = 0.0;
+    double tot = 0.0, by = 0.0, fl = 0.0;
     for (auto &r : s->prof.recs) {
         if (r.cls != cls || !r.a || !r.b) continue;
         float t = 0.f;
@@ -632,10 +644,12 @@ qsim_status qsim_profile_read(qsim_state s, int cls, int64_t *launches, double *
         ++cnt;
         tot += t;
         by += r.bytes;
+        fl += r.flops;
     }
     if (launches) *launches = cnt;
     if (ms) *ms = tot;
     if (bytes) *bytes = by;
+    if (flops) *flops = fl;
     return QSIM_OK;
 }
 

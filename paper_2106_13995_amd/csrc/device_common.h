@@ -1,0 +1,34 @@
+// Device helpers shared by the HIP kernel files.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace qsim {
+
+template <typename T> struct C2;
+template <> struct C2<float> { using type = float2; };
+template <> struct C2<double> { using type = double2; };
+
+template <typename T> using c2_t = typename C2<T>::type;
+
+// acc += u * v for complex numbers held as (re, im) pairs.
+template <typename T>
+__device__ __forceinline__ void cfma(T &accr, T &acci, T ur, T ui, T vr, T vi) {
+    accr = fma(ur, vr, accr);
+    accr = fma(-ui, vi, accr);
+    acci = fma(ur, vi, acci);
+    acci = fma(ui, vr, acci);
+}
+
+// Inserts a zero bit at each of the ascending positions pos[0..np-1].
+__device__ __forceinline__ uint64_t insert_zeros(uint64_t x, const int *pos, int np) {
+    for (int i = 0; i < np; ++i) {
+        const uint64_t lo = x & ((1ull << pos[i]) - 1ull);
+        x = ((x - lo) << 1) | lo;
+    }
+    return x;
+}
+
+}  // namespace qsim

@@ -1,0 +1,330 @@
+// Register-staged tile passes for gfx950.
+//
+// One workgroup of 256 threads (four 64-wide waves) owns a tile of 2^m
+// amplitudes; each thread keeps 2^r of them (r = m - 8) in registers.  A
+// stage assigns r tile-local positions to register bits and the other 8 to
+// thread bits; the stage's dense gates act on register bits only, so they run
+// without touching LDS, and its diagonal gates act anywhere (every thread
+// knows the full index of each amplitude it holds).  Between stages the tile
+// is written to LDS under one layout and read back under the next, through an
+// XOR-swizzled address map chosen on the host to keep lanes in distinct
+// banks.  The tile is read from and written back to HBM once per pass.
+#include <hip/hip_runtime.h>
+
+#include "device_common.h"
+#include "qsim_internal.h"
+
+namespace qsim {
+
+constexpr int kRegThreads = 256;
+
+template <typename T>
+struct RegArgs {
+    c2_t<T> *psi;
+    const RegStage *stages;
+    const RegOp *ops;
+    const c2_t<T> *pool;
+    int nstages, nops, npool;
+    int m, L, H;
+    int hpos[16];
+    int8_t ld_t[8], ld_r[kRegBitsMax], st_t[8], st_r[kRegBitsMax];
+};
+
+// Deposits the bits of j into the set bits of mask (compile-time).
+__host__ __device__ constexpr int deposit(int j, int mask) {
+    int out = 0, b = 0;
+    for (int p = 0; p < 31; ++p)
+        if ((mask >> p) & 1) {
+            if ((j >> b) & 1) out |= 1 << p;
+            ++b;
+        }
+    return out;
+}
+
+__host__ __device__ constexpr int popcount_c(int v) {
+    int c = 0;
+    while (v) {
+        c += v & 1;
+        v >>= 1;
+    }
+    return c;
+}
+
+// Dense gate on the register bits of MASK: for every group of register
+// indices that agree outside MASK, multiply by the 2^k x 2^k matrix.
+template <typename T, int R, int MASK>
+__device__ __forceinline__ void apply_mask(T *vr, T *vi, const c2_t<T> *U) {
+    constexpr int K = popcount_c(MASK);
+    constexpr int D = 1 << K;
+    constexpr int NA = 1 << R;
+    if constexpr (K >= 3) {
+        // row by row: one matrix row in registers at a time, outputs kept
+        // aside until every row has read the inputs
+        T outr[NA], outi[NA];
+#pragma unroll
+        for (int rr = 0; rr < D; ++rr) {
+            T ur[D], ui[D];
+#pragma unroll
+            for (int c = 0; c < D; ++c) {
+                const c2_t<T> u = U[rr * D + c];
+                ur[c] = u.x;
+                ui[c] = u.y;
+            }
+#pragma unroll
+            for (int g = 0; g < NA; ++g) {
+                if (g & MASK) continue;
+                T orr = T(0), oi = T(0);
+#pragma unroll
+                for (int c = 0; c < D; ++c)
+                    cfma(orr, oi, ur[c], ui[c], vr[g | deposit(c, MASK)], vi[g | deposit(c, MASK)]);
+                outr[g | deposit(rr, MASK)] = orr;
+                outi[g | deposit(rr, MASK)] = oi;
+            }
+        }
+#pragma unroll
+        for (int i = 0; i < NA; ++i) {
+            vr[i] = outr[i];
+            vi[i] = outi[i];
+        }
+        return;
+    }
+    T ur[D * D], ui[D * D];
+    {
+#pragma unroll
+        for (int e = 0; e < D * D; ++e) {
+            const c2_t<T> u = U[e];
+            ur[e] = u.x;
+            ui[e] = u.y;
+        }
+    }
+#pragma unroll
+    for (int g = 0; g < NA; ++g) {
+        if (g & MASK) continue;
+        T xr[D], xi[D];
+#pragma unroll
+        for (int j = 0; j < D; ++j) {
+            xr[j] = vr[g | deposit(j, MASK)];
+            xi[j] = vi[g | deposit(j, MASK)];
+        }
+#pragma unroll
+        for (int rr = 0; rr < D; ++rr) {
+            T orr = T(0), oi = T(0);
+#pragma unroll
+            for (int c = 0; c < D; ++c) cfma(orr, oi, ur[rr * D + c], ui[rr * D + c], xr[c], xi[c]);
+            vr[g | deposit(rr, MASK)] = orr;
+            vi[g | deposit(rr, MASK)] = oi;
+        }
+    }
+}
+
+template <typename T, int R, int MASK>
+__device__ __forceinline__ void dispatch_dense(int rmask, T *vr, T *vi, const c2_t<T> *U) {
+    if constexpr (MASK < (1 << R)) {
+        if constexpr (popcount_c(MASK) <= 3) {
+            if (rmask == MASK) {
+                apply_mask<T, R, MASK>(vr, vi, U);
+                return;
+            }
+        }
+        dispatch_dense<T, R, MASK + 1>(rmask, vr, vi, U);
+    }
+}
+
+// Diagonal gate: the diagonal index of register amplitude i collects bits
+// from the tile's fixed (out-of-tile) qubits, the thread id and i itself.
+template <typename T, int R>
+__device__ __forceinline__ void apply_diag(T *vr, T *vi, const RegOp &op, const c2_t<T> *Dg, uint64_t base,
+                                           uint32_t t) {
+    constexpr int NA = 1 << R;
+    int jt = 0;
+    for (int b = 0; b < op.nout; ++b) jt |= int((base >> op.gp[b]) & 1ull) << op.gj[b];
+    for (int b = 0; b < op.nthr; ++b) jt |= int((t >> op.tb[b]) & 1u) << op.tj[b];
+    if (op.type == 2) {
+        // one non-unit entry: amplitude i changes only where its index bits match
+        int regj = 0, rval = 0;
+        for (int b = 0; b < op.nreg; ++b) {
+            regj |= 1 << op.rj[b];
+            rval |= ((op.jmatch >> op.rj[b]) & 1) << op.rb[b];
+        }
+        if (((jt ^ op.jmatch) & ~regj) != 0) return;
+        const c2_t<T> d = Dg[op.jmatch];
+        const int rmask = op.rmask;
+#pragma unroll
+        for (int i = 0; i < NA; ++i) {
+            if ((i & rmask) != rval) continue;
+            const T xr = vr[i], xi = vi[i];
+            vr[i] = d.x * xr - d.y * xi;
+            vi[i] = d.x * xi + d.y * xr;
+        }
+    } else {
+#pragma unroll
+        for (int i = 0; i < NA; ++i) {
+            int j = jt;
+            for (int b = 0; b < op.nreg; ++b) j |= ((i >> op.rb[b]) & 1) << op.rj[b];
+            const c2_t<T> d = Dg[j];
+            const T xr = vr[i], xi = vi[i];
+            vr[i] = d.x * xr - d.y * xi;
+            vi[i] = d.x * xi + d.y * xr;
+        }
+    }
+}
+
+template <typename T>
+__device__ __forceinline__ uint32_t thread_part(uint32_t t, const uint16_t *vec) {
+    uint32_t a = 0;
+#pragma unroll
+    for (int b = 0; b < 8; ++b)
+        if ((t >> b) & 1u) a ^= vec[b];
+    return a;
+}
+
+template <typename T, int R>
+__global__ void __launch_bounds__(kRegThreads) k_tile_reg(const RegArgs<T> a) {
+    constexpr int NA = 1 << R;
+    extern __shared__ char lds_raw[];
+    c2_t<T> *lds = reinterpret_cast<c2_t<T> *>(lds_raw);
+    const uint32_t M = 1u << a.m;
+    RegStage *sst = reinterpret_cast<RegStage *>(lds + M);
+    RegOp *sop = reinterpret_cast<RegOp *>(sst + a.nstages);
+    const size_t pool_off = ((sizeof(c2_t<T>) << a.m) + sizeof(RegStage) * size_t(a.nstages) +
+                             sizeof(RegOp) * size_t(a.nops) + 15) & ~size_t(15);
+    c2_t<T> *spool = reinterpret_cast<c2_t<T> *>(lds_raw + pool_off);
+    const uint32_t t = threadIdx.x;
+    {
+        const int *src = reinterpret_cast<const int *>(a.stages);
+        int *dst = reinterpret_cast<int *>(sst);
+        const int ns = a.nstages * int(sizeof(RegStage) / sizeof(int));
+        for (int w = int(t); w < ns; w += kRegThreads) dst[w] = src[w];
+        src = reinterpret_cast<const int *>(a.ops);
+        dst = reinterpret_cast<int *>(sop);
+        const int no = a.nops * int(sizeof(RegOp) / sizeof(int));
+        for (int w = int(t); w < no; w += kRegThreads) dst[w] = src[w];
+        for (int e = int(t); e < a.npool; e += kRegThreads) spool[e] = a.pool[e];
+    }
+    uint64_t base = uint64_t(blockIdx.x) << a.L;
+    for (int i = 0; i < a.H; ++i) {
+        const uint64_t lo = base & ((1ull << a.hpos[i]) - 1ull);
+        base = ((base - lo) << 1) | lo;
+    }
+    T vr[NA], vi[NA];
+    {
+        uint64_t gt = base;
+#pragma unroll
+        for (int b = 0; b < 8; ++b) gt |= uint64_t((t >> b) & 1u) << a.ld_t[b];
+#pragma unroll
+        for (int i = 0; i < NA; ++i) {
+            uint64_t gi = 0;
+#pragma unroll
+            for (int b = 0; b < R; ++b)
+                if ((i >> b) & 1) gi |= 1ull << a.ld_r[b];
+            const c2_t<T> w = a.psi[gt | gi];
+            vr[i] = w.x;
+            vi[i] = w.y;
+        }
+    }
+    __syncthreads();
+    for (int s = 0; s < a.nstages; ++s) {
+        const RegStage &st = sst[s];
+        if (s > 0) {
+            const uint32_t aw = thread_part<T>(t, st.wr_t);
+#pragma unroll
+            for (int i = 0; i < NA; ++i) {
+                uint32_t ai = aw;
+#pragma unroll
+                for (int b = 0; b < R; ++b)
+                    if ((i >> b) & 1) ai ^= st.wr_r[b];
+                c2_t<T> w;
+                w.x = vr[i];
+                w.y = vi[i];
+                lds[ai] = w;
+            }
+            __syncthreads();
+            const uint32_t ar = thread_part<T>(t, st.rd_t);
+#pragma unroll
+            for (int i = 0; i < NA; ++i) {
+                uint32_t ai = ar;
+#pragma unroll
+                for (int b = 0; b < R; ++b)
+                    if ((i >> b) & 1) ai ^= st.rd_r[b];
+                const c2_t<T> w = lds[ai];
+                vr[i] = w.x;
+                vi[i] = w.y;
+            }
+            __syncthreads();
+        }
+        for (int o = st.op_begin; o < st.op_end; ++o) {
+            const RegOp &op = sop[o];
+            const c2_t<T> *U = spool + op.moff;
+            if (op.type == 0)
+                dispatch_dense<T, R, 1>(op.rmask, vr, vi, U);
+            else
+                apply_diag<T, R>(vr, vi, op, U, base, t);
+        }
+    }
+    {
+        uint64_t gt = base;
+#pragma unroll
+        for (int b = 0; b < 8; ++b) gt |= uint64_t((t >> b) & 1u) << a.st_t[b];
+#pragma unroll
+        for (int i = 0; i < NA; ++i) {
+            uint64_t gi = 0;
+#pragma unroll
+            for (int b = 0; b < R; ++b)
+                if ((i >> b) & 1) gi |= 1ull << a.st_r[b];
+            c2_t<T> w;
+            w.x = vr[i];
+            w.y = vi[i];
+            a.psi[gt | gi] = w;
+        }
+    }
+}
+
+template <typename T, int R>
+static hipError_t launch_reg_t(qsim_state s, const Plan &plan, const Pass &p) {
+    RegArgs<T> a{};
+    a.psi = static_cast<c2_t<T> *>(s->data);
+    const char *dev = static_cast<const char *>(plan.dev);
+    a.stages = reinterpret_cast<const RegStage *>(dev + plan.reg_stages_dev_off) + p.stage_begin;
+    a.ops = reinterpret_cast<const RegOp *>(dev + plan.reg_ops_dev_off) + p.rop_begin;
+    a.pool = reinterpret_cast<const c2_t<T> *>(dev + plan.pool_dev_off) + p.pool_begin;
+    a.nstages = p.stage_end - p.stage_begin;
+    a.nops = p.rop_end - p.rop_begin;
+    a.npool = p.pool_end - p.pool_begin;
+    a.m = p.m;
+    a.L = p.L;
+    a.H = int(p.hpos.size());
+    if (a.H > 16 || a.L + a.H != a.m || a.m != R + 8) return hipErrorInvalidValue;
+    for (int i = 0; i < a.H; ++i) a.hpos[i] = p.hpos[i];
+    for (int b = 0; b < 8; ++b) {
+        a.ld_t[b] = p.ld_t[b];
+        a.st_t[b] = p.st_t[b];
+    }
+    for (int b = 0; b < kRegBitsMax; ++b) {
+        a.ld_r[b] = p.ld_r[b];
+        a.st_r[b] = p.st_r[b];
+    }
+    const size_t head = (sizeof(c2_t<T>) << p.m) + sizeof(RegStage) * size_t(a.nstages) +
+                        sizeof(RegOp) * size_t(a.nops);
+    const size_t lds = ((head + 15) & ~size_t(15)) + sizeof(c2_t<T>) * size_t(a.npool);
+    const void *fn = reinterpret_cast<const void *>(&k_tile_reg<T, R>);
+    if (lds > 65536) {
+        if (lds > 160 * 1024) return hipErrorInvalidValue;
+        hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, int(lds));
+        if (e != hipSuccess) return e;
+    }
+    const uint64_t ntiles = 1ull << (s->n - p.m);
+    hipLaunchKernelGGL((k_tile_reg<T, R>), dim3(unsigned(ntiles)), dim3(kRegThreads), lds, s->stream, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_tile_reg_pass(qsim_state s, const Plan &plan, const Pass &p) {
+    const bool f = s->dtype == QSIM_C64;
+    switch (p.reg_r) {
+        case 3: return f ? launch_reg_t<float, 3>(s, plan, p) : launch_reg_t<double, 3>(s, plan, p);
+        case 4: return f ? launch_reg_t<float, 4>(s, plan, p) : launch_reg_t<double, 4>(s, plan, p);
+        case 5: return f ? launch_reg_t<float, 5>(s, plan, p) : launch_reg_t<double, 5>(s, plan, p);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+}  // namespace qsim

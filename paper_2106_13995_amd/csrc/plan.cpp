@@ -107,6 +107,7 @@ static Pass sweep_pass(const HostGate &g, int n, int dtype) {
         p.M.resize(d);
         for (int j = 0; j < d; ++j) p.M[j] = s.M[j * d + j];
         p.bytes = diag_bytes(s, n, dtype);
+        p.flops = 6.0 * p.bytes / (2.0 * double(amp_bytes(dtype)));
         return p;
     }
     HostGate red;
@@ -121,13 +122,18 @@ static Pass sweep_pass(const HostGate &g, int n, int dtype) {
     for (int i = 0; i < nc; ++i) p.ctrls[i] = ctrls[i];
     p.M = s.M;
     p.bytes = 2.0 * std::ldexp(1.0, n - nc) * double(amp_bytes(dtype));
+    p.flops = 8.0 * double(1 << s.k) * std::ldexp(1.0, n - nc);
     return p;
 }
 
+bool build_reg_program(Plan &plan, Pass &p, uint64_t q, const int *local_of,
+                       const std::vector<const HostGate *> &gates);
+
 struct TileBuilder {
     int n, dtype, m, L;
+    bool reg;
     Plan &plan;
-    TileBuilder(Plan &p, int n_, int dt, int m_) : n(n_), dtype(dt), m(m_), L(0), plan(p) {
+    TileBuilder(Plan &p, int n_, int dt, int m_, bool reg_) : n(n_), dtype(dt), m(m_), L(0), reg(reg_), plan(p) {
         L = std::min(m, low_tile_qubits(dt));
     }
 
@@ -150,6 +156,32 @@ struct TileBuilder {
             }
         p.op_begin = int(plan.tile_ops.size());
         p.pool_begin = int(plan.tile_pool.size());
+        p.bytes = 2.0 * std::ldexp(1.0, n) * double(amp_bytes(dtype));
+        p.logical_gates = int(gs.size());
+        p.flops = 0.0;
+        for (const HostGate *g : gs) {
+            const int d = 1 << g->k;
+            if (is_diagonal(*g)) {
+                int nonunit = 0;
+                for (int j = 0; j < d; ++j)
+                    if (g->M[size_t(j) * d + j] != cd(1.0)) ++nonunit;
+                p.flops += 6.0 * double(nonunit) * std::ldexp(1.0, n - g->k);
+            } else {
+                p.flops += 8.0 * double(d) * std::ldexp(1.0, n);
+            }
+        }
+        if (reg) {
+            const size_t nrop = plan.reg_ops.size(), nst = plan.reg_stages.size(), npool = plan.tile_pool.size();
+            if (build_reg_program(plan, p, q, local_of, gs)) {
+                p.op_end = p.op_begin;
+                plan.passes.push_back(std::move(p));
+                return;
+            }
+            plan.reg_ops.resize(nrop);
+            plan.reg_stages.resize(nst);
+            plan.tile_pool.resize(npool);
+            p.reg_r = 0;
+        }
         for (const HostGate *g : gs) {
             TileOp op{};
             HostGate s = sorted_targets(*g);
@@ -181,11 +213,9 @@ struct TileBuilder {
                 plan.tile_pool.insert(plan.tile_pool.end(), s.M.begin(), s.M.end());
             }
             plan.tile_ops.push_back(op);
-            p.logical_gates += 1;
         }
         p.op_end = int(plan.tile_ops.size());
         p.pool_end = int(plan.tile_pool.size());
-        p.bytes = 2.0 * std::ldexp(1.0, n) * double(amp_bytes(dtype));
         plan.passes.push_back(std::move(p));
     }
 };
@@ -206,14 +236,14 @@ void build_plan(Plan &plan, const std::vector<HostGate> &gates_in, const PlanOpt
                 plan.passes.push_back(sweep_pass(g, n, dtype));
             } else {
                 // wide dense block: a one-gate tile pass over its qubits
-                TileBuilder tb(plan, n, dtype, std::min(n, max_tile_m(dtype)));
+                TileBuilder tb(plan, n, dtype, std::min(n, default_tile_m(dtype)), false);
                 uint64_t q = (1ull << tb.L) - 1;
                 q |= qmask(g);
                 tb.emit(q, {&g});
             }
         }
     } else {
-        TileBuilder tb(plan, n, dtype, po.tile_m);
+        TileBuilder tb(plan, n, dtype, po.tile_m, po.reg_tiles);
         const uint64_t low = (1ull << tb.L) - 1;
         std::vector<char> done(gates.size(), 0);
         size_t remaining = gates.size();

@@ -78,6 +78,35 @@ struct TileOp {
     int32_t gbit[QSIM_MAX_K];
 };
 
+// Register-staged tile passes.  A thread holds 2^r amplitudes of a 2^m tile
+// in registers (r = m - 8, 256 threads).  A stage fixes which r tile-local
+// positions are register bits (R) and which 8 are thread bits (T); dense ops
+// of the stage act on register bits only, diagonal ops anywhere.  Between
+// stages the tile is exchanged through LDS with an XOR-swizzled address map.
+constexpr int kRegBitsMax = 5;
+
+struct RegOp {
+    int32_t type;     // 0 dense in registers, 1 diagonal (table), 2 diagonal with one non-unit entry
+    int32_t k;
+    int32_t rmask;    // dense: register bits of the targets (ascending = matrix bit order)
+    int32_t moff;     // pool offset of the matrix / diagonal (complex entries)
+    int32_t nreg, nthr, nout;
+    int32_t jmatch;   // type 2: index of the non-unit diagonal entry
+    int8_t rb[QSIM_MAX_K], rj[QSIM_MAX_K];   // targets in register bits: bit, diagonal-index bit
+    int8_t tb[QSIM_MAX_K], tj[QSIM_MAX_K];   // targets in thread bits
+    int8_t gp[QSIM_MAX_K], gj[QSIM_MAX_K];   // targets outside the tile: global qubit
+    int32_t pad_;
+};
+
+struct RegStage {
+    int32_t op_begin, op_end;   // RegOps of this stage, relative to the pass's first
+    // exchange into this stage (stage 0 is loaded from HBM instead): LDS
+    // address, in amplitudes, contributed by each thread / register bit of
+    // the previous layout (write) and of this stage's layout (read)
+    uint16_t wr_t[8], wr_r[kRegBitsMax], rd_t[8], rd_r[kRegBitsMax];
+    uint16_t pad_;
+};
+
 struct Pass {
     PassKind kind;
     // sweep passes
@@ -92,9 +121,16 @@ struct Pass {
     std::vector<int> hpos;            // global positions of the other m - L tile qubits, ascending
     int op_begin = 0, op_end = 0;     // range in Plan::tile_ops
     int pool_begin = 0, pool_end = 0; // range in Plan::tile_pool
+    // register-staged form (used when reg_r > 0)
+    int reg_r = 0;
+    int rop_begin = 0, rop_end = 0;   // range in Plan::reg_ops
+    int stage_begin = 0, stage_end = 0;
+    int8_t ld_t[8] = {}, ld_r[kRegBitsMax] = {};   // global qubit of each thread / register bit (load)
+    int8_t st_t[8] = {}, st_r[kRegBitsMax] = {};   // (store)
     // accounting
     int logical_gates = 0;
     double bytes = 0;                 // algorithmic HBM bytes
+    double flops = 0;                 // algorithmic floating-point operations
 };
 
 struct Plan {
@@ -103,6 +139,9 @@ struct Plan {
     std::vector<Pass> passes;
     std::vector<TileOp> tile_ops;
     std::vector<cd> tile_pool;        // matrices / diagonals of tile ops
+    std::vector<RegOp> reg_ops;
+    std::vector<RegStage> reg_stages;
+    size_t reg_ops_dev_off = 0, reg_stages_dev_off = 0;
     // device copies (tile ops + pool rounded to the state precision)
     void *dev = nullptr;
     size_t dev_bytes = 0;
@@ -116,6 +155,7 @@ struct PlanOptions {
     int fuse_k = 1;
     int tile_m = -1;
     int use_mfma = -1;
+    bool reg_tiles = true;   // register-staged tile passes where eligible
 };
 
 PlanOptions resolve_options(const qsim_options *o, int n, int dtype);
@@ -133,7 +173,7 @@ struct Profile {
     struct Rec {
         int cls;
         hipEvent_t a, b;
-        double bytes;
+        double bytes, flops;
     };
     std::vector<Rec> recs;
     std::vector<hipEvent_t> pool;
@@ -176,6 +216,7 @@ size_t amp_bytes(int dtype);
 hipError_t launch_dense_sweep(qsim_state s, const Pass &p);
 hipError_t launch_diag_sweep(qsim_state s, const Pass &p);
 hipError_t launch_tile_pass(qsim_state s, const Plan &plan, const Pass &p);
+hipError_t launch_tile_reg_pass(qsim_state s, const Plan &plan, const Pass &p);
 hipError_t launch_set_basis(qsim_state s, uint64_t index);
 
 // Expectation: writes partial sums to `partials` (double) and returns the
@@ -185,7 +226,7 @@ hipError_t launch_expect_group(qsim_state s, uint64_t xmask, const void *dev_ter
 hipError_t launch_reduce(qsim_state s, const double *partials, int count, double *out);
 
 // Profiling hooks around launches.
-void prof_begin(qsim_state s, int cls, double bytes);
+void prof_begin(qsim_state s, int cls, double bytes, double flops = 0.0);
 void prof_end(qsim_state s);
 
 }  // namespace qsim

@@ -1,0 +1,268 @@
+// Host side of register-staged tile passes: splits a tile pass's gates into
+// stages whose dense gates act on the stage's register bits, and builds the
+// XOR-swizzled LDS address maps of the exchanges between stages.
+#include <algorithm>
+#include <cstring>
+
+#include "qsim_internal.h"
+
+namespace qsim {
+
+namespace {
+
+struct LocalGate {
+    const HostGate *g;      // targets ascending (sorted_targets form)
+    bool diag;
+    uint32_t lmask;         // tile-local positions of in-tile targets
+    uint64_t qmask;         // global qubits
+};
+
+int popc(uint64_t v) { return __builtin_popcountll(v); }
+
+// Rank over GF(2) of a set of bit vectors.
+int gf2_rank(uint32_t *v, int n) {
+    int rank = 0;
+    for (int bit = 31; bit >= 0 && rank < n; --bit) {
+        int piv = -1;
+        for (int i = rank; i < n; ++i)
+            if ((v[i] >> bit) & 1u) { piv = i; break; }
+        if (piv < 0) continue;
+        std::swap(v[rank], v[piv]);
+        for (int i = 0; i < n; ++i)
+            if (i != rank && ((v[i] >> bit) & 1u)) v[i] ^= v[rank];
+        ++rank;
+    }
+    return rank;
+}
+
+// Number of bank constraints a thread layout satisfies under address map
+// `addr` (amplitude units): the lanes of each group of 2^g consecutive lanes
+// (g = wb - 1 and g = wb) must fall in distinct bank slots, i.e. the low g
+// bits of their address vectors must be independent.
+int bank_score(const int *T, const uint32_t *addr, int wb) {
+    int score = 0;
+    for (int g = wb - 1; g <= wb; ++g) {
+        uint32_t v[8];
+        for (int b = 0; b < g; ++b) v[b] = addr[T[b]] & ((1u << g) - 1u);
+        if (gf2_rank(v, g) == g) ++score;
+    }
+    return score;
+}
+
+void split_layout(uint32_t R, int m, int *Rpos, int *Tpos) {
+    int nr = 0, nt = 0;
+    for (int p = 0; p < m; ++p) {
+        if ((R >> p) & 1u)
+            Rpos[nr++] = p;
+        else
+            Tpos[nt++] = p;
+    }
+}
+
+// Picks the XOR swizzle of one exchange so that both the writing and the
+// reading layout access LDS without bank conflicts where possible.
+void make_exchange(int m, int wb, uint32_t Rw, uint32_t Rr, RegStage &st, uint64_t seed) {
+    int Rwp[kRegBitsMax], Twp[16], Rrp[kRegBitsMax], Trp[16];
+    split_layout(Rw, m, Rwp, Twp);
+    split_layout(Rr, m, Rrp, Trp);
+    const int r = popc(Rw);
+    uint32_t best[16] = {};
+    int best_score = -1;
+    uint64_t x = seed * 0x9E3779B97F4A7C15ull + 1;
+    for (int attempt = 0; attempt < 4096 && best_score < 4; ++attempt) {
+        uint32_t addr[16];
+        for (int p = 0; p < m; ++p) {
+            uint32_t sw = 0;
+            if (p >= wb && attempt > 0) {
+                x ^= x << 13; x ^= x >> 7; x ^= x << 17;
+                sw = uint32_t(x) & ((1u << wb) - 1u);
+            }
+            addr[p] = (1u << p) ^ sw;
+        }
+        const int sc = bank_score(Twp, addr, wb) + bank_score(Trp, addr, wb);
+        if (sc > best_score) {
+            best_score = sc;
+            std::memcpy(best, addr, sizeof(uint32_t) * m);
+        }
+    }
+    for (int b = 0; b < 8; ++b) {
+        st.wr_t[b] = uint16_t(best[Twp[b]]);
+        st.rd_t[b] = uint16_t(best[Trp[b]]);
+    }
+    for (int b = 0; b < kRegBitsMax; ++b) {
+        st.wr_r[b] = b < r ? uint16_t(best[Rwp[b]]) : 0;
+        st.rd_r[b] = b < r ? uint16_t(best[Rrp[b]]) : 0;
+    }
+}
+
+int index_in(const int *arr, int n, int v) {
+    for (int i = 0; i < n; ++i)
+        if (arr[i] == v) return i;
+    return -1;
+}
+
+// Next register set: the positions of the first dense gates (in dependency
+// order) that fit r bits together.
+uint32_t next_register_set(const std::vector<LocalGate> &gs, const std::vector<char> &done, int r) {
+    uint32_t R = 0;
+    uint64_t blocked = 0;
+    for (size_t i = 0; i < gs.size(); ++i) {
+        if (done[i]) continue;
+        const LocalGate &lg = gs[i];
+        if (lg.qmask & blocked) {
+            blocked |= lg.qmask;
+            continue;
+        }
+        if (lg.diag) continue;
+        if (popc(R | lg.lmask) <= r)
+            R |= lg.lmask;
+        else
+            blocked |= lg.qmask;
+    }
+    return R;
+}
+
+// Pads R to r positions with the highest unused positions (keeping the low
+// positions on thread bits, where consecutive lanes read consecutive
+// addresses).
+uint32_t pad_high(uint32_t R, int r, int m) {
+    for (int p = m - 1; p >= 0 && popc(R) < r; --p) R |= 1u << p;
+    return R;
+}
+
+}  // namespace
+
+bool build_reg_program(Plan &plan, Pass &p, uint64_t q, const int *local_of,
+                       const std::vector<const HostGate *> &gates) {
+    const int m = p.m;
+    const int r = m - 8;
+    if (r < 3 || r > kRegBitsMax) return false;
+    const int wb = plan.dtype == QSIM_C128 ? 4 : 5;
+    const int nlow = std::min(6, m - r);   // lane positions that should stay on thread bits for HBM access
+
+    std::vector<HostGate> sorted;
+    sorted.reserve(gates.size());
+    std::vector<LocalGate> gs;
+    for (const HostGate *g : gates) sorted.push_back(sorted_targets(*g));
+    for (const HostGate &s : sorted) {
+        LocalGate lg{&s, is_diagonal(s), 0u, 0ull};
+        for (int b = 0; b < s.k; ++b) {
+            lg.qmask |= 1ull << s.targets[b];
+            if ((q >> s.targets[b]) & 1) lg.lmask |= 1u << local_of[s.targets[b]];
+        }
+        if (!lg.diag && s.k > 3) return false;
+        gs.push_back(lg);
+    }
+    const uint32_t lowmask = (1u << nlow) - 1u;
+    const uint32_t top = pad_high(0, r, m);
+
+    std::vector<char> done(gs.size(), 0);
+    std::vector<std::pair<uint32_t, std::vector<int>>> stages;
+    uint32_t R = pad_high(next_register_set(gs, done, r), r, m);
+    if (R & lowmask) R = top;   // load with lanes on the low positions, exchange after
+    size_t remaining = gs.size();
+    for (int guard = 0; guard < 4 * int(gs.size()) + 4; ++guard) {
+        std::vector<int> chosen;
+        uint64_t blocked = 0;
+        for (size_t i = 0; i < gs.size(); ++i) {
+            if (done[i]) continue;
+            const LocalGate &lg = gs[i];
+            if (lg.qmask & blocked) {
+                blocked |= lg.qmask;
+                continue;
+            }
+            if (lg.diag || (lg.lmask & ~R) == 0) {
+                chosen.push_back(int(i));
+                done[i] = 1;
+                --remaining;
+            } else {
+                blocked |= lg.qmask;
+            }
+        }
+        stages.push_back({R, chosen});
+        if (!remaining) break;
+        R = pad_high(next_register_set(gs, done, r), r, m);
+    }
+    if (remaining) return false;
+    if (stages.back().first & lowmask) stages.push_back({top, {}});
+
+    // emit
+    p.reg_r = r;
+    p.rop_begin = int(plan.reg_ops.size());
+    p.stage_begin = int(plan.reg_stages.size());
+    // local position -> global qubit
+    int gpos_of_local[16];
+    for (int b = 0; b < 64; ++b)
+        if ((q >> b) & 1) gpos_of_local[local_of[b]] = b;
+    auto set_layout_globals = [&](uint32_t Rm, int8_t *gt, int8_t *gr) {
+        int Rp[kRegBitsMax], Tp[16];
+        split_layout(Rm, m, Rp, Tp);
+        for (int b = 0; b < 8; ++b) gt[b] = int8_t(gpos_of_local[Tp[b]]);
+        for (int b = 0; b < r; ++b) gr[b] = int8_t(gpos_of_local[Rp[b]]);
+    };
+    set_layout_globals(stages.front().first, p.ld_t, p.ld_r);
+    set_layout_globals(stages.back().first, p.st_t, p.st_r);
+
+    uint32_t prevR = 0;
+    for (size_t si = 0; si < stages.size(); ++si) {
+        const uint32_t Rm = stages[si].first;
+        RegStage st{};
+        if (si > 0) make_exchange(m, wb, prevR, Rm, st, si);
+        int Rp[kRegBitsMax], Tp[16];
+        split_layout(Rm, m, Rp, Tp);
+        st.op_begin = int(plan.reg_ops.size()) - p.rop_begin;
+        for (int gi : stages[si].second) {
+            const LocalGate &lg = gs[size_t(gi)];
+            const HostGate &s = *lg.g;
+            RegOp op{};
+            op.k = s.k;
+            op.moff = int(plan.tile_pool.size()) - p.pool_begin;
+            const int d = 1 << s.k;
+            if (!lg.diag) {
+                op.type = 0;
+                for (int b = 0; b < s.k; ++b) op.rmask |= 1 << index_in(Rp, r, local_of[s.targets[b]]);
+                plan.tile_pool.insert(plan.tile_pool.end(), s.M.begin(), s.M.end());
+            } else {
+                int nonunit = 0, last = -1;
+                for (int j = 0; j < d; ++j) {
+                    const cd v = s.M[size_t(j) * d + j];
+                    plan.tile_pool.push_back(v);
+                    if (v != cd(1.0)) { ++nonunit; last = j; }
+                }
+                op.type = nonunit == 1 ? 2 : 1;
+                op.jmatch = last;
+                for (int b = 0; b < s.k; ++b) {
+                    const int t = s.targets[b];
+                    if ((q >> t) & 1) {
+                        const int lp = local_of[t];
+                        const int ri = index_in(Rp, r, lp);
+                        if (ri >= 0) {
+                            op.rb[op.nreg] = int8_t(ri);
+                            op.rj[op.nreg] = int8_t(b);
+                            op.rmask |= 1 << ri;
+                            ++op.nreg;
+                        } else {
+                            op.tb[op.nthr] = int8_t(index_in(Tp, 8, lp));
+                            op.tj[op.nthr] = int8_t(b);
+                            ++op.nthr;
+                        }
+                    } else {
+                        op.gp[op.nout] = int8_t(t);
+                        op.gj[op.nout] = int8_t(b);
+                        ++op.nout;
+                    }
+                }
+            }
+            plan.reg_ops.push_back(op);
+        }
+        st.op_end = int(plan.reg_ops.size()) - p.rop_begin;
+        plan.reg_stages.push_back(st);
+        prevR = Rm;
+    }
+    p.rop_end = int(plan.reg_ops.size());
+    p.stage_end = int(plan.reg_stages.size());
+    p.pool_end = int(plan.tile_pool.size());
+    return true;
+}
+
+}  // namespace qsim
