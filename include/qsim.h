@@ -182,6 +182,26 @@ qsim_status qsim_apply_circuit(qsim_state s, const qsim_circuit *c, const double
  * Synchronises the state's stream.  Qubit masks must lie below 2^n. */
 qsim_status qsim_expectation(qsim_state s, const qsim_pauli_sum *H, double *out_host);
 
+/* Energy and gradient of a variational circuit by the adjoint method.
+ *
+ * E(theta) = <psi_L|H|psi_L> with psi_L = C(theta) psi_0, where psi_0 is the
+ * state's content on entry.  Runs the circuit forward, forms
+ * lambda = H psi_L, then sweeps the ops from last to first: for an op
+ * exp(-i theta_j G / 2) (RX, RY or RZ with param >= 0) it adds
+ * Im <lambda|G|psi> to dE/dtheta_j (the product rule over repeated use of
+ * theta_j), and applies the op's inverse to both psi and lambda.  This
+ * differentiation is not in the paper, whose motivating use is training
+ * variational models with simulated expectation values (Sec. I).
+ *
+ * params: host, nparams doubles; energy: host double; grad: host, nparams
+ * doubles (overwritten; entries no op uses are 0).  Parametric ops of other
+ * kinds return QSIM_ERR_UNSUPPORTED before any device work.  On return the
+ * state holds psi_0 again, up to rounding.  Uses one extra state-sized
+ * device buffer per state (allocated on first use, kept until qsim_free).
+ * Synchronises the state's stream. */
+qsim_status qsim_adjoint_grad(qsim_state s, const qsim_circuit *c, const double *params, int64_t nparams,
+                              const qsim_pauli_sum *H, const qsim_options *opts, double *energy, double *grad);
+
 /* Plans a circuit for an n-qubit state of `dtype` without touching any
  * device (host-only): validates the ops as qsim_apply_circuit does and
  * reports how many passes of each kind (QSIM_KCLASS_*, `counts` has
@@ -208,8 +228,9 @@ typedef enum {
     QSIM_KCLASS_SWEEP_DIAG = 1,   /* diagonal-gate sweeps */
     QSIM_KCLASS_TILE = 2,         /* LDS tile passes */
     QSIM_KCLASS_MFMA = 3,         /* MFMA fused-block passes */
-    QSIM_KCLASS_EXPECT = 4,       /* expectation passes */
-    QSIM_KCLASS_COUNT_ = 5
+    QSIM_KCLASS_EXPECT = 4,       /* expectation passes (and lambda = H psi) */
+    QSIM_KCLASS_ADJOINT = 5,      /* reverse tile passes of the adjoint method */
+    QSIM_KCLASS_COUNT_ = 6
 } qsim_kernel_class;
 
 qsim_status qsim_profile_enable(qsim_state s, int on);

@@ -39,7 +39,7 @@ GATE_CODES: Dict[str, int] = {
     "ccx": 17, "ccz": 18,
 }
 
-KCLASS = {"sweep_dense": 0, "sweep_diag": 1, "tile": 2, "mfma": 3, "expect": 4}
+KCLASS = {"sweep_dense": 0, "sweep_diag": 1, "tile": 2, "mfma": 3, "expect": 4, "adjoint": 5}
 
 MAX_K = 6
 
@@ -48,7 +48,7 @@ EXPORTS = (
     "qsim_alloc", "qsim_wrap", "qsim_free", "qsim_set_stream", "qsim_state_info",
     "qsim_set_basis", "qsim_copy_to_host", "qsim_copy_from_host", "qsim_apply_gate",
     "qsim_apply_circuit", "qsim_expectation", "qsim_last_error", "qsim_profile_enable",
-    "qsim_profile_read", "qsim_plan_summary",
+    "qsim_profile_read", "qsim_plan_summary", "qsim_adjoint_grad",
 )
 
 
@@ -116,6 +116,9 @@ def _load() -> ctypes.CDLL:
         "qsim_apply_circuit": ([P, ctypes.POINTER(QsimCircuit), ctypes.POINTER(ctypes.c_double), i64,
                                 ctypes.POINTER(QsimOptions)], S),
         "qsim_expectation": ([P, ctypes.POINTER(QsimPauliSum), ctypes.POINTER(ctypes.c_double)], S),
+        "qsim_adjoint_grad": ([P, ctypes.POINTER(QsimCircuit), ctypes.POINTER(ctypes.c_double), i64,
+                               ctypes.POINTER(QsimPauliSum), ctypes.POINTER(QsimOptions),
+                               ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)], S),
         "qsim_last_error": ([], ctypes.c_char_p),
         "qsim_plan_summary": ([i32, i32, ctypes.POINTER(QsimCircuit), ctypes.POINTER(ctypes.c_double), i64,
                                ctypes.POINTER(QsimOptions), ctypes.POINTER(i64), ctypes.POINTER(ctypes.c_double),
@@ -260,6 +263,17 @@ def qsim_plan_summary(n: int, dtype: int, circ, params: Optional[np.ndarray] = N
     return {name: counts[i] for name, i in KCLASS.items()}, by.value, fl.value
 
 
+def qsim_adjoint_grad(h: int, packed: PackedCircuit, params: np.ndarray, packedH: PackedPauliSum,
+                      opts: Optional[QsimOptions] = None) -> Tuple[float, np.ndarray]:
+    p = np.ascontiguousarray(params, dtype=np.float64)
+    grad = np.zeros(p.size)
+    e = ctypes.c_double()
+    _check(_lib.qsim_adjoint_grad(ctypes.c_void_p(h), ctypes.byref(packed.c), _dptr(p), p.size,
+                                  ctypes.byref(packedH.h), ctypes.byref(opts) if opts is not None else None,
+                                  ctypes.byref(e), _dptr(grad)))
+    return e.value, grad
+
+
 def qsim_profile_enable(h: int, on: bool) -> None:
     _check(_lib.qsim_profile_enable(ctypes.c_void_p(h), 1 if on else 0))
 
@@ -326,6 +340,12 @@ class State:
     def expectation(self, H) -> float:
         return qsim_expectation(self.handle, PackedPauliSum(H))
 
+    def adjoint_grad(self, circ, params: np.ndarray, H, fuse_k: int = 0, tile_m: int = 0):
+        """(energy, gradient) of <psi|C^dag H C|psi> for the state's current
+        content psi; the state is returned to psi (up to rounding)."""
+        return qsim_adjoint_grad(self.handle, self.packed(circ), params, PackedPauliSum(H),
+                                 make_options(fuse_k, tile_m, 0))
+
     def to_numpy(self) -> np.ndarray:
         out = np.empty(1 << self.n, dtype=np.complex64 if self.dtype == QSIM_C64 else np.complex128)
         qsim_copy_to_host(self.handle, out)
@@ -340,3 +360,34 @@ class State:
 
     def profile_read(self, cls: str) -> Tuple[int, float, float, float]:
         return qsim_profile_read(self.handle, KCLASS[cls])
+
+
+# ------------------------------------------------------------ autograd
+
+def _expectation_function():
+    import torch
+
+    class Expectation(torch.autograd.Function):
+        """E(theta) = <0|C(theta)^dag H C(theta)|0> as a differentiable torch
+        function; forward and the adjoint gradient run in one library call and
+        backward scales the stored gradient by the incoming grad."""
+
+        @staticmethod
+        def forward(ctx, params, state, circ, H):
+            p = params.detach().to("cpu", torch.float64).numpy()
+            state.set_basis(0)
+            e, g = state.adjoint_grad(circ, p, H)
+            ctx.save_for_backward(torch.as_tensor(g, dtype=params.dtype, device=params.device))
+            return torch.as_tensor(e, dtype=params.dtype, device=params.device)
+
+        @staticmethod
+        def backward(ctx, grad_out):
+            (g,) = ctx.saved_tensors
+            return grad_out * g, None, None, None
+
+    return Expectation
+
+
+def expectation(params, state: "State", circ, H):
+    """Differentiable energy of `circ` applied to |0...0> in `state`."""
+    return _expectation_function().apply(params, state, circ, H)

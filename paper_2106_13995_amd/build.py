@@ -11,7 +11,8 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 OBJ = os.path.join(ROOT, "_build", "qsim")
 LIB = os.path.join(HERE, "libqsim.so")
-SOURCES = ["abi.cpp", "gates.cpp", "plan.cpp", "stages.cpp", "kernels.hip", "kernels_reg.hip"]
+SOURCES = ["abi.cpp", "gates.cpp", "plan.cpp", "stages.cpp", "kernels.hip", "kernels_reg.hip",
+           "kernels_adjoint.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"

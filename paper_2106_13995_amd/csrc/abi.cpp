@@ -403,6 +403,7 @@ qsim_status qsim_free(qsim_state s) {
     (void)hipStreamSynchronize(s->stream);
     s->plans.clear();
     s->transient.reset();
+    if (s->adj_lam) (void)hipFree(s->adj_lam);
     prof_clear(s);
     for (hipEvent_t e : s->prof.pool) (void)hipEventDestroy(e);
     if (s->pinned_ev) (void)hipEventDestroy(s->pinned_ev);
@@ -615,6 +616,153 @@ qsim_status qsim_plan_summary(int n, qsim_dtype dtype, const qsim_circuit *c, co
         for (int i = 0; i < QSIM_KCLASS_COUNT_; ++i) counts[i] = cnt[i];
     if (bytes) *bytes = by;
     if (flops) *flops = fl;
+    return QSIM_OK;
+}
+
+qsim_status qsim_adjoint_grad(qsim_state s, const qsim_circuit *c, const double *params, int64_t nparams,
+                              const qsim_pauli_sum *H, const qsim_options *opts, double *energy, double *grad) {
+    qsim_status st = check_state(s);
+    if (st != QSIM_OK) return st;
+    if (!c || !H || !energy) return set_error(QSIM_ERR_ARG, "NULL argument");
+    if (c->n != s->n) return set_error(QSIM_ERR_ARG, "circuit width does not match the state");
+    if (c->nops < 0 || (c->nops > 0 && !c->ops)) return set_error(QSIM_ERR_ARG, "bad op array");
+    if (nparams < 0 || (nparams > 0 && (!params || !grad))) return set_error(QSIM_ERR_ARG, "bad parameter arrays");
+    if (H->nterms < 0 || (H->nterms > 0 && !H->terms)) return set_error(QSIM_ERR_ARG, "bad Pauli sum");
+    const uint64_t lim = (1ull << s->n) - 1;
+    for (int t = 0; t < H->nterms; ++t)
+        if ((H->terms[t].xmask & ~lim) || (H->terms[t].zmask & ~lim))
+            return set_error(QSIM_ERR_ARG, "Pauli mask has a bit at or above n");
+    // validate every op and collect the reverse sweep: probe, then inverse
+    std::vector<HostGate> gates(size_t(c->nops));
+    for (int i = 0; i < c->nops; ++i) {
+        st = make_gate(c, i, params, nparams, gates[size_t(i)]);
+        if (st != QSIM_OK) return st;
+    }
+    std::vector<HostGate> items;
+    std::vector<int> slot_param;
+    items.reserve(2 * gates.size());
+    for (int i = c->nops - 1; i >= 0; --i) {
+        const qsim_op &op = c->ops[i];
+        if (op.param >= 0) {
+            int gen = 0;
+            if (op.kind == QSIM_GATE_RX) gen = 1;
+            else if (op.kind == QSIM_GATE_RY) gen = 2;
+            else if (op.kind == QSIM_GATE_RZ) gen = 3;
+            else
+                return set_error(QSIM_ERR_UNSUPPORTED,
+                                 "op " + std::to_string(i) + ": gradients need RX, RY or RZ for parametric ops");
+            HostGate pr;
+            pr.k = 1;
+            pr.targets[0] = op.targets[0];
+            pr.probe_gen = gen;
+            pr.probe_slot = int(slot_param.size());
+            slot_param.push_back(op.param);
+            items.push_back(pr);
+        }
+        const HostGate &g = gates[size_t(i)];
+        HostGate inv = g;
+        const int d = 1 << g.k;
+        for (int r = 0; r < d; ++r)
+            for (int cc = 0; cc < d; ++cc) inv.M[size_t(r) * d + cc] = std::conj(g.M[size_t(cc) * d + r]);
+        items.push_back(std::move(inv));
+    }
+    // forward: psi <- C psi
+    Plan *fwd = nullptr;
+    st = get_plan(s, c, params, nparams, opts, &fwd);
+    if (st != QSIM_OK) return st;
+    st = run_plan(s, *fwd);
+    if (st != QSIM_OK) return st;
+    const size_t sbytes = amp_bytes(s->dtype) << s->n;
+    if (!s->adj_lam) {
+        if (hipMalloc(&s->adj_lam, sbytes) != hipSuccess) {
+            (void)hipGetLastError();
+            s->adj_lam = nullptr;
+            return set_error(QSIM_ERR_OOM, "cannot allocate the adjoint state");
+        }
+    }
+    // reverse plan
+    std::unique_ptr<Plan> rev(new (std::nothrow) Plan());
+    if (!rev) return set_error(QSIM_ERR_OOM, "host allocation failed");
+    rev->n = s->n;
+    rev->dtype = s->dtype;
+    const int adj_m = s->dtype == QSIM_C128 ? 10 : 11;
+    build_adjoint_plan(*rev, items, adj_m);
+    st = upload_plan(s, *rev);
+    if (st != QSIM_OK) return st;
+    const int nprobes = int(slot_param.size());
+    const int mtile = std::min(s->n, adj_m);
+    const int ntiles = 1 << (s->n - mtile);
+    // scratch: [energy partials][groups][terms][probe partials][probe sums + energy]
+    struct DevGroup {
+        uint64_t x;
+        int32_t first, count;
+    };
+    struct DevTerm {
+        double wr, wi;
+        uint64_t z, pad;
+    };
+    std::map<uint64_t, std::vector<int>> bygroup;
+    for (int t = 0; t < H->nterms; ++t) bygroup[H->terms[t].xmask].push_back(t);
+    const int egrid = pauli_apply_grid(1ull << s->n);
+    auto align = [](size_t v) { return (v + 255) & ~size_t(255); };
+    const size_t off_groups = align(sizeof(double) * size_t(egrid));
+    const size_t gbytes = sizeof(DevGroup) * std::max<size_t>(1, bygroup.size());
+    const size_t off_terms = align(off_groups + gbytes);
+    const size_t tbytes = sizeof(DevTerm) * size_t(std::max(1, H->nterms));
+    const size_t off_pp = align(off_terms + tbytes);
+    const size_t off_sums = align(off_pp + sizeof(double) * size_t(nprobes) * size_t(ntiles));
+    const size_t total = off_sums + sizeof(double) * size_t(nprobes + 1);
+    st = ensure_scratch(s, total);
+    if (st != QSIM_OK) return st;
+    st = ensure_pinned(s, off_terms - off_groups + tbytes);
+    if (st != QSIM_OK) return st;
+    char *hp = static_cast<char *>(s->pinned);
+    DevGroup *hg = reinterpret_cast<DevGroup *>(hp);
+    DevTerm *ht = reinterpret_cast<DevTerm *>(hp + (off_terms - off_groups));
+    int ng = 0, slot = 0;
+    for (auto &kv : bygroup) {
+        hg[ng].x = kv.first;
+        hg[ng].first = slot;
+        hg[ng].count = int(kv.second.size());
+        ++ng;
+        for (int t : kv.second) {
+            const qsim_pauli_term &pt = H->terms[t];
+            const int ny = __builtin_popcountll(pt.xmask & pt.zmask) & 3;
+            const double re[4] = {1, 0, -1, 0}, im[4] = {0, 1, 0, -1};
+            ht[slot].wr = pt.coeff * re[ny];
+            ht[slot].wi = pt.coeff * im[ny];
+            ht[slot].z = pt.zmask;
+            ht[slot].pad = 0;
+            ++slot;
+        }
+    }
+    char *scr = static_cast<char *>(s->scratch);
+    st = upload_staged(s, scr + off_groups, off_terms - off_groups + tbytes);
+    if (st != QSIM_OK) return st;
+    double *epart = reinterpret_cast<double *>(scr);
+    double *pp = reinterpret_cast<double *>(scr + off_pp);
+    double *sums = reinterpret_cast<double *>(scr + off_sums);
+    // lambda <- H psi, energy partials
+    prof_begin(s, QSIM_KCLASS_EXPECT, 2.0 * double(sbytes) * double(std::max(1, ng)));
+    QSIM_HIP(s, launch_pauli_apply(s, s->adj_lam, scr + off_groups, ng, scr + off_terms, epart), "pauli apply");
+    prof_end(s);
+    QSIM_HIP(s, launch_reduce(s, epart, egrid, sums + nprobes), "reduce");
+    // reverse sweep over (psi, lambda)
+    for (const Pass &p : rev->passes) {
+        prof_begin(s, QSIM_KCLASS_ADJOINT, p.bytes, 2.0 * p.flops);
+        hipError_t e = launch_adjoint_pass(s, *rev, p, s->adj_lam, pp);
+        prof_end(s);
+        if (e != hipSuccess) return device_error(s, e, "adjoint pass");
+    }
+    QSIM_HIP(s, launch_reduce_rows(s, pp, nprobes, ntiles, sums), "reduce rows");
+    std::vector<double> hs(size_t(nprobes) + 1);
+    QSIM_HIP(s, hipMemcpyAsync(hs.data(), sums, sizeof(double) * hs.size(), hipMemcpyDeviceToHost, s->stream),
+             "hipMemcpyAsync");
+    QSIM_HIP(s, hipStreamSynchronize(s->stream), "hipStreamSynchronize");
+    s->pinned_ev_pending = false;
+    *energy = hs[size_t(nprobes)];
+    for (int64_t j = 0; j < nparams; ++j) grad[j] = 0.0;
+    for (int k = 0; k < nprobes; ++k) grad[slot_param[size_t(k)]] += hs[size_t(k)];
     return QSIM_OK;
 }
 

@@ -31,4 +31,21 @@ __device__ __forceinline__ uint64_t insert_zeros(uint64_t x, const int *pos, int
     return x;
 }
 
+constexpr int kBlockThreads = 256;
+
+// Sum of one double per thread over a 256-thread block (four 64-wide waves);
+// the result is valid in thread 0.  Fixed order: bitwise reproducible.
+__device__ __forceinline__ double block_sum(double v) {
+    __shared__ double red[kBlockThreads / 64];
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    const int w = threadIdx.x / 64, lane = threadIdx.x % 64;
+    __syncthreads();
+    if (lane == 0) red[w] = v;
+    __syncthreads();
+    double t = 0.0;
+    if (threadIdx.x == 0)
+        for (int i = 0; i < kBlockThreads / 64; ++i) t += red[i];
+    return t;
+}
+
 }  // namespace qsim

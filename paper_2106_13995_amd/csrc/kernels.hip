@@ -8,6 +8,7 @@
 
 #include "device_common.h"
 #include "qsim_internal.h"
+#include "tile_ops.h"
 
 namespace qsim {
 
@@ -189,182 +190,6 @@ hipError_t launch_diag_sweep(qsim_state s, const Pass &p) {
 
 // ------------------------------------------------------------ LDS tile pass
 
-constexpr int kTileThreads = 256;
-constexpr int kMaxTileHigh = 16;
-
-template <typename T>
-struct TileArgs {
-    c2_t<T> *psi;
-    const TileOp *ops;          // this pass's ops (global memory)
-    const c2_t<T> *pool;        // this pass's matrices / diagonals (global memory)
-    int nops;
-    int npool;                  // complex entries in the pool
-    int m, L, H;
-    int hpos[kMaxTileHigh];
-};
-
-// Global index offset of tile-local index l: the low L bits stay, bit L+i of
-// l moves to hpos[i].
-template <typename T>
-__device__ __forceinline__ uint64_t tile_scatter(const TileArgs<T> &a, uint32_t l) {
-    uint64_t g = l & ((1u << a.L) - 1u);
-    const uint32_t h = l >> a.L;
-    for (int i = 0; i < a.H; ++i) g |= uint64_t((h >> i) & 1u) << a.hpos[i];
-    return g;
-}
-
-__device__ __forceinline__ uint32_t insert_zeros32(uint32_t x, const int *pos, int np) {
-    for (int i = 0; i < np; ++i) {
-        const uint32_t lo = x & ((1u << pos[i]) - 1u);
-        x = ((x - lo) << 1) | lo;
-    }
-    return x;
-}
-
-// Dense op on k <= 3 local positions: one thread per group of 2^k amplitudes.
-// The matrix is read from LDS (the same address in every lane).
-template <typename T, int K>
-__device__ __forceinline__ void tile_dense_small(c2_t<T> *lds, const TileOp &op, const c2_t<T> *U, uint32_t M) {
-    constexpr int D = 1 << K;
-    const uint32_t ngroups = M >> K;
-    int pos[K];
-#pragma unroll
-    for (int b = 0; b < K; ++b) pos[b] = op.pos[b];
-    uint32_t off[D];
-#pragma unroll
-    for (int j = 0; j < D; ++j) {
-        uint32_t o = 0;
-#pragma unroll
-        for (int b = 0; b < K; ++b)
-            if ((j >> b) & 1) o |= 1u << pos[b];
-        off[j] = o;
-    }
-    // small matrices live in registers for the whole op
-    T ur[K <= 2 ? D * D : 1], ui[K <= 2 ? D * D : 1];
-    if constexpr (K <= 2) {
-#pragma unroll
-        for (int e = 0; e < D * D; ++e) { ur[e] = U[e].x; ui[e] = U[e].y; }
-    }
-    for (uint32_t g = threadIdx.x; g < ngroups; g += kTileThreads) {
-        uint32_t x = g;
-#pragma unroll
-        for (int b = 0; b < K; ++b) {
-            const uint32_t lo = x & ((1u << pos[b]) - 1u);
-            x = ((x - lo) << 1) | lo;
-        }
-        T vr[D], vi[D];
-#pragma unroll
-        for (int j = 0; j < D; ++j) {
-            const c2_t<T> w = lds[x + off[j]];
-            vr[j] = w.x; vi[j] = w.y;
-        }
-#pragma unroll
-        for (int r = 0; r < D; ++r) {
-            T orr = T(0), oi = T(0);
-#pragma unroll
-            for (int c = 0; c < D; ++c) {
-                if constexpr (K <= 2) {
-                    cfma(orr, oi, ur[r * D + c], ui[r * D + c], vr[c], vi[c]);
-                } else {
-                    const c2_t<T> u = U[r * D + c];
-                    cfma(orr, oi, u.x, u.y, vr[c], vi[c]);
-                }
-            }
-            c2_t<T> w;
-            w.x = orr; w.y = oi;
-            lds[x + off[r]] = w;
-        }
-    }
-}
-
-// Dense op on k = 4..6 local positions: every output (group, row) is
-// computed into registers from LDS, then written after a barrier.
-template <typename T, int K>
-__device__ __forceinline__ void tile_dense_wide(c2_t<T> *lds, const TileOp &op, const c2_t<T> *U, uint32_t M) {
-    constexpr int D = 1 << K;
-    int pos[K];
-#pragma unroll
-    for (int b = 0; b < K; ++b) pos[b] = op.pos[b];
-    auto offset = [&pos](uint32_t j) {
-        uint32_t o = 0;
-#pragma unroll
-        for (int b = 0; b < K; ++b) o |= ((j >> b) & 1u) << pos[b];
-        return o;
-    };
-    constexpr int kMaxPer = (1 << 13) / kTileThreads;   // M <= 2^13
-    T orr[kMaxPer], oi[kMaxPer];
-    const uint32_t per = (M + kTileThreads - 1) / kTileThreads;
-#pragma unroll
-    for (int i = 0; i < kMaxPer; ++i) {
-        const uint32_t e = threadIdx.x + uint32_t(i) * kTileThreads;
-        T ar = T(0), ai = T(0);
-        if (uint32_t(i) < per && e < M) {
-            const uint32_t r = e % D, g = e / D;
-            uint32_t x = g;
-#pragma unroll
-            for (int b = 0; b < K; ++b) {
-                const uint32_t lo = x & ((1u << pos[b]) - 1u);
-                x = ((x - lo) << 1) | lo;
-            }
-            for (int c = 0; c < D; ++c) {
-                const c2_t<T> v = lds[x + offset(uint32_t(c))];
-                const c2_t<T> u = U[r * D + c];
-                cfma(ar, ai, u.x, u.y, v.x, v.y);
-            }
-        }
-        orr[i] = ar;
-        oi[i] = ai;
-    }
-    __syncthreads();
-#pragma unroll
-    for (int i = 0; i < kMaxPer; ++i) {
-        const uint32_t e = threadIdx.x + uint32_t(i) * kTileThreads;
-        if (uint32_t(i) >= per || e >= M) continue;
-        const uint32_t r = e % D, g = e / D;
-        uint32_t x = g;
-#pragma unroll
-        for (int b = 0; b < K; ++b) {
-            const uint32_t lo = x & ((1u << pos[b]) - 1u);
-            x = ((x - lo) << 1) | lo;
-        }
-        c2_t<T> w;
-        w.x = orr[i]; w.y = oi[i];
-        lds[x + offset(r)] = w;
-    }
-}
-
-// Diagonal op: the bits of targets outside the tile are fixed for the whole
-// tile (taken from its base index); the loop runs over the groups of the
-// in-tile targets and skips diagonal entries equal to 1 (a branch that is
-// uniform across the workgroup).
-template <typename T>
-__device__ __forceinline__ void tile_diag(c2_t<T> *lds, const TileOp &op, const c2_t<T> *Dg, uint64_t base,
-                                          uint32_t M) {
-    int jfix = 0;
-    for (int i = 0; i < op.k - op.kin; ++i) jfix |= int((base >> op.gpos[i]) & 1ull) << op.gbit[i];
-    const int kin = op.kin;
-    const uint32_t ngroups = M >> kin;
-    for (int c = 0; c < (1 << kin); ++c) {
-        int j = jfix;
-        uint32_t off = 0;
-        for (int i = 0; i < kin; ++i)
-            if ((c >> i) & 1) {
-                j |= 1 << op.jbit[i];
-                off |= 1u << op.pos[i];
-            }
-        const c2_t<T> d = Dg[j];
-        if (d.x == T(1) && d.y == T(0)) continue;
-        for (uint32_t g = threadIdx.x; g < ngroups; g += kTileThreads) {
-            const uint32_t x = insert_zeros32(g, op.pos, kin) + off;
-            const c2_t<T> w = lds[x];
-            c2_t<T> o;
-            o.x = d.x * w.x - d.y * w.y;
-            o.y = d.x * w.y + d.y * w.x;
-            lds[x] = o;
-        }
-    }
-}
-
 // LDS layout: [tile: 2^m amplitudes][ops][pool].
 template <typename T, int KMAX>
 __global__ void __launch_bounds__(kTileThreads) k_tile_pass(const TileArgs<T> a) {
@@ -489,18 +314,6 @@ struct ExpTerm {
 };
 
 constexpr int kExpThreads = 256;
-
-__device__ __forceinline__ double block_sum(double v) {
-    __shared__ double red[kExpThreads / 64];
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-    const int w = threadIdx.x / 64, lane = threadIdx.x % 64;
-    if (lane == 0) red[w] = v;
-    __syncthreads();
-    double t = 0.0;
-    if (threadIdx.x == 0)
-        for (int i = 0; i < kExpThreads / 64; ++i) t += red[i];
-    return t;
-}
 
 // Sum over y of Re[w_t (-1)^{|(y^x) & z_t|} conj(psi_y) psi_{y^x}] for every
 // term of the group, accumulated in double.

@@ -160,6 +160,7 @@ struct TileBuilder {
         p.logical_gates = int(gs.size());
         p.flops = 0.0;
         for (const HostGate *g : gs) {
+            if (g->probe_gen) continue;
             const int d = 1 << g->k;
             if (is_diagonal(*g)) {
                 int nonunit = 0;
@@ -184,6 +185,15 @@ struct TileBuilder {
         }
         for (const HostGate *g : gs) {
             TileOp op{};
+            if (g->probe_gen) {
+                op.type = 3;
+                op.k = 1;
+                op.kin = g->probe_gen;
+                op.pos[0] = local_of[g->targets[0]];
+                op.moff = g->probe_slot;
+                plan.tile_ops.push_back(op);
+                continue;
+            }
             HostGate s = sorted_targets(*g);
             op.k = s.k;
             op.moff = int(plan.tile_pool.size()) - p.pool_begin;
@@ -220,6 +230,51 @@ struct TileBuilder {
     }
 };
 
+// Greedy grouping of ops into tile passes in dependency order: an op joins
+// the pass if its qubits fit the tile (diagonal ops always fit); an op that
+// does not fit blocks its qubits for the rest of the pass.
+// At most this many ops per pass, so that a pass's op list and matrices stay
+// well inside the LDS next to its tile(s).
+static const size_t kMaxOpsPerPass = 128;
+
+static void group_tiles(TileBuilder &tb, const std::vector<HostGate> &gates) {
+    const uint64_t low = (1ull << tb.L) - 1;
+    std::vector<char> done(gates.size(), 0);
+    size_t remaining = gates.size();
+    size_t first = 0;
+    while (remaining) {
+        while (done[first]) ++first;
+        uint64_t q = low;
+        uint64_t blocked = 0;
+        std::vector<const HostGate *> chosen;
+        for (size_t i = first; i < gates.size() && chosen.size() < kMaxOpsPerPass; ++i) {
+            if (done[i]) continue;
+            const HostGate &g = gates[i];
+            const uint64_t gm = qmask(g);
+            if (gm & blocked) {
+                blocked |= gm;
+                continue;
+            }
+            if (is_diagonal(g) || __builtin_popcountll(q | gm) <= tb.m) {
+                if (!is_diagonal(g)) q |= gm;
+                chosen.push_back(&g);
+                done[i] = 1;
+                --remaining;
+            } else {
+                blocked |= gm;
+            }
+        }
+        if (chosen.empty()) break;   // cannot happen: k <= 6 < m - L
+        tb.emit(q, chosen);
+    }
+}
+
+void build_adjoint_plan(Plan &plan, const std::vector<HostGate> &items, int tile_m) {
+    TileBuilder tb(plan, plan.n, plan.dtype, std::min(plan.n, tile_m), false);
+    group_tiles(tb, items);
+    for (Pass &p : plan.passes) p.bytes *= 2.0;   // two states per pass
+}
+
 void build_plan(Plan &plan, const std::vector<HostGate> &gates_in, const PlanOptions &po) {
     const int n = plan.n, dtype = plan.dtype;
     std::vector<HostGate> gates = fuse_gates(gates_in, po.fuse_k);
@@ -244,44 +299,7 @@ void build_plan(Plan &plan, const std::vector<HostGate> &gates_in, const PlanOpt
         }
     } else {
         TileBuilder tb(plan, n, dtype, po.tile_m, po.reg_tiles);
-        const uint64_t low = (1ull << tb.L) - 1;
-        std::vector<char> done(gates.size(), 0);
-        size_t remaining = gates.size();
-        size_t first = 0;
-        while (remaining) {
-            while (done[first]) ++first;
-            uint64_t q = low;
-            uint64_t blocked = 0;
-            std::vector<const HostGate *> chosen;
-            for (size_t i = first; i < gates.size(); ++i) {
-                if (done[i]) continue;
-                const HostGate &g = gates[i];
-                const uint64_t gm = qmask(g);
-                if (gm & blocked) {
-                    blocked |= gm;
-                    continue;
-                }
-                if (is_diagonal(g)) {
-                    chosen.push_back(&g);
-                    done[i] = 1;
-                    --remaining;
-                    continue;
-                }
-                if (__builtin_popcountll(q | gm) <= tb.m) {
-                    q |= gm;
-                    chosen.push_back(&g);
-                    done[i] = 1;
-                    --remaining;
-                } else {
-                    blocked |= gm;
-                }
-            }
-            if (chosen.empty()) {
-                // a gate wider than the tile: cannot happen for k <= 6 < m
-                break;
-            }
-            tb.emit(q, chosen);
-        }
+        group_tiles(tb, gates);
     }
     // logical gate counts for sweep passes
     for (Pass &p : plan.passes)

@@ -35,6 +35,10 @@ struct HostGate {
     int targets[QSIM_MAX_K] = {0, 0, 0, 0, 0, 0};
     std::vector<cd> M;
     int src_op = -1;   // index of the circuit op it came from (-1 for fused blocks)
+    // adjoint probes: Im <lambda|G|psi> with G = X (1), Y (2), Z (3) on
+    // targets[0]; no matrix, does not change either state
+    int probe_gen = 0;
+    int probe_slot = -1;
 };
 
 // Builds the matrix of a named gate; returns its arity, or -1 for an unknown kind.
@@ -163,6 +167,11 @@ PlanOptions resolve_options(const qsim_options *o, int n, int dtype);
 // Builds passes from normalised gates.
 void build_plan(Plan &plan, const std::vector<HostGate> &gates, const PlanOptions &po);
 
+// Reverse-sweep plan of the adjoint method: tile passes over (psi, lambda)
+// holding, for each op from last to first, its probe (if parametric) and its
+// inverse.
+void build_adjoint_plan(Plan &plan, const std::vector<HostGate> &items, int tile_m);
+
 // Fusion: greedy merge into blocks of at most fuse_k qubits.
 std::vector<HostGate> fuse_gates(const std::vector<HostGate> &gates, int fuse_k);
 
@@ -205,6 +214,7 @@ struct qsim_state_s {
     qsim::Profile prof;
     std::vector<qsim::CachedPlan> plans;
     std::unique_ptr<qsim::Plan> transient;   // last uncached plan (single gates)
+    void *adj_lam = nullptr;                 // second state of the adjoint method
     uint64_t use_clock = 0;
 };
 
@@ -224,6 +234,13 @@ hipError_t launch_set_basis(qsim_state s, uint64_t index);
 hipError_t launch_expect_group(qsim_state s, uint64_t xmask, const void *dev_terms, int nterms,
                                double *partials, int *nwritten);
 hipError_t launch_reduce(qsim_state s, const double *partials, int count, double *out);
+
+// Adjoint differentiation.
+int pauli_apply_grid(uint64_t N);
+hipError_t launch_pauli_apply(qsim_state s, void *lam, const void *groups, int ngroups, const void *terms,
+                              double *partials);
+hipError_t launch_adjoint_pass(qsim_state s, const Plan &plan, const Pass &p, void *lam, double *probe_partials);
+hipError_t launch_reduce_rows(qsim_state s, const double *in, int rows, int cols, double *out);
 
 // Profiling hooks around launches.
 void prof_begin(qsim_state s, int cls, double bytes, double flops = 0.0);

@@ -1,0 +1,171 @@
+"""Adjoint gradients on the GPU against the oracle's parameter-shift and
+finite-difference gradients, and against GPU finite differences at the
+20-qubit, 400-parameter ansatz size.
+
+Bars: complex128 energy <= 1e-12 absolute, gradient <= 1e-10 relative L2
+against parameter shift and <= 1e-6 absolute against central differences
+(h = 1e-4); complex64 gradient <= 1e-4 relative L2 against complex128.
+"""
+import numpy as np
+import pytest
+
+import oracle as O
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def q():
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2106_13995_amd as q
+    return q
+
+
+def rel(a, b):
+    return float(np.linalg.norm(np.asarray(a) - np.asarray(b)) / max(np.linalg.norm(b), 1e-300))
+
+
+@pytest.mark.parametrize("n,layers", [(1, 1), (3, 2), (6, 3), (11, 2)])
+def test_ansatz_gradient_matches_parameter_shift(q, n, layers):
+    circ = W.ansatz_circuit(n, layers)
+    p = W.ansatz_params(n, layers, seed=40 + n)
+    H = W.chain_observable(n) if n > 1 else W.PauliSum(1, [1.0, 0.5], [0, 1], [1, 0])
+    s = q.State(n, "c128")
+    e, g = s.adjoint_grad(circ, p, H)
+    assert abs(e - O.energy(circ, p, H)) < 1e-12
+    ps = O.param_shift_grad(circ, p, H)
+    assert rel(g, ps) < 1e-10
+    s.close()
+
+
+def test_mixed_circuit_with_shared_parameters(q):
+    """Fixed gates interleaved with RX/RY/RZ, one parameter used by two ops,
+    a parameter no op uses, and an observable with Y terms."""
+    n = 8
+    rng = np.random.default_rng(41)
+    ops = []
+    for layer in range(3):
+        for qb in range(n):
+            ops.append(W.op("h", qb) if (qb + layer) % 3 == 0 else W.op("u3", qb, angles=rng.uniform(0, 6, 3)))
+        ops.append(W.op("rx", 0, param=0))
+        ops.append(W.op("ry", 5, param=1 + layer))
+        ops.append(W.op("rz", 3, param=4))
+        ops.append(W.op("rx", 6, param=4))     # shared with the RZ above
+        for a in range(layer % 2, n - 1, 2):
+            ops.append(W.op("cz", a, a + 1))
+        ops.append(W.op("ccx", 1, 2, 7))
+        ops.append(W.op("cx", 7, 4))
+    circ = W.Circuit(n, ops, 7)
+    p = rng.uniform(0, 2 * np.pi, 7)          # index 5, 6 unused
+    H = W.random_pauli_sum(n, 10, rng)
+    s = q.State(n, "c128")
+    e, g = s.adjoint_grad(circ, p, H)
+    assert abs(e - O.energy(circ, p, H)) < 1e-12
+    ps = O.param_shift_grad(circ, p, H)
+    assert rel(g, ps) < 1e-10
+    assert g[5] == 0.0 and g[6] == 0.0
+    s.close()
+
+
+def test_state_restored_and_nonzero_input(q):
+    n, layers = 9, 2
+    circ = W.ansatz_circuit(n, layers)
+    p = W.ansatz_params(n, layers, seed=42)
+    H = W.chain_observable(n)
+    psi0 = W.random_state(n, np.random.default_rng(43))
+    s = q.State(n, "c128")
+    s.from_numpy(psi0)
+    e, g = s.adjoint_grad(circ, p, H)
+    assert O.rel_l2(s.to_numpy(), psi0) < 1e-12
+    psi = O.apply_circuit(circ, psi0, params=p)
+    assert abs(e - O.expectation(psi, H)) < 1e-12
+    # the shift rule applied by hand from the same input state
+    j = 7
+    vals = []
+    for sh in (0.5 * np.pi, -0.5 * np.pi):
+        pp = p.copy()
+        pp[j] += sh
+        vals.append(O.expectation(O.apply_circuit(circ, psi0, params=pp), H))
+    assert abs(g[j] - 0.5 * (vals[0] - vals[1])) < 1e-11
+    s.close()
+
+
+def test_unsupported_parametric_kind(q):
+    circ = W.Circuit(3, [W.op("h", 0), W.op("u3", 1, param=0)], 3)
+    s = q.State(3, "c128")
+    before = s.to_numpy()
+    with pytest.raises(q.QsimError) as err:
+        s.adjoint_grad(circ, np.zeros(3), W.chain_observable(3))
+    assert err.value.status == q.QSIM_ERR_UNSUPPORTED
+    np.testing.assert_array_equal(s.to_numpy(), before)
+    s.close()
+
+
+def test_c64_against_c128(q):
+    n, layers = 12, 4
+    circ = W.ansatz_circuit(n, layers)
+    p = W.ansatz_params(n, layers, seed=44)
+    H = W.chain_observable(n)
+    s1, s2 = q.State(n, "c64"), q.State(n, "c128")
+    e1, g1 = s1.adjoint_grad(circ, p, H)
+    e2, g2 = s2.adjoint_grad(circ, p, H)
+    assert abs(e1 - e2) < 1e-4
+    assert rel(g1, g2) < 1e-4
+    s1.close()
+    s2.close()
+
+
+def test_ansatz20_full_size(q):
+    """The 20-qubit, 10-layer ansatz (400 parameters) with sum Z_iZ_{i+1} +
+    0.5 sum X_i: energy against the oracle; sampled gradient entries against
+    GPU central differences (h = 1e-4) and the GPU shift rule, complex128;
+    the complex64 gradient against the complex128 one."""
+    n, layers = 20, 10
+    circ = W.ansatz_circuit(n, layers)
+    p = W.ansatz_params(n, layers, seed=4)
+    H = W.chain_observable(n)
+    s = q.State(n, "c128")
+    e, g = s.adjoint_grad(circ, p, H)
+    assert abs(e - O.energy(circ, p, H)) < 1e-11
+    rng = np.random.default_rng(45)
+    sample = sorted(set(rng.choice(p.size, size=8, replace=False).tolist()) | {0, p.size - 1})
+
+    def gpu_energy(pp):
+        s.set_basis(0)
+        s.apply_circuit(circ, params=pp)
+        return s.expectation(H)
+
+    for j in sample:
+        vals = {}
+        for sh in (1e-4, -1e-4, 0.5 * np.pi, -0.5 * np.pi):
+            pp = p.copy()
+            pp[j] += sh
+            vals[sh] = gpu_energy(pp)
+        fd = (vals[1e-4] - vals[-1e-4]) / 2e-4
+        shift = 0.5 * (vals[0.5 * np.pi] - vals[-0.5 * np.pi])
+        assert abs(g[j] - fd) < 1e-6, (j, g[j], fd)
+        assert abs(g[j] - shift) < 1e-10 * max(1.0, abs(shift)), (j, g[j], shift)
+    s.close()
+    s64 = q.State(n, "c64")
+    e64, g64 = s64.adjoint_grad(circ, p, H)
+    assert abs(e64 - e) < 1e-4
+    assert rel(g64, g) < 1e-4
+    s64.close()
+
+
+def test_autograd_function(q):
+    torch = pytest.importorskip("torch")
+    n, layers = 5, 2
+    circ = W.ansatz_circuit(n, layers)
+    p = W.ansatz_params(n, layers, seed=46)
+    H = W.chain_observable(n)
+    s = q.State(n, "c128")
+    theta = torch.tensor(p, dtype=torch.float64, requires_grad=True)
+    E = q.expectation(theta, s, circ, H)
+    (2.0 * E).backward()
+    assert abs(E.item() - O.energy(circ, p, H)) < 1e-12
+    assert rel(theta.grad.numpy(), 2.0 * O.param_shift_grad(circ, p, H)) < 1e-10
+    s.close()
