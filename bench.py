@@ -18,6 +18,8 @@ import os
 import sys
 import time
 
+import numpy as np
+
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
@@ -48,6 +50,7 @@ def parse():
     ap.add_argument("--cpu-gates", type=int, default=4, help="gates of the circuit the oracle times")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--calib-copy", action="store_true", help="run a plain device copy of the state size")
+    ap.add_argument("--no-adjoint", action="store_true", help="skip the 20-qubit adjoint-gradient figure")
     return ap.parse_args()
 
 
@@ -111,6 +114,45 @@ def time_mode(torch, s, circ, steps, warmup, fuse_k, tile_m):
             stats[cls] = (n, ms, by, fl)
     s.profile(False)
     return wall, ev_ms, stats
+
+
+def adjoint_bench(torch, q, W, dtype: str, reps: int = 5, shift_sample: int = 16):
+    """Energy + full gradient of the 20-qubit, 10-layer RY.RZ + CNOT-ladder
+    ansatz (400 parameters) with sum Z_iZ_{i+1} + 0.5 sum X_i, by the adjoint
+    method, against the parameter-shift rule on the same GPU (two forward
+    runs and expectations per parameter; timed on a sample, scaled to 400)."""
+    n, layers = 20, 10
+    circ = W.ansatz_circuit(n, layers)
+    p = W.ansatz_params(n, layers, seed=4)
+    H = W.chain_observable(n)
+    s = q.State(n, dtype)
+    s.adjoint_grad(circ, p, H)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        s.set_basis(0)
+        e, g = s.adjoint_grad(circ, p, H)
+    torch.cuda.synchronize()
+    adj = (time.perf_counter() - t0) / reps
+    # parameter shift, same GPU, same options
+    def energy(pp):
+        s.set_basis(0)
+        s.apply_circuit(circ, params=pp)
+        return s.expectation(H)
+    energy(p)
+    idx = list(range(0, p.size, max(1, p.size // shift_sample)))[:shift_sample]
+    t0 = time.perf_counter()
+    for j in idx:
+        for sh in (0.5 * np.pi, -0.5 * np.pi):
+            pp = p.copy()
+            pp[j] += sh
+            energy(pp)
+    shift = (time.perf_counter() - t0) / len(idx) * p.size
+    s.close()
+    return {"workload": f"ansatz {n} qubits, {layers} layers, {p.size} parameters, {dtype}",
+            "grads_per_s": round(1.0 / adj, 2), "ms_per_gradient": round(adj * 1e3, 3),
+            "energy": e, "param_shift_ms_same_gpu": round(shift * 1e3, 1),
+            "speedup_vs_param_shift": round(shift / adj, 1)}
 
 
 def calib_copy(torch, n: int, dtype: str):
@@ -191,6 +233,10 @@ def main():
     del s
     torch.cuda.empty_cache()
 
+    adjoint = None
+    if not a.no_adjoint:
+        adjoint = {dt: adjoint_bench(torch, q, W, dt) for dt in ("c64", "c128")}
+
     cpu = None
     if not a.no_cpu:
         cpu = cpu_baseline(circ, a.cpu_gates)
@@ -217,6 +263,7 @@ def main():
         "norm": norm,
         "roofline": roofline,
         "cpu_baseline": cpu,
+        "adjoint": adjoint,
     }
     if extra:
         out["variants"] = extra

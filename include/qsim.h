@@ -202,6 +202,35 @@ qsim_status qsim_expectation(qsim_state s, const qsim_pauli_sum *H, double *out_
 qsim_status qsim_adjoint_grad(qsim_state s, const qsim_circuit *c, const double *params, int64_t nparams,
                               const qsim_pauli_sum *H, const qsim_options *opts, double *energy, double *grad);
 
+/* Batched forward + adjoint runs of many independent circuits, for callers
+ * that evaluate thousands of small variational circuits (paper, Sec. I: the
+ * parameters of a model are adapted from simulated outputs; Sec. III: small
+ * circuits lose to host-device overhead).
+ *
+ * qsim_batch_create validates every circuit (1 <= n <= 26; parametric ops
+ * must be RX, RY or RZ), builds one device program per distinct structure
+ * (circuit ops, fixed angles and matrices, observable), allocates device
+ * memory (programs, outputs, and for circuits wider than one LDS tile a
+ * psi/lambda slot per workgroup) and captures the whole run -- parameter
+ * upload, one persistent kernel, result download -- in a HIP graph.
+ * Circuit i reads its parameters from params[param_offsets[i] ..
+ * param_offsets[i+1]) (param indices in its ops are relative to that block),
+ * is applied to |0...0>, and yields energies[i] = <psi|Hs[i]|psi> and, when
+ * want_grad, grads over the same block.  `opts` is reserved (may be NULL).
+ *
+ * qsim_batch_run copies params (host) in, replays the graph on `hip_stream`,
+ * waits, and copies energies (ncirc doubles) and grads (host) out.  Calls on
+ * one batch must be serialised.  qsim_batch_info reports the persistent grid
+ * size, the number of distinct programs and the widest circuit. */
+typedef struct qsim_batch_s *qsim_batch;
+
+qsim_status qsim_batch_create(int ncirc, const qsim_circuit *circs, const int64_t *param_offsets,
+                              const qsim_pauli_sum *Hs, qsim_dtype dtype, int want_grad, const qsim_options *opts,
+                              qsim_batch *out);
+qsim_status qsim_batch_run(qsim_batch b, const double *params, double *energies, double *grads, void *hip_stream);
+qsim_status qsim_batch_info(qsim_batch b, int *grid, int *programs, int *max_n);
+qsim_status qsim_batch_free(qsim_batch b);
+
 /* Plans a circuit for an n-qubit state of `dtype` without touching any
  * device (host-only): validates the ops as qsim_apply_circuit does and
  * reports how many passes of each kind (QSIM_KCLASS_*, `counts` has

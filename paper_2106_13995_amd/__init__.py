@@ -48,7 +48,8 @@ EXPORTS = (
     "qsim_alloc", "qsim_wrap", "qsim_free", "qsim_set_stream", "qsim_state_info",
     "qsim_set_basis", "qsim_copy_to_host", "qsim_copy_from_host", "qsim_apply_gate",
     "qsim_apply_circuit", "qsim_expectation", "qsim_last_error", "qsim_profile_enable",
-    "qsim_profile_read", "qsim_plan_summary", "qsim_adjoint_grad",
+    "qsim_profile_read", "qsim_plan_summary", "qsim_adjoint_grad", "qsim_batch_create", "qsim_batch_run",
+    "qsim_batch_info", "qsim_batch_free",
 )
 
 
@@ -124,6 +125,12 @@ def _load() -> ctypes.CDLL:
                                ctypes.POINTER(QsimOptions), ctypes.POINTER(i64), ctypes.POINTER(ctypes.c_double),
                                ctypes.POINTER(ctypes.c_double)], S),
         "qsim_profile_enable": ([P, i32], S),
+        "qsim_batch_create": ([i32, ctypes.POINTER(QsimCircuit), ctypes.POINTER(i64), ctypes.POINTER(QsimPauliSum),
+                               i32, i32, ctypes.POINTER(QsimOptions), ctypes.POINTER(P)], S),
+        "qsim_batch_run": ([P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double),
+                            ctypes.POINTER(ctypes.c_double), P], S),
+        "qsim_batch_info": ([P, ctypes.POINTER(i32), ctypes.POINTER(i32), ctypes.POINTER(i32)], S),
+        "qsim_batch_free": ([P], S),
         "qsim_profile_read": ([P, i32, ctypes.POINTER(i64), ctypes.POINTER(ctypes.c_double),
                                ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)], S),
     }
@@ -360,6 +367,60 @@ class State:
 
     def profile_read(self, cls: str) -> Tuple[int, float, float, float]:
         return qsim_profile_read(self.handle, KCLASS[cls])
+
+
+# ------------------------------------------------------------ batches
+
+class Batch:
+    """Many independent circuits (each on |0...0>, each with its own parameter
+    block and observable) run forward (+ adjoint) in one replayed graph."""
+
+    def __init__(self, circuits, observables, dtype: str = "c64", want_grad: bool = True):
+        self.ncirc = len(circuits)
+        self.packed = [PackedCircuit(c) for c in circuits]
+        self.Hp = [PackedPauliSum(H) for H in observables]
+        offs = [0]
+        for c in circuits:
+            offs.append(offs[-1] + int(c.nparams))
+        self.offsets = np.asarray(offs, dtype=np.int64)
+        self.nparams = int(offs[-1])
+        carr = (QsimCircuit * self.ncirc)(*[p.c for p in self.packed])
+        harr = (QsimPauliSum * self.ncirc)(*[h.h for h in self.Hp])
+        self._keep = (carr, harr)
+        h = ctypes.c_void_p()
+        _check(_lib.qsim_batch_create(self.ncirc, carr, self.offsets.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
+                                      harr, DTYPES[dtype], 1 if want_grad else 0, None, ctypes.byref(h)))
+        self.handle = h.value
+        self.want_grad = want_grad
+
+    def info(self) -> Tuple[int, int, int]:
+        g, p, m = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+        _check(_lib.qsim_batch_info(ctypes.c_void_p(self.handle), ctypes.byref(g), ctypes.byref(p), ctypes.byref(m)))
+        return g.value, p.value, m.value
+
+    def run(self, params: np.ndarray, stream: int = 0):
+        p = np.ascontiguousarray(params, dtype=np.float64)
+        if p.size != self.nparams:
+            raise ValueError(f"expected {self.nparams} parameters, got {p.size}")
+        energies = np.zeros(self.ncirc)
+        grads = np.zeros(max(1, self.nparams))
+        if not stream:
+            import torch
+            stream = torch.cuda.current_stream().cuda_stream
+        _check(_lib.qsim_batch_run(ctypes.c_void_p(self.handle), _dptr(p), _dptr(energies), _dptr(grads),
+                                   ctypes.c_void_p(stream)))
+        return energies, (grads[:self.nparams] if self.want_grad else None)
+
+    def close(self) -> None:
+        if getattr(self, "handle", None):
+            _check(_lib.qsim_batch_free(ctypes.c_void_p(self.handle)))
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 # ------------------------------------------------------------ autograd

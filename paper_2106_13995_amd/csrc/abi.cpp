@@ -197,7 +197,7 @@ static qsim_status run_plan(qsim_state s, Plan &plan) {
 }
 
 // Validates one op and returns its normalised gate.
-static qsim_status make_gate(const qsim_circuit *c, int i, const double *params, int64_t nparams, HostGate &g) {
+qsim_status make_gate(const qsim_circuit *c, int i, const double *params, int64_t nparams, HostGate &g) {
     const qsim_op &op = c->ops[i];
     const int n = c->n;
     char buf[160];

@@ -97,7 +97,7 @@ int named_gate_matrix(int kind, const double *a, cd *U) {
 }
 
 bool is_diagonal(const HostGate &g) {
-    if (g.probe_gen) return false;
+    if (g.probe_gen || g.rot_gen) return false;
     const int d = 1 << g.k;
     for (int r = 0; r < d; ++r)
         for (int c = 0; c < d; ++c)

@@ -1,0 +1,317 @@
+// Batched forward + adjoint runs of many independent circuits in one
+// persistent launch (gfx950).
+//
+// Each workgroup repeatedly takes the next circuit from an atomic counter
+// (circuits are queued largest first) and runs it alone: the forward tile
+// passes on psi, lambda = H psi with the energy, then the reverse tile passes
+// on (psi, lambda) with the per-parameter probes Im <lambda|G|psi>.  A
+// circuit whose state fits one tile keeps psi and lambda in LDS for the
+// whole run; larger ones keep them in a per-workgroup slot of device memory
+// and stream tiles through LDS.  Circuits of the same structure share one
+// program; rotation matrices are formed on the device from each circuit's
+// own parameters.  Every workgroup leaves the loop once the counter passes
+// the number of circuits, so the grid always drains.
+#include <hip/hip_runtime.h>
+
+#include "batch.h"
+#include "device_common.h"
+#include "qsim_internal.h"
+#include "tile_ops.h"
+
+namespace qsim {
+
+template <typename T>
+struct BatchArgs {
+    const BatchCircuit *circs;
+    const int32_t *order;
+    const BatchProgram *progs;
+    const BatchPass *passes;
+    const TileOp *ops;
+    const c2_t<T> *pool;
+    const BatchHGroup *hgroups;
+    const BatchHTerm *hterms;
+    const double *params;
+    double *energies;
+    double *grads;
+    c2_t<T> *arena;
+    uint64_t slot_amps;     // amplitudes per state in a workgroup's slot
+    int *counter;
+    int ncirc;
+    int want_grad;
+    int mmax;
+};
+
+// Rotation exp(-i theta G / 2) (or its inverse) on local position p.
+template <typename T>
+__device__ __forceinline__ void tile_rotation(c2_t<T> *lds, int p, int gen, double theta, uint32_t M) {
+    double sn, cs;
+    sincos(0.5 * theta, &sn, &cs);
+    // [[a, b], [c, d]] as (re, im)
+    T ar, ai, br, bi, cr, ci, dr, di;
+    if (gen == 1) {        // X: [[c, -is], [-is, c]]
+        ar = T(cs); ai = T(0); br = T(0); bi = T(-sn); cr = T(0); ci = T(-sn); dr = T(cs); di = T(0);
+    } else if (gen == 2) { // Y: [[c, -s], [s, c]]
+        ar = T(cs); ai = T(0); br = T(-sn); bi = T(0); cr = T(sn); ci = T(0); dr = T(cs); di = T(0);
+    } else {               // Z: diag(e^{-i t/2}, e^{i t/2})
+        ar = T(cs); ai = T(-sn); br = T(0); bi = T(0); cr = T(0); ci = T(0); dr = T(cs); di = T(sn);
+    }
+    const uint32_t bit = 1u << p;
+    for (uint32_t g = threadIdx.x; g < (M >> 1); g += kTileThreads) {
+        const uint32_t lo = g & (bit - 1u);
+        const uint32_t x = ((g - lo) << 1) | lo;
+        const c2_t<T> u = lds[x], v = lds[x | bit];
+        T o0r = T(0), o0i = T(0), o1r = T(0), o1i = T(0);
+        cfma(o0r, o0i, ar, ai, u.x, u.y);
+        cfma(o0r, o0i, br, bi, v.x, v.y);
+        cfma(o1r, o1i, cr, ci, u.x, u.y);
+        cfma(o1r, o1i, dr, di, v.x, v.y);
+        c2_t<T> w0, w1;
+        w0.x = o0r; w0.y = o0i;
+        w1.x = o1r; w1.y = o1i;
+        lds[x] = w0;
+        lds[x | bit] = w1;
+    }
+}
+
+template <typename T>
+__device__ __forceinline__ double batch_probe(const c2_t<T> *lp, const c2_t<T> *ll, int p, int gen, uint32_t M) {
+    double acc = 0.0;
+    const uint32_t bit = 1u << p;
+    for (uint32_t l = threadIdx.x; l < M; l += kTileThreads) {
+        const c2_t<T> lam = ll[l];
+        const bool one = (l & bit) != 0;
+        double gr, gi;
+        if (gen == 3) {
+            const c2_t<T> v = lp[l];
+            gr = one ? -double(v.x) : double(v.x);
+            gi = one ? -double(v.y) : double(v.y);
+        } else {
+            const c2_t<T> v = lp[l ^ bit];
+            if (gen == 1) {
+                gr = double(v.x);
+                gi = double(v.y);
+            } else {
+                gr = one ? -double(v.y) : double(v.y);
+                gi = one ? double(v.x) : -double(v.x);
+            }
+        }
+        acc += double(lam.x) * gi - double(lam.y) * gr;
+    }
+    return acc;
+}
+
+// Ops of one pass on one tile (psi only, or psi and lambda).
+template <typename T>
+__device__ void batch_tile_ops(const BatchArgs<T> &a, const BatchPass &ps, c2_t<T> *lp, c2_t<T> *ll, bool both,
+                               uint64_t base, uint32_t M, const double *prm, double *grd) {
+    for (int o = ps.op_begin; o < ps.op_end; ++o) {
+        const TileOp &op = a.ops[o];
+        if (op.type == 3) {
+            const double v = block_sum(batch_probe<T>(lp, ll, op.pos[0], op.kin, M));
+            if (threadIdx.x == 0) grd[op.moff] += v;
+        } else if (op.type == 4) {
+            const double th = op.jbit[0] ? -prm[op.moff] : prm[op.moff];
+            tile_rotation<T>(lp, op.pos[0], op.kin, th, M);
+            if (both) tile_rotation<T>(ll, op.pos[0], op.kin, th, M);
+        } else if (op.type == 1) {
+            const c2_t<T> *U = a.pool + op.moff;
+            tile_diag<T>(lp, op, U, base, M);
+            if (both) tile_diag<T>(ll, op, U, base, M);
+        } else {
+            const c2_t<T> *U = a.pool + op.moff;
+            switch (op.k) {
+                case 1:
+                    tile_dense_small<T, 1>(lp, op, U, M);
+                    if (both) tile_dense_small<T, 1>(ll, op, U, M);
+                    break;
+                case 2:
+                    tile_dense_small<T, 2>(lp, op, U, M);
+                    if (both) tile_dense_small<T, 2>(ll, op, U, M);
+                    break;
+                default:
+                    tile_dense_small<T, 3>(lp, op, U, M);
+                    if (both) tile_dense_small<T, 3>(ll, op, U, M);
+                    break;
+            }
+        }
+        __syncthreads();
+    }
+}
+
+template <typename T>
+__device__ __forceinline__ uint64_t batch_scatter(const BatchPass &ps, uint32_t l) {
+    uint64_t g = l & ((1u << ps.L) - 1u);
+    const uint32_t h = l >> ps.L;
+    for (int i = 0; i < ps.H; ++i) g |= uint64_t((h >> i) & 1u) << ps.hpos[i];
+    return g;
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kTileThreads) k_batch(const BatchArgs<T> a) {
+    extern __shared__ char lds_raw[];
+    __shared__ int s_next;
+    c2_t<T> *lp = reinterpret_cast<c2_t<T> *>(lds_raw);
+    c2_t<T> *ll = lp + (1u << a.mmax);
+    c2_t<T> *gpsi = a.arena + uint64_t(blockIdx.x) * 2ull * a.slot_amps;
+    c2_t<T> *glam = gpsi + a.slot_amps;
+    for (;;) {
+        __syncthreads();
+        if (threadIdx.x == 0) s_next = atomicAdd(a.counter, 1);
+        __syncthreads();
+        const int qi = s_next;
+        if (qi >= a.ncirc) break;
+        const BatchCircuit &cc = a.circs[a.order[qi]];
+        const BatchProgram &pg = a.progs[cc.prog];
+        const double *prm = a.params + cc.param_off;
+        double *grd = a.grads + cc.param_off;
+        const int n = pg.n;
+        const uint32_t M = 1u << pg.m;
+        const uint32_t ntiles = 1u << (n - pg.m);
+        const bool single = ntiles == 1;
+        const uint64_t N = 1ull << n;
+        if (a.want_grad)
+            for (int j = threadIdx.x; j < cc.nparams; j += kTileThreads) grd[j] = 0.0;
+        // psi = |0...0>
+        if (single) {
+            for (uint32_t l = threadIdx.x; l < M; l += kTileThreads) {
+                c2_t<T> w;
+                w.x = (l == 0) ? T(1) : T(0);
+                w.y = T(0);
+                lp[l] = w;
+            }
+        }
+        __syncthreads();
+        // forward
+        for (int pi = pg.fwd_begin; pi < pg.fwd_end; ++pi) {
+            const BatchPass &ps = a.passes[pi];
+            for (uint32_t t = 0; t < ntiles; ++t) {
+                uint64_t base = uint64_t(t) << ps.L;
+                for (int i = 0; i < ps.H; ++i) {
+                    const uint64_t lo = base & ((1ull << ps.hpos[i]) - 1ull);
+                    base = ((base - lo) << 1) | lo;
+                }
+                if (!single) {
+                    for (uint32_t l = threadIdx.x; l < M; l += kTileThreads) {
+                        const uint64_t gi = base | batch_scatter<T>(ps, l);
+                        c2_t<T> w;
+                        if (pi == pg.fwd_begin) {
+                            w.x = (gi == 0) ? T(1) : T(0);
+                            w.y = T(0);
+                        } else {
+                            w = gpsi[gi];
+                        }
+                        lp[l] = w;
+                    }
+                    __syncthreads();
+                }
+                batch_tile_ops<T>(a, ps, lp, ll, false, base, M, prm, grd);
+                if (!single) {
+                    for (uint32_t l = threadIdx.x; l < M; l += kTileThreads) gpsi[base | batch_scatter<T>(ps, l)] = lp[l];
+                    __syncthreads();
+                }
+            }
+            __threadfence();
+            __syncthreads();
+        }
+        // lambda = H psi and the energy
+        {
+            const c2_t<T> *src = single ? lp : gpsi;
+            c2_t<T> *dst = single ? ll : glam;
+            double e = 0.0;
+            for (uint64_t y = threadIdx.x; y < N; y += kTileThreads) {
+                double ar = 0.0, ai = 0.0;
+                for (int g = pg.hg_begin; g < pg.hg_end; ++g) {
+                    const BatchHGroup gr = a.hgroups[g];
+                    const uint64_t sy = y ^ gr.x;
+                    const c2_t<T> b = src[sy];
+                    double sr = 0.0, si = 0.0;
+                    for (int t = gr.first; t < gr.first + gr.count; ++t) {
+                        const BatchHTerm h = a.hterms[t];
+                        const double sg = (__popcll(sy & h.z) & 1) ? -1.0 : 1.0;
+                        sr += sg * h.wr;
+                        si += sg * h.wi;
+                    }
+                    ar += sr * double(b.x) - si * double(b.y);
+                    ai += sr * double(b.y) + si * double(b.x);
+                }
+                const c2_t<T> p = src[y];
+                e += double(p.x) * ar + double(p.y) * ai;
+                c2_t<T> o;
+                o.x = T(ar);
+                o.y = T(ai);
+                dst[y] = o;
+            }
+            const double tot = block_sum(e);
+            if (threadIdx.x == 0) a.energies[a.order[qi]] = tot;
+            __threadfence();
+            __syncthreads();
+        }
+        if (!a.want_grad) continue;
+        // reverse sweep on (psi, lambda)
+        for (int pi = pg.rev_begin; pi < pg.rev_end; ++pi) {
+            const BatchPass &ps = a.passes[pi];
+            for (uint32_t t = 0; t < ntiles; ++t) {
+                uint64_t base = uint64_t(t) << ps.L;
+                for (int i = 0; i < ps.H; ++i) {
+                    const uint64_t lo = base & ((1ull << ps.hpos[i]) - 1ull);
+                    base = ((base - lo) << 1) | lo;
+                }
+                if (!single) {
+                    for (uint32_t l = threadIdx.x; l < M; l += kTileThreads) {
+                        const uint64_t gi = base | batch_scatter<T>(ps, l);
+                        lp[l] = gpsi[gi];
+                        ll[l] = glam[gi];
+                    }
+                    __syncthreads();
+                }
+                batch_tile_ops<T>(a, ps, lp, ll, true, base, M, prm, grd);
+                if (!single) {
+                    for (uint32_t l = threadIdx.x; l < M; l += kTileThreads) {
+                        const uint64_t gi = base | batch_scatter<T>(ps, l);
+                        gpsi[gi] = lp[l];
+                        glam[gi] = ll[l];
+                    }
+                    __syncthreads();
+                }
+            }
+            __threadfence();
+            __syncthreads();
+        }
+    }
+}
+
+__global__ void k_zero_counter(int *counter) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) counter[0] = 0;
+}
+
+template <typename T>
+static hipError_t launch_batch_t(hipStream_t stream, const BatchDevice &d, int grid) {
+    BatchArgs<T> a{};
+    a.circs = d.circs;
+    a.order = d.order;
+    a.progs = d.progs;
+    a.passes = d.passes;
+    a.ops = d.ops;
+    a.pool = static_cast<const c2_t<T> *>(d.pool);
+    a.hgroups = d.hgroups;
+    a.hterms = d.hterms;
+    a.params = d.params;
+    a.energies = d.energies;
+    a.grads = d.grads;
+    a.arena = static_cast<c2_t<T> *>(d.arena);
+    a.slot_amps = d.slot_amps;
+    a.counter = d.counter;
+    a.ncirc = d.ncirc;
+    a.want_grad = d.want_grad;
+    a.mmax = d.mmax;
+    const size_t lds = 2 * (sizeof(c2_t<T>) << d.mmax);
+    hipLaunchKernelGGL(k_zero_counter, dim3(1), dim3(64), 0, stream, d.counter);
+    hipLaunchKernelGGL((k_batch<T>), dim3(grid), dim3(kTileThreads), lds, stream, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_batch(hipStream_t stream, int dtype, const BatchDevice &d, int grid) {
+    return dtype == QSIM_C64 ? launch_batch_t<float>(stream, d, grid) : launch_batch_t<double>(stream, d, grid);
+}
+
+}  // namespace qsim

@@ -161,6 +161,10 @@ struct TileBuilder {
         p.flops = 0.0;
         for (const HostGate *g : gs) {
             if (g->probe_gen) continue;
+            if (g->rot_gen) {
+                p.flops += 16.0 * std::ldexp(1.0, n);
+                continue;
+            }
             const int d = 1 << g->k;
             if (is_diagonal(*g)) {
                 int nonunit = 0;
@@ -191,6 +195,16 @@ struct TileBuilder {
                 op.kin = g->probe_gen;
                 op.pos[0] = local_of[g->targets[0]];
                 op.moff = g->probe_slot;
+                plan.tile_ops.push_back(op);
+                continue;
+            }
+            if (g->rot_gen) {
+                op.type = 4;
+                op.k = 1;
+                op.kin = g->rot_gen;
+                op.pos[0] = local_of[g->targets[0]];
+                op.moff = g->rot_param;
+                op.jbit[0] = g->rot_inv;
                 plan.tile_ops.push_back(op);
                 continue;
             }
@@ -267,6 +281,11 @@ static void group_tiles(TileBuilder &tb, const std::vector<HostGate> &gates) {
         if (chosen.empty()) break;   // cannot happen: k <= 6 < m - L
         tb.emit(q, chosen);
     }
+}
+
+void build_tile_plan(Plan &plan, const std::vector<HostGate> &items, int tile_m) {
+    TileBuilder tb(plan, plan.n, plan.dtype, std::min(plan.n, tile_m), false);
+    group_tiles(tb, items);
 }
 
 void build_adjoint_plan(Plan &plan, const std::vector<HostGate> &items, int tile_m) {

@@ -39,7 +39,17 @@ struct HostGate {
     // targets[0]; no matrix, does not change either state
     int probe_gen = 0;
     int probe_slot = -1;
+    // batch programs: a rotation exp(-i theta G / 2) on targets[0] whose
+    // matrix is formed on the device from parameter rot_param (G = X, Y, Z for
+    // rot_gen 1, 2, 3; rot_inv applies the inverse)
+    int rot_gen = 0;
+    int rot_param = -1;
+    int rot_inv = 0;
 };
+
+// Validates op i of a circuit and returns its normalised gate (matrix built
+// from the op's angles or parameters).
+qsim_status make_gate(const qsim_circuit *c, int i, const double *params, int64_t nparams, HostGate &g);
 
 // Builds the matrix of a named gate; returns its arity, or -1 for an unknown kind.
 int named_gate_matrix(int kind, const double *angles, cd *U);
@@ -171,6 +181,9 @@ void build_plan(Plan &plan, const std::vector<HostGate> &gates, const PlanOption
 // holding, for each op from last to first, its probe (if parametric) and its
 // inverse.
 void build_adjoint_plan(Plan &plan, const std::vector<HostGate> &items, int tile_m);
+
+// LDS-resident tile passes (no register staging) over the given ops.
+void build_tile_plan(Plan &plan, const std::vector<HostGate> &items, int tile_m);
 
 // Fusion: greedy merge into blocks of at most fuse_k qubits.
 std::vector<HostGate> fuse_gates(const std::vector<HostGate> &gates, int fuse_k);
