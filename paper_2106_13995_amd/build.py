@@ -12,7 +12,8 @@ CSRC = os.path.join(HERE, "csrc")
 OBJ = os.path.join(ROOT, "_build", "qsim")
 LIB = os.path.join(HERE, "libqsim.so")
 SOURCES = ["abi.cpp", "gates.cpp", "plan.cpp", "stages.cpp", "kernels.hip", "kernels_reg.hip",
-           "kernels_adjoint.hip", "batch.cpp", "kernels_batch.hip"]
+           "kernels_adjoint.hip", "batch.cpp", "kernels_batch.hip",
+           "kernels_mfma.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"

@@ -139,8 +139,10 @@ static qsim_status upload_plan(qsim_state s, Plan &plan) {
     plan.reg_ops_dev_off = align(plan.reg_stages_dev_off + st_bytes);
     const size_t rop_bytes = plan.reg_ops.size() * sizeof(RegOp);
     plan.pool_dev_off = align(plan.reg_ops_dev_off + rop_bytes);
-    const size_t total = plan.pool_dev_off + plan.tile_pool.size() * amp_bytes(plan.dtype);
-    if (ops_bytes == 0 && st_bytes == 0 && rop_bytes == 0 && plan.tile_pool.empty()) {
+    plan.real_pool_dev_off = align(plan.pool_dev_off + plan.tile_pool.size() * amp_bytes(plan.dtype));
+    const size_t real_bytes = plan.real_pool.size() * amp_bytes(plan.dtype) / 2;
+    const size_t total = plan.real_pool_dev_off + real_bytes;
+    if (ops_bytes == 0 && st_bytes == 0 && rop_bytes == 0 && plan.tile_pool.empty() && plan.real_pool.empty()) {
         plan.uploaded = true;
         return QSIM_OK;
     }
@@ -158,10 +160,15 @@ static qsim_status upload_plan(qsim_state s, Plan &plan) {
     if (ops_bytes) std::memcpy(h, plan.tile_ops.data(), ops_bytes);
     if (st_bytes) std::memcpy(h + plan.reg_stages_dev_off, plan.reg_stages.data(), st_bytes);
     if (rop_bytes) std::memcpy(h + plan.reg_ops_dev_off, plan.reg_ops.data(), rop_bytes);
-    if (plan.dtype == QSIM_C64)
+    if (plan.dtype == QSIM_C64) {
         pack_pool<float>(plan.tile_pool, h + plan.pool_dev_off);
-    else
+        float *r = reinterpret_cast<float *>(h + plan.real_pool_dev_off);
+        for (size_t i = 0; i < plan.real_pool.size(); ++i) r[i] = float(plan.real_pool[i]);
+    } else {
         pack_pool<double>(plan.tile_pool, h + plan.pool_dev_off);
+        if (!plan.real_pool.empty())
+            std::memcpy(h + plan.real_pool_dev_off, plan.real_pool.data(), sizeof(double) * plan.real_pool.size());
+    }
     QSIM_HIP(s, hipMemcpyAsync(plan.dev, plan.host_pinned, total, hipMemcpyHostToDevice, s->stream),
              "hipMemcpyAsync(plan)");
     plan.dev_bytes = total;
@@ -186,6 +193,10 @@ static qsim_status run_plan(qsim_state s, Plan &plan) {
             case PASS_TILE:
                 prof_begin(s, QSIM_KCLASS_TILE, p.bytes, p.flops);
                 e = p.reg_r > 0 ? launch_tile_reg_pass(s, plan, p) : launch_tile_pass(s, plan, p);
+                break;
+            case PASS_MFMA:
+                prof_begin(s, QSIM_KCLASS_MFMA, p.bytes, p.flops);
+                e = launch_mfma_pass(s, plan, p);
                 break;
             default:
                 return set_error(QSIM_ERR_UNSUPPORTED, "pass kind not supported");

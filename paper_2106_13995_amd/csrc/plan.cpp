@@ -129,6 +129,32 @@ static Pass sweep_pass(const HostGate &g, int n, int dtype) {
 bool build_reg_program(Plan &plan, Pass &p, uint64_t q, const int *local_of,
                        const std::vector<const HostGate *> &gates);
 
+// Dense block on k >= 4 qubits as a real-embedded matrix product:
+// B = [[Re U^T, Im U^T], [-Im U^T, Re U^T]] (2D x 2D, row-major).
+static Pass mfma_pass(Plan &plan, const HostGate &g) {
+    const HostGate s = sorted_targets(g);
+    Pass p;
+    p.kind = PASS_MFMA;
+    p.k = s.k;
+    for (int b = 0; b < s.k; ++b) p.targets[b] = s.targets[b];
+    const int D = 1 << s.k, W = 2 * D;
+    p.pool_begin = int(plan.real_pool.size());
+    plan.real_pool.resize(plan.real_pool.size() + size_t(W) * W);
+    double *B = plan.real_pool.data() + p.pool_begin;
+    for (int c = 0; c < D; ++c)
+        for (int j = 0; j < D; ++j) {
+            const cd u = s.M[size_t(c) * D + j];
+            B[size_t(j) * W + c] = u.real();
+            B[size_t(D + j) * W + c] = -u.imag();
+            B[size_t(j) * W + D + c] = u.imag();
+            B[size_t(D + j) * W + D + c] = u.real();
+        }
+    p.pool_end = int(plan.real_pool.size());
+    p.bytes = 2.0 * std::ldexp(1.0, plan.n) * double(amp_bytes(plan.dtype));
+    p.flops = 8.0 * double(D) * std::ldexp(1.0, plan.n);
+    return p;
+}
+
 struct TileBuilder {
     int n, dtype, m, L;
     bool reg;
@@ -308,6 +334,8 @@ void build_plan(Plan &plan, const std::vector<HostGate> &gates_in, const PlanOpt
             const int nc = diag ? 0 : extract_controls(g, red, ctrls);
             if (diag || g.k - nc <= 3) {
                 plan.passes.push_back(sweep_pass(g, n, dtype));
+            } else if (po.use_mfma >= 0) {
+                plan.passes.push_back(mfma_pass(plan, g));
             } else {
                 // wide dense block: a one-gate tile pass over its qubits
                 TileBuilder tb(plan, n, dtype, std::min(n, default_tile_m(dtype)), false);

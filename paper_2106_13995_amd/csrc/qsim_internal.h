@@ -156,6 +156,8 @@ struct Plan {
     std::vector<RegOp> reg_ops;
     std::vector<RegStage> reg_stages;
     size_t reg_ops_dev_off = 0, reg_stages_dev_off = 0;
+    std::vector<double> real_pool;    // real-embedded block matrices of MFMA passes
+    size_t real_pool_dev_off = 0;
     // device copies (tile ops + pool rounded to the state precision)
     void *dev = nullptr;
     size_t dev_bytes = 0;
@@ -240,6 +242,7 @@ hipError_t launch_dense_sweep(qsim_state s, const Pass &p);
 hipError_t launch_diag_sweep(qsim_state s, const Pass &p);
 hipError_t launch_tile_pass(qsim_state s, const Plan &plan, const Pass &p);
 hipError_t launch_tile_reg_pass(qsim_state s, const Plan &plan, const Pass &p);
+hipError_t launch_mfma_pass(qsim_state s, const Plan &plan, const Pass &p);
 hipError_t launch_set_basis(qsim_state s, uint64_t index);
 
 // Expectation: writes partial sums to `partials` (double) and returns the

@@ -22,6 +22,7 @@ MODES = {
     "fuse4": dict(fuse_k=4, tile_m=-1),
     "fuse5": dict(fuse_k=5, tile_m=-1),
     "fuse6": dict(fuse_k=6, tile_m=-1),
+    "fuse5_lds": dict(fuse_k=5, tile_m=-1, use_mfma=-1),
     "fuse3_tile": dict(fuse_k=3, tile_m=0),
     "fuse5_tile": dict(fuse_k=5, tile_m=0),
 }
@@ -149,7 +150,7 @@ def test_grid_circuit_16q(qs, dtype, mode):
 
 
 @pytest.mark.parametrize("n", [1, 2, 3, 5, 7])
-@pytest.mark.parametrize("mode", ["sweep", "tile", "fuse3", "fuse3_tile"])
+@pytest.mark.parametrize("mode", ["sweep", "tile", "fuse3", "fuse3_tile", "fuse6"])
 def test_small_registers(qs, n, mode):
     rng = np.random.default_rng(106 + n)
     circ = W.random_circuit(n, 30, rng, max_matrix_k=min(n, 3))
@@ -185,6 +186,25 @@ def test_parametric_circuit(qs, mode):
     s.set_basis(0)
     s.apply_circuit(circ, params=p2, **MODES[mode])
     assert O.rel_l2(s.to_numpy(), O.apply_circuit(circ, params=p2)) <= TOL["c128"]
+
+
+@pytest.mark.parametrize("dtype", ["c64", "c128"])
+@pytest.mark.parametrize("k", [4, 5, 6])
+def test_mfma_block_every_placement(qs, dtype, k):
+    """Fused dense blocks on the matrix cores: low, high, mixed and scattered
+    targets, including registers smaller than one 64-row workgroup tile."""
+    rng = np.random.default_rng(120 + k)
+    for n in (k, k + 3, 16):
+        psi0 = _rounded(W.random_state(n, rng), dtype)
+        s = _state(qs, n, dtype, psi0)
+        ref = psi0.copy()
+        sets = [list(range(k)), list(range(n - k, n)), [int(t) for t in rng.choice(n, size=k, replace=False)]]
+        for tg in sets:
+            U = W.random_unitary(k, rng)
+            s.apply_gate(tg, U)
+            O.apply_matrix(ref, tg, U)
+        assert O.rel_l2(s.to_numpy(), ref) <= TOL[dtype], n
+        s.close()
 
 
 # ------------------------------------------------------------ closed forms through the oracle
