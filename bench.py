@@ -52,6 +52,7 @@ def parse():
     ap.add_argument("--calib-copy", action="store_true", help="run a plain device copy of the state size")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the 20-qubit adjoint-gradient figure")
     ap.add_argument("--no-batch", action="store_true", help="skip the 4096-circuit batch figure")
+    ap.add_argument("--no-sweeps", action="store_true", help="skip the single-gate sweep figures")
     return ap.parse_args()
 
 
@@ -201,6 +202,41 @@ def batch_bench(torch, q, W, dtype: str = "c64", reps: int = 3, loop_sample: int
             "loop_sample": len(sample)}
 
 
+def sweep_bench(torch, q, W, n: int = 30, dtype: str = "c64", reps: int = 5):
+    """Single dense gates applied to the whole 2^n state (one HBM sweep each):
+    k = 1..3 on the gate-sweep kernel, k = 4..6 on the matrix-core kernel, at
+    low, high and mixed target positions.  Each launch reads and writes every
+    amplitude once: 2 * 2^n * bytes-per-amplitude."""
+    rng = np.random.default_rng(7)
+    s = q.State(n, dtype)
+    amp = 8 if dtype == "c64" else 16
+    sets = {1: [[0], [1], [2], [4], [8], [15], [n - 1]],
+            2: [[0, 1], [n - 2, n - 1], [3, n - 5]],
+            3: [[0, 1, 2], [n - 3, n - 2, n - 1], [2, 14, n - 1]],
+            4: [[0, 1, 2, 3], [n - 4, n - 3, n - 2, n - 1]],
+            5: [[0, 1, 2, 3, 4], [n - 5, n - 4, n - 3, n - 2, n - 1]],
+            6: [[0, 1, 2, 3, 4, 5], [n - 6, n - 5, n - 4, n - 3, n - 2, n - 1]]}
+    out = {}
+    for k, tsets in sets.items():
+        for tg in tsets:
+            U = W.random_unitary(k, rng)
+            s.apply_gate(tg, U)
+            torch.cuda.synchronize()
+            s.profile(True)
+            for _ in range(reps):
+                s.apply_gate(tg, U)
+            cls = "mfma" if k >= 4 else "sweep_dense"
+            cnt, ms, by, fl = s.profile_read(cls)
+            s.profile(False)
+            gbs = by / (ms / 1e3) / 1e9
+            out[f"k{k}_t{'-'.join(map(str, tg))}"] = {
+                "kernel": cls, "avg_ms": round(ms / cnt, 4), "gbs": round(gbs, 1),
+                "hbm_frac": round(gbs / HBM_PEAK_GBS, 4), "tflops": round(fl / (ms / 1e3) / 1e12, 2)}
+    s.close()
+    return {"workload": f"one dense k-qubit gate on a {n}-qubit {dtype} state (2 x {2 ** n * amp} B per launch)",
+            "results": out}
+
+
 def calib_copy(torch, n: int, dtype: str):
     real = torch.float32 if dtype == "c64" else torch.float64
     a = torch.ones(2 << n, dtype=real, device="cuda")
@@ -285,6 +321,9 @@ def main():
     batch = None
     if not a.no_batch:
         batch = batch_bench(torch, q, W)
+    sweeps = None
+    if not a.no_sweeps:
+        sweeps = sweep_bench(torch, q, W, n=a.n, dtype=a.dtype)
 
     cpu = None
     if not a.no_cpu:
@@ -314,6 +353,7 @@ def main():
         "cpu_baseline": cpu,
         "adjoint": adjoint,
         "batch": batch,
+        "gate_sweeps": sweeps,
     }
     if extra:
         out["variants"] = extra

@@ -231,6 +231,20 @@ qsim_status qsim_batch_run(qsim_batch b, const double *params, double *energies,
 qsim_status qsim_batch_info(qsim_batch b, int *grid, int *programs, int *max_n);
 qsim_status qsim_batch_free(qsim_batch b);
 
+/* Autotuner: applies the circuit with each candidate option set (plain
+ * sweeps; LDS tile passes of three tile sizes with fusion widths 1..3;
+ * matrix-core blocks of 4..6 qubits), once to warm up and `reps` times timed
+ * with HIP events, and writes the fastest set to *best and its mean time per
+ * application to *best_ms (may be NULL).  The state's content is overwritten
+ * (the circuit runs (reps + 1) times per candidate).  The choice is stored
+ * per circuit structure (ops and matrices; parameter values excluded), width
+ * and dtype in a process-wide table, appended to the file named by the
+ * environment variable QSIM_TUNE_CACHE when set (and read from it on first
+ * use); qsim_apply_circuit and qsim_adjoint_grad use it whenever their
+ * options are NULL or all zero. */
+qsim_status qsim_autotune(qsim_state s, const qsim_circuit *c, const double *params, int64_t nparams, int reps,
+                          qsim_options *best, double *best_ms);
+
 /* Plans a circuit for an n-qubit state of `dtype` without touching any
  * device (host-only): validates the ops as qsim_apply_circuit does and
  * reports how many passes of each kind (QSIM_KCLASS_*, `counts` has

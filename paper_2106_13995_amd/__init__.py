@@ -49,7 +49,7 @@ EXPORTS = (
     "qsim_set_basis", "qsim_copy_to_host", "qsim_copy_from_host", "qsim_apply_gate",
     "qsim_apply_circuit", "qsim_expectation", "qsim_last_error", "qsim_profile_enable",
     "qsim_profile_read", "qsim_plan_summary", "qsim_adjoint_grad", "qsim_batch_create", "qsim_batch_run",
-    "qsim_batch_info", "qsim_batch_free",
+    "qsim_batch_info", "qsim_batch_free", "qsim_autotune",
 )
 
 
@@ -131,6 +131,8 @@ def _load() -> ctypes.CDLL:
                             ctypes.POINTER(ctypes.c_double), P], S),
         "qsim_batch_info": ([P, ctypes.POINTER(i32), ctypes.POINTER(i32), ctypes.POINTER(i32)], S),
         "qsim_batch_free": ([P], S),
+        "qsim_autotune": ([P, ctypes.POINTER(QsimCircuit), ctypes.POINTER(ctypes.c_double), i64, i32,
+                           ctypes.POINTER(QsimOptions), ctypes.POINTER(ctypes.c_double)], S),
         "qsim_profile_read": ([P, i32, ctypes.POINTER(i64), ctypes.POINTER(ctypes.c_double),
                                ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)], S),
     }
@@ -352,6 +354,16 @@ class State:
         content psi; the state is returned to psi (up to rounding)."""
         return qsim_adjoint_grad(self.handle, self.packed(circ), params, PackedPauliSum(H),
                                  make_options(fuse_k, tile_m, 0))
+
+    def autotune(self, circ, params: Optional[np.ndarray] = None, reps: int = 2):
+        """Times the candidate options for `circ` on this state (overwriting it)
+        and returns (options dict, ms per application) of the fastest."""
+        p = None if params is None else np.ascontiguousarray(params, dtype=np.float64)
+        best = QsimOptions()
+        ms = ctypes.c_double()
+        _check(_lib.qsim_autotune(ctypes.c_void_p(self.handle), ctypes.byref(self.packed(circ).c), _dptr(p),
+                                  0 if p is None else p.size, reps, ctypes.byref(best), ctypes.byref(ms)))
+        return {"fuse_k": best.fuse_k, "tile_m": best.tile_m, "use_mfma": best.use_mfma}, ms.value
 
     def to_numpy(self) -> np.ndarray:
         out = np.empty(1 << self.n, dtype=np.complex64 if self.dtype == QSIM_C64 else np.complex128)

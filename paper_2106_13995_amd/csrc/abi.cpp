@@ -301,6 +301,9 @@ static const size_t kMaxCachedPlans = 16;
 
 static qsim_status get_plan(qsim_state s, const qsim_circuit *c, const double *params, int64_t nparams,
                             const qsim_options *opts, Plan **out, bool cache = true) {
+    qsim_options tuned{};
+    const bool automatic = !opts || (opts->fuse_k == 0 && opts->tile_m == 0 && opts->use_mfma == 0);
+    if (automatic && tuned_options(c, s->n, s->dtype, &tuned)) opts = &tuned;
     const PlanOptions po = resolve_options(opts, s->n, s->dtype);
     std::string key;
     if (cache) {
@@ -774,6 +777,57 @@ qsim_status qsim_adjoint_grad(qsim_state s, const qsim_circuit *c, const double 
     *energy = hs[size_t(nprobes)];
     for (int64_t j = 0; j < nparams; ++j) grad[j] = 0.0;
     for (int k = 0; k < nprobes; ++k) grad[slot_param[size_t(k)]] += hs[size_t(k)];
+    return QSIM_OK;
+}
+
+qsim_status qsim_autotune(qsim_state s, const qsim_circuit *c, const double *params, int64_t nparams, int reps,
+                          qsim_options *best, double *best_ms) {
+    qsim_status st = check_state(s);
+    if (st != QSIM_OK) return st;
+    if (!c || !best) return set_error(QSIM_ERR_ARG, "NULL argument");
+    if (c->n != s->n) return set_error(QSIM_ERR_ARG, "circuit width does not match the state");
+    if (c->nops < 1 || !c->ops) return set_error(QSIM_ERR_ARG, "empty circuit");
+    if (reps < 1) return set_error(QSIM_ERR_ARG, "reps must be at least 1");
+    // candidates: plain sweeps; LDS tiles of three sizes with fusion 1..3;
+    // matrix-core blocks of 4..6 qubits
+    std::vector<qsim_options> cands;
+    cands.push_back({1, -1, -1, 0});
+    const int mlo = s->dtype == QSIM_C128 ? 10 : 11;
+    for (int m = mlo; m <= mlo + 2; ++m) {
+        if (m > s->n && m > mlo) break;
+        for (int f = 1; f <= 3; ++f) cands.push_back({f, m, -1, 0});
+    }
+    for (int f = 4; f <= 6; ++f)
+        if (f <= s->n) cands.push_back({f, -1, 1, 0});
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    QSIM_HIP(s, hipEventCreate(&e0), "hipEventCreate");
+    QSIM_HIP(s, hipEventCreate(&e1), "hipEventCreate");
+    double best_t = 1e300;
+    qsim_options chosen = cands[0];
+    for (const qsim_options &o : cands) {
+        Plan *plan = nullptr;
+        st = get_plan(s, c, params, nparams, &o, &plan);
+        if (st == QSIM_OK) st = run_plan(s, *plan);   // warm-up (and upload)
+        if (st != QSIM_OK) break;
+        QSIM_HIP(s, hipEventRecord(e0, s->stream), "hipEventRecord");
+        for (int r = 0; r < reps && st == QSIM_OK; ++r) st = run_plan(s, *plan);
+        if (st != QSIM_OK) break;
+        QSIM_HIP(s, hipEventRecord(e1, s->stream), "hipEventRecord");
+        QSIM_HIP(s, hipEventSynchronize(e1), "hipEventSynchronize");
+        float ms = 0.f;
+        QSIM_HIP(s, hipEventElapsedTime(&ms, e0, e1), "hipEventElapsedTime");
+        const double t = double(ms) / reps;
+        if (t < best_t) {
+            best_t = t;
+            chosen = o;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (st != QSIM_OK) return st;
+    remember_tuning(c, s->n, s->dtype, chosen);
+    *best = chosen;
+    if (best_ms) *best_ms = best_t;
     return QSIM_OK;
 }
 

@@ -31,6 +31,23 @@ __device__ __forceinline__ uint64_t insert_zeros(uint64_t x, const int *pos, int
     return x;
 }
 
+typedef float f32x2 __attribute__((ext_vector_type(2)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef double f64x2 __attribute__((ext_vector_type(2)));
+
+// Loads and stores of one or two amplitudes; NT marks them nontemporal
+// (streamed once through HBM, not worth keeping in the caches).
+template <bool NT, typename V>
+__device__ __forceinline__ V ld(const void *p) {
+    if constexpr (NT) return __builtin_nontemporal_load(static_cast<const V *>(p));
+    else return *static_cast<const V *>(p);
+}
+template <bool NT, typename V>
+__device__ __forceinline__ void st(void *p, V v) {
+    if constexpr (NT) __builtin_nontemporal_store(v, static_cast<V *>(p));
+    else *static_cast<V *>(p) = v;
+}
+
 constexpr int kBlockThreads = 256;
 
 // Sum of one double per thread over a 256-thread block (four 64-wide waves);

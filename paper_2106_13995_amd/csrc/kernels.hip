@@ -29,7 +29,9 @@ struct DenseArgs {
 // One thread applies the gate to V consecutive groups (V = 2 moves two
 // complex64 amplitudes per 16-byte access; needs the lowest inserted
 // position >= 1 so that the two groups are adjacent in memory).
-template <typename T, int K, int V>
+// NT: nontemporal accesses, used when the lowest inserted position is >= 4
+// (the 2^k streams of a group then lie in different cache lines).
+template <typename T, int K, int V, bool NT>
 __global__ void __launch_bounds__(kSweepThreads)
 k_dense_sweep(c2_t<T> *__restrict__ psi, const DenseArgs<T, K> a, uint64_t nthreads) {
     const uint64_t tid = uint64_t(blockIdx.x) * kSweepThreads + threadIdx.x;
@@ -40,10 +42,13 @@ k_dense_sweep(c2_t<T> *__restrict__ psi, const DenseArgs<T, K> a, uint64_t nthre
 #pragma unroll
     for (int j = 0; j < D; ++j) {
         if constexpr (V == 2) {
-            const float4 w = *reinterpret_cast<const float4 *>(psi + x + a.toff[j]);
+            const f32x4 w = ld<NT, f32x4>(psi + x + a.toff[j]);
             vr[j][0] = w.x; vi[j][0] = w.y; vr[j][1] = w.z; vi[j][1] = w.w;
+        } else if constexpr (sizeof(T) == 8) {
+            const f64x2 w = ld<NT, f64x2>(psi + x + a.toff[j]);
+            vr[j][0] = w.x; vi[j][0] = w.y;
         } else {
-            const c2_t<T> w = psi[x + a.toff[j]];
+            const f32x2 w = ld<NT, f32x2>(psi + x + a.toff[j]);
             vr[j][0] = w.x; vi[j][0] = w.y;
         }
     }
@@ -59,11 +64,11 @@ k_dense_sweep(c2_t<T> *__restrict__ psi, const DenseArgs<T, K> a, uint64_t nthre
             for (int v = 0; v < V; ++v) cfma(orr[v], oi[v], ur, ui, vr[c][v], vi[c][v]);
         }
         if constexpr (V == 2) {
-            *reinterpret_cast<float4 *>(psi + x + a.toff[r]) = make_float4(orr[0], oi[0], orr[1], oi[1]);
+            st<NT, f32x4>(psi + x + a.toff[r], f32x4{orr[0], oi[0], orr[1], oi[1]});
+        } else if constexpr (sizeof(T) == 8) {
+            st<NT, f64x2>(psi + x + a.toff[r], f64x2{orr[0], oi[0]});
         } else {
-            c2_t<T> w;
-            w.x = orr[0]; w.y = oi[0];
-            psi[x + a.toff[r]] = w;
+            st<NT, f32x2>(psi + x + a.toff[r], f32x2{orr[0], oi[0]});
         }
     }
 }
@@ -95,13 +100,27 @@ static hipError_t dense_sweep_t(qsim_state s, const Pass &p) {
     }
     const uint64_t groups = 1ull << (s->n - np);
     auto *psi = static_cast<c2_t<T> *>(s->data);
-    if (std::is_same<T, float>::value && all[0] >= 1 && groups >= 2) {
-        const uint64_t nt = groups / 2;
-        const dim3 grid(unsigned((nt + kSweepThreads - 1) / kSweepThreads));
-        hipLaunchKernelGGL((k_dense_sweep<T, K, 2>), grid, dim3(kSweepThreads), 0, s->stream, psi, a, nt);
-    } else {
+    const bool nt = all[0] >= 4;
+    if constexpr (std::is_same<T, float>::value) {
+        if (all[0] >= 1 && groups >= 2) {
+            const uint64_t nthr = groups / 2;
+            const dim3 grid(unsigned((nthr + kSweepThreads - 1) / kSweepThreads));
+            if (nt)
+                hipLaunchKernelGGL((k_dense_sweep<T, K, 2, true>), grid, dim3(kSweepThreads), 0, s->stream, psi, a,
+                                   nthr);
+            else
+                hipLaunchKernelGGL((k_dense_sweep<T, K, 2, false>), grid, dim3(kSweepThreads), 0, s->stream, psi, a,
+                                   nthr);
+            return hipGetLastError();
+        }
+    }
+    {
         const dim3 grid(unsigned((groups + kSweepThreads - 1) / kSweepThreads));
-        hipLaunchKernelGGL((k_dense_sweep<T, K, 1>), grid, dim3(kSweepThreads), 0, s->stream, psi, a, groups);
+        if (nt)
+            hipLaunchKernelGGL((k_dense_sweep<T, K, 1, true>), grid, dim3(kSweepThreads), 0, s->stream, psi, a, groups);
+        else
+            hipLaunchKernelGGL((k_dense_sweep<T, K, 1, false>), grid, dim3(kSweepThreads), 0, s->stream, psi, a,
+                               groups);
     }
     return hipGetLastError();
 }

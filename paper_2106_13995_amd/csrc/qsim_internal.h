@@ -176,6 +176,11 @@ struct PlanOptions {
 
 PlanOptions resolve_options(const qsim_options *o, int n, int dtype);
 
+// Options the autotuner chose for this circuit structure (ops and matrices,
+// not parameter values) on n qubits of `dtype`, if it has run for it.
+bool tuned_options(const qsim_circuit *c, int n, int dtype, qsim_options *out);
+void remember_tuning(const qsim_circuit *c, int n, int dtype, const qsim_options &o);
+
 // Builds passes from normalised gates.
 void build_plan(Plan &plan, const std::vector<HostGate> &gates, const PlanOptions &po);
 

@@ -293,3 +293,16 @@ def test_invalid_gate_leaves_state_unchanged(qs):
     with pytest.raises(qs.QsimError):
         s.apply_circuit(W.Circuit(n, [W.op("h", 1), W.Op("cx", (2, 9))]))
     np.testing.assert_array_equal(s.to_numpy(), psi0)
+
+
+def test_autotune_choice_is_used_and_correct(qs, tmp_path, monkeypatch):
+    circ = W.random_grid_circuit(4, 4, depth=12, seed=3)
+    s = _state(qs, 16, "c64")
+    best, ms = s.autotune(circ, reps=1)
+    assert ms > 0
+    assert best["fuse_k"] in range(1, 7) and best["tile_m"] in (-1, 11, 12, 13)
+    # automatic options now take the tuned choice; results stay within the bar
+    s.set_basis(0)
+    s.apply_circuit(circ)
+    assert O.rel_l2(s.to_numpy(), O.apply_circuit(circ)) <= TOL["c64"]
+    s.close()
