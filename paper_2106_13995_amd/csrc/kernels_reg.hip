@@ -18,6 +18,14 @@ namespace qsim {
 
 constexpr int kRegThreads = 256;
 
+// Op descriptors, stage descriptors and gate matrices are read through the
+// constant address space: uniform loads become scalar loads into SGPRs, which
+// the vector FMAs take as operands directly.
+#define QSIM_CONST __attribute__((address_space(4)))
+typedef const QSIM_CONST RegOp CRegOp;
+typedef const QSIM_CONST RegStage CRegStage;
+template <typename T> using CT = const QSIM_CONST T;   // interleaved (re, im) matrix entries
+
 template <typename T>
 struct RegArgs {
     c2_t<T> *psi;
@@ -27,7 +35,7 @@ struct RegArgs {
     int nstages, nops, npool;
     int m, L, H;
     int hpos[16];
-    int8_t ld_t[8], ld_r[kRegBitsMax], st_t[8], st_r[kRegBitsMax];
+    int32_t ld_t[8], ld_r[kRegBitsMax], st_t[8], st_r[kRegBitsMax];
 };
 
 // Deposits the bits of j into the set bits of mask (compile-time).
@@ -53,7 +61,7 @@ __host__ __device__ constexpr int popcount_c(int v) {
 // Dense gate on the register bits of MASK: for every group of register
 // indices that agree outside MASK, multiply by the 2^k x 2^k matrix.
 template <typename T, int R, int MASK>
-__device__ __forceinline__ void apply_mask(T *vr, T *vi, const c2_t<T> *U) {
+__device__ __forceinline__ void apply_mask(T *vr, T *vi, CT<T> *U) {
     constexpr int K = popcount_c(MASK);
     constexpr int D = 1 << K;
     constexpr int NA = 1 << R;
@@ -66,9 +74,8 @@ __device__ __forceinline__ void apply_mask(T *vr, T *vi, const c2_t<T> *U) {
             T ur[D], ui[D];
 #pragma unroll
             for (int c = 0; c < D; ++c) {
-                const c2_t<T> u = U[rr * D + c];
-                ur[c] = u.x;
-                ui[c] = u.y;
+                ur[c] = U[2 * (rr * D + c)];
+                ui[c] = U[2 * (rr * D + c) + 1];
             }
 #pragma unroll
             for (int g = 0; g < NA; ++g) {
@@ -92,9 +99,8 @@ __device__ __forceinline__ void apply_mask(T *vr, T *vi, const c2_t<T> *U) {
     {
 #pragma unroll
         for (int e = 0; e < D * D; ++e) {
-            const c2_t<T> u = U[e];
-            ur[e] = u.x;
-            ui[e] = u.y;
+            ur[e] = U[2 * e];
+            ui[e] = U[2 * e + 1];
         }
     }
 #pragma unroll
@@ -118,7 +124,7 @@ __device__ __forceinline__ void apply_mask(T *vr, T *vi, const c2_t<T> *U) {
 }
 
 template <typename T, int R, int MASK>
-__device__ __forceinline__ void dispatch_dense(int rmask, T *vr, T *vi, const c2_t<T> *U) {
+__device__ __forceinline__ void dispatch_dense(int rmask, T *vr, T *vi, CT<T> *U) {
     if constexpr (MASK < (1 << R)) {
         if constexpr (popcount_c(MASK) <= 3) {
             if (rmask == MASK) {
@@ -133,8 +139,7 @@ __device__ __forceinline__ void dispatch_dense(int rmask, T *vr, T *vi, const c2
 // Diagonal gate: the diagonal index of register amplitude i collects bits
 // from the tile's fixed (out-of-tile) qubits, the thread id and i itself.
 template <typename T, int R>
-__device__ __forceinline__ void apply_diag(T *vr, T *vi, const RegOp &op, const c2_t<T> *Dg, uint64_t base,
-                                           uint32_t t) {
+__device__ __forceinline__ void apply_diag(T *vr, T *vi, CRegOp &op, CT<T> *Dg, uint64_t base, uint32_t t) {
     constexpr int NA = 1 << R;
     int jt = 0;
     for (int b = 0; b < op.nout; ++b) jt |= int((base >> op.gp[b]) & 1ull) << op.gj[b];
@@ -147,30 +152,30 @@ __device__ __forceinline__ void apply_diag(T *vr, T *vi, const RegOp &op, const 
             rval |= ((op.jmatch >> op.rj[b]) & 1) << op.rb[b];
         }
         if (((jt ^ op.jmatch) & ~regj) != 0) return;
-        const c2_t<T> d = Dg[op.jmatch];
+        const T dx = Dg[2 * op.jmatch], dy = Dg[2 * op.jmatch + 1];
         const int rmask = op.rmask;
 #pragma unroll
         for (int i = 0; i < NA; ++i) {
             if ((i & rmask) != rval) continue;
             const T xr = vr[i], xi = vi[i];
-            vr[i] = d.x * xr - d.y * xi;
-            vi[i] = d.x * xi + d.y * xr;
+            vr[i] = dx * xr - dy * xi;
+            vi[i] = dx * xi + dy * xr;
         }
     } else {
 #pragma unroll
         for (int i = 0; i < NA; ++i) {
             int j = jt;
             for (int b = 0; b < op.nreg; ++b) j |= ((i >> op.rb[b]) & 1) << op.rj[b];
-            const c2_t<T> d = Dg[j];
+            const T dx = Dg[2 * j], dy = Dg[2 * j + 1];
             const T xr = vr[i], xi = vi[i];
-            vr[i] = d.x * xr - d.y * xi;
-            vi[i] = d.x * xi + d.y * xr;
+            vr[i] = dx * xr - dy * xi;
+            vi[i] = dx * xi + dy * xr;
         }
     }
 }
 
 template <typename T>
-__device__ __forceinline__ uint32_t thread_part(uint32_t t, const uint16_t *vec) {
+__device__ __forceinline__ uint32_t thread_part(uint32_t t, const QSIM_CONST uint32_t *vec) {
     uint32_t a = 0;
 #pragma unroll
     for (int b = 0; b < 8; ++b)
@@ -183,24 +188,10 @@ __global__ void __launch_bounds__(kRegThreads) k_tile_reg(const RegArgs<T> a) {
     constexpr int NA = 1 << R;
     extern __shared__ char lds_raw[];
     c2_t<T> *lds = reinterpret_cast<c2_t<T> *>(lds_raw);
-    const uint32_t M = 1u << a.m;
-    RegStage *sst = reinterpret_cast<RegStage *>(lds + M);
-    RegOp *sop = reinterpret_cast<RegOp *>(sst + a.nstages);
-    const size_t pool_off = ((sizeof(c2_t<T>) << a.m) + sizeof(RegStage) * size_t(a.nstages) +
-                             sizeof(RegOp) * size_t(a.nops) + 15) & ~size_t(15);
-    c2_t<T> *spool = reinterpret_cast<c2_t<T> *>(lds_raw + pool_off);
+    CRegStage *sst = (CRegStage *)(a.stages);
+    CRegOp *sop = (CRegOp *)(a.ops);
+    CT<T> *spool = (CT<T> *)(a.pool);
     const uint32_t t = threadIdx.x;
-    {
-        const int *src = reinterpret_cast<const int *>(a.stages);
-        int *dst = reinterpret_cast<int *>(sst);
-        const int ns = a.nstages * int(sizeof(RegStage) / sizeof(int));
-        for (int w = int(t); w < ns; w += kRegThreads) dst[w] = src[w];
-        src = reinterpret_cast<const int *>(a.ops);
-        dst = reinterpret_cast<int *>(sop);
-        const int no = a.nops * int(sizeof(RegOp) / sizeof(int));
-        for (int w = int(t); w < no; w += kRegThreads) dst[w] = src[w];
-        for (int e = int(t); e < a.npool; e += kRegThreads) spool[e] = a.pool[e];
-    }
     uint64_t base = uint64_t(blockIdx.x) << a.L;
     for (int i = 0; i < a.H; ++i) {
         const uint64_t lo = base & ((1ull << a.hpos[i]) - 1ull);
@@ -222,9 +213,8 @@ __global__ void __launch_bounds__(kRegThreads) k_tile_reg(const RegArgs<T> a) {
             vi[i] = w.y;
         }
     }
-    __syncthreads();
     for (int s = 0; s < a.nstages; ++s) {
-        const RegStage &st = sst[s];
+        CRegStage &st = sst[s];
         if (s > 0) {
             const uint32_t aw = thread_part<T>(t, st.wr_t);
 #pragma unroll
@@ -253,8 +243,8 @@ __global__ void __launch_bounds__(kRegThreads) k_tile_reg(const RegArgs<T> a) {
             __syncthreads();
         }
         for (int o = st.op_begin; o < st.op_end; ++o) {
-            const RegOp &op = sop[o];
-            const c2_t<T> *U = spool + op.moff;
+            CRegOp &op = sop[o];
+            CT<T> *U = spool + 2 * op.moff;
             if (op.type == 0)
                 dispatch_dense<T, R, 1>(op.rmask, vr, vi, U);
             else
@@ -303,15 +293,7 @@ static hipError_t launch_reg_t(qsim_state s, const Plan &plan, const Pass &p) {
         a.ld_r[b] = p.ld_r[b];
         a.st_r[b] = p.st_r[b];
     }
-    const size_t head = (sizeof(c2_t<T>) << p.m) + sizeof(RegStage) * size_t(a.nstages) +
-                        sizeof(RegOp) * size_t(a.nops);
-    const size_t lds = ((head + 15) & ~size_t(15)) + sizeof(c2_t<T>) * size_t(a.npool);
-    const void *fn = reinterpret_cast<const void *>(&k_tile_reg<T, R>);
-    if (lds > 65536) {
-        if (lds > 160 * 1024) return hipErrorInvalidValue;
-        hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, int(lds));
-        if (e != hipSuccess) return e;
-    }
+    const size_t lds = sizeof(c2_t<T>) << p.m;
     const uint64_t ntiles = 1ull << (s->n - p.m);
     hipLaunchKernelGGL((k_tile_reg<T, R>), dim3(unsigned(ntiles)), dim3(kRegThreads), lds, s->stream, a);
     return hipGetLastError();

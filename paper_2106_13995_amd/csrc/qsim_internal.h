@@ -106,10 +106,10 @@ struct RegOp {
     int32_t moff;     // pool offset of the matrix / diagonal (complex entries)
     int32_t nreg, nthr, nout;
     int32_t jmatch;   // type 2: index of the non-unit diagonal entry
-    int8_t rb[QSIM_MAX_K], rj[QSIM_MAX_K];   // targets in register bits: bit, diagonal-index bit
-    int8_t tb[QSIM_MAX_K], tj[QSIM_MAX_K];   // targets in thread bits
-    int8_t gp[QSIM_MAX_K], gj[QSIM_MAX_K];   // targets outside the tile: global qubit
-    int32_t pad_;
+    // (32-bit fields throughout: the kernel reads them with scalar loads)
+    int32_t rb[QSIM_MAX_K], rj[QSIM_MAX_K];   // targets in register bits: bit, diagonal-index bit
+    int32_t tb[QSIM_MAX_K], tj[QSIM_MAX_K];   // targets in thread bits
+    int32_t gp[QSIM_MAX_K], gj[QSIM_MAX_K];   // targets outside the tile: global qubit
 };
 
 struct RegStage {
@@ -117,8 +117,7 @@ struct RegStage {
     // exchange into this stage (stage 0 is loaded from HBM instead): LDS
     // address, in amplitudes, contributed by each thread / register bit of
     // the previous layout (write) and of this stage's layout (read)
-    uint16_t wr_t[8], wr_r[kRegBitsMax], rd_t[8], rd_r[kRegBitsMax];
-    uint16_t pad_;
+    uint32_t wr_t[8], wr_r[kRegBitsMax], rd_t[8], rd_r[kRegBitsMax];
 };
 
 struct Pass {

@@ -86,12 +86,12 @@ void make_exchange(int m, int wb, uint32_t Rw, uint32_t Rr, RegStage &st, uint64
         }
     }
     for (int b = 0; b < 8; ++b) {
-        st.wr_t[b] = uint16_t(best[Twp[b]]);
-        st.rd_t[b] = uint16_t(best[Trp[b]]);
+        st.wr_t[b] = best[Twp[b]];
+        st.rd_t[b] = best[Trp[b]];
     }
     for (int b = 0; b < kRegBitsMax; ++b) {
-        st.wr_r[b] = b < r ? uint16_t(best[Rwp[b]]) : 0;
-        st.rd_r[b] = b < r ? uint16_t(best[Rrp[b]]) : 0;
+        st.wr_r[b] = b < r ? best[Rwp[b]] : 0u;
+        st.rd_r[b] = b < r ? best[Rrp[b]] : 0u;
     }
 }
 
@@ -237,18 +237,18 @@ bool build_reg_program(Plan &plan, Pass &p, uint64_t q, const int *local_of,
                         const int lp = local_of[t];
                         const int ri = index_in(Rp, r, lp);
                         if (ri >= 0) {
-                            op.rb[op.nreg] = int8_t(ri);
-                            op.rj[op.nreg] = int8_t(b);
+                            op.rb[op.nreg] = ri;
+                            op.rj[op.nreg] = b;
                             op.rmask |= 1 << ri;
                             ++op.nreg;
                         } else {
-                            op.tb[op.nthr] = int8_t(index_in(Tp, 8, lp));
-                            op.tj[op.nthr] = int8_t(b);
+                            op.tb[op.nthr] = index_in(Tp, 8, lp);
+                            op.tj[op.nthr] = b;
                             ++op.nthr;
                         }
                     } else {
-                        op.gp[op.nout] = int8_t(t);
-                        op.gj[op.nout] = int8_t(b);
+                        op.gp[op.nout] = t;
+                        op.gj[op.nout] = b;
                         ++op.nout;
                     }
                 }

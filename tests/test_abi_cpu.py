@@ -141,3 +141,45 @@ def test_set_basis_validation(fake_state):
 def test_null_handles():
     assert q._lib.qsim_set_basis(None, 0) == q.QSIM_ERR_ARG
     assert q._lib.qsim_free(None) == q.QSIM_OK
+
+
+# ------------------------------------------------------------ host planner (no device work)
+
+def _summary(circ, n=None, dtype=1, **opts):
+    return q.qsim_plan_summary(n or circ.n, dtype, circ, opts=q.make_options(**opts) if opts else None)
+
+
+def test_plan_summary_sweeps_count_every_gate():
+    circ = W.random_grid_circuit(5, 6, depth=20, seed=2)
+    counts, by, fl = _summary(circ, fuse_k=1, tile_m=-1)
+    assert counts["sweep_dense"] == circ.count("u3") and counts["sweep_diag"] == circ.count("cz")
+    N, s = 2 ** 30, 8
+    # a U3 sweep moves 2 N s bytes, a CZ only the quarter with both bits set
+    assert by == 600 * 2 * N * s + 245 * 2 * (N // 4) * s
+    assert fl == 600 * 16 * N + 245 * 6 * (N // 4)
+
+
+def test_plan_summary_controls_and_diagonals():
+    ops = [W.op("cx", 3, 17), W.op("ccx", 1, 2, 20), W.op("ccz", 4, 5, 6), W.op("cp", 7, 8, angles=(0.3,))]
+    circ = W.Circuit(24, ops)
+    counts, by, fl = _summary(circ, fuse_k=1, tile_m=-1)
+    N, s = 2 ** 24, 8
+    assert counts["sweep_dense"] == 2 and counts["sweep_diag"] == 2
+    assert by == 2 * (N // 2) * s + 2 * (N // 4) * s + 2 * (N // 8) * s + 2 * (N // 4) * s
+
+
+def test_plan_summary_tiles_fewer_passes_and_same_flops():
+    circ = W.random_grid_circuit(5, 6, depth=20, seed=2)
+    c_sw, b_sw, f_sw = _summary(circ, fuse_k=1, tile_m=-1)
+    c_t, b_t, f_t = _summary(circ, fuse_k=1, tile_m=12)
+    assert 10 <= c_t["tile"] <= 40
+    assert b_t == c_t["tile"] * 2 * 2 ** 30 * 8
+    assert f_t == f_sw                       # same gate arithmetic, grouped differently
+    c_f, b_f, f_f = _summary(circ, fuse_k=5, tile_m=-1)
+    assert c_f["mfma"] > 0 and sum(c_f.values()) < sum(c_sw.values())
+
+
+def test_plan_summary_rejects_bad_ops_without_device():
+    bad = W.Circuit(8, [W.Op("cz", (2, 2))])
+    with pytest.raises(q.QsimError):
+        _summary(bad)
