@@ -24,11 +24,17 @@ FLAGS = [
     "-Wall", "-Wno-unused-command-line-argument",
     "-I", os.path.join(ROOT, "include"),
 ]
+# Per-source additions.  Register tiles: SimplifyCFG's sinking of common
+# stores out of the per-mask branches turns the amplitude arrays into
+# pointer phis, which demotes them to scratch memory; keep them in VGPRs.
+EXTRA = {
+    "kernels_reg.hip": ["-mllvm", "-simplifycfg-sink-common=false"],
+}
 
 
 def _compile(src: str) -> str:
     obj = os.path.join(OBJ, src + ".o")
-    cmd = [HIPCC, *FLAGS, "-x", "hip", "-c", os.path.join(CSRC, src), "-o", obj]
+    cmd = [HIPCC, *FLAGS, *EXTRA.get(src, []), "-x", "hip", "-c", os.path.join(CSRC, src), "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"compiling {src} failed:\n{r.stdout}\n{r.stderr}")

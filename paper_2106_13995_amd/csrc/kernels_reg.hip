@@ -208,9 +208,16 @@ __global__ void __launch_bounds__(kRegThreads) k_tile_reg(const RegArgs<T> a) {
 #pragma unroll
             for (int b = 0; b < R; ++b)
                 if ((i >> b) & 1) gi |= 1ull << a.ld_r[b];
-            const c2_t<T> w = a.psi[gt | gi];
-            vr[i] = w.x;
-            vi[i] = w.y;
+            // every amplitude is read once per pass: nontemporal
+            if constexpr (sizeof(T) == 4) {
+                const f32x2 w = ld<true, f32x2>(a.psi + (gt | gi));
+                vr[i] = w.x;
+                vi[i] = w.y;
+            } else {
+                const f64x2 w = ld<true, f64x2>(a.psi + (gt | gi));
+                vr[i] = w.x;
+                vi[i] = w.y;
+            }
         }
     }
     for (int s = 0; s < a.nstages; ++s) {
@@ -261,10 +268,10 @@ __global__ void __launch_bounds__(kRegThreads) k_tile_reg(const RegArgs<T> a) {
 #pragma unroll
             for (int b = 0; b < R; ++b)
                 if ((i >> b) & 1) gi |= 1ull << a.st_r[b];
-            c2_t<T> w;
-            w.x = vr[i];
-            w.y = vi[i];
-            a.psi[gt | gi] = w;
+            if constexpr (sizeof(T) == 4)
+                st<true, f32x2>(a.psi + (gt | gi), f32x2{vr[i], vi[i]});
+            else
+                st<true, f64x2>(a.psi + (gt | gi), f64x2{vr[i], vi[i]});
         }
     }
 }
