@@ -31,6 +31,7 @@ HBM_PEAK_GBS = 8000.0
 ALU_PEAK_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
 KERNEL_SOURCES = {
     "tile": ["kernels_reg.hip", "kernels.hip"],
+    "tile_jit": ["jit.cpp", "stages.cpp", "gates.cpp"],
     "sweep_dense": ["kernels.hip"],
     "sweep_diag": ["kernels.hip"],
 }
@@ -46,7 +47,7 @@ def parse():
     ap.add_argument("--dtype", default="c64")
     ap.add_argument("--fuse-k", type=int, default=0)
     ap.add_argument("--tile-m", type=int, default=0)
-    ap.add_argument("--modes", default="", help="comma list of extra fuse_k:tile_m variants to time")
+    ap.add_argument("--modes", default="", help="comma list of extra fuse_k:tile_m[:split_1q] variants to time")
     ap.add_argument("--cpu-gates", type=int, default=4, help="gates of the circuit the oracle times")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--calib-copy", action="store_true", help="run a plain device copy of the state size")
@@ -94,9 +95,9 @@ def cpu_baseline(circ, ngates: int):
                       f"1 thread, {dt:.1f} s (includes one copy of the 2^{circ.n}-amplitude input)"}
 
 
-def time_mode(torch, s, circ, steps, warmup, fuse_k, tile_m):
+def time_mode(torch, s, circ, steps, warmup, fuse_k, tile_m, split_1q=0):
     for _ in range(warmup):
-        s.apply_circuit(circ, fuse_k=fuse_k, tile_m=tile_m)
+        s.apply_circuit(circ, fuse_k=fuse_k, tile_m=tile_m, split_1q=split_1q)
     torch.cuda.synchronize()
     s.profile(True)
     start = torch.cuda.Event(enable_timing=True)
@@ -105,13 +106,13 @@ def time_mode(torch, s, circ, steps, warmup, fuse_k, tile_m):
     t0 = time.perf_counter()
     start.record()
     for _ in range(steps):
-        s.apply_circuit(circ, fuse_k=fuse_k, tile_m=tile_m)
+        s.apply_circuit(circ, fuse_k=fuse_k, tile_m=tile_m, split_1q=split_1q)
     stop.record()
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     ev_ms = start.elapsed_time(stop)
     stats = {}
-    for cls in ("sweep_dense", "sweep_diag", "tile", "mfma"):
+    for cls in ("sweep_dense", "sweep_diag", "tile", "tile_jit", "mfma"):
         n, ms, by, fl = s.profile_read(cls)
         if n:
             stats[cls] = (n, ms, by, fl)
@@ -313,10 +314,10 @@ def main():
 
     extra = {}
     for m in [x for x in a.modes.split(",") if x]:
-        fk, tm = (int(v) for v in m.split(":"))
+        fk, tm, *sp = (int(v) for v in m.split(":"))
         s.set_basis(0)
         k = max(1, a.steps // 2)
-        w2, e2, st2 = time_mode(torch, s, circ, k, 1, fk, tm)
+        w2, e2, st2 = time_mode(torch, s, circ, k, 1, fk, tm, sp[0] if sp else 0)
         extra[m] = {"ms_per_step": round(e2 / k, 3), "gate_apps_per_s": round(ngates * k / (e2 / 1e3), 1),
                     "passes_per_step": sum(v[0] for v in st2.values()) // k}
 

@@ -122,12 +122,18 @@ typedef struct {
  *   tile_m:  -1 = every gate / block is its own sweep over the state;
  *            m in [4, 13] (c64) / [4, 12] (c128) = group gates into passes
  *            that hold 2^m-amplitude tiles in LDS; 0 = automatic.
- *   use_mfma: -1 never, 1 whenever a fused block has k >= 4, 0 automatic. */
+ *   use_mfma: -1 never, 1 whenever a fused block has k >= 4, 0 automatic.
+ *   split_1q: single-qubit unitaries in tile passes.  1 (and 0, automatic):
+ *            each is written as g diag(1, b) O diag(1, a) with O a real
+ *            rotation; O runs as three in-place multiply-adds per amplitude
+ *            component and the phases travel, merged, to the next gate that
+ *            does not commute with them.  -1: every gate is applied as its
+ *            complex 2 x 2 matrix.  Both are exact up to rounding. */
 typedef struct {
     int32_t fuse_k;
     int32_t tile_m;
     int32_t use_mfma;
-    int32_t reserved_;
+    int32_t split_1q;
 } qsim_options;
 
 typedef struct qsim_state_s *qsim_state;
@@ -273,7 +279,8 @@ typedef enum {
     QSIM_KCLASS_MFMA = 3,         /* MFMA fused-block passes */
     QSIM_KCLASS_EXPECT = 4,       /* expectation passes (and lambda = H psi) */
     QSIM_KCLASS_ADJOINT = 5,      /* reverse tile passes of the adjoint method */
-    QSIM_KCLASS_COUNT_ = 6
+    QSIM_KCLASS_TILE_JIT = 6,     /* register tile passes compiled at run time */
+    QSIM_KCLASS_COUNT_ = 7
 } qsim_kernel_class;
 
 qsim_status qsim_profile_enable(qsim_state s, int on);

@@ -39,7 +39,7 @@ GATE_CODES: Dict[str, int] = {
     "ccx": 17, "ccz": 18,
 }
 
-KCLASS = {"sweep_dense": 0, "sweep_diag": 1, "tile": 2, "mfma": 3, "expect": 4, "adjoint": 5}
+KCLASS = {"sweep_dense": 0, "sweep_diag": 1, "tile": 2, "mfma": 3, "expect": 4, "adjoint": 5, "tile_jit": 6}
 
 MAX_K = 6
 
@@ -80,7 +80,7 @@ class QsimPauliSum(ctypes.Structure):
 
 class QsimOptions(ctypes.Structure):
     _fields_ = [("fuse_k", ctypes.c_int32), ("tile_m", ctypes.c_int32), ("use_mfma", ctypes.c_int32),
-                ("reserved_", ctypes.c_int32)]
+                ("split_1q", ctypes.c_int32)]
 
 
 def _hip_runtimes() -> set:
@@ -233,8 +233,8 @@ class PackedCircuit:
         self.nops = len(circ.ops)
 
 
-def make_options(fuse_k: int = 0, tile_m: int = 0, use_mfma: int = 0) -> QsimOptions:
-    return QsimOptions(fuse_k, tile_m, use_mfma, 0)
+def make_options(fuse_k: int = 0, tile_m: int = 0, use_mfma: int = 0, split_1q: int = 0) -> QsimOptions:
+    return QsimOptions(fuse_k, tile_m, use_mfma, split_1q)
 
 
 def qsim_apply_circuit(h: int, packed: PackedCircuit, params: Optional[np.ndarray] = None,
@@ -343,8 +343,8 @@ class State:
         return pc
 
     def apply_circuit(self, circ, params: Optional[np.ndarray] = None, fuse_k: int = 0, tile_m: int = 0,
-                      use_mfma: int = 0) -> None:
-        qsim_apply_circuit(self.handle, self.packed(circ), params, make_options(fuse_k, tile_m, use_mfma))
+                      use_mfma: int = 0, split_1q: int = 0) -> None:
+        qsim_apply_circuit(self.handle, self.packed(circ), params, make_options(fuse_k, tile_m, use_mfma, split_1q))
 
     def expectation(self, H) -> float:
         return qsim_expectation(self.handle, PackedPauliSum(H))
@@ -363,7 +363,8 @@ class State:
         ms = ctypes.c_double()
         _check(_lib.qsim_autotune(ctypes.c_void_p(self.handle), ctypes.byref(self.packed(circ).c), _dptr(p),
                                   0 if p is None else p.size, reps, ctypes.byref(best), ctypes.byref(ms)))
-        return {"fuse_k": best.fuse_k, "tile_m": best.tile_m, "use_mfma": best.use_mfma}, ms.value
+        return {"fuse_k": best.fuse_k, "tile_m": best.tile_m, "use_mfma": best.use_mfma,
+                "split_1q": best.split_1q}, ms.value
 
     def to_numpy(self) -> np.ndarray:
         out = np.empty(1 << self.n, dtype=np.complex64 if self.dtype == QSIM_C64 else np.complex128)

@@ -13,7 +13,7 @@ OBJ = os.path.join(ROOT, "_build", "qsim")
 LIB = os.path.join(HERE, "libqsim.so")
 SOURCES = ["abi.cpp", "gates.cpp", "plan.cpp", "stages.cpp", "kernels.hip", "kernels_reg.hip",
            "kernels_adjoint.hip", "batch.cpp", "kernels_batch.hip",
-           "kernels_mfma.hip", "autotune.cpp"]
+           "kernels_mfma.hip", "autotune.cpp", "jit.cpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
@@ -51,7 +51,9 @@ def build(verbose: bool = False) -> str:
     with ThreadPoolExecutor(max_workers=min(8, len(SOURCES))) as ex:
         objs = list(ex.map(_compile, SOURCES))
     tmp = LIB + ".tmp"
-    cmd = [HIPCC, "-shared", "-fPIC", f"--offload-arch={ARCH}", "-o", tmp, *objs]
+    # libhiprtc: resolved at load time to the copy the process already holds
+    # (torch's, same soname) when torch is imported first
+    cmd = [HIPCC, "-shared", "-fPIC", f"--offload-arch={ARCH}", "-o", tmp, *objs, "-lhiprtc"]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"linking libqsim.so failed:\n{r.stdout}\n{r.stderr}")

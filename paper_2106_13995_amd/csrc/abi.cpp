@@ -179,7 +179,8 @@ static qsim_status upload_plan(qsim_state s, Plan &plan) {
 static qsim_status run_plan(qsim_state s, Plan &plan) {
     qsim_status st = upload_plan(s, plan);
     if (st != QSIM_OK) return st;
-    for (const Pass &p : plan.passes) {
+    for (size_t i = 0; i < plan.passes.size(); ++i) {
+        const Pass &p = plan.passes[i];
         hipError_t e = hipSuccess;
         switch (p.kind) {
             case PASS_DENSE:
@@ -191,8 +192,13 @@ static qsim_status run_plan(qsim_state s, Plan &plan) {
                 e = launch_diag_sweep(s, p);
                 break;
             case PASS_TILE:
-                prof_begin(s, QSIM_KCLASS_TILE, p.bytes, p.flops);
-                e = p.reg_r > 0 ? launch_tile_reg_pass(s, plan, p) : launch_tile_pass(s, plan, p);
+                if (p.reg_r > 0 && i < plan.jit_fn.size() && plan.jit_fn[i]) {
+                    prof_begin(s, QSIM_KCLASS_TILE_JIT, p.bytes, p.flops);
+                    e = launch_jit_pass(s, plan, p, plan.jit_fn[i]);
+                } else {
+                    prof_begin(s, QSIM_KCLASS_TILE, p.bytes, p.flops);
+                    e = p.reg_r > 0 ? launch_tile_reg_pass(s, plan, p) : launch_tile_pass(s, plan, p);
+                }
                 break;
             case PASS_MFMA:
                 prof_begin(s, QSIM_KCLASS_MFMA, p.bytes, p.flops);
@@ -302,7 +308,8 @@ static const size_t kMaxCachedPlans = 16;
 static qsim_status get_plan(qsim_state s, const qsim_circuit *c, const double *params, int64_t nparams,
                             const qsim_options *opts, Plan **out, bool cache = true) {
     qsim_options tuned{};
-    const bool automatic = !opts || (opts->fuse_k == 0 && opts->tile_m == 0 && opts->use_mfma == 0);
+    const bool automatic =
+        !opts || (opts->fuse_k == 0 && opts->tile_m == 0 && opts->use_mfma == 0 && opts->split_1q == 0);
     if (automatic && tuned_options(c, s->n, s->dtype, &tuned)) opts = &tuned;
     const PlanOptions po = resolve_options(opts, s->n, s->dtype);
     std::string key;
@@ -325,6 +332,17 @@ static qsim_status get_plan(qsim_state s, const qsim_circuit *c, const double *p
     plan->n = s->n;
     plan->dtype = s->dtype;
     build_plan(*plan, gates, po);
+    // compiled tiles for fixed circuits only: the split form's structure
+    // depends on the gate values, so a parameter sweep would recompile
+    bool parametric = false;
+    for (int i = 0; i < c->nops; ++i) parametric = parametric || c->ops[i].param >= 0;
+    if (cache && !parametric && jit_wanted(s->n)) {
+        std::string err;
+        if (jit_prepare(s, *plan, err) != QSIM_OK) {
+            plan->jit_fn.clear();
+            if (jit_mode() == 1) return set_error(QSIM_ERR_DEVICE, err);
+        }
+    }
     if (!cache) {
         // one transient plan per state; its device buffer may still be read
         // by queued kernels, so wait before replacing one that has it
@@ -503,6 +521,14 @@ qsim_status qsim_apply_gate(qsim_state s, const int *targets, int k, const doubl
     return run_plan(s, *plan);
 }
 
+static qsim_status check_options(const qsim_options *opts) {
+    if (!opts) return QSIM_OK;
+    if (opts->fuse_k < 0 || opts->fuse_k > QSIM_MAX_K) return set_error(QSIM_ERR_ARG, "fuse_k outside [0, 6]");
+    if (opts->tile_m > 0 && opts->tile_m < 7) return set_error(QSIM_ERR_ARG, "tile_m must be -1, 0 or at least 7");
+    if (opts->split_1q < -1 || opts->split_1q > 1) return set_error(QSIM_ERR_ARG, "split_1q outside [-1, 1]");
+    return QSIM_OK;
+}
+
 qsim_status qsim_apply_circuit(qsim_state s, const qsim_circuit *c, const double *params, int64_t nparams,
                                const qsim_options *opts) {
     qsim_status st = check_state(s);
@@ -511,11 +537,8 @@ qsim_status qsim_apply_circuit(qsim_state s, const qsim_circuit *c, const double
     if (c->n != s->n) return set_error(QSIM_ERR_ARG, "circuit width does not match the state");
     if (c->nops < 0 || (c->nops > 0 && !c->ops)) return set_error(QSIM_ERR_ARG, "bad op array");
     if (nparams < 0) return set_error(QSIM_ERR_ARG, "nparams is negative");
-    if (opts) {
-        if (opts->fuse_k < 0 || opts->fuse_k > QSIM_MAX_K) return set_error(QSIM_ERR_ARG, "fuse_k outside [0, 6]");
-        if (opts->tile_m > 0 && opts->tile_m < 7)
-            return set_error(QSIM_ERR_ARG, "tile_m must be -1, 0 or at least 7");
-    }
+    st = check_options(opts);
+    if (st != QSIM_OK) return st;
     if (c->nops == 0) return QSIM_OK;
     Plan *plan = nullptr;
     st = get_plan(s, c, params, nparams, opts, &plan);
@@ -606,6 +629,7 @@ qsim_status qsim_plan_summary(int n, qsim_dtype dtype, const qsim_circuit *c, co
     if (n < 1 || n > max_qubits(dtype)) return set_error(QSIM_ERR_ARG, "n outside the supported range");
     if (!c || c->n != n) return set_error(QSIM_ERR_ARG, "circuit is NULL or its width is not n");
     if (c->nops < 0 || (c->nops > 0 && !c->ops)) return set_error(QSIM_ERR_ARG, "bad op array");
+    if (check_options(opts) != QSIM_OK) return QSIM_ERR_ARG;
     std::vector<HostGate> gates(size_t(c->nops));
     for (int i = 0; i < c->nops; ++i) {
         qsim_status st = make_gate(c, i, params, nparams, gates[size_t(i)]);
@@ -793,9 +817,12 @@ qsim_status qsim_autotune(qsim_state s, const qsim_circuit *c, const double *par
     std::vector<qsim_options> cands;
     cands.push_back({1, -1, -1, 0});
     const int mlo = s->dtype == QSIM_C128 ? 10 : 11;
+    // (compiled register tiles: the split single-qubit form without fusion
+    // has the least arithmetic; one compilation per tile size)
+    const int fmax = jit_wanted(s->n) ? 1 : 3;
     for (int m = mlo; m <= mlo + 2; ++m) {
         if (m > s->n && m > mlo) break;
-        for (int f = 1; f <= 3; ++f) cands.push_back({f, m, -1, 0});
+        for (int f = 1; f <= fmax; ++f) cands.push_back({f, m, -1, 0});
     }
     for (int f = 4; f <= 6; ++f)
         if (f <= s->n) cands.push_back({f, -1, 1, 0});

@@ -158,6 +158,10 @@ HostGate sorted_targets(const HostGate &g) {
     HostGate s;
     s.k = g.k;
     s.src_op = g.src_op;
+    s.rot_real = g.rot_real;
+    s.rot_c = g.rot_c;
+    s.rot_s = g.rot_s;
+    s.phase_in = g.phase_in;
     int perm[QSIM_MAX_K];  // perm[i] = original local bit of sorted bit i
     for (int i = 0; i < g.k; ++i) perm[i] = i;
     std::sort(perm, perm + g.k, [&](int a, int b) { return g.targets[a] < g.targets[b]; });
@@ -211,6 +215,105 @@ HostGate fuse_pair(const HostGate &first, const HostGate &second) {
             if (b == cd(0.0)) continue;
             for (int c = 0; c < D; ++c) out.M[r * D + c] += b * A[j * D + c];
         }
+    return out;
+}
+
+// ------------------------------------------------------------ single-qubit split
+
+namespace {
+
+// U = g diag(1, b) [[c, -s], [s, c]] diag(1, a) with c = |U00|, s = |U10|
+// and unit g, a, b, for a 2 x 2 unitary U that is not diagonal.  The phases
+// come from normalised matrix entries, not from angles, so that exact
+// entries (0, +-1, +-i) give exact phases.  Returns false when U is not
+// unitary to 1e-12 or the factors do not reproduce it to 1e-12.
+bool euler_split(const std::vector<cd> &U, double &c, double &s, cd &g, cd &a, cd &b) {
+    const cd u00 = U[0], u01 = U[1], u10 = U[2], u11 = U[3];
+    const double n0 = std::norm(u00) + std::norm(u10), n1 = std::norm(u01) + std::norm(u11);
+    const cd ip = std::conj(u00) * u01 + std::conj(u10) * u11;
+    if (std::abs(n0 - 1.0) > 1e-12 || std::abs(n1 - 1.0) > 1e-12 || std::abs(ip) > 1e-12) return false;
+    c = std::abs(u00);
+    s = std::abs(u10);
+    if (s == 0.0) return false;
+    g = c > 0.0 ? u00 / c : u10 / s;
+    b = (u10 / g) / s;
+    a = (-u01 / g) / s;
+    const cd r[4] = {g * c, -g * s * a, g * b * s, g * b * c * a};
+    for (int i = 0; i < 4; ++i)
+        if (std::abs(r[i] - U[size_t(i)]) > 1e-12) return false;
+    return true;
+}
+
+HostGate phase_gate(int q, cd lo, cd hi) {
+    HostGate d;
+    d.k = 1;
+    d.targets[0] = q;
+    d.M = {lo, cd(0.0), cd(0.0), hi};
+    return d;
+}
+
+}  // namespace
+
+std::vector<HostGate> split_single_qubit(const std::vector<HostGate> &gates, int n) {
+    // pending[q]: diag(1, pending[q]) still owed on qubit q
+    std::vector<cd> pending(size_t(n), cd(1.0));
+    cd global(1.0);
+    std::vector<HostGate> out;
+    out.reserve(gates.size() + size_t(n) + 1);
+    auto flush = [&](int q) {
+        if (pending[size_t(q)] == cd(1.0)) return;
+        out.push_back(phase_gate(q, cd(1.0), pending[size_t(q)]));
+        pending[size_t(q)] = cd(1.0);
+    };
+    for (const HostGate &g : gates) {
+        const bool special = g.probe_gen || g.rot_gen || g.rot_real;
+        const bool diag = !special && is_diagonal(g);
+        if (g.k == 1 && !special) {
+            const int q = g.targets[0];
+            if (diag && g.M[0] != cd(0.0)) {
+                // diag(u0, u1) = u0 diag(1, u1 / u0): merges into the owed phase
+                pending[size_t(q)] *= g.M[3] / g.M[0];
+                global *= g.M[0];
+                continue;
+            }
+            double c, s;
+            cd gg, a, b;
+            if (!diag && euler_split(g.M, c, s, gg, a, b)) {
+                HostGate r;
+                r.k = 1;
+                r.targets[0] = q;
+                r.src_op = g.src_op;
+                r.rot_real = c == 0.0 ? 2 : 1;
+                r.rot_c = c;
+                r.rot_s = r.rot_real == 2 ? 1.0 : s;
+                r.phase_in = a * pending[size_t(q)];
+                r.M = {cd(r.rot_c), -r.rot_s * r.phase_in, cd(r.rot_s), r.rot_c * r.phase_in};
+                out.push_back(std::move(r));
+                pending[size_t(q)] = b;
+                global *= gg;
+                continue;
+            }
+        }
+        // diagonal gates commute with the owed phases; anything else settles
+        // them on its qubits first
+        if (!diag)
+            for (int i = 0; i < g.k; ++i) flush(g.targets[i]);
+        out.push_back(g);
+    }
+    int last = -1;
+    for (int q = 0; q < n; ++q)
+        if (pending[size_t(q)] != cd(1.0)) {
+            flush(q);
+            last = int(out.size()) - 1;
+        }
+    if (global != cd(1.0)) {
+        if (last >= 0) {
+            out[size_t(last)].M[0] *= global;
+            out[size_t(last)].M[3] *= global;
+        } else {
+            out.push_back(phase_gate(0, global, global));
+        }
+    }
     return out;
 }
 

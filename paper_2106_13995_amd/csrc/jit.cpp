@@ -1,0 +1,335 @@
+// Run-time compiled register-staged tile passes.
+//
+// The register tile kernel interprets each pass's op list, and a data-
+// dependent branch per op over 2^r register amplitudes costs the compiler a
+// full copy of the amplitude registers at every join.  For large states the
+// planner's register program is instead written out as straight-line HIP
+// source, one kernel per pass (amplitudes as named scalars, register and
+// layout indices as constants, matrices and parameters still read from the
+// uploaded pool), compiled once with hipRTC for gfx950 and kept for the life
+// of the process, keyed by the source text: plans that differ only in gate
+// angles share their code.
+#include <hip/hiprtc.h>
+
+#include <cstdarg>
+#include <cstdio>
+#include <cstdlib>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <string>
+
+#include "qsim_internal.h"
+
+namespace qsim {
+
+namespace {
+
+struct Src {
+    std::string s;
+    void operator()(const char *fmt, ...) {
+        char buf[512];
+        va_list ap;
+        va_start(ap, fmt);
+        const int n = vsnprintf(buf, sizeof buf, fmt, ap);
+        va_end(ap);
+        if (n > 0) s.append(buf, size_t(std::min(n, int(sizeof buf) - 1)));
+        s.push_back('\n');
+    }
+};
+
+int popc32(uint32_t v) { return __builtin_popcount(v); }
+
+int deposit_bits(int j, int mask) {
+    int out = 0, b = 0;
+    for (int p = 0; p < 31; ++p)
+        if ((mask >> p) & 1) {
+            if ((j >> b) & 1) out |= 1 << p;
+            ++b;
+        }
+    return out;
+}
+
+// Emits one pass as kernel `name`.
+void gen_pass(Src &o, const Plan &plan, const Pass &p, const char *name) {
+    const bool f = plan.dtype == QSIM_C64;
+    const char *T = f ? "float" : "double";
+    const char *V = f ? "f2" : "d2";
+    const char *FMA = f ? "__builtin_fmaf" : "__builtin_fma";
+    const int R = p.reg_r, NA = 1 << R;
+    o("extern \"C\" __global__ void __launch_bounds__(256) %s(%s *psi, const %s *Pg) {", name, V, T);
+    o("  const QC %s *P = (const QC %s *)Pg;", T, T);
+    o("  extern __shared__ %s lds[];", V);
+    o("  const unsigned t = threadIdx.x;");
+    o("  unsigned long long base = (unsigned long long)blockIdx.x << %d;", p.L);
+    for (int h : p.hpos) o("  base = ((base >> %d) << %d) | (base & 0x%llxull);", h, h + 1, (1ull << h) - 1ull);
+    for (int i = 0; i < NA; ++i) o("  %s ar%d, ai%d;", T, i, i);
+    // load
+    o("  {");
+    o("    unsigned long long gt = base;");
+    for (int b = 0; b < 8; ++b) o("    gt |= (unsigned long long)((t >> %d) & 1u) << %d;", b, int(p.ld_t[b]));
+    for (int i = 0; i < NA; ++i) {
+        unsigned long long off = 0;
+        for (int b = 0; b < R; ++b)
+            if ((i >> b) & 1) off |= 1ull << p.ld_r[b];
+        o("    { const %s w = __builtin_nontemporal_load(psi + (gt | 0x%llxull)); ar%d = w.x; ai%d = w.y; }", V, off,
+          i, i);
+    }
+    o("  }");
+    for (int si = p.stage_begin; si < p.stage_end; ++si) {
+        const RegStage &st = plan.reg_stages[size_t(si)];
+        if (si > p.stage_begin) {
+            o("  {");
+            o("    unsigned aw = 0u, ar_ = 0u;");
+            for (int b = 0; b < 8; ++b) {
+                if (st.wr_t[b]) o("    aw ^= (0u - ((t >> %d) & 1u)) & %uu;", b, st.wr_t[b]);
+                if (st.rd_t[b]) o("    ar_ ^= (0u - ((t >> %d) & 1u)) & %uu;", b, st.rd_t[b]);
+            }
+            for (int i = 0; i < NA; ++i) {
+                uint32_t c = 0;
+                for (int b = 0; b < R; ++b)
+                    if ((i >> b) & 1) c ^= st.wr_r[b];
+                o("    lds[aw ^ %uu] = %s{ar%d, ai%d};", c, V, i, i);
+            }
+            o("    __syncthreads();");
+            for (int i = 0; i < NA; ++i) {
+                uint32_t c = 0;
+                for (int b = 0; b < R; ++b)
+                    if ((i >> b) & 1) c ^= st.rd_r[b];
+                o("    { const %s w = lds[ar_ ^ %uu]; ar%d = w.x; ai%d = w.y; }", V, c, i, i);
+            }
+            o("    __syncthreads();");
+            o("  }");
+        }
+        for (int oi = p.rop_begin + st.op_begin; oi < p.rop_begin + st.op_end; ++oi) {
+            const RegOp &op = plan.reg_ops[size_t(oi)];
+            const int m2 = 2 * op.moff;
+            switch (op.type) {
+                case 0: {   // dense on register mask, complex matrix
+                    const int K = popc32(uint32_t(op.rmask)), D = 1 << K;
+                    o("  {");
+                    for (int g = 0; g < NA; ++g) {
+                        if (g & op.rmask) continue;
+                        o("    {");
+                        for (int c = 0; c < D; ++c) {
+                            const int ix = g | deposit_bits(c, op.rmask);
+                            o("      const %s x%dr = ar%d, x%di = ai%d;", T, c, ix, c, ix);
+                        }
+                        for (int rr = 0; rr < D; ++rr) {
+                            const int ix = g | deposit_bits(rr, op.rmask);
+                            const int e0 = m2 + 2 * rr * D;
+                            o("      { %s yr = P[%d] * x0r, yi = P[%d] * x0i;", T, e0, e0);
+                            o("        yr = %s(-P[%d], x0i, yr); yi = %s(P[%d], x0r, yi);", FMA, e0 + 1, FMA, e0 + 1);
+                            for (int c = 1; c < D; ++c) {
+                                const int e = e0 + 2 * c;
+                                o("        yr = %s(P[%d], x%dr, yr); yr = %s(-P[%d], x%di, yr);", FMA, e, c, FMA,
+                                  e + 1, c);
+                                o("        yi = %s(P[%d], x%di, yi); yi = %s(P[%d], x%dr, yi);", FMA, e, c, FMA,
+                                  e + 1, c);
+                            }
+                            o("        ar%d = yr; ai%d = yi; }", ix, ix);
+                        }
+                        o("    }");
+                    }
+                    o("  }");
+                    break;
+                }
+                case 3: {   // real rotation by lifting on one register bit
+                    const int B = op.rb[0];
+                    o("  { const %s p = P[%d], u = P[%d];", T, m2, m2 + 1);
+                    for (int g = 0; g < NA; ++g) {
+                        if (g & (1 << B)) continue;
+                        const int h = g | (1 << B);
+                        o("    ar%d = %s(p, ar%d, ar%d); ai%d = %s(p, ai%d, ai%d);", g, FMA, h, g, g, FMA, h, g);
+                        o("    ar%d = %s(u, ar%d, ar%d); ai%d = %s(u, ai%d, ai%d);", h, FMA, g, h, h, FMA, g, h);
+                        o("    ar%d = %s(p, ar%d, ar%d); ai%d = %s(p, ai%d, ai%d);", g, FMA, h, g, g, FMA, h, g);
+                    }
+                    o("  }");
+                    break;
+                }
+                case 5: {   // (x0, x1) <- (-x1, x0)
+                    const int B = op.rb[0];
+                    o("  {");
+                    for (int g = 0; g < NA; ++g) {
+                        if (g & (1 << B)) continue;
+                        const int h = g | (1 << B);
+                        o("    { const %s tr = ar%d, ti = ai%d; ar%d = -ar%d; ai%d = -ai%d; ar%d = tr; ai%d = ti; }", T, g,
+                          g, g, h, g, h, h, h);
+                    }
+                    o("  }");
+                    break;
+                }
+                case 4: {   // phase table over the register bits (entry 0 is 1)
+                    o("  {");
+                    for (int i = 1; i < NA; ++i) {
+                        const int e = m2 + 2 * i;
+                        o("    { const %s dx = P[%d], dy = P[%d], xr = ar%d;", T, e, e + 1, i);
+                        o("      ar%d = %s(dx, xr, -dy * ai%d); ai%d = %s(dx, ai%d, dy * xr); }", i, FMA, i, i, FMA,
+                          i);
+                    }
+                    o("  }");
+                    break;
+                }
+                case 6: {   // factor on the all-ones amplitudes of the op's bits
+                    const uint64_t gmask = uint64_t(uint32_t(op.gp[0])) | (uint64_t(uint32_t(op.gp[1])) << 32);
+                    const uint32_t tmask = uint32_t(op.tb[0]);
+                    o("  { %s dx = P[%d], dy = P[%d];", T, m2, m2 + 1);
+                    if (gmask || tmask) {
+                        // amplitudes whose other bits do not match multiply by 1 (exact)
+                        o("    const bool on = ((base & 0x%llxull) == 0x%llxull) && ((t & %uu) == %uu);",
+                          (unsigned long long)gmask, (unsigned long long)gmask, tmask, tmask);
+                        o("    dx = on ? dx : %s(1); dy = on ? dy : %s(0);", T, T);
+                    }
+                    for (int i = 0; i < NA; ++i) {
+                        if ((i & op.rmask) != op.rmask) continue;
+                        o("    { const %s xr = ar%d; ar%d = %s(dx, xr, -dy * ai%d); ai%d = %s(dx, ai%d, dy * xr); }", T,
+                          i, i, FMA, i, i, FMA, i);
+                    }
+                    o("  }");
+                    break;
+                }
+                default: {   // any other diagonal: index from out-of-tile, thread and register bits
+                    o("  { int jt = 0;");
+                    for (int b = 0; b < op.nout; ++b)
+                        o("    jt |= int((base >> %d) & 1ull) << %d;", int(op.gp[b]), int(op.gj[b]));
+                    for (int b = 0; b < op.nthr; ++b)
+                        o("    jt |= int((t >> %d) & 1u) << %d;", int(op.tb[b]), int(op.tj[b]));
+                    for (int i = 0; i < NA; ++i) {
+                        int jr = 0;
+                        for (int b = 0; b < op.nreg; ++b) jr |= ((i >> op.rb[b]) & 1) << op.rj[b];
+                        o("    { const int j = %d + 2 * (jt | %d); const %s dx = Pg[j], dy = Pg[j + 1], xr = ar%d;", m2,
+                          jr, T, i);
+                        o("      ar%d = %s(dx, xr, -dy * ai%d); ai%d = %s(dx, ai%d, dy * xr); }", i, FMA, i, i, FMA,
+                          i);
+                    }
+                    o("  }");
+                    break;
+                }
+            }
+        }
+    }
+    // store
+    o("  {");
+    o("    unsigned long long gt = base;");
+    for (int b = 0; b < 8; ++b) o("    gt |= (unsigned long long)((t >> %d) & 1u) << %d;", b, int(p.st_t[b]));
+    for (int i = 0; i < NA; ++i) {
+        unsigned long long off = 0;
+        for (int b = 0; b < R; ++b)
+            if ((i >> b) & 1) off |= 1ull << p.st_r[b];
+        o("    __builtin_nontemporal_store(%s{ar%d, ai%d}, psi + (gt | 0x%llxull));", V, i, i, off);
+    }
+    o("  }");
+    o("}");
+}
+
+struct JitModule {
+    hipModule_t mod = nullptr;
+    std::vector<hipFunction_t> fns;
+};
+
+std::mutex g_mu;
+// (device, program text) -> loaded module; modules stay loaded until exit
+std::map<std::pair<int, std::string>, std::shared_ptr<JitModule>> g_modules;
+std::string g_last_log;
+
+int env_int(const char *name, int dflt) {
+    const char *v = std::getenv(name);
+    return v && *v ? std::atoi(v) : dflt;
+}
+
+}  // namespace
+
+int jit_mode() { return env_int("QSIM_JIT", -1); }
+
+bool jit_wanted(int n) {
+    const int mode = jit_mode();
+    if (mode == 0) return false;
+    return n >= env_int("QSIM_JIT_MIN_QUBITS", 18);
+}
+
+std::string jit_source(const Plan &plan, std::vector<int> &which) {
+    Src o;
+    o("typedef float f2 __attribute__((ext_vector_type(2)));");
+    o("typedef double d2 __attribute__((ext_vector_type(2)));");
+    o("#define QC __attribute__((address_space(4)))");
+    which.clear();
+    for (size_t i = 0; i < plan.passes.size(); ++i) {
+        const Pass &p = plan.passes[i];
+        if (p.kind != PASS_TILE || p.reg_r <= 0) continue;
+        char name[48];
+        snprintf(name, sizeof name, "qsim_tile_jit_%zu", which.size());
+        gen_pass(o, plan, p, name);
+        which.push_back(int(i));
+    }
+    return o.s;
+}
+
+qsim_status jit_prepare(qsim_state s, Plan &plan, std::string &err) {
+    plan.jit_fn.assign(plan.passes.size(), nullptr);
+    std::vector<int> which;
+    const std::string text = jit_source(plan, which);
+    if (which.empty()) return QSIM_OK;
+    std::lock_guard<std::mutex> lk(g_mu);
+    const auto key = std::make_pair(s->device, text);
+    auto it = g_modules.find(key);
+    std::shared_ptr<JitModule> jm;
+    if (it != g_modules.end()) {
+        jm = it->second;
+    } else {
+        hiprtcProgram prog;
+        if (hiprtcCreateProgram(&prog, text.c_str(), "qsim_tiles.hip", 0, nullptr, nullptr) != HIPRTC_SUCCESS) {
+            err = "hiprtcCreateProgram failed";
+            return QSIM_ERR_DEVICE;
+        }
+        // packed FP32 instructions stay off, as for the prebuilt kernels
+        const char *opts[] = {"--offload-arch=gfx950", "-O3", "-Xclang", "-target-feature", "-Xclang",
+                              "-packed-fp32-ops"};
+        const hiprtcResult rc = hiprtcCompileProgram(prog, 6, opts);
+        if (rc != HIPRTC_SUCCESS) {
+            size_t ls = 0;
+            hiprtcGetProgramLogSize(prog, &ls);
+            std::string log(ls, '\0');
+            if (ls) hiprtcGetProgramLog(prog, &log[0]);
+            hiprtcDestroyProgram(&prog);
+            err = "run-time compilation of tile passes failed: " + log.substr(0, 400);
+            return QSIM_ERR_DEVICE;
+        }
+        size_t cs = 0;
+        hiprtcGetCodeSize(prog, &cs);
+        std::vector<char> code(cs);
+        hiprtcGetCode(prog, code.data());
+        hiprtcDestroyProgram(&prog);
+        jm = std::make_shared<JitModule>();
+        if (hipModuleLoadData(&jm->mod, code.data()) != hipSuccess) {
+            err = "loading the compiled tile passes failed";
+            return QSIM_ERR_DEVICE;
+        }
+        for (size_t k = 0; k < which.size(); ++k) {
+            char name[48];
+            snprintf(name, sizeof name, "qsim_tile_jit_%zu", k);
+            hipFunction_t fn = nullptr;
+            if (hipModuleGetFunction(&fn, jm->mod, name) != hipSuccess) {
+                err = "compiled tile pass missing from its module";
+                return QSIM_ERR_DEVICE;
+            }
+            jm->fns.push_back(fn);
+        }
+        g_modules[key] = jm;
+    }
+    for (size_t k = 0; k < which.size(); ++k) plan.jit_fn[size_t(which[k])] = jm->fns[k];
+    return QSIM_OK;
+}
+
+hipError_t launch_jit_pass(qsim_state s, const Plan &plan, const Pass &p, hipFunction_t fn) {
+    const bool f = s->dtype == QSIM_C64;
+    const size_t amp = f ? 8 : 16;
+    void *psi = s->data;
+    const char *pool = static_cast<const char *>(plan.dev) + plan.pool_dev_off + size_t(p.pool_begin) * amp;
+    const void *pool_arg = pool;
+    void *args[] = {&psi, &pool_arg};
+    const size_t lds = amp << p.m;
+    const uint64_t ntiles = 1ull << (s->n - p.m);
+    return hipModuleLaunchKernel(fn, unsigned(ntiles), 1, 1, 256, 1, 1, unsigned(lds), s->stream, args, nullptr);
+}
+
+}  // namespace qsim

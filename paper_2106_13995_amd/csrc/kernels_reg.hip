@@ -136,6 +136,83 @@ __device__ __forceinline__ void dispatch_dense(int rmask, T *vr, T *vi, CT<T> *U
     }
 }
 
+// Real rotation [[c, -s], [s, c]] on register bit B as three lifting steps,
+// in place: x0 += p x1, x1 += u x0, x0 += p x1 (p = -s / (1 + c), u = s).
+template <typename T, int R, int B>
+__device__ __forceinline__ void lift_bit(T *vr, T *vi, T p, T u) {
+#pragma unroll
+    for (int g = 0; g < (1 << R); ++g) {
+        if (g & (1 << B)) continue;
+        const int h = g | (1 << B);
+        vr[g] = fma(p, vr[h], vr[g]);
+        vi[g] = fma(p, vi[h], vi[g]);
+        vr[h] = fma(u, vr[g], vr[h]);
+        vi[h] = fma(u, vi[g], vi[h]);
+        vr[g] = fma(p, vr[h], vr[g]);
+        vi[g] = fma(p, vi[h], vi[g]);
+    }
+}
+
+// [[0, -1], [1, 0]] on register bit B: (x0, x1) <- (-x1, x0).
+template <typename T, int R, int B>
+__device__ __forceinline__ void swap_bit(T *vr, T *vi) {
+#pragma unroll
+    for (int g = 0; g < (1 << R); ++g) {
+        if (g & (1 << B)) continue;
+        const int h = g | (1 << B);
+        const T xr = vr[g], xi = vi[g];
+        vr[g] = -vr[h];
+        vi[g] = -vi[h];
+        vr[h] = xr;
+        vi[h] = xi;
+    }
+}
+
+template <typename T, int R, int B>
+__device__ __forceinline__ void dispatch_bit(int bit, int type, T *vr, T *vi, CT<T> *P) {
+    if constexpr (B < R) {
+        if (bit == B) {
+            if (type == 3)
+                lift_bit<T, R, B>(vr, vi, P[0], P[1]);
+            else
+                swap_bit<T, R, B>(vr, vi);
+            return;
+        }
+        dispatch_bit<T, R, B + 1>(bit, type, vr, vi, P);
+    }
+}
+
+// Phase table over the register bits: amplitude i times entry i (entry 0 is
+// 1 by construction: every merged phase sits on a bit's 1 half).
+template <typename T, int R>
+__device__ __forceinline__ void apply_table(T *vr, T *vi, CT<T> *P) {
+#pragma unroll
+    for (int i = 1; i < (1 << R); ++i) {
+        const T dx = P[2 * i], dy = P[2 * i + 1];
+        const T xr = vr[i], xi = vi[i];
+        vr[i] = dx * xr - dy * xi;
+        vi[i] = dx * xi + dy * xr;
+    }
+}
+
+// Factor (dx, dy) on the register amplitudes whose bits in MASK are all 1.
+template <typename T, int R, int MASK>
+__device__ __forceinline__ void dispatch_ones(int rmask, T *vr, T *vi, T dx, T dy) {
+    if constexpr (MASK < (1 << R)) {
+        if (rmask == MASK) {
+#pragma unroll
+            for (int i = 0; i < (1 << R); ++i) {
+                if ((i & MASK) != MASK) continue;
+                const T xr = vr[i], xi = vi[i];
+                vr[i] = dx * xr - dy * xi;
+                vi[i] = dx * xi + dy * xr;
+            }
+            return;
+        }
+        dispatch_ones<T, R, MASK + 1>(rmask, vr, vi, dx, dy);
+    }
+}
+
 // Diagonal gate: the diagonal index of register amplitude i collects bits
 // from the tile's fixed (out-of-tile) qubits, the thread id and i itself.
 template <typename T, int R>
@@ -171,6 +248,57 @@ __device__ __forceinline__ void apply_diag(T *vr, T *vi, CRegOp &op, CT<T> *Dg, 
             vr[i] = dx * xr - dy * xi;
             vi[i] = dx * xi + dy * xr;
         }
+    }
+}
+
+// Op codes (host side: op_code): dense on register mask m < 32 -> m; lifting
+// rotation on bit b -> 64 + b; signed exchange on bit b -> 72 + b; factor on
+// the all-ones amplitudes of register mask m -> 128 + m; phase table -> 200;
+// any other diagonal -> 201.  One flat compare chain on the uniform code, one
+// join: the amplitude registers keep a single home across ops.
+template <int C, int R>
+__host__ __device__ constexpr bool code_valid() {
+    if (C < 32) return C > 0 && C < (1 << R) && popcount_c(C) <= 3;
+    if (C >= 64 && C < 72) return C - 64 < R;
+    if (C >= 72 && C < 80) return C - 72 < R;
+    if (C >= 128 && C < 160) return C - 128 < (1 << R);
+    return C == 200 || C == 201;
+}
+
+template <typename T, int R, int C>
+__device__ __forceinline__ void run_op(int code, T *vr, T *vi, CRegOp &op, CT<T> *U, uint64_t base, uint32_t t) {
+    if constexpr (C <= 201) {
+        if constexpr (code_valid<C, R>()) {
+            if (code == C) {
+                if constexpr (C < 32) {
+                    apply_mask<T, R, C>(vr, vi, U);
+                } else if constexpr (C < 72) {
+                    lift_bit<T, R, C - 64>(vr, vi, U[0], U[1]);
+                } else if constexpr (C < 80) {
+                    swap_bit<T, R, C - 72>(vr, vi);
+                } else if constexpr (C < 160) {
+                    const uint64_t gmask = uint64_t(uint32_t(op.gp[0])) | (uint64_t(uint32_t(op.gp[1])) << 32);
+                    const uint32_t tm = uint32_t(op.tb[0]);
+                    // amplitudes whose out-of-tile or thread bits do not match
+                    // multiply by 1 (exact)
+                    const bool on = ((base & gmask) == gmask) && ((t & tm) == tm);
+                    const T dx = on ? U[0] : T(1), dy = on ? U[1] : T(0);
+#pragma unroll
+                    for (int i = 0; i < (1 << R); ++i) {
+                        if ((i & (C - 128)) != (C - 128)) continue;
+                        const T xr = vr[i], xi = vi[i];
+                        vr[i] = dx * xr - dy * xi;
+                        vi[i] = dx * xi + dy * xr;
+                    }
+                } else if constexpr (C == 200) {
+                    apply_table<T, R>(vr, vi, U);
+                } else {
+                    apply_diag<T, R>(vr, vi, op, U, base, t);
+                }
+                return;
+            }
+        }
+        run_op<T, R, C + 1>(code, vr, vi, op, U, base, t);
     }
 }
 
@@ -251,11 +379,7 @@ __global__ void __launch_bounds__(kRegThreads) k_tile_reg(const RegArgs<T> a) {
         }
         for (int o = st.op_begin; o < st.op_end; ++o) {
             CRegOp &op = sop[o];
-            CT<T> *U = spool + 2 * op.moff;
-            if (op.type == 0)
-                dispatch_dense<T, R, 1>(op.rmask, vr, vi, U);
-            else
-                apply_diag<T, R>(vr, vi, op, U, base, t);
+            run_op<T, R, 0>(op.code, vr, vi, op, spool + 2 * op.moff, base, t);
         }
     }
     {

@@ -35,6 +35,7 @@ PlanOptions resolve_options(const qsim_options *o, int n, int dtype) {
     else
         po.tile_m = std::min(n, std::min(o->tile_m, max_tile_m(dtype)));
     po.use_mfma = o->use_mfma;
+    po.split_1q = o->split_1q >= 0;
     return po;
 }
 
@@ -184,27 +185,38 @@ struct TileBuilder {
         p.pool_begin = int(plan.tile_pool.size());
         p.bytes = 2.0 * std::ldexp(1.0, n) * double(amp_bytes(dtype));
         p.logical_gates = int(gs.size());
-        p.flops = 0.0;
-        for (const HostGate *g : gs) {
-            if (g->probe_gen) continue;
-            if (g->rot_gen) {
-                p.flops += 16.0 * std::ldexp(1.0, n);
-                continue;
+        // arithmetic of the gates as the pass applies them
+        auto pass_flops = [&](bool regform) {
+            double f = 0.0;
+            const double N = std::ldexp(1.0, n);
+            for (const HostGate *g : gs) {
+                if (g->probe_gen) continue;
+                if (g->rot_gen) {
+                    f += 16.0 * N;
+                    continue;
+                }
+                const int d = 1 << g->k;
+                if (g->rot_real && regform) {
+                    // three multiply-adds per component and pair; the input
+                    // phase multiplies half the amplitudes
+                    if (g->rot_real == 1) f += 6.0 * N;
+                    if (g->phase_in != cd(1.0)) f += 3.0 * N;
+                } else if (is_diagonal(*g)) {
+                    int nonunit = 0;
+                    for (int j = 0; j < d; ++j)
+                        if (g->M[size_t(j) * d + j] != cd(1.0)) ++nonunit;
+                    f += 6.0 * double(nonunit) * std::ldexp(1.0, n - g->k);
+                } else {
+                    f += 8.0 * double(d) * N;
+                }
             }
-            const int d = 1 << g->k;
-            if (is_diagonal(*g)) {
-                int nonunit = 0;
-                for (int j = 0; j < d; ++j)
-                    if (g->M[size_t(j) * d + j] != cd(1.0)) ++nonunit;
-                p.flops += 6.0 * double(nonunit) * std::ldexp(1.0, n - g->k);
-            } else {
-                p.flops += 8.0 * double(d) * std::ldexp(1.0, n);
-            }
-        }
+            return f;
+        };
         if (reg) {
             const size_t nrop = plan.reg_ops.size(), nst = plan.reg_stages.size(), npool = plan.tile_pool.size();
             if (build_reg_program(plan, p, q, local_of, gs)) {
                 p.op_end = p.op_begin;
+                p.flops = pass_flops(true);
                 plan.passes.push_back(std::move(p));
                 return;
             }
@@ -213,6 +225,7 @@ struct TileBuilder {
             plan.tile_pool.resize(npool);
             p.reg_r = 0;
         }
+        p.flops = pass_flops(false);
         for (const HostGate *g : gs) {
             TileOp op{};
             if (g->probe_gen) {
@@ -345,6 +358,7 @@ void build_plan(Plan &plan, const std::vector<HostGate> &gates_in, const PlanOpt
             }
         }
     } else {
+        if (po.reg_tiles && po.split_1q) gates = split_single_qubit(gates, n);
         TileBuilder tb(plan, n, dtype, po.tile_m, po.reg_tiles);
         group_tiles(tb, gates);
     }

@@ -45,11 +45,26 @@ struct HostGate {
     int rot_gen = 0;
     int rot_param = -1;
     int rot_inv = 0;
+    // split single-qubit unitary (forward tile plans): the gate is
+    // O diag(1, phase_in) with O = [[c, -s], [s, c]], c, s >= 0; M holds that
+    // product for paths that apply it as a plain matrix.  rot_real 1: O by
+    // lifting steps, 2: c == 0 (O exchanges the pair with one sign change)
+    int rot_real = 0;
+    double rot_c = 1.0, rot_s = 0.0;
+    cd phase_in = 1.0;
 };
 
 // Validates op i of a circuit and returns its normalised gate (matrix built
 // from the op's angles or parameters).
 qsim_status make_gate(const qsim_circuit *c, int i, const double *params, int64_t nparams, HostGate &g);
+
+// Rewrites a gate list for tile passes: every single-qubit unitary U
+// becomes g diag(1, b) O diag(1, a) (O real); diag(1, b) is carried forward
+// over gates that commute with it and merged into the next split gate's
+// input phase, or emitted as a diagonal gate before the first gate that
+// does not commute with it; the global factor is folded into a final
+// diagonal gate.  Non-unitary or diagonal gates pass through unchanged.
+std::vector<HostGate> split_single_qubit(const std::vector<HostGate> &gates, int n);
 
 // Builds the matrix of a named gate; returns its arity, or -1 for an unknown kind.
 int named_gate_matrix(int kind, const double *angles, cd *U);
@@ -100,7 +115,15 @@ struct TileOp {
 constexpr int kRegBitsMax = 5;
 
 struct RegOp {
-    int32_t type;     // 0 dense in registers, 1 diagonal (table), 2 diagonal with one non-unit entry
+    // 0 dense in registers, 1 diagonal (table), 2 diagonal with one non-unit
+    // entry, 3 real rotation on one register bit by lifting (pool entry
+    // (p, u)), 4 phase table over the register bits (2^r pool entries),
+    // 5 signed exchange on one register bit (x0, x1) <- (-x1, x0), 6 one
+    // factor (pool entry moff) on the amplitudes whose target bits are all
+    // 1: register bits rmask, thread bits tb[0] (a mask of thread-id bits),
+    // out-of-tile qubits gp[0] | gp[1] << 32 (a mask of global qubits)
+    int32_t type;
+    int32_t code;     // kernel dispatch code (set from the fields below by op_code)
     int32_t k;
     int32_t rmask;    // dense: register bits of the targets (ascending = matrix bit order)
     int32_t moff;     // pool offset of the matrix / diagonal (complex entries)
@@ -163,14 +186,27 @@ struct Plan {
     size_t pool_dev_off = 0;          // byte offset of the pool inside dev
     void *host_pinned = nullptr;
     bool uploaded = false;
+    // run-time compiled kernels of register-staged passes (null: interpreted)
+    std::vector<hipFunction_t> jit_fn;
     ~Plan();
 };
+
+// Run-time compiled register tiles, for circuits without parametric ops.
+// QSIM_JIT=0 turns them off, =1 makes a failed compilation an error
+// (default: used from QSIM_JIT_MIN_QUBITS = 18 qubits on, and a failed
+// compilation leaves the passes interpreted).
+int jit_mode();
+bool jit_wanted(int n);
+std::string jit_source(const Plan &plan, std::vector<int> &which);   // HIP source of the compiled passes
+qsim_status jit_prepare(qsim_state s, Plan &plan, std::string &err);
+hipError_t launch_jit_pass(qsim_state s, const Plan &plan, const Pass &p, hipFunction_t fn);
 
 struct PlanOptions {
     int fuse_k = 1;
     int tile_m = -1;
     int use_mfma = -1;
     bool reg_tiles = true;   // register-staged tile passes where eligible
+    bool split_1q = true;    // split single-qubit unitaries in tile passes
 };
 
 PlanOptions resolve_options(const qsim_options *o, int n, int dtype);

@@ -211,9 +211,52 @@ bool build_reg_program(Plan &plan, Pass &p, uint64_t q, const int *local_of,
         int Rp[kRegBitsMax], Tp[16];
         split_layout(Rm, m, Rp, Tp);
         st.op_begin = int(plan.reg_ops.size()) - p.rop_begin;
+        // input phases of split rotations whose register bit no earlier op of
+        // the stage changes commute to the stage's start, where they merge
+        // into one table over the register bits
+        std::vector<cd> table(size_t(1) << r, cd(1.0));
+        bool use_table = false;
+        uint32_t touched = 0;
+        std::vector<RegOp> sops;
+        auto pool_off = [&]() { return int(plan.tile_pool.size()) - p.pool_begin; };
         for (int gi : stages[si].second) {
             const LocalGate &lg = gs[size_t(gi)];
             const HostGate &s = *lg.g;
+            if (!lg.diag && s.rot_real) {
+                const int ri = index_in(Rp, r, local_of[s.targets[0]]);
+                if (s.phase_in != cd(1.0)) {
+                    if (!((touched >> ri) & 1u)) {
+                        for (size_t i = 0; i < table.size(); ++i)
+                            if ((i >> ri) & 1u) table[i] *= s.phase_in;
+                        use_table = true;
+                    } else {
+                        RegOp ph{};
+                        ph.type = 6;
+                        ph.k = 1;
+                        ph.moff = pool_off();
+                        plan.tile_pool.push_back(s.phase_in);
+                        ph.rmask = 1 << ri;
+                        sops.push_back(ph);
+                    }
+                }
+                RegOp op{};
+                op.k = 1;
+                op.rmask = 1 << ri;
+                op.rb[0] = ri;
+                op.moff = pool_off();
+                if (s.rot_real == 1) {
+                    // lifting: x0 += p x1; x1 += u x0; x0 += p x1 gives
+                    // [[c, -s], [s, c]] for p = -s / (1 + c), u = s
+                    op.type = 3;
+                    plan.tile_pool.push_back(cd(-s.rot_s / (1.0 + s.rot_c), s.rot_s));
+                } else {
+                    op.type = 5;
+                    plan.tile_pool.push_back(cd(0.0));
+                }
+                sops.push_back(op);
+                touched |= 1u << ri;
+                continue;
+            }
             RegOp op{};
             op.k = s.k;
             op.moff = int(plan.tile_pool.size()) - p.pool_begin;
@@ -221,6 +264,7 @@ bool build_reg_program(Plan &plan, Pass &p, uint64_t q, const int *local_of,
             if (!lg.diag) {
                 op.type = 0;
                 for (int b = 0; b < s.k; ++b) op.rmask |= 1 << index_in(Rp, r, local_of[s.targets[b]]);
+                touched |= uint32_t(op.rmask);
                 plan.tile_pool.insert(plan.tile_pool.end(), s.M.begin(), s.M.end());
             } else {
                 int nonunit = 0, last = -1;
@@ -252,14 +296,51 @@ bool build_reg_program(Plan &plan, Pass &p, uint64_t q, const int *local_of,
                         ++op.nout;
                     }
                 }
+                if (nonunit == 1 && last == d - 1) {
+                    // the all-ones entry (CZ, CP, CCZ, phase gates): masks
+                    // instead of index arithmetic
+                    RegOp f{};
+                    f.type = 6;
+                    f.k = s.k;
+                    f.moff = op.moff + last;
+                    uint32_t tmask = 0;
+                    uint64_t gmask = 0;
+                    for (int b = 0; b < op.nreg; ++b) f.rmask |= 1 << op.rb[b];
+                    for (int b = 0; b < op.nthr; ++b) tmask |= 1u << op.tb[b];
+                    for (int b = 0; b < op.nout; ++b) gmask |= 1ull << op.gp[b];
+                    f.tb[0] = int32_t(tmask);
+                    f.gp[0] = int32_t(uint32_t(gmask));
+                    f.gp[1] = int32_t(uint32_t(gmask >> 32));
+                    op = f;
+                }
             }
-            plan.reg_ops.push_back(op);
+            sops.push_back(op);
         }
+        if (use_table) {
+            RegOp t{};
+            t.type = 4;
+            t.k = r;
+            t.moff = pool_off();
+            plan.tile_pool.insert(plan.tile_pool.end(), table.begin(), table.end());
+            plan.reg_ops.push_back(t);
+        }
+        plan.reg_ops.insert(plan.reg_ops.end(), sops.begin(), sops.end());
         st.op_end = int(plan.reg_ops.size()) - p.rop_begin;
         plan.reg_stages.push_back(st);
         prevR = Rm;
     }
     p.rop_end = int(plan.reg_ops.size());
+    for (int o = p.rop_begin; o < p.rop_end; ++o) {
+        RegOp &op = plan.reg_ops[size_t(o)];
+        switch (op.type) {
+            case 0: op.code = op.rmask; break;
+            case 3: op.code = 64 + op.rb[0]; break;
+            case 5: op.code = 72 + op.rb[0]; break;
+            case 6: op.code = 128 + op.rmask; break;
+            case 4: op.code = 200; break;
+            default: op.code = 201; break;
+        }
+    }
     p.stage_end = int(plan.reg_stages.size());
     p.pool_end = int(plan.tile_pool.size());
     return true;

@@ -23,6 +23,7 @@ from collections import defaultdict
 HERE = os.path.dirname(os.path.abspath(__file__))
 KERNEL_SOURCES = {
     "tile": ["kernels_reg.hip", "kernels.hip"],
+    "tile_jit": ["jit.cpp", "stages.cpp", "gates.cpp"],
     "sweep_dense": ["kernels.hip"],
     "sweep_diag": ["kernels.hip"],
 }

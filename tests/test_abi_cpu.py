@@ -171,12 +171,36 @@ def test_plan_summary_controls_and_diagonals():
 def test_plan_summary_tiles_fewer_passes_and_same_flops():
     circ = W.random_grid_circuit(5, 6, depth=20, seed=2)
     c_sw, b_sw, f_sw = _summary(circ, fuse_k=1, tile_m=-1)
-    c_t, b_t, f_t = _summary(circ, fuse_k=1, tile_m=12)
+    c_t, b_t, f_t = _summary(circ, fuse_k=1, tile_m=12, split_1q=-1)
     assert 10 <= c_t["tile"] <= 40
     assert b_t == c_t["tile"] * 2 * 2 ** 30 * 8
     assert f_t == f_sw                       # same gate arithmetic, grouped differently
     c_f, b_f, f_f = _summary(circ, fuse_k=5, tile_m=-1)
     assert c_f["mfma"] > 0 and sum(c_f.values()) < sum(c_sw.values())
+
+
+def test_plan_summary_split_rotations():
+    # every U3 becomes a real rotation (6 flop per amplitude by lifting) plus
+    # an input phase on half the amplitudes (3); CZ arithmetic is unchanged
+    circ = W.random_grid_circuit(5, 6, depth=20, seed=2)
+    c_p, b_p, f_p = _summary(circ, fuse_k=1, tile_m=12, split_1q=-1)
+    c_s, b_s, f_s = _summary(circ, fuse_k=1, tile_m=12)
+    N = 2 ** 30
+    assert b_s == c_s["tile"] * 2 * N * 8
+    u3 = circ.count("u3")
+    other = f_p - u3 * 16 * N                 # CZ arithmetic, the same in both plans
+    # U3s at 9 flop per amplitude, plus at most one phase per qubit left over
+    # at the end (6 flop on half the amplitudes, the global factor on all)
+    assert u3 * 9 * N + other <= f_s <= u3 * 9 * N + other + (30 * 3 + 6) * N
+    assert f_s < 0.6 * f_p
+    # exact gates keep exact phases: X and H split with phase -1, S merges
+    ops = [W.op("x", 0), W.op("h", 1), W.op("s", 1), W.op("h", 1), W.op("cx", 0, 1)]
+    c1, b1, f1 = _summary(W.Circuit(10, ops), fuse_k=1, tile_m=10)
+    assert c1["tile"] == 1 and f1 > 0
+
+
+def test_split_option_validation(fake_state):
+    assert _circuit_status(fake_state, W.ghz_circuit(8), opts=q.make_options(split_1q=2)) == q.QSIM_ERR_ARG
 
 
 def test_plan_summary_rejects_bad_ops_without_device():

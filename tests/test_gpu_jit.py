@@ -1,0 +1,136 @@
+"""GPU parity of the run-time compiled register tiles against the CPU oracle.
+
+The library compiles register-staged tile passes to straight-line kernels
+for states of 18 qubits and more; these tests force that path on at every
+width (a failed compilation is then an error, not a silent fallback to the
+interpreted passes) and compare with the complex128 oracle under the same
+bars as the other parity tests.
+"""
+import os
+
+import numpy as np
+import pytest
+
+import oracle as O
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+TOL = {"c64": 2e-5, "c128": 1e-12}
+MODES = {
+    "tile": dict(fuse_k=1, tile_m=0),
+    "tile12": dict(fuse_k=1, tile_m=12),
+    "tile_complex": dict(fuse_k=1, tile_m=0, split_1q=-1),
+    "fuse2_tile": dict(fuse_k=2, tile_m=0),
+    "fuse3_tile": dict(fuse_k=3, tile_m=0),
+}
+
+
+@pytest.fixture(scope="module")
+def qs():
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2106_13995_amd as q
+    saved = {k: os.environ.get(k) for k in ("QSIM_JIT", "QSIM_JIT_MIN_QUBITS")}
+    os.environ["QSIM_JIT"] = "1"
+    os.environ["QSIM_JIT_MIN_QUBITS"] = "1"
+    yield q
+    for k, v in saved.items():
+        if v is None:
+            os.environ.pop(k, None)
+        else:
+            os.environ[k] = v
+
+
+def _state(q, n, dtype, psi0=None):
+    s = q.State(n, dtype)
+    if psi0 is not None:
+        s.from_numpy(psi0)
+    return s
+
+
+def _rounded(psi, dtype):
+    return psi.astype(np.complex64).astype(np.complex128) if dtype == "c64" else psi.copy()
+
+
+@pytest.mark.parametrize("dtype", ["c64", "c128"])
+@pytest.mark.parametrize("mode", sorted(MODES))
+def test_line12_depth20(qs, dtype, mode):
+    circ = W.random_line_circuit(12, 20, seed=1)
+    s = _state(qs, 12, dtype)
+    s.apply_circuit(circ, **MODES[mode])
+    assert O.rel_l2(s.to_numpy(), O.apply_circuit(circ)) <= TOL[dtype]
+
+
+@pytest.mark.parametrize("dtype", ["c64", "c128"])
+@pytest.mark.parametrize("mode", ["tile", "tile_complex", "fuse2_tile"])
+def test_random_mixed_circuit(qs, dtype, mode):
+    """Named gates of every kind, dense matrices up to 4 qubits (those passes
+    stay in the LDS tile kernel), non-trivial input state."""
+    n = 14
+    rng = np.random.default_rng(205)
+    circ = W.random_circuit(n, 150, rng, max_matrix_k=4)
+    psi0 = _rounded(W.random_state(n, rng), dtype)
+    s = _state(qs, n, dtype, psi0)
+    s.apply_circuit(circ, **MODES[mode])
+    assert O.rel_l2(s.to_numpy(), O.apply_circuit(circ, psi0)) <= TOL[dtype]
+
+
+@pytest.mark.parametrize("dtype", ["c64", "c128"])
+@pytest.mark.parametrize("mode", ["tile", "tile12", "tile_complex"])
+def test_grid_circuit_16q(qs, dtype, mode):
+    circ = W.random_grid_circuit(4, 4, depth=12, seed=2)
+    s = _state(qs, 16, dtype)
+    s.apply_circuit(circ, **MODES[mode])
+    assert O.rel_l2(s.to_numpy(), O.apply_circuit(circ)) <= TOL[dtype]
+
+
+def test_grid_circuit_20q_c64(qs):
+    """A 5 x 4 grid at the full depth of the benchmark circuit: many passes,
+    each with several register stages."""
+    circ = W.random_grid_circuit(5, 4, depth=20, seed=2)
+    s = _state(qs, 20, "c64")
+    s.profile(True)
+    s.apply_circuit(circ, fuse_k=1, tile_m=12)
+    launches, _, _, _ = s.profile_read("tile_jit")
+    assert launches > 0 and s.profile_read("tile")[0] == 0   # every tile pass compiled
+    assert O.rel_l2(s.to_numpy(), O.apply_circuit(circ)) <= TOL["c64"]
+
+
+@pytest.mark.parametrize("mode", ["tile", "tile_complex"])
+def test_multiplier_basis_inputs_bit_exact(qs, mode):
+    """X, CX and CCX only: the split form of X is an exchange with a sign and a
+    phase of -1, both exact, so basis inputs map to basis outputs bit for bit."""
+    bits = 3
+    L = W.MultiplierLayout(bits)
+    rng = np.random.default_rng(207)
+    for a, b in rng.integers(0, 1 << bits, size=(3, 2)):
+        circ = W.multiplier_circuit(int(a), int(b), bits)
+        s = _state(qs, L.n, "c64")
+        s.apply_circuit(circ, **MODES[mode])
+        idx = int(O.classical_run(circ, [0])[0])
+        assert idx == L.basis_index(int(a), int(b), int(a * b))
+        ref = np.zeros(1 << L.n, dtype=np.complex64)
+        ref[idx] = 1.0
+        np.testing.assert_array_equal(s.to_numpy(), ref)
+
+
+@pytest.mark.parametrize("dtype", ["c64", "c128"])
+def test_bound_ansatz_and_parametric_form(qs, dtype):
+    """The ansatz with its angles bound into the ops is compiled; the same
+    circuit with parametric ops stays interpreted (its kernels' structure
+    would follow the parameter values).  Both agree with the oracle."""
+    n, L = 12, 4
+    circ = W.ansatz_circuit(n, L)
+    p = W.ansatz_params(n, L, seed=4)
+    ref = O.apply_circuit(circ, params=p)
+    bound = W.Circuit(n, [W.op(o.kind, *o.targets, angles=(p[o.param],)) if o.param >= 0 else o
+                          for o in circ.ops])
+    for c, params, cls in ((bound, None, "tile_jit"), (circ, p, "tile")):
+        s = _state(qs, n, dtype)
+        s.profile(True)
+        s.apply_circuit(c, params=params, fuse_k=1, tile_m=12)
+        assert s.profile_read(cls)[0] > 0
+        assert O.rel_l2(s.to_numpy(), ref) <= TOL[dtype]
+        s.close()

@@ -25,6 +25,9 @@ MODES = {
     "fuse5_lds": dict(fuse_k=5, tile_m=-1, use_mfma=-1),
     "fuse3_tile": dict(fuse_k=3, tile_m=0),
     "fuse5_tile": dict(fuse_k=5, tile_m=0),
+    "tile_complex": dict(fuse_k=1, tile_m=0, split_1q=-1),
+    "tile12_split": dict(fuse_k=1, tile_m=12, split_1q=1),
+    "fuse2_tile": dict(fuse_k=2, tile_m=0),
 }
 
 
