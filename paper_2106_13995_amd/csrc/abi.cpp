@@ -819,8 +819,9 @@ qsim_status qsim_autotune(qsim_state s, const qsim_circuit *c, const double *par
     const int mlo = s->dtype == QSIM_C128 ? 10 : 11;
     // (compiled register tiles: the split single-qubit form without fusion
     // has the least arithmetic; one compilation per tile size)
-    const int fmax = jit_wanted(s->n) ? 1 : 3;
-    for (int m = mlo; m <= mlo + 2; ++m) {
+    const bool jit = jit_wanted(s->n);
+    const int fmax = jit ? 1 : 3;
+    for (int m = jit ? mlo + 1 : mlo; m <= mlo + 2; ++m) {
         if (m > s->n && m > mlo) break;
         for (int f = 1; f <= fmax; ++f) cands.push_back({f, m, -1, 0});
     }

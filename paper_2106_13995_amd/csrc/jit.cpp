@@ -50,13 +50,72 @@ int deposit_bits(int j, int mask) {
     return out;
 }
 
-// Emits one pass as kernel `name`.
-void gen_pass(Src &o, const Plan &plan, const Pass &p, const char *name) {
+// Exact literal of x in the kernel's precision.
+std::string lit(double x, bool f) {
+    char buf[64];
+    if (f)
+        snprintf(buf, sizeof buf, "%af", double(float(x)));
+    else
+        snprintf(buf, sizeof buf, "%a", x);
+    return buf;
+}
+
+// Multiplies register amplitude i by the factor v, whose value is known
+// here; `on` is a lane predicate (nullptr: every lane).  Exact factors
+// (-1, +-i) are sign changes and exchanges; other unit factors on every lane
+// are a rotation of (re, im) by three in-place lifting steps (a sign change
+// first when Re v < 0 keeps the steps bounded); the rest is a complex
+// product with the pool entry P[e], P[e + 1].
+double emit_factor(Src &o, bool f, int i, std::complex<double> v, const char *on, int e) {
+    const char *T = f ? "float" : "double";
+    const char *FMA = f ? "__builtin_fmaf" : "__builtin_fma";
+    if (v == std::complex<double>(1.0)) return 0.0;
+    if (v == std::complex<double>(-1.0)) {
+        if (on)
+            o("    ar%d = %s ? -ar%d : ar%d; ai%d = %s ? -ai%d : ai%d;", i, on, i, i, i, on, i, i);
+        else
+            o("    ar%d = -ar%d; ai%d = -ai%d;", i, i, i, i);
+        return 0.0;
+    }
+    if (v == std::complex<double>(0.0, 1.0) || v == std::complex<double>(0.0, -1.0)) {
+        const bool plus = v.imag() > 0;   // i (x + iy) = -y + ix; -i (x + iy) = y - ix
+        if (on)
+            o("    { const %s xr = ar%d; ar%d = %s ? %sai%d : ar%d; ai%d = %s ? %sxr : ai%d; }", T, i, i, on,
+              plus ? "-" : "", i, i, i, on, plus ? "" : "-", i);
+        else
+            o("    { const %s xr = ar%d; ar%d = %sai%d; ai%d = %sxr; }", T, i, i, plus ? "-" : "", i, i,
+              plus ? "" : "-");
+        return 0.0;
+    }
+    if (!on && std::abs(std::abs(v) - 1.0) < 1e-12) {
+        double c = v.real(), s = v.imag();
+        if (c < 0) {
+            o("    ar%d = -ar%d; ai%d = -ai%d;", i, i, i, i);
+            c = -c;
+            s = -s;
+        }
+        const std::string P = lit(-s / (1.0 + c), f), U = lit(s, f);
+        o("    ar%d = %s(%s, ai%d, ar%d); ai%d = %s(%s, ar%d, ai%d); ar%d = %s(%s, ai%d, ar%d);", i, FMA, P.c_str(), i,
+          i, i, FMA, U.c_str(), i, i, i, FMA, P.c_str(), i, i);
+        return 6.0;
+    }
+    o("    { %s dx = P[%d], dy = P[%d];", T, e, e + 1);
+    if (on) o("      dx = %s ? dx : %s(1); dy = %s ? dy : %s(0);", on, T, on, T);
+    o("      const %s xr = ar%d; ar%d = %s(dx, xr, -dy * ai%d); ai%d = %s(dx, ai%d, dy * xr); }", T, i, i, FMA, i, i,
+      FMA, i);
+    return 6.0;
+}
+
+// Emits one pass as kernel `name`; returns the arithmetic it performs per
+// thread (flops; a multiply-add counts 2).
+double gen_pass(Src &o, const Plan &plan, const Pass &p, const char *name) {
+    double fl = 0.0;
     const bool f = plan.dtype == QSIM_C64;
     const char *T = f ? "float" : "double";
     const char *V = f ? "f2" : "d2";
     const char *FMA = f ? "__builtin_fmaf" : "__builtin_fma";
     const int R = p.reg_r, NA = 1 << R;
+    auto pool_at = [&](int rel) { return plan.tile_pool[size_t(p.pool_begin + rel)]; };
     o("extern \"C\" __global__ void __launch_bounds__(256) %s(%s *psi, const %s *Pg) {", name, V, T);
     o("  const QC %s *P = (const QC %s *)Pg;", T, T);
     o("  extern __shared__ %s lds[];", V);
@@ -107,6 +166,7 @@ void gen_pass(Src &o, const Plan &plan, const Pass &p, const char *name) {
             switch (op.type) {
                 case 0: {   // dense on register mask, complex matrix
                     const int K = popc32(uint32_t(op.rmask)), D = 1 << K;
+                    fl += 8.0 * D * NA;   // a complex multiply-add per matrix entry and amplitude
                     o("  {");
                     for (int g = 0; g < NA; ++g) {
                         if (g & op.rmask) continue;
@@ -136,6 +196,7 @@ void gen_pass(Src &o, const Plan &plan, const Pass &p, const char *name) {
                 }
                 case 3: {   // real rotation by lifting on one register bit
                     const int B = op.rb[0];
+                    fl += 6.0 * NA;   // three multiply-adds per component and pair
                     o("  { const %s p = P[%d], u = P[%d];", T, m2, m2 + 1);
                     for (int g = 0; g < NA; ++g) {
                         if (g & (1 << B)) continue;
@@ -161,29 +222,21 @@ void gen_pass(Src &o, const Plan &plan, const Pass &p, const char *name) {
                 }
                 case 4: {   // phase table over the register bits (entry 0 is 1)
                     o("  {");
-                    for (int i = 1; i < NA; ++i) {
-                        const int e = m2 + 2 * i;
-                        o("    { const %s dx = P[%d], dy = P[%d], xr = ar%d;", T, e, e + 1, i);
-                        o("      ar%d = %s(dx, xr, -dy * ai%d); ai%d = %s(dx, ai%d, dy * xr); }", i, FMA, i, i, FMA,
-                          i);
-                    }
+                    for (int i = 1; i < NA; ++i)
+                        fl += emit_factor(o, f, i, pool_at(op.moff + i), nullptr, m2 + 2 * i);
                     o("  }");
                     break;
                 }
                 case 6: {   // factor on the all-ones amplitudes of the op's bits
                     const uint64_t gmask = uint64_t(uint32_t(op.gp[0])) | (uint64_t(uint32_t(op.gp[1])) << 32);
                     const uint32_t tmask = uint32_t(op.tb[0]);
-                    o("  { %s dx = P[%d], dy = P[%d];", T, m2, m2 + 1);
-                    if (gmask || tmask) {
-                        // amplitudes whose other bits do not match multiply by 1 (exact)
+                    o("  {");
+                    if (gmask || tmask)
                         o("    const bool on = ((base & 0x%llxull) == 0x%llxull) && ((t & %uu) == %uu);",
                           (unsigned long long)gmask, (unsigned long long)gmask, tmask, tmask);
-                        o("    dx = on ? dx : %s(1); dy = on ? dy : %s(0);", T, T);
-                    }
                     for (int i = 0; i < NA; ++i) {
                         if ((i & op.rmask) != op.rmask) continue;
-                        o("    { const %s xr = ar%d; ar%d = %s(dx, xr, -dy * ai%d); ai%d = %s(dx, ai%d, dy * xr); }", T,
-                          i, i, FMA, i, i, FMA, i);
+                        fl += emit_factor(o, f, i, pool_at(op.moff), (gmask || tmask) ? "on" : nullptr, m2);
                     }
                     o("  }");
                     break;
@@ -202,6 +255,7 @@ void gen_pass(Src &o, const Plan &plan, const Pass &p, const char *name) {
                         o("      ar%d = %s(dx, xr, -dy * ai%d); ai%d = %s(dx, ai%d, dy * xr); }", i, FMA, i, i, FMA,
                           i);
                     }
+                    fl += 6.0 * NA;
                     o("  }");
                     break;
                 }
@@ -220,6 +274,7 @@ void gen_pass(Src &o, const Plan &plan, const Pass &p, const char *name) {
     }
     o("  }");
     o("}");
+    return fl;
 }
 
 struct JitModule {
@@ -247,7 +302,7 @@ bool jit_wanted(int n) {
     return n >= env_int("QSIM_JIT_MIN_QUBITS", 18);
 }
 
-std::string jit_source(const Plan &plan, std::vector<int> &which) {
+std::string jit_source(const Plan &plan, std::vector<int> &which, std::vector<double> *flops) {
     Src o;
     o("typedef float f2 __attribute__((ext_vector_type(2)));");
     o("typedef double d2 __attribute__((ext_vector_type(2)));");
@@ -258,7 +313,8 @@ std::string jit_source(const Plan &plan, std::vector<int> &which) {
         if (p.kind != PASS_TILE || p.reg_r <= 0) continue;
         char name[48];
         snprintf(name, sizeof name, "qsim_tile_jit_%zu", which.size());
-        gen_pass(o, plan, p, name);
+        const double fpt = gen_pass(o, plan, p, name);
+        if (flops) flops->push_back(fpt * 256.0 * std::ldexp(1.0, plan.n - p.m));
         which.push_back(int(i));
     }
     return o.s;
@@ -267,7 +323,8 @@ std::string jit_source(const Plan &plan, std::vector<int> &which) {
 qsim_status jit_prepare(qsim_state s, Plan &plan, std::string &err) {
     plan.jit_fn.assign(plan.passes.size(), nullptr);
     std::vector<int> which;
-    const std::string text = jit_source(plan, which);
+    std::vector<double> flops;
+    const std::string text = jit_source(plan, which, &flops);
     if (which.empty()) return QSIM_OK;
     std::lock_guard<std::mutex> lk(g_mu);
     const auto key = std::make_pair(s->device, text);
@@ -281,10 +338,12 @@ qsim_status jit_prepare(qsim_state s, Plan &plan, std::string &err) {
             err = "hiprtcCreateProgram failed";
             return QSIM_ERR_DEVICE;
         }
-        // packed FP32 instructions stay off, as for the prebuilt kernels
+        // packed FP32 instructions stay off, as for the prebuilt kernels;
+        // CodeGenPrepare and the SLP vectoriser change nothing in this
+        // straight-line code and take a quarter of the compile time
         const char *opts[] = {"--offload-arch=gfx950", "-O3", "-Xclang", "-target-feature", "-Xclang",
-                              "-packed-fp32-ops"};
-        const hiprtcResult rc = hiprtcCompileProgram(prog, 6, opts);
+                              "-packed-fp32-ops", "-mllvm", "-disable-cgp", "-fno-slp-vectorize"};
+        const hiprtcResult rc = hiprtcCompileProgram(prog, 9, opts);
         if (rc != HIPRTC_SUCCESS) {
             size_t ls = 0;
             hiprtcGetProgramLogSize(prog, &ls);
@@ -316,7 +375,10 @@ qsim_status jit_prepare(qsim_state s, Plan &plan, std::string &err) {
         }
         g_modules[key] = jm;
     }
-    for (size_t k = 0; k < which.size(); ++k) plan.jit_fn[size_t(which[k])] = jm->fns[k];
+    for (size_t k = 0; k < which.size(); ++k) {
+        plan.jit_fn[size_t(which[k])] = jm->fns[k];
+        plan.passes[size_t(which[k])].flops = flops[k];
+    }
     return QSIM_OK;
 }
 

@@ -197,7 +197,8 @@ struct Plan {
 // compilation leaves the passes interpreted).
 int jit_mode();
 bool jit_wanted(int n);
-std::string jit_source(const Plan &plan, std::vector<int> &which);   // HIP source of the compiled passes
+// HIP source of the compiled passes; `flops` receives each one's arithmetic
+std::string jit_source(const Plan &plan, std::vector<int> &which, std::vector<double> *flops = nullptr);
 qsim_status jit_prepare(qsim_state s, Plan &plan, std::string &err);
 hipError_t launch_jit_pass(qsim_state s, const Plan &plan, const Pass &p, hipFunction_t fn);
 
