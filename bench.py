@@ -227,7 +227,8 @@ def sweep_bench(torch, q, W, n: int = 30, dtype: str = "c64", reps: int = 5):
             s.profile(True)
             for _ in range(reps):
                 s.apply_gate(tg, U)
-            cls = "mfma" if k >= 4 else "sweep_dense"
+            # the kernel class that ran (low-target gates go to a one-gate tile)
+            cls = max(("sweep_dense", "tile", "mfma"), key=lambda c: s.profile_read(c)[0])
             cnt, ms, by, fl = s.profile_read(cls)
             s.profile(False)
             gbs = by / (ms / 1e3) / 1e9

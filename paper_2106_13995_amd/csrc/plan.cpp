@@ -345,7 +345,16 @@ void build_plan(Plan &plan, const std::vector<HostGate> &gates_in, const PlanOpt
             int ctrls[QSIM_MAX_K];
             const bool diag = is_diagonal(g);
             const int nc = diag ? 0 : extract_controls(g, red, ctrls);
-            if (diag || g.k - nc <= 3) {
+            int tlow = 64;
+            for (int b = 0; b < red.k && !diag; ++b) tlow = std::min(tlow, red.targets[b]);
+            if (!diag && po.reg_tiles && g.k <= 3 && g.k - nc >= 2 && tlow <= 2 && n >= default_tile_m(dtype)) {
+                // two or more targets among the lowest qubits: a sweep's
+                // threads would each gather a few adjacent amplitudes with
+                // strided accesses; a one-gate register tile reads whole
+                // lines and applies the gate on register bits
+                TileBuilder tb(plan, n, dtype, default_tile_m(dtype), true);
+                tb.emit(((1ull << tb.L) - 1) | qmask(g), {&g});
+            } else if (diag || g.k - nc <= 3) {
                 plan.passes.push_back(sweep_pass(g, n, dtype));
             } else if (po.use_mfma >= 0) {
                 plan.passes.push_back(mfma_pass(plan, g));

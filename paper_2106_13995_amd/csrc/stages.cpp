@@ -219,24 +219,70 @@ bool build_reg_program(Plan &plan, Pass &p, uint64_t q, const int *local_of,
         uint32_t touched = 0;
         std::vector<RegOp> sops;
         auto pool_off = [&]() { return int(plan.tile_pool.size()) - p.pool_begin; };
-        for (int gi : stages[si].second) {
+        const std::vector<int> &sg = stages[si].second;
+        // register bit a gate acts on non-diagonally (-1: none / several)
+        auto rot_bit = [&](int gi) {
+            const LocalGate &lg = gs[size_t(gi)];
+            return (!lg.diag && lg.g->rot_real) ? index_in(Rp, r, local_of[lg.g->targets[0]]) : -1;
+        };
+        auto nondiag_mask = [&](int gi) {
+            const LocalGate &lg = gs[size_t(gi)];
+            uint32_t mk = 0;
+            if (lg.diag) return mk;
+            for (int b = 0; b < lg.g->k; ++b) mk |= 1u << index_in(Rp, r, local_of[lg.g->targets[b]]);
+            return mk;
+        };
+        std::vector<char> phase_done(sg.size(), 0);
+        for (size_t pos = 0; pos < sg.size(); ++pos) {
+            const int gi = sg[pos];
             const LocalGate &lg = gs[size_t(gi)];
             const HostGate &s = *lg.g;
             if (!lg.diag && s.rot_real) {
                 const int ri = index_in(Rp, r, local_of[s.targets[0]]);
-                if (s.phase_in != cd(1.0)) {
+                if (s.phase_in != cd(1.0) && !phase_done[pos]) {
                     if (!((touched >> ri) & 1u)) {
                         for (size_t i = 0; i < table.size(); ++i)
                             if ((i >> ri) & 1u) table[i] *= s.phase_in;
                         use_table = true;
                     } else {
-                        RegOp ph{};
-                        ph.type = 6;
-                        ph.k = 1;
-                        ph.moff = pool_off();
-                        plan.tile_pool.push_back(s.phase_in);
-                        ph.rmask = 1 << ri;
-                        sops.push_back(ph);
+                        // later rotations whose phases may move up to here:
+                        // their bit is already changed in this stage and no
+                        // op in between acts on it non-diagonally
+                        std::vector<size_t> group{pos};
+                        uint32_t blocked = 1u << ri;
+                        for (size_t q2 = pos + 1; q2 < sg.size(); ++q2) {
+                            const int c = rot_bit(sg[q2]);
+                            const HostGate &h = *gs[size_t(sg[q2])].g;
+                            if (c >= 0 && h.phase_in != cd(1.0) && !phase_done[q2] && ((touched >> c) & 1u) &&
+                                !((blocked >> c) & 1u))
+                                group.push_back(q2);
+                            blocked |= nondiag_mask(sg[q2]);
+                        }
+                        if (group.size() >= 2) {
+                            // one table over the register bits for all of them
+                            std::vector<cd> mid(size_t(1) << r, cd(1.0));
+                            for (size_t gq : group) {
+                                const int c = rot_bit(sg[gq]);
+                                const cd ph = gs[size_t(sg[gq])].g->phase_in;
+                                for (size_t i = 0; i < mid.size(); ++i)
+                                    if ((i >> c) & 1u) mid[i] *= ph;
+                                phase_done[gq] = 1;
+                            }
+                            RegOp t{};
+                            t.type = 4;
+                            t.k = r;
+                            t.moff = pool_off();
+                            plan.tile_pool.insert(plan.tile_pool.end(), mid.begin(), mid.end());
+                            sops.push_back(t);
+                        } else {
+                            RegOp ph{};
+                            ph.type = 6;
+                            ph.k = 1;
+                            ph.moff = pool_off();
+                            plan.tile_pool.push_back(s.phase_in);
+                            ph.rmask = 1 << ri;
+                            sops.push_back(ph);
+                        }
                     }
                 }
                 RegOp op{};
@@ -257,6 +303,7 @@ bool build_reg_program(Plan &plan, Pass &p, uint64_t q, const int *local_of,
                 touched |= 1u << ri;
                 continue;
             }
+            (void)pos;
             RegOp op{};
             op.k = s.k;
             op.moff = int(plan.tile_pool.size()) - p.pool_begin;
