@@ -181,62 +181,92 @@ __global__ void __launch_bounds__(kMfmaThreads) k_fused_mfma(const MfmaArgs<T> a
     }
 }
 
-// Targets other than the lowest qubits: a group's amplitudes lie far apart;
-// one workgroup per block of 64 rows, B read through the caches.
-template <typename T, int K>
+// Targets other than the lowest qubits: a group's amplitudes lie far apart,
+// and each local index j is a separate run of consecutive groups in memory.
+// One workgroup per block of ROWS groups (many blocks in flight per compute
+// unit); ROWS up to 256 makes each run 1-2 KiB long, and each wave takes
+// ROWS / 64 sixteen-row blocks, so every B element it loads through the
+// caches serves that many products.
+template <typename T, int K, int ROWS>
 __global__ void __launch_bounds__(kMfmaThreads) k_fused_mfma_rows(const MfmaArgs<T> a) {
     constexpr int D = 1 << K;
     constexpr int W = 2 * D;          // real row width
-    constexpr int S = W + 4;          // LDS row stride (keeps 16 rows x 4 columns in distinct banks)
+    constexpr int NB = W / 16, KS = W / 4, RB = ROWS / 64;
     using Op = MfmaOp<T>;
     using acc_t = typename Op::acc;
     extern __shared__ char lds_raw[];
     T *sA = reinterpret_cast<T *>(lds_raw);
-    const uint64_t g0 = uint64_t(blockIdx.x) * kMfmaRows;
-    // gather 64 rows; consecutive threads take consecutive rows of one column
-    // (one workgroup per row block: many blocks in flight per compute unit,
-    // which the scattered columns of high targets need)
-    for (int e = threadIdx.x; e < kMfmaRows * D; e += kMfmaThreads) {
-        const int r = e % kMfmaRows, j = e / kMfmaRows;
+    const uint64_t g0 = uint64_t(blockIdx.x) * ROWS;
+    // consecutive threads take consecutive groups of one local index; every
+    // load of the thread is issued before the first LDS store waits on one
+    constexpr int PER = ROWS * D / kMfmaThreads;
+    c2_t<T> v[PER];
+#pragma unroll
+    for (int i = 0; i < PER; ++i) {
+        const int e = threadIdx.x + i * kMfmaThreads;
+        const int r = e % ROWS, j = e / ROWS;
         const uint64_t g = g0 + r;
-        T re = T(0), im = T(0);
-        if (g < a.ngroups) {
-            const c2_t<T> v = a.psi[insert_zeros(g, a.pos, K) + a.toff[j]];
-            re = v.x;
-            im = v.y;
-        }
-        sA[r * S + j] = re;
-        sA[r * S + D + j] = im;
+        v[i].x = T(0);
+        v[i].y = T(0);
+        if (g < a.ngroups) v[i] = a.psi[insert_zeros(g, a.pos, K) + a.toff[j]];
+    }
+#pragma unroll
+    for (int i = 0; i < PER; ++i) {
+        const int e = threadIdx.x + i * kMfmaThreads;
+        const int r = e % ROWS, j = e / ROWS;
+        sA[sidx<W>(r, j)] = v[i].x;
+        sA[sidx<W>(r, D + j)] = v[i].y;
     }
     __syncthreads();
     const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
-    const int arow = wave * 16 + (lane % 16);   // A operand: row lane%16, column lane/16 of the k-step
-    const int kq = lane / 16;
-    acc_t c[W / 16];
+    const int kq = lane / 16, lc = lane % 16;
+    const int row0 = wave * 16 * RB;   // this wave's rows: row0 .. row0 + 16 RB - 1
+    acc_t c[RB][NB];
 #pragma unroll
-    for (int nb = 0; nb < W / 16; ++nb) c[nb] = acc_t{};
-#pragma unroll 4
-    for (int s = 0; s < W / 4; ++s) {
-        const T av = sA[arow * S + 4 * s + kq];
-        const T *brow = a.B + size_t(4 * s + kq) * W + (lane % 16);
+    for (int rb = 0; rb < RB; ++rb)
 #pragma unroll
-        for (int nb = 0; nb < W / 16; ++nb) c[nb] = Op::mma(av, brow[nb * 16], c[nb]);
+        for (int nb = 0; nb < NB; ++nb) c[rb][nb] = acc_t{};
+#pragma unroll 2
+    for (int s = 0; s < KS; ++s) {
+        T bv[NB];
+        const T *brow = a.B + size_t(4 * s + kq) * W + lc;
+#pragma unroll
+        for (int nb = 0; nb < NB; ++nb) bv[nb] = brow[nb * 16];
+#pragma unroll
+        for (int rb = 0; rb < RB; ++rb) {
+            const T av = sA[sidx<W>(row0 + rb * 16 + lc, 4 * s + kq)];
+#pragma unroll
+            for (int nb = 0; nb < NB; ++nb) c[rb][nb] = Op::mma(av, bv[nb], c[rb][nb]);
+        }
     }
-    // each wave overwrites only its own 16 rows, after reading all of them
+    // each wave overwrites only its own rows, after reading all of them
 #pragma unroll
-    for (int nb = 0; nb < W / 16; ++nb)
+    for (int rb = 0; rb < RB; ++rb)
 #pragma unroll
-        for (int i = 0; i < 4; ++i) sA[(wave * 16 + Op::out_row(lane, i)) * S + nb * 16 + (lane % 16)] = c[nb][i];
+        for (int nb = 0; nb < NB; ++nb)
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+                sA[sidx<W>(row0 + rb * 16 + Op::out_row(lane, i), nb * 16 + lc)] = c[rb][nb][i];
     __syncthreads();
-    for (int e = threadIdx.x; e < kMfmaRows * D; e += kMfmaThreads) {
-        const int r = e % kMfmaRows, j = e / kMfmaRows;
+#pragma unroll
+    for (int i = 0; i < PER; ++i) {
+        const int e = threadIdx.x + i * kMfmaThreads;
+        const int r = e % ROWS, j = e / ROWS;
         const uint64_t g = g0 + r;
         if (g >= a.ngroups) continue;
-        c2_t<T> v;
-        v.x = sA[r * S + j];
-        v.y = sA[r * S + D + j];
-        a.psi[insert_zeros(g, a.pos, K) + a.toff[j]] = v;
+        c2_t<T> w;
+        w.x = sA[sidx<W>(r, j)];
+        w.y = sA[sidx<W>(r, D + j)];
+        a.psi[insert_zeros(g, a.pos, K) + a.toff[j]] = w;
     }
+}
+
+// Rows per workgroup of the scattered-target kernel, measured on a 30-qubit
+// complex64 / 29-qubit complex128 state: 256 except complex128 at k = 4, 6
+// (64), where the smaller block keeps more workgroups per compute unit.
+template <typename T, int K>
+constexpr int rows_per_block() {
+    return (sizeof(T) == 8 && K != 5) ? 64 : 256;
 }
 
 template <typename T, int K>
@@ -260,13 +290,15 @@ static hipError_t mfma_t(qsim_state s, const Plan &plan, const Pass &p) {
     constexpr int W = 2 * (1 << K);
     const size_t lds = sizeof(T) * (size_t(kMfmaRows) * W + (b_mode<T, K>() == 1 ? size_t(W) * W : 0));
     if (!lowt) {
-        const size_t lds_rows = sizeof(T) * size_t(kMfmaRows) * (W + 4);
-        const void *fr = reinterpret_cast<const void *>(&k_fused_mfma_rows<T, K>);
+        constexpr int ROWS = rows_per_block<T, K>();
+        const size_t lds_rows = sizeof(T) * size_t(ROWS) * W;
         if (lds_rows > 65536) {
-            hipError_t e = hipFuncSetAttribute(fr, hipFuncAttributeMaxDynamicSharedMemorySize, int(lds_rows));
+            hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_fused_mfma_rows<T, K, ROWS>),
+                                               hipFuncAttributeMaxDynamicSharedMemorySize, int(lds_rows));
             if (e != hipSuccess) return e;
         }
-        hipLaunchKernelGGL((k_fused_mfma_rows<T, K>), dim3(unsigned(a.nblocks)), dim3(kMfmaThreads), lds_rows,
+        const uint64_t blocks = (a.ngroups + ROWS - 1) / ROWS;
+        hipLaunchKernelGGL((k_fused_mfma_rows<T, K, ROWS>), dim3(unsigned(blocks)), dim3(kMfmaThreads), lds_rows,
                            s->stream, a);
         return hipGetLastError();
     }
