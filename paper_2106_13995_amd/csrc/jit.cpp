@@ -110,6 +110,7 @@ double emit_factor(Src &o, bool f, int i, std::complex<double> v, const char *on
 // thread (flops; a multiply-add counts 2).
 double gen_pass(Src &o, const Plan &plan, const Pass &p, const char *name) {
     double fl = 0.0;
+    double scale = 1.0;   // product of the factors the scaled rotations leave out
     const bool f = plan.dtype == QSIM_C64;
     const char *T = f ? "float" : "double";
     const char *V = f ? "f2" : "d2";
@@ -194,16 +195,33 @@ double gen_pass(Src &o, const Plan &plan, const Pass &p, const char *name) {
                     o("  }");
                     break;
                 }
-                case 3: {   // real rotation by lifting on one register bit
+                case 3: {   // real rotation [[c, -s], [s, c]] on one register bit
+                    // As c [[1, -t], [t, 1]] (t = s / c, when c >= s) or
+                    // s [[v, -1], [1, v]] (v = c / s): two multiply-adds per
+                    // component and pair.  The factor c or s is the same for
+                    // every amplitude; the pass multiplies these factors on
+                    // the host and applies their product once, at the store.
+                    // (The pool entry holds the lifting form p = -s / (1 + c),
+                    // u = s, used by the interpreted kernel.)
                     const int B = op.rb[0];
-                    fl += 6.0 * NA;   // three multiply-adds per component and pair
-                    o("  { const %s p = P[%d], u = P[%d];", T, m2, m2 + 1);
+                    const cd pu = pool_at(op.moff);
+                    const double sv = pu.imag(), cv = -sv / pu.real() - 1.0;
+                    const bool tform = cv >= sv;
+                    const std::string q = lit(tform ? sv / cv : cv / sv, f), mq = lit(tform ? -sv / cv : 0.0, f);
+                    scale *= tform ? cv : sv;
+                    fl += 4.0 * NA;
+                    o("  {");
                     for (int g = 0; g < NA; ++g) {
                         if (g & (1 << B)) continue;
                         const int h = g | (1 << B);
-                        o("    ar%d = %s(p, ar%d, ar%d); ai%d = %s(p, ai%d, ai%d);", g, FMA, h, g, g, FMA, h, g);
-                        o("    ar%d = %s(u, ar%d, ar%d); ai%d = %s(u, ai%d, ai%d);", h, FMA, g, h, h, FMA, g, h);
-                        o("    ar%d = %s(p, ar%d, ar%d); ai%d = %s(p, ai%d, ai%d);", g, FMA, h, g, g, FMA, h, g);
+                        for (const char *c : {"ar", "ai"}) {
+                            if (tform)
+                                o("    { const %s y = %s(%s, %s%d, %s%d); %s%d = %s(%s, %s%d, %s%d); %s%d = y; }", T, FMA,
+                                  mq.c_str(), c, h, c, g, c, h, FMA, q.c_str(), c, g, c, h, c, g);
+                            else
+                                o("    { const %s y = %s(%s, %s%d, -%s%d); %s%d = %s(%s, %s%d, %s%d); %s%d = y; }", T, FMA,
+                                  q.c_str(), c, g, c, h, c, h, FMA, q.c_str(), c, h, c, g, c, g);
+                        }
                     }
                     o("  }");
                     break;
@@ -262,8 +280,13 @@ double gen_pass(Src &o, const Plan &plan, const Pass &p, const char *name) {
             }
         }
     }
-    // store
+    // store (with the product of the rotations' factors)
     o("  {");
+    if (scale != 1.0) {
+        const std::string sc = lit(scale, f);
+        for (int i = 0; i < NA; ++i) o("    ar%d *= %s; ai%d *= %s;", i, sc.c_str(), i, sc.c_str());
+        fl += 2.0 * NA;
+    }
     o("    unsigned long long gt = base;");
     for (int b = 0; b < 8; ++b) o("    gt |= (unsigned long long)((t >> %d) & 1u) << %d;", b, int(p.st_t[b]));
     for (int i = 0; i < NA; ++i) {
