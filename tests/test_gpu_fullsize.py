@@ -128,3 +128,58 @@ def test_multiplier29_superposition(env):
     assert np.max(np.abs(got - 2.0 ** -3.5)) < 1e-6
     assert abs(norm2(s) - 1.0) < 1e-5
     s.close()
+
+
+def _after_dense(n, u3s, pairs, targets, U, idx):
+    """Amplitudes at `idx` of (layer 0 state) followed by the dense gate U on
+    `targets` (local bit b = targets[b]), from the closed form of layer 0 at
+    the 2^k indices each output needs."""
+    k = len(targets)
+    tmask = 0
+    for t in targets:
+        tmask |= 1 << t
+    offs = np.zeros(1 << k, dtype=np.uint64)
+    for j in range(1 << k):
+        o = 0
+        for b in range(k):
+            if (j >> b) & 1:
+                o |= 1 << targets[b]
+        offs[j] = o
+    base = idx.astype(np.uint64) & np.uint64(~tmask & ((1 << n) - 1))
+    rows = np.zeros(idx.size, dtype=np.int64)
+    for b, t in enumerate(targets):
+        rows |= ((idx >> t) & 1).astype(np.int64) << b
+    need = (base[:, None] | offs[None, :]).reshape(-1)
+    before = O.product_cz_amplitudes(n, u3s, pairs, need).reshape(idx.size, 1 << k)
+    return np.einsum("sj,sj->s", U[rows], before)
+
+
+@pytest.mark.parametrize("dtype,n,targets,tol", [
+    ("c64", 34, [29, 30, 31, 32, 33], 2e-5),   # 128 GiB; k = 5 on scattered (high) targets
+    ("c128", 33, [0, 1, 2, 3], 1e-12),        # 128 GiB; k = 4 on the lowest qubits
+])
+def test_max_width_state(env, dtype, n, targets, tol):
+    """Beyond 2^32 amplitudes (64-bit indexing everywhere): layer 0 of a
+    2 x n/2 grid circuit (compiled tile passes), then a dense block on the
+    matrix cores, against the closed form at 4096 sampled indices."""
+    q, torch = env
+    rows = 2
+    cols = n // rows
+    if rows * cols != n:
+        cols, rows = n, 1
+    circ = W.random_grid_circuit(rows, cols, depth=1, seed=5)
+    rng = np.random.default_rng(40 + n)
+    U = W.random_unitary(len(targets), rng)
+    s = q.State(n, dtype)
+    s.apply_circuit(circ)
+    s.apply_gate(targets, U)
+    idx = sample_indices(n, 4096, seed=41)
+    idx[:2] = [0, (1 << n) - 1]
+    got = amplitudes(s, idx)
+    u3s = [o for o in circ.ops if o.kind == "u3"]
+    ref = _after_dense(n, u3s, W.grid_cz_pairs(rows, cols, 0), targets, U, idx.astype(np.int64))
+    assert O.rel_l2(got, ref) <= tol
+    assert abs(norm2(s) - 1.0) < 10 * tol
+    s.close()
+    del s
+    torch.cuda.empty_cache()
