@@ -41,11 +41,22 @@ struct BatchArgs {
     int mmax;
 };
 
-// Rotation exp(-i theta G / 2) (or its inverse) on local position p.
+// Per-circuit tables in LDS: cos and sin of half of each rotation angle
+// (formed once per circuit instead of once per op and tile), and the
+// per-wave partial sums of a tile's probes, added to the gradient in a fixed
+// order when the tile is done.
+constexpr int kBatchTrig = 512;
+constexpr int kProbeSlots = 64;
+struct BatchShared {
+    double cs[kBatchTrig], sn[kBatchTrig];
+    double probe[kProbeSlots][kTileThreads / 64];
+    int probe_param[kProbeSlots];
+};
+
+// Rotation exp(-i theta G / 2) (or its inverse) on local position p, given
+// cs = cos(theta / 2) and sn = sin(theta / 2).
 template <typename T>
-__device__ __forceinline__ void tile_rotation(c2_t<T> *lds, int p, int gen, double theta, uint32_t M) {
-    double sn, cs;
-    sincos(0.5 * theta, &sn, &cs);
+__device__ __forceinline__ void tile_rotation(c2_t<T> *lds, int p, int gen, double cs, double sn, uint32_t M) {
     // [[a, b], [c, d]] as (re, im)
     T ar, ai, br, bi, cr, ci, dr, di;
     if (gen == 1) {        // X: [[c, -is], [-is, c]]
@@ -100,19 +111,47 @@ __device__ __forceinline__ double batch_probe(const c2_t<T> *lp, const c2_t<T> *
     return acc;
 }
 
+// Sums the tile's pending probe partials into the gradient (thread 0, in
+// probe order, waves in order: the same order a block-wide sum uses).
+__device__ __forceinline__ void flush_probes(BatchShared &sh, int np, double *grd) {
+    if (threadIdx.x == 0)
+        for (int k = 0; k < np; ++k) {
+            double t = 0.0;
+            for (int w = 0; w < kTileThreads / 64; ++w) t += sh.probe[k][w];
+            grd[sh.probe_param[k]] += t;
+        }
+}
+
 // Ops of one pass on one tile (psi only, or psi and lambda).
 template <typename T>
 __device__ void batch_tile_ops(const BatchArgs<T> &a, const BatchPass &ps, c2_t<T> *lp, c2_t<T> *ll, bool both,
-                               uint64_t base, uint32_t M, const double *prm, double *grd) {
+                               uint64_t base, uint32_t M, const double *prm, double *grd, BatchShared &sh,
+                               bool trig) {
+    int np = 0;
     for (int o = ps.op_begin; o < ps.op_end; ++o) {
         const TileOp &op = a.ops[o];
         if (op.type == 3) {
-            const double v = block_sum(batch_probe<T>(lp, ll, op.pos[0], op.kin, M));
-            if (threadIdx.x == 0) grd[op.moff] += v;
+            // per-wave sum now, across waves when the tile is done
+            double v = batch_probe<T>(lp, ll, op.pos[0], op.kin, M);
+            for (int sft = 32; sft > 0; sft >>= 1) v += __shfl_xor(v, sft, 64);
+            if (threadIdx.x % 64 == 0) sh.probe[np][threadIdx.x / 64] = v;
+            if (threadIdx.x == 0) sh.probe_param[np] = op.moff;
+            if (++np == kProbeSlots) {
+                __syncthreads();
+                flush_probes(sh, np, grd);
+                np = 0;
+            }
         } else if (op.type == 4) {
-            const double th = op.jbit[0] ? -prm[op.moff] : prm[op.moff];
-            tile_rotation<T>(lp, op.pos[0], op.kin, th, M);
-            if (both) tile_rotation<T>(ll, op.pos[0], op.kin, th, M);
+            double cs, sn;
+            if (trig) {
+                cs = sh.cs[op.moff];
+                sn = sh.sn[op.moff];
+            } else {
+                sincos(0.5 * prm[op.moff], &sn, &cs);
+            }
+            if (op.jbit[0]) sn = -sn;
+            tile_rotation<T>(lp, op.pos[0], op.kin, cs, sn, M);
+            if (both) tile_rotation<T>(ll, op.pos[0], op.kin, cs, sn, M);
         } else if (op.type == 1) {
             const c2_t<T> *U = a.pool + op.moff;
             tile_diag<T>(lp, op, U, base, M);
@@ -136,6 +175,7 @@ __device__ void batch_tile_ops(const BatchArgs<T> &a, const BatchPass &ps, c2_t<
         }
         __syncthreads();
     }
+    flush_probes(sh, np, grd);
 }
 
 template <typename T>
@@ -150,6 +190,7 @@ template <typename T>
 __global__ void __launch_bounds__(kTileThreads) k_batch(const BatchArgs<T> a) {
     extern __shared__ char lds_raw[];
     __shared__ int s_next;
+    __shared__ BatchShared sh;
     c2_t<T> *lp = reinterpret_cast<c2_t<T> *>(lds_raw);
     c2_t<T> *ll = lp + (1u << a.mmax);
     c2_t<T> *gpsi = a.arena + uint64_t(blockIdx.x) * 2ull * a.slot_amps;
@@ -171,6 +212,9 @@ __global__ void __launch_bounds__(kTileThreads) k_batch(const BatchArgs<T> a) {
         const uint64_t N = 1ull << n;
         if (a.want_grad)
             for (int j = threadIdx.x; j < cc.nparams; j += kTileThreads) grd[j] = 0.0;
+        const bool trig = cc.nparams <= kBatchTrig;
+        if (trig)
+            for (int j = threadIdx.x; j < cc.nparams; j += kTileThreads) sincos(0.5 * prm[j], &sh.sn[j], &sh.cs[j]);
         // psi = |0...0>
         if (single) {
             for (uint32_t l = threadIdx.x; l < M; l += kTileThreads) {
@@ -204,7 +248,7 @@ __global__ void __launch_bounds__(kTileThreads) k_batch(const BatchArgs<T> a) {
                     }
                     __syncthreads();
                 }
-                batch_tile_ops<T>(a, ps, lp, ll, false, base, M, prm, grd);
+                batch_tile_ops<T>(a, ps, lp, ll, false, base, M, prm, grd, sh, trig);
                 if (!single) {
                     for (uint32_t l = threadIdx.x; l < M; l += kTileThreads) gpsi[base | batch_scatter<T>(ps, l)] = lp[l];
                     __syncthreads();
@@ -264,7 +308,7 @@ __global__ void __launch_bounds__(kTileThreads) k_batch(const BatchArgs<T> a) {
                     }
                     __syncthreads();
                 }
-                batch_tile_ops<T>(a, ps, lp, ll, true, base, M, prm, grd);
+                batch_tile_ops<T>(a, ps, lp, ll, true, base, M, prm, grd, sh, trig);
                 if (!single) {
                     for (uint32_t l = threadIdx.x; l < M; l += kTileThreads) {
                         const uint64_t gi = base | batch_scatter<T>(ps, l);
