@@ -10,8 +10,11 @@
 
 namespace qsim {
 
-// Tile qubits of batch passes: psi and lambda tiles share LDS (2 x 16 KiB).
-inline int batch_tile_max(int dtype) { return dtype == QSIM_C128 ? 10 : 11; }
+// Tile qubits of batch passes: psi and lambda tiles share LDS (2 x 32 KiB;
+// measured on the 4096-circuit mix: 2^12 complex64 amplitudes per tile beat
+// 2^11, which has twice the tiles and barriers, and 2^13, which leaves one
+// workgroup per compute unit).
+inline int batch_tile_max(int dtype) { return dtype == QSIM_C128 ? 11 : 12; }
 
 struct BatchCircuit {
     int32_t prog;        // program (shared structure)

@@ -349,6 +349,11 @@ static hipError_t launch_batch_t(hipStream_t stream, const BatchDevice &d, int g
     a.want_grad = d.want_grad;
     a.mmax = d.mmax;
     const size_t lds = 2 * (sizeof(c2_t<T>) << d.mmax);
+    if (lds > 65536) {
+        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_batch<T>),
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, int(lds));
+        if (e != hipSuccess) return e;
+    }
     hipLaunchKernelGGL(k_zero_counter, dim3(1), dim3(64), 0, stream, d.counter);
     hipLaunchKernelGGL((k_batch<T>), dim3(grid), dim3(kTileThreads), lds, stream, a);
     return hipGetLastError();
