@@ -148,12 +148,33 @@ k_adjoint_tile(const TileArgs<T> a, c2_t<T> *__restrict__ lam, double *__restric
         ll[l] = lam[g];
     }
     __syncthreads();
+    // probes: summed within each wave at the op, across the four waves (in
+    // the fixed order of a block-wide sum) when the tile is done or the
+    // slots are full, so a probe costs no barrier of its own
+    constexpr int kSlots = 64;
+    __shared__ double wpart[kSlots][kTileThreads / 64];
+    __shared__ int wslot[kSlots];
+    int np = 0;
+    auto flush = [&]() {
+        if (threadIdx.x < np) {
+            double t = 0.0;
+            for (int w = 0; w < kTileThreads / 64; ++w) t += wpart[threadIdx.x][w];
+            probe_partials[size_t(wslot[threadIdx.x]) * ntiles + blockIdx.x] = t;
+        }
+    };
     for (int o = 0; o < a.nops; ++o) {
         const TileOp &op = sops[o];
         const c2_t<T> *U = spool + op.moff;
         if (op.type == 3) {
-            const double v = block_sum(tile_probe<T>(lp, ll, op.pos[0], op.kin, M));
-            if (threadIdx.x == 0) probe_partials[size_t(op.moff) * ntiles + blockIdx.x] = v;
+            double v = tile_probe<T>(lp, ll, op.pos[0], op.kin, M);
+            for (int sft = 32; sft > 0; sft >>= 1) v += __shfl_xor(v, sft, 64);
+            if (threadIdx.x % 64 == 0) wpart[np][threadIdx.x / 64] = v;
+            if (threadIdx.x == 0) wslot[np] = op.moff;
+            if (++np == kSlots) {
+                __syncthreads();
+                flush();
+                np = 0;
+            }
         } else if (op.type == 1) {
             tile_diag<T>(lp, op, U, base, M);
             tile_diag<T>(ll, op, U, base, M);
@@ -176,6 +197,7 @@ k_adjoint_tile(const TileArgs<T> a, c2_t<T> *__restrict__ lam, double *__restric
         }
         __syncthreads();
     }
+    flush();
     for (uint32_t l = threadIdx.x; l < M; l += kTileThreads) {
         const uint64_t g = base | tile_scatter(a, l);
         a.psi[g] = lp[l];
