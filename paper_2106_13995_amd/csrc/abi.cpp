@@ -723,7 +723,9 @@ qsim_status qsim_adjoint_grad(qsim_state s, const qsim_circuit *c, const double 
     if (!rev) return set_error(QSIM_ERR_OOM, "host allocation failed");
     rev->n = s->n;
     rev->dtype = s->dtype;
-    const int adj_m = s->dtype == QSIM_C128 ? 10 : 11;
+    // 2^10 amplitudes per state and tile for both precisions: measured on the
+    // 20-qubit ansatz, smaller tiles put more workgroups on the chip
+    const int adj_m = 10;
     build_adjoint_plan(*rev, items, adj_m);
     st = upload_plan(s, *rev);
     if (st != QSIM_OK) return st;
