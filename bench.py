@@ -95,6 +95,26 @@ def cpu_baseline(circ, ngates: int):
                       f"1 thread, {dt:.1f} s (includes one copy of the 2^{circ.n}-amplitude input)"}
 
 
+def expectation_bench(torch, q, W, s, reps: int = 5):
+    """<psi|H|psi> of the chain observable sum Z_iZ_{i+1} + 0.5 sum X_i on the
+    circuit's output state: bytes are each pass's algorithmic read of the state
+    (and of the partner amplitudes for X terms)."""
+    H = W.chain_observable(s.n)
+    s.expectation(H)
+    torch.cuda.synchronize()
+    s.profile(True)
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        val = s.expectation(H)
+    wall = (time.perf_counter() - t0) / reps
+    n, ms, by, fl = s.profile_read("expect")
+    s.profile(False)
+    gbs = by / (ms / 1e3) / 1e9 if ms > 0 else 0.0
+    return {"workload": f"sum Z_iZ_(i+1) + 0.5 sum X_i on the {s.n}-qubit output state",
+            "ms": round(wall * 1e3, 3), "kernel_ms": round(ms / reps, 3), "launches": n // reps,
+            "gbs": round(gbs, 1), "hbm_frac": round(gbs / HBM_PEAK_GBS, 4), "value": val}
+
+
 def time_mode(torch, s, circ, steps, warmup, fuse_k, tile_m, split_1q=0):
     for _ in range(warmup):
         s.apply_circuit(circ, fuse_k=fuse_k, tile_m=tile_m, split_1q=split_1q)
@@ -322,6 +342,7 @@ def main():
         extra[m] = {"ms_per_step": round(e2 / k, 3), "gate_apps_per_s": round(ngates * k / (e2 / 1e3), 1),
                     "passes_per_step": sum(v[0] for v in st2.values()) // k}
 
+    expect = expectation_bench(torch, q, W, s)
     s.close()
     del s
     torch.cuda.empty_cache()
@@ -366,6 +387,7 @@ def main():
         "adjoint": adjoint,
         "batch": batch,
         "gate_sweeps": sweeps,
+        "expectation": expect,
     }
     if extra:
         out["variants"] = extra

@@ -588,6 +588,64 @@ qsim_status qsim_expectation(qsim_state s, const qsim_pauli_sum *H, double *out_
             ++slot;
         }
     }
+    // Groups whose X mask fits a tile (the low L qubits and m - L others) are
+    // evaluated several to a pass over the state; the rest one pass each.
+    const int mt = std::min(s->n, s->dtype == QSIM_C128 ? 11 : 12);
+    const int Lt = std::min(mt, s->dtype == QSIM_C128 ? 4 : 5);
+    std::vector<ExpTilePass> tpasses;
+    std::vector<uint64_t> tmask;           // tile qubits of each pass
+    std::vector<size_t> single;            // groups evaluated alone
+    {
+        std::vector<std::vector<size_t>> members;
+        uint64_t hm = 0;
+        for (size_t gi = 0; gi < spans.size(); ++gi) {
+            const uint64_t hx = spans[gi].first >> Lt << Lt;
+            if (__builtin_popcountll(hx) > mt - Lt) {
+                single.push_back(gi);
+                continue;
+            }
+            if (members.empty() || __builtin_popcountll(hm | hx) > mt - Lt ||
+                members.back().size() == size_t(kExpTileGroups)) {
+                members.emplace_back();
+                hm = 0;
+            }
+            hm |= hx;
+            members.back().push_back(gi);
+            if (tmask.size() < members.size()) tmask.push_back(0);
+            tmask.back() = hm;
+        }
+        for (size_t pi = 0; pi < members.size(); ++pi) {
+            ExpTilePass tp{};
+            tp.m = mt;
+            tp.L = Lt;
+            uint64_t hq = tmask[pi];
+            for (int q = Lt; q < s->n && __builtin_popcountll(hq) < mt - Lt; ++q) hq |= 1ull << q;
+            tmask[pi] = hq | ((1ull << Lt) - 1);
+            int local_of[64];
+            for (int q = 0; q < Lt; ++q) local_of[q] = q;
+            for (int q = Lt; q < s->n; ++q)
+                if ((hq >> q) & 1) {
+                    local_of[q] = Lt + tp.H;
+                    tp.hpos[tp.H++] = q;
+                }
+            auto to_local = [&](uint64_t v) {
+                uint32_t o = 0;
+                for (int q = 0; q < s->n; ++q)
+                    if (((v & tmask[pi]) >> q) & 1) o |= 1u << local_of[q];
+                return o;
+            };
+            for (size_t gi : members[pi]) {
+                const int first = spans[gi].second;
+                const int cnt = (gi + 1 < spans.size() ? spans[gi + 1].second : slot) - first;
+                ExpTileGroup &g = tp.groups[tp.ngroups++];
+                g.xl = to_local(spans[gi].first);
+                g.first = first;
+                g.count = cnt;
+                for (int t = first; t < first + cnt; ++t) ht[t].pad = to_local(ht[t].z);
+            }
+            tpasses.push_back(tp);
+        }
+    }
     char *scr = static_cast<char *>(s->scratch);
     double *partials = reinterpret_cast<double *>(scr);
     DevTerm *dterms = reinterpret_cast<DevTerm *>(scr + terms_off);
@@ -597,7 +655,15 @@ qsim_status qsim_expectation(qsim_state s, const qsim_pauli_sum *H, double *out_
         if (st != QSIM_OK) return st;
     }
     int total = 0;
-    for (size_t gi = 0; gi < spans.size(); ++gi) {
+    for (const ExpTilePass &tp : tpasses) {
+        int wrote = 0;
+        prof_begin(s, QSIM_KCLASS_EXPECT, double(amp_bytes(s->dtype) << s->n));
+        hipError_t e = launch_expect_tiles(s, tp, dterms, partials + total, &wrote);
+        prof_end(s);
+        if (e != hipSuccess) return device_error(s, e, "expectation launch");
+        total += wrote;
+    }
+    for (size_t gi : single) {
         const int first = spans[gi].second;
         const int cnt = (gi + 1 < spans.size() ? spans[gi + 1].second : slot) - first;
         int wrote = 0;

@@ -381,6 +381,82 @@ hipError_t launch_expect_group(qsim_state s, uint64_t xmask, const void *dev_ter
     return hipGetLastError();
 }
 
+// Tiled groups: each workgroup takes tiles blockIdx.x, + gridDim.x, ...; per
+// tile it loads the 2^m amplitudes into LDS (consecutive lanes on the low
+// qubits), then for every group sums Re[w (-1)^{|(y^x) & z|} conj(psi_y)
+// psi_{y^x}] over the tile: the parity splits into the tile's fixed
+// out-of-tile bits (uniform: scalar unit) and the local bits.  Wave sums
+// accumulate per group in LDS in tile order; the workgroup writes one
+// partial per group.
+template <typename T>
+__global__ void __launch_bounds__(kExpThreads)
+k_expect_tile(const c2_t<T> *__restrict__ psi, const ExpTilePass p, const ExpTerm *__restrict__ terms,
+              uint64_t ntiles, double *__restrict__ partials) {
+    extern __shared__ char lds_raw[];
+    c2_t<T> *lds = reinterpret_cast<c2_t<T> *>(lds_raw);
+    __shared__ double wsum[kExpTileGroups][kExpThreads / 64];
+    const uint32_t M = 1u << p.m;
+    const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
+    for (int g = threadIdx.x; g < kExpTileGroups * (kExpThreads / 64); g += kExpThreads)
+        wsum[g / (kExpThreads / 64)][g % (kExpThreads / 64)] = 0.0;
+    for (uint64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
+        uint64_t base = t << p.L;
+        for (int i = 0; i < p.H; ++i) {
+            const uint64_t lo = base & ((1ull << p.hpos[i]) - 1ull);
+            base = ((base - lo) << 1) | lo;
+        }
+        __syncthreads();   // the previous tile's readers are done
+        for (uint32_t l = threadIdx.x; l < M; l += kExpThreads) {
+            uint64_t gi = base | (l & ((1u << p.L) - 1u));
+            const uint32_t h = l >> p.L;
+            for (int i = 0; i < p.H; ++i) gi |= uint64_t((h >> i) & 1u) << p.hpos[i];
+            lds[l] = psi[gi];
+        }
+        __syncthreads();
+        for (int g = 0; g < p.ngroups; ++g) {
+            const ExpTileGroup gr = p.groups[g];
+            double acc = 0.0;
+            for (uint32_t l = threadIdx.x; l < M; l += kExpThreads) {
+                const c2_t<T> a = lds[l], b = lds[l ^ gr.xl];
+                const double pr = double(a.x) * double(b.x) + double(a.y) * double(b.y);
+                const double pi = double(a.x) * double(b.y) - double(a.y) * double(b.x);
+                double sm = 0.0;
+                for (int tt = gr.first; tt < gr.first + gr.count; ++tt) {
+                    const ExpTerm e = terms[tt];
+                    const uint32_t zo = uint32_t(__popcll(base & e.z));
+                    const double v = e.wr * pr - e.wi * pi;
+                    sm += ((uint32_t(__popc((l ^ gr.xl) & uint32_t(e.pad_))) ^ zo) & 1u) ? -v : v;
+                }
+                acc += sm;
+            }
+            for (int sft = 32; sft > 0; sft >>= 1) acc += __shfl_xor(acc, sft, 64);
+            if (lane == 0) wsum[g][wave] += acc;
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x < p.ngroups) {
+        double tot = 0.0;
+        for (int w = 0; w < kExpThreads / 64; ++w) tot += wsum[threadIdx.x][w];
+        partials[size_t(threadIdx.x) * gridDim.x + blockIdx.x] = tot;
+    }
+}
+
+hipError_t launch_expect_tiles(qsim_state s, const ExpTilePass &p, const void *dev_terms, double *partials,
+                               int *nwritten) {
+    const uint64_t ntiles = 1ull << (s->n - p.m);
+    const int grid = int(std::min<uint64_t>(ntiles, 2048));
+    const ExpTerm *terms = static_cast<const ExpTerm *>(dev_terms);
+    const size_t lds = (s->dtype == QSIM_C64 ? 8u : 16u) << p.m;
+    if (s->dtype == QSIM_C64)
+        hipLaunchKernelGGL((k_expect_tile<float>), dim3(grid), dim3(kExpThreads), lds, s->stream,
+                           static_cast<const c2_t<float> *>(s->data), p, terms, ntiles, partials);
+    else
+        hipLaunchKernelGGL((k_expect_tile<double>), dim3(grid), dim3(kExpThreads), lds, s->stream,
+                           static_cast<const c2_t<double> *>(s->data), p, terms, ntiles, partials);
+    *nwritten = grid * p.ngroups;
+    return hipGetLastError();
+}
+
 __global__ void __launch_bounds__(kExpThreads) k_reduce(const double *__restrict__ partials, int count, double *out) {
     double acc = 0.0;
     for (int i = threadIdx.x; i < count; i += kExpThreads) acc += partials[i];

@@ -292,6 +292,25 @@ hipError_t launch_expect_group(qsim_state s, uint64_t xmask, const void *dev_ter
                                double *partials, int *nwritten);
 hipError_t launch_reduce(qsim_state s, const double *partials, int count, double *out);
 
+// Several term groups in one pass over the state: tiles of 2^m amplitudes
+// (the low L qubits and the H qubits hpos[]) in LDS, every group whose X mask
+// lies inside the tile evaluated from there.  Terms carry, in their pad
+// field, the local image of their Z mask.  Writes ngroups * grid partials
+// (group-major) and returns the count.
+constexpr int kExpTileGroups = 64;
+struct ExpTileGroup {
+    uint32_t xl;          // X mask in tile-local bits
+    int32_t first, count; // term range
+    int32_t pad_;
+};
+struct ExpTilePass {
+    int32_t m, L, H, ngroups;
+    int32_t hpos[16];
+    ExpTileGroup groups[kExpTileGroups];
+};
+hipError_t launch_expect_tiles(qsim_state s, const ExpTilePass &p, const void *dev_terms, double *partials,
+                               int *nwritten);
+
 // Adjoint differentiation.
 int pauli_apply_grid(uint64_t N);
 hipError_t launch_pauli_apply(qsim_state s, void *lam, const void *groups, int ngroups, const void *terms,

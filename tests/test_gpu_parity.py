@@ -309,3 +309,26 @@ def test_autotune_choice_is_used_and_correct(qs, tmp_path, monkeypatch):
     s.apply_circuit(circ)
     assert O.rel_l2(s.to_numpy(), O.apply_circuit(circ)) <= TOL["c64"]
     s.close()
+
+
+@pytest.mark.parametrize("dtype", ["c64", "c128"])
+def test_expectation_tiled_and_wide_groups(qs, dtype):
+    """Several X-mask groups per pass over the state (single X and Y terms,
+    diagonal ZZ terms with bits inside and outside a tile) next to groups whose
+    X mask is too wide for one tile (evaluated alone), at 20 qubits."""
+    n = 20
+    rng = np.random.default_rng(109)
+    psi = _rounded(W.random_state(n, rng), dtype)
+    coeffs, xs, zs = [], [], []
+    for i in range(n):
+        coeffs.append(0.5 + 0.1 * i); xs.append(1 << i); zs.append(0)              # X_i
+        coeffs.append(-0.3); xs.append(1 << i); zs.append(1 << i)                   # Y_i
+        coeffs.append(1.0); xs.append(0); zs.append((1 << i) | (1 << ((i + 7) % n)))  # Z_i Z_{i+7}
+    for _ in range(6):                                                              # wide X masks
+        xm = int(rng.integers(1, 1 << n)) | (0xFF << 10)
+        coeffs.append(float(rng.normal())); xs.append(xm); zs.append(int(rng.integers(0, 1 << n)))
+    H = W.PauliSum(n, coeffs, xs, zs)
+    s = _state(qs, n, dtype, psi)
+    got = s.expectation(H)
+    ref = O.expectation(psi, H)
+    assert abs(got - ref) <= (1e-4 if dtype == "c64" else 1e-11) * max(1.0, abs(ref))
