@@ -53,6 +53,7 @@ def parse():
     ap.add_argument("--calib-copy", action="store_true", help="run a plain device copy of the state size")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the 20-qubit adjoint-gradient figure")
     ap.add_argument("--no-batch", action="store_true", help="skip the 4096-circuit batch figure")
+    ap.add_argument("--no-multiplier", action="store_true", help="skip the 29-qubit multiplier figure")
     ap.add_argument("--no-sweeps", action="store_true", help="skip the single-gate sweep figures")
     ap.add_argument("--no-tune", action="store_true", help="skip autotuning during warm-up")
     return ap.parse_args()
@@ -260,6 +261,48 @@ def sweep_bench(torch, q, W, n: int = 30, dtype: str = "c64", reps: int = 5):
             "results": out}
 
 
+def multiplier_bench(torch, q, W, reps: int = 5):
+    """The 29-qubit ripple-carry multiplier (7-bit a and b, 14-bit product,
+    one ancilla; 196 CX + 154 CCX) after H on every bit of a and X gates that
+    load b, complex64, so every run carries all 128 products at once.  Bytes
+    are stated in two models: per gate, the amplitudes it can change (CX half
+    the state, CCX a quarter, one-qubit gates all of it), and a dense sweep
+    per gate; the rate is gates over kernel time."""
+    b = int(W.multiplier_inputs(1, 7, seed=3)[0, 1])
+    circ = W.multiplier_circuit(0, b, 7, superpose_a=True)
+    n, amp = circ.n, 8
+    N = 1 << n
+    sparse = sum(2 * (N >> max(0, len(o.targets) - 1)) * amp if o.kind in ("cx", "ccx") else 2 * N * amp
+                 for o in circ.ops)
+    dense = len(circ.ops) * 2 * N * amp
+    s = q.State(n, "c64")
+    s.apply_circuit(circ)
+    torch.cuda.synchronize()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    s.profile(True)
+    ev0.record()
+    for _ in range(reps):
+        s.set_basis(0)
+        s.apply_circuit(circ)
+    ev1.record()
+    torch.cuda.synchronize()
+    stats = {}
+    for cls in ("sweep_dense", "sweep_diag", "tile", "tile_jit", "mfma"):
+        cnt, ms, by, fl = s.profile_read(cls)
+        if cnt:
+            stats[cls] = {"launches": cnt // reps, "ms": round(ms / reps, 3)}
+    s.profile(False)
+    kms = sum(v["ms"] for v in stats.values())
+    s.close()
+    return {"workload": f"{n}-qubit multiplier, b = {b}, a in uniform superposition, {len(circ.ops)} gates "
+                        f"(H, X, CX, CCX), complex64",
+            "ms": round(ev0.elapsed_time(ev1) / reps, 3), "kernel_ms": round(kms, 3),
+            "gates_per_s": round(len(circ.ops) / (kms / 1e3), 1), "passes": stats,
+            "bytes_per_gate_model": sparse, "bytes_dense_model": dense,
+            "gbs_per_gate_model": round(sparse / (kms / 1e3) / 1e9, 1),
+            "gbs_dense_model": round(dense / (kms / 1e3) / 1e9, 1)}
+
+
 def calib_copy(torch, n: int, dtype: str):
     real = torch.float32 if dtype == "c64" else torch.float64
     a = torch.ones(2 << n, dtype=real, device="cuda")
@@ -353,6 +396,9 @@ def main():
     batch = None
     if not a.no_batch:
         batch = batch_bench(torch, q, W)
+    mult = None
+    if not a.no_multiplier:
+        mult = multiplier_bench(torch, q, W)
     sweeps = None
     if not a.no_sweeps:
         sweeps = sweep_bench(torch, q, W, n=a.n, dtype=a.dtype)
@@ -388,6 +434,7 @@ def main():
         "batch": batch,
         "gate_sweeps": sweeps,
         "expectation": expect,
+        "multiplier": mult,
     }
     if extra:
         out["variants"] = extra

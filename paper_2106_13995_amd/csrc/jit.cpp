@@ -18,6 +18,7 @@
 #include <memory>
 #include <mutex>
 #include <string>
+#include <vector>
 
 #include "qsim_internal.h"
 
@@ -119,7 +120,9 @@ double gen_pass(Src &o, const Plan &plan, const Pass &p, const char *name) {
     auto pool_at = [&](int rel) { return plan.tile_pool[size_t(p.pool_begin + rel)]; };
     o("extern \"C\" __global__ void __launch_bounds__(256) %s(%s *psi, const %s *Pg) {", name, V, T);
     o("  const QC %s *P = (const QC %s *)Pg;", T, T);
-    o("  extern __shared__ %s lds[];", V);
+    // A static tile: its address is a link-time constant that folds into
+    // the LDS instructions' offsets (a dynamic array costs an add per access).
+    o("  __shared__ %s lds[%d];", V, 1 << p.m);
     o("  const unsigned t = threadIdx.x;");
     o("  unsigned long long base = (unsigned long long)blockIdx.x << %d;", p.L);
     for (int h : p.hpos) o("  base = ((base >> %d) << %d) | (base & 0x%llxull);", h, h + 1, (1ull << h) - 1ull);
@@ -139,24 +142,50 @@ double gen_pass(Src &o, const Plan &plan, const Pass &p, const char *name) {
     for (int si = p.stage_begin; si < p.stage_end; ++si) {
         const RegStage &st = plan.reg_stages[size_t(si)];
         if (si > p.stage_begin) {
+            // The swizzled slot of register i is (thread part) ^ c_i.  Bits of
+            // c_i where the thread part is always zero add instead of mixing,
+            // so they go to the instruction's constant offset; only the
+            // distinct remainders (c_i restricted to the thread part's bits)
+            // cost an address computation each.
             o("  {");
             o("    unsigned aw = 0u, ar_ = 0u;");
+            uint32_t tw = 0, tr = 0;
             for (int b = 0; b < 8; ++b) {
+                tw |= st.wr_t[b];
+                tr |= st.rd_t[b];
                 if (st.wr_t[b]) o("    aw ^= (0u - ((t >> %d) & 1u)) & %uu;", b, st.wr_t[b]);
                 if (st.rd_t[b]) o("    ar_ ^= (0u - ((t >> %d) & 1u)) & %uu;", b, st.rd_t[b]);
             }
-            for (int i = 0; i < NA; ++i) {
-                uint32_t c = 0;
-                for (int b = 0; b < R; ++b)
-                    if ((i >> b) & 1) c ^= st.wr_r[b];
-                o("    lds[aw ^ %uu] = %s{ar%d, ai%d};", c, V, i, i);
+            o("    char *const lb = (char *)lds;");
+            auto slots = [&](const uint32_t *rbits, uint32_t tmask, const char *tv, const char *pre) {
+                std::map<uint32_t, int> mixed;
+                std::vector<std::pair<uint32_t, uint32_t>> at;
+                at.resize(size_t(NA));
+                for (int i = 0; i < NA; ++i) {
+                    uint32_t c = 0;
+                    for (int b = 0; b < R; ++b)
+                        if ((i >> b) & 1) c ^= rbits[b];
+                    at[size_t(i)] = {c & tmask, c & ~tmask};
+                    if (!mixed.count(c & tmask)) {
+                        const int id = int(mixed.size());
+                        mixed[c & tmask] = id;
+                        o("    const unsigned %s%d = (%s ^ %uu) * %du;", pre, id, tv, c & tmask, f ? 8 : 16);
+                    }
+                }
+                return std::make_pair(mixed, at);
+            };
+            {
+                auto [mixed, at] = slots(st.wr_r, tw, "aw", "w");
+                for (int i = 0; i < NA; ++i)
+                    o("    *(%s *)(lb + w%d + %uu) = %s{ar%d, ai%d};", V, mixed[at[size_t(i)].first],
+                      at[size_t(i)].second * (f ? 8u : 16u), V, i, i);
             }
             o("    __syncthreads();");
-            for (int i = 0; i < NA; ++i) {
-                uint32_t c = 0;
-                for (int b = 0; b < R; ++b)
-                    if ((i >> b) & 1) c ^= st.rd_r[b];
-                o("    { const %s w = lds[ar_ ^ %uu]; ar%d = w.x; ai%d = w.y; }", V, c, i, i);
+            {
+                auto [mixed, at] = slots(st.rd_r, tr, "ar_", "r");
+                for (int i = 0; i < NA; ++i)
+                    o("    { const %s w = *(const %s *)(lb + r%d + %uu); ar%d = w.x; ai%d = w.y; }", V, V,
+                      mixed[at[size_t(i)].first], at[size_t(i)].second * (f ? 8u : 16u), i, i);
             }
             o("    __syncthreads();");
             o("  }");
@@ -255,6 +284,44 @@ double gen_pass(Src &o, const Plan &plan, const Pass &p, const char *name) {
                     for (int i = 0; i < NA; ++i) {
                         if ((i & op.rmask) != op.rmask) continue;
                         fl += emit_factor(o, f, i, pool_at(op.moff), (gmask || tmask) ? "on" : nullptr, m2);
+                    }
+                    o("  }");
+                    break;
+                }
+                case 7: {   // 2 x 2 block on bit rb[0] where every control is 1
+                    const int B = op.rb[0], rc = op.rmask;
+                    const uint64_t gmask = uint64_t(uint32_t(op.gp[0])) | (uint64_t(uint32_t(op.gp[1])) << 32);
+                    const uint32_t tmask = uint32_t(op.tb[0]);
+                    const bool cond = gmask || tmask;
+                    const cd u[4] = {pool_at(op.moff), pool_at(op.moff + 1), pool_at(op.moff + 2),
+                                     pool_at(op.moff + 3)};
+                    // an exchange (X under controls: CX, CCX) moves values only
+                    const bool perm = u[0] == cd(0.0) && u[3] == cd(0.0) && u[1] == cd(1.0) && u[2] == cd(1.0);
+                    o("  {");
+                    if (cond)
+                        o("    const bool on = ((base & 0x%llxull) == 0x%llxull) && ((t & %uu) == %uu);",
+                          (unsigned long long)gmask, (unsigned long long)gmask, tmask, tmask);
+                    for (int g = 0; g < NA; ++g) {
+                        if ((g & (1 << B)) || (g & rc) != rc) continue;
+                        const int h = g | (1 << B);
+                        o("    { const %s x0r = ar%d, x0i = ai%d, x1r = ar%d, x1i = ai%d;", T, g, g, h, h);
+                        if (perm) {
+                            o("      const %s y0r = x1r, y0i = x1i, y1r = x0r, y1i = x0i;", T);
+                        } else {
+                            fl += 32.0;
+                            for (int rr = 0; rr < 2; ++rr) {
+                                const int e0 = m2 + 4 * rr, e1 = e0 + 2;
+                                o("      const %s y%dr = %s(P[%d], x0r, %s(-P[%d], x0i, %s(P[%d], x1r, -P[%d] * x1i)));", T,
+                                  rr, FMA, e0, FMA, e0 + 1, FMA, e1, e1 + 1);
+                                o("      const %s y%di = %s(P[%d], x0i, %s(P[%d], x0r, %s(P[%d], x1i, P[%d] * x1r)));", T,
+                                  rr, FMA, e0, FMA, e0 + 1, FMA, e1, e1 + 1);
+                            }
+                        }
+                        if (cond)
+                            o("      ar%d = on ? y0r : x0r; ai%d = on ? y0i : x0i; ar%d = on ? y1r : x1r; ai%d = on ? y1i : "
+                              "x1i; }", g, g, h, h);
+                        else
+                            o("      ar%d = y0r; ai%d = y0i; ar%d = y1r; ai%d = y1i; }", g, g, h, h);
                     }
                     o("  }");
                     break;
@@ -412,9 +479,9 @@ hipError_t launch_jit_pass(qsim_state s, const Plan &plan, const Pass &p, hipFun
     const char *pool = static_cast<const char *>(plan.dev) + plan.pool_dev_off + size_t(p.pool_begin) * amp;
     const void *pool_arg = pool;
     void *args[] = {&psi, &pool_arg};
-    const size_t lds = amp << p.m;
     const uint64_t ntiles = 1ull << (s->n - p.m);
-    return hipModuleLaunchKernel(fn, unsigned(ntiles), 1, 1, 256, 1, 1, unsigned(lds), s->stream, args, nullptr);
+    // the tile is a static LDS array of the kernel (at most 64 KiB)
+    return hipModuleLaunchKernel(fn, unsigned(ntiles), 1, 1, 256, 1, 1, 0u, s->stream, args, nullptr);
 }
 
 }  // namespace qsim

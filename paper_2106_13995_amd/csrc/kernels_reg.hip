@@ -254,20 +254,50 @@ __device__ __forceinline__ void apply_diag(T *vr, T *vi, CRegOp &op, CT<T> *Dg, 
 // Op codes (host side: op_code): dense on register mask m < 32 -> m; lifting
 // rotation on bit b -> 64 + b; signed exchange on bit b -> 72 + b; factor on
 // the all-ones amplitudes of register mask m -> 128 + m; phase table -> 200;
-// any other diagonal -> 201.  One flat compare chain on the uniform code, one
-// join: the amplitude registers keep a single home across ops.
+// any other diagonal -> 201; 2 x 2 block on bit b under controls -> 210 + b.
+// One flat compare chain on the uniform code, one join: the amplitude
+// registers keep a single home across ops.
 template <int C, int R>
 __host__ __device__ constexpr bool code_valid() {
     if (C < 32) return C > 0 && C < (1 << R) && popcount_c(C) <= 3;
     if (C >= 64 && C < 72) return C - 64 < R;
     if (C >= 72 && C < 80) return C - 72 < R;
     if (C >= 128 && C < 160) return C - 128 < (1 << R);
+    if (C >= 210 && C < 218) return C - 210 < R;
     return C == 200 || C == 201;
+}
+
+// 2 x 2 block U on register bit B, applied to the pairs whose register
+// control bits (rmask) are 1, in lanes and blocks whose thread and
+// out-of-tile control bits are 1; elsewhere the pair is kept as it is
+// (a select, so the amplitudes stay in place).
+template <typename T, int R, int B>
+__device__ __forceinline__ void controlled_bit(T *vr, T *vi, CRegOp &op, CT<T> *U, uint64_t base, uint32_t t) {
+    const uint64_t gmask = uint64_t(uint32_t(op.gp[0])) | (uint64_t(uint32_t(op.gp[1])) << 32);
+    const uint32_t tm = uint32_t(op.tb[0]);
+    const bool on = ((base & gmask) == gmask) && ((t & tm) == tm);
+    const int rc = op.rmask;
+    const T u0r = U[0], u0i = U[1], u1r = U[2], u1i = U[3], u2r = U[4], u2i = U[5], u3r = U[6], u3i = U[7];
+#pragma unroll
+    for (int g = 0; g < (1 << R); ++g) {
+        if (g & (1 << B)) continue;
+        const int h = g | (1 << B);
+        const bool act = on && ((g & rc) == rc);
+        const T x0r = vr[g], x0i = vi[g], x1r = vr[h], x1i = vi[h];
+        const T y0r = u0r * x0r - u0i * x0i + u1r * x1r - u1i * x1i;
+        const T y0i = u0r * x0i + u0i * x0r + u1r * x1i + u1i * x1r;
+        const T y1r = u2r * x0r - u2i * x0i + u3r * x1r - u3i * x1i;
+        const T y1i = u2r * x0i + u2i * x0r + u3r * x1i + u3i * x1r;
+        vr[g] = act ? y0r : x0r;
+        vi[g] = act ? y0i : x0i;
+        vr[h] = act ? y1r : x1r;
+        vi[h] = act ? y1i : x1i;
+    }
 }
 
 template <typename T, int R, int C>
 __device__ __forceinline__ void run_op(int code, T *vr, T *vi, CRegOp &op, CT<T> *U, uint64_t base, uint32_t t) {
-    if constexpr (C <= 201) {
+    if constexpr (C <= 217) {
         if constexpr (code_valid<C, R>()) {
             if (code == C) {
                 if constexpr (C < 32) {
@@ -292,8 +322,10 @@ __device__ __forceinline__ void run_op(int code, T *vr, T *vi, CRegOp &op, CT<T>
                     }
                 } else if constexpr (C == 200) {
                     apply_table<T, R>(vr, vi, U);
-                } else {
+                } else if constexpr (C == 201) {
                     apply_diag<T, R>(vr, vi, op, U, base, t);
+                } else {
+                    controlled_bit<T, R, C - 210>(vr, vi, op, U, base, t);
                 }
                 return;
             }

@@ -165,8 +165,10 @@ struct TileBuilder {
     }
 
     // Adds a tile pass over qubit set `q` (must contain the low L qubits)
-    // holding the given gates, in order.
-    void emit(uint64_t q, const std::vector<const HostGate *> &gs) {
+    // holding the given gates, in order.  With `need_reg` the pass must run
+    // as a register program (it holds controlled gates whose controls lie
+    // outside the tile); if it cannot, nothing is added and false returned.
+    bool emit(uint64_t q, const std::vector<const HostGate *> &gs, bool need_reg = false) {
         Pass p;
         p.kind = PASS_TILE;
         p.m = m;
@@ -196,6 +198,19 @@ struct TileBuilder {
                     continue;
                 }
                 const int d = 1 << g->k;
+                if (regform && !is_diagonal(*g) && g->k > 1) {
+                    HostGate red;
+                    int ctl[QSIM_MAX_K];
+                    const int nc = extract_controls(*g, red, ctl);
+                    if (red.k == 1) {
+                        // a controlled one-qubit block: a complex 2 x 2 product
+                        // where the controls are 1, nothing for a permutation
+                        const bool perm = red.M[0] == cd(0.0) && red.M[3] == cd(0.0) &&
+                                          red.M[1] == cd(1.0) && red.M[2] == cd(1.0);
+                        if (!perm) f += 16.0 * std::ldexp(1.0, n - nc);
+                        continue;
+                    }
+                }
                 if (g->rot_real && regform) {
                     // three multiply-adds per component and pair; the input
                     // phase multiplies half the amplitudes
@@ -218,13 +233,14 @@ struct TileBuilder {
                 p.op_end = p.op_begin;
                 p.flops = pass_flops(true);
                 plan.passes.push_back(std::move(p));
-                return;
+                return true;
             }
             plan.reg_ops.resize(nrop);
             plan.reg_stages.resize(nst);
             plan.tile_pool.resize(npool);
             p.reg_r = 0;
         }
+        if (need_reg) return false;
         p.flops = pass_flops(false);
         for (const HostGate *g : gs) {
             TileOp op{};
@@ -280,45 +296,79 @@ struct TileBuilder {
         p.op_end = int(plan.tile_ops.size());
         p.pool_end = int(plan.tile_pool.size());
         plan.passes.push_back(std::move(p));
+        return true;
     }
 };
 
 // Greedy grouping of ops into tile passes in dependency order: an op joins
-// the pass if its qubits fit the tile (diagonal ops always fit); an op that
-// does not fit blocks its qubits for the rest of the pass.
+// the pass if the qubits it needs in the tile fit (diagonal ops always fit);
+// an op that does not fit blocks its qubits for the rest of the pass.  When
+// the pass runs as a register program, a one-qubit block under exact
+// controls needs only its target in the tile (its controls become lane and
+// block masks); a pass that then fails to become a register program is
+// grouped again with every qubit of such ops in the tile.
 // At most this many ops per pass, so that a pass's op list and matrices stay
 // well inside the LDS next to its tile(s).
 static const size_t kMaxOpsPerPass = 128;
 
 static void group_tiles(TileBuilder &tb, const std::vector<HostGate> &gates) {
     const uint64_t low = (1ull << tb.L) - 1;
-    std::vector<char> done(gates.size(), 0);
-    size_t remaining = gates.size();
+    const int r = tb.m - 8;
+    const bool reg_ctl = tb.reg && r >= 3 && r <= kRegBitsMax;
+    const size_t ng = gates.size();
+    std::vector<uint64_t> full(ng), target(ng);
+    std::vector<char> diag(ng), wide(ng);
+    for (size_t i = 0; i < ng; ++i) {
+        const HostGate &g = gates[i];
+        full[i] = target[i] = qmask(g);
+        diag[i] = is_diagonal(g);
+        if (!diag[i] && reg_ctl && g.k > 1) {
+            HostGate red;
+            int ctl[QSIM_MAX_K];
+            extract_controls(g, red, ctl);
+            if (red.k == 1) target[i] = 1ull << red.targets[0];
+        }
+        // dense on more than three qubits: no register program holds it
+        wide[i] = !diag[i] && target[i] == full[i] && g.k > 3;
+    }
+    std::vector<char> done(ng, 0);
+    size_t remaining = ng;
     size_t first = 0;
     while (remaining) {
         while (done[first]) ++first;
-        uint64_t q = low;
-        uint64_t blocked = 0;
-        std::vector<const HostGate *> chosen;
-        for (size_t i = first; i < gates.size() && chosen.size() < kMaxOpsPerPass; ++i) {
-            if (done[i]) continue;
-            const HostGate &g = gates[i];
-            const uint64_t gm = qmask(g);
-            if (gm & blocked) {
-                blocked |= gm;
-                continue;
+        bool placed = false;
+        for (int attempt = 0; attempt < 2 && !placed; ++attempt) {
+            const bool relax = reg_ctl && attempt == 0;
+            uint64_t q = low;
+            uint64_t blocked = 0;
+            bool any_relaxed = false, any_wide = false;
+            std::vector<size_t> idx;
+            for (size_t i = first; i < ng && idx.size() < kMaxOpsPerPass; ++i) {
+                if (done[i]) continue;
+                const uint64_t gm = full[i];
+                if ((gm & blocked) || (wide[i] && any_relaxed)) {
+                    blocked |= gm;
+                    continue;
+                }
+                const uint64_t need = diag[i] ? 0 : (relax && !any_wide ? target[i] : gm);
+                if (diag[i] || __builtin_popcountll(q | need) <= tb.m) {
+                    q |= need;
+                    idx.push_back(i);
+                    any_relaxed |= !diag[i] && need != gm;
+                    any_wide |= bool(wide[i]);
+                } else {
+                    blocked |= gm;
+                }
             }
-            if (is_diagonal(g) || __builtin_popcountll(q | gm) <= tb.m) {
-                if (!is_diagonal(g)) q |= gm;
-                chosen.push_back(&g);
-                done[i] = 1;
-                --remaining;
-            } else {
-                blocked |= gm;
-            }
+            if (idx.empty()) return;   // cannot happen: k <= 6 < m - L
+            std::vector<const HostGate *> chosen;
+            for (size_t i : idx) chosen.push_back(&gates[i]);
+            if (!tb.emit(q, chosen, any_relaxed)) continue;
+            for (size_t i : idx) done[i] = 1;
+            remaining -= idx.size();
+            placed = true;
         }
-        if (chosen.empty()) break;   // cannot happen: k <= 6 < m - L
-        tb.emit(q, chosen);
+        if (!placed) return;
     }
 }
 

@@ -13,8 +13,14 @@ namespace {
 struct LocalGate {
     const HostGate *g;      // targets ascending (sorted_targets form)
     bool diag;
-    uint32_t lmask;         // tile-local positions of in-tile targets
+    uint32_t lmask;         // tile-local positions the stage must hold in registers
     uint64_t qmask;         // global qubits
+    // a one-qubit gate under exact controls (CX, CCX, ...): `red` is the 2 x 2
+    // block it applies where every control is 1; only its target needs a
+    // register bit, the controls may sit anywhere
+    const HostGate *red = nullptr;
+    int nctl = 0;
+    int ctl[QSIM_MAX_K] = {};
 };
 
 int popc(uint64_t v) { return __builtin_popcountll(v); }
@@ -66,6 +72,12 @@ void make_exchange(int m, int wb, uint32_t Rw, uint32_t Rr, RegStage &st, uint64
     split_layout(Rw, m, Rwp, Twp);
     split_layout(Rr, m, Rrp, Trp);
     const int r = popc(Rw);
+    // Only positions that are among the low lane bits of either layout
+    // decide bank conflicts.  Every other position keeps its plain bit, so
+    // the register parts of the addresses mostly stay clear of the bits the
+    // thread part can set and the kernel adds them as constant offsets.
+    uint32_t lanes = 0;
+    for (int b = 0; b < wb; ++b) lanes |= (1u << Twp[b]) | (1u << Trp[b]);
     uint32_t best[16] = {};
     int best_score = -1;
     uint64_t x = seed * 0x9E3779B97F4A7C15ull + 1;
@@ -73,7 +85,7 @@ void make_exchange(int m, int wb, uint32_t Rw, uint32_t Rr, RegStage &st, uint64
         uint32_t addr[16];
         for (int p = 0; p < m; ++p) {
             uint32_t sw = 0;
-            if (p >= wb && attempt > 0) {
+            if (p >= wb && attempt > 0 && ((lanes >> p) & 1u)) {
                 x ^= x << 13; x ^= x >> 7; x ^= x << 17;
                 sw = uint32_t(x) & ((1u << wb) - 1u);
             }
@@ -140,8 +152,9 @@ bool build_reg_program(Plan &plan, Pass &p, uint64_t q, const int *local_of,
     const int wb = plan.dtype == QSIM_C128 ? 4 : 5;
     const int nlow = std::min(6, m - r);   // lane positions that should stay on thread bits for HBM access
 
-    std::vector<HostGate> sorted;
+    std::vector<HostGate> sorted, reduced;
     sorted.reserve(gates.size());
+    reduced.reserve(gates.size());
     std::vector<LocalGate> gs;
     for (const HostGate *g : gates) sorted.push_back(sorted_targets(*g));
     for (const HostGate &s : sorted) {
@@ -150,7 +163,19 @@ bool build_reg_program(Plan &plan, Pass &p, uint64_t q, const int *local_of,
             lg.qmask |= 1ull << s.targets[b];
             if ((q >> s.targets[b]) & 1) lg.lmask |= 1u << local_of[s.targets[b]];
         }
-        if (!lg.diag && s.k > 3) return false;
+        if (!lg.diag && s.k > 1) {
+            HostGate red;
+            const int nc = extract_controls(s, red, lg.ctl);
+            if (red.k == 1) {
+                if (!((q >> red.targets[0]) & 1)) return false;
+                reduced.push_back(std::move(red));
+                lg.red = &reduced.back();
+                lg.nctl = nc;
+                lg.lmask = 1u << local_of[lg.red->targets[0]];
+            }
+        }
+        if (!lg.diag && !lg.red && s.k > 3) return false;
+        if (!lg.diag && !lg.red && (lg.qmask & ~q)) return false;   // every target must be in the tile
         gs.push_back(lg);
     }
     const uint32_t lowmask = (1u << nlow) - 1u;
@@ -229,6 +254,7 @@ bool build_reg_program(Plan &plan, Pass &p, uint64_t q, const int *local_of,
             const LocalGate &lg = gs[size_t(gi)];
             uint32_t mk = 0;
             if (lg.diag) return mk;
+            if (lg.red) return 1u << index_in(Rp, r, local_of[lg.red->targets[0]]);
             for (int b = 0; b < lg.g->k; ++b) mk |= 1u << index_in(Rp, r, local_of[lg.g->targets[b]]);
             return mk;
         };
@@ -304,6 +330,37 @@ bool build_reg_program(Plan &plan, Pass &p, uint64_t q, const int *local_of,
                 continue;
             }
             (void)pos;
+            if (lg.red) {
+                // controlled one-qubit block: target on a register bit,
+                // controls as register, thread and out-of-tile masks
+                RegOp op{};
+                op.type = 7;
+                op.k = 1;
+                op.rb[0] = index_in(Rp, r, local_of[lg.red->targets[0]]);
+                op.moff = pool_off();
+                plan.tile_pool.insert(plan.tile_pool.end(), lg.red->M.begin(), lg.red->M.end());
+                uint32_t tmask = 0;
+                uint64_t gmask = 0;
+                for (int c = 0; c < lg.nctl; ++c) {
+                    const int qc = lg.ctl[c];
+                    if ((q >> qc) & 1) {
+                        const int lp = local_of[qc];
+                        const int ri = index_in(Rp, r, lp);
+                        if (ri >= 0)
+                            op.rmask |= 1 << ri;
+                        else
+                            tmask |= 1u << index_in(Tp, 8, lp);
+                    } else {
+                        gmask |= 1ull << qc;
+                    }
+                }
+                op.tb[0] = int32_t(tmask);
+                op.gp[0] = int32_t(uint32_t(gmask));
+                op.gp[1] = int32_t(uint32_t(gmask >> 32));
+                touched |= 1u << op.rb[0];
+                sops.push_back(op);
+                continue;
+            }
             RegOp op{};
             op.k = s.k;
             op.moff = int(plan.tile_pool.size()) - p.pool_begin;
@@ -385,6 +442,7 @@ bool build_reg_program(Plan &plan, Pass &p, uint64_t q, const int *local_of,
             case 5: op.code = 72 + op.rb[0]; break;
             case 6: op.code = 128 + op.rmask; break;
             case 4: op.code = 200; break;
+            case 7: op.code = 210 + op.rb[0]; break;
             default: op.code = 201; break;
         }
     }

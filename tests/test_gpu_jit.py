@@ -78,6 +78,23 @@ def test_random_mixed_circuit(qs, dtype, mode):
 
 
 @pytest.mark.parametrize("dtype", ["c64", "c128"])
+@pytest.mark.parametrize("mode", ["tile", "tile12", "fuse2_tile"])
+def test_controlled_blocks(qs, dtype, mode):
+    """CX, CCX and random 2 x 2 blocks under one or two controls, whose
+    controls the compiled passes take as register, lane and block masks."""
+    from test_gpu_parity import controlled_circuit
+    n = 14
+    rng = np.random.default_rng(211)
+    circ = controlled_circuit(n, 160, rng)
+    psi0 = _rounded(W.random_state(n, rng), dtype)
+    s = _state(qs, n, dtype, psi0)
+    s.profile(True)
+    s.apply_circuit(circ, **MODES[mode])
+    assert s.profile_read("tile_jit")[0] > 0
+    assert O.rel_l2(s.to_numpy(), O.apply_circuit(circ, psi0)) <= TOL[dtype]
+
+
+@pytest.mark.parametrize("dtype", ["c64", "c128"])
 @pytest.mark.parametrize("mode", ["tile", "tile12", "tile_complex"])
 def test_grid_circuit_16q(qs, dtype, mode):
     circ = W.random_grid_circuit(4, 4, depth=12, seed=2)

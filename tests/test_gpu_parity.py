@@ -142,6 +142,46 @@ def test_random_mixed_circuit(qs, dtype, mode):
     assert O.rel_l2(s.to_numpy(), ref) <= TOL[dtype]
 
 
+def controlled_circuit(n, nops, rng):
+    """U3 gates, CX / CCX, and dense matrices that are a random 2 x 2 block
+    under one or two controls (identity elsewhere), on random qubits: in a
+    12-qubit tile of a 14-qubit state the controls land on register, thread
+    and out-of-tile bits."""
+    ops = []
+    for _ in range(nops):
+        kind = rng.integers(4)
+        if kind == 0:
+            ops.append(W.op("u3", int(rng.integers(n)), angles=rng.uniform(0, 2 * np.pi, 3)))
+        elif kind == 1:
+            a, b = rng.choice(n, 2, replace=False)
+            ops.append(W.op("cx", int(a), int(b)))
+        elif kind == 2:
+            a, b, c = rng.choice(n, 3, replace=False)
+            ops.append(W.op("ccx", int(a), int(b), int(c)))
+        else:
+            nc = int(rng.integers(1, 3))
+            qs_ = [int(x) for x in rng.choice(n, nc + 1, replace=False)]
+            d = 1 << (nc + 1)
+            M = np.eye(d, dtype=np.complex128)
+            M[d - 2:, d - 2:] = W.random_unitary(1, rng)
+            # target = qs_[0] is matrix bit 0; every control bit is 1 on the last two rows
+            ops.append(W.matrix_op(qs_, M))
+    return W.Circuit(n, ops)
+
+
+@pytest.mark.parametrize("dtype", ["c64", "c128"])
+@pytest.mark.parametrize("mode", ["sweep", "tile", "tile12_split", "fuse2_tile", "fuse5_tile"])
+def test_controlled_blocks(qs, dtype, mode):
+    n = 14
+    rng = np.random.default_rng(111)
+    circ = controlled_circuit(n, 160, rng)
+    psi0 = _rounded(W.random_state(n, rng), dtype)
+    ref = O.apply_circuit(circ, psi0)
+    s = _state(qs, n, dtype, psi0)
+    s.apply_circuit(circ, **MODES[mode])
+    assert O.rel_l2(s.to_numpy(), ref) <= TOL[dtype]
+
+
 @pytest.mark.parametrize("dtype", ["c64", "c128"])
 @pytest.mark.parametrize("mode", ["sweep", "tile", "fuse4", "fuse5_tile"])
 def test_grid_circuit_16q(qs, dtype, mode):
