@@ -277,14 +277,22 @@ double gen_pass(Src &o, const Plan &plan, const Pass &p, const char *name) {
                 case 6: {   // factor on the all-ones amplitudes of the op's bits
                     const uint64_t gmask = uint64_t(uint32_t(op.gp[0])) | (uint64_t(uint32_t(op.gp[1])) << 32);
                     const uint32_t tmask = uint32_t(op.tb[0]);
+                    // A condition on out-of-tile bits only holds for whole
+                    // blocks: a uniform branch, taken by the blocks it holds
+                    // in, in place of a select on every lane of every block.
+                    const bool lane_cond = tmask != 0, block_cond = gmask && !tmask;
                     o("  {");
-                    if (gmask || tmask)
+                    if (lane_cond)
                         o("    const bool on = ((base & 0x%llxull) == 0x%llxull) && ((t & %uu) == %uu);",
                           (unsigned long long)gmask, (unsigned long long)gmask, tmask, tmask);
+                    if (block_cond)
+                        o("    if ((base & 0x%llxull) == 0x%llxull) {", (unsigned long long)gmask,
+                          (unsigned long long)gmask);
                     for (int i = 0; i < NA; ++i) {
                         if ((i & op.rmask) != op.rmask) continue;
-                        fl += emit_factor(o, f, i, pool_at(op.moff), (gmask || tmask) ? "on" : nullptr, m2);
+                        fl += emit_factor(o, f, i, pool_at(op.moff), lane_cond ? "on" : nullptr, m2);
                     }
+                    if (block_cond) o("    }");
                     o("  }");
                     break;
                 }
@@ -292,7 +300,8 @@ double gen_pass(Src &o, const Plan &plan, const Pass &p, const char *name) {
                     const int B = op.rb[0], rc = op.rmask;
                     const uint64_t gmask = uint64_t(uint32_t(op.gp[0])) | (uint64_t(uint32_t(op.gp[1])) << 32);
                     const uint32_t tmask = uint32_t(op.tb[0]);
-                    const bool cond = gmask || tmask;
+                    // lane conditions select; block conditions branch (as for type 6)
+                    const bool cond = tmask != 0, block_cond = gmask && !tmask;
                     const cd u[4] = {pool_at(op.moff), pool_at(op.moff + 1), pool_at(op.moff + 2),
                                      pool_at(op.moff + 3)};
                     // an exchange (X under controls: CX, CCX) moves values only
@@ -301,6 +310,9 @@ double gen_pass(Src &o, const Plan &plan, const Pass &p, const char *name) {
                     if (cond)
                         o("    const bool on = ((base & 0x%llxull) == 0x%llxull) && ((t & %uu) == %uu);",
                           (unsigned long long)gmask, (unsigned long long)gmask, tmask, tmask);
+                    if (block_cond)
+                        o("    if ((base & 0x%llxull) == 0x%llxull) {", (unsigned long long)gmask,
+                          (unsigned long long)gmask);
                     for (int g = 0; g < NA; ++g) {
                         if ((g & (1 << B)) || (g & rc) != rc) continue;
                         const int h = g | (1 << B);
@@ -323,6 +335,7 @@ double gen_pass(Src &o, const Plan &plan, const Pass &p, const char *name) {
                         else
                             o("      ar%d = y0r; ai%d = y0i; ar%d = y1r; ai%d = y1i; }", g, g, h, h);
                     }
+                    if (block_cond) o("    }");
                     o("  }");
                     break;
                 }
