@@ -8,6 +8,7 @@ which stays resident in HBM.  Prints one JSON line.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--fuse-k F] [--tile-m M]
     python bench.py --calib-copy      # plain 8 GiB device copy (counter calibration)
+    python bench.py --width-sweep     # both circuit families, 13 to 30 qubits
 """
 from __future__ import annotations
 
@@ -56,6 +57,8 @@ def parse():
     ap.add_argument("--no-multiplier", action="store_true", help="skip the 29-qubit multiplier figure")
     ap.add_argument("--no-sweeps", action="store_true", help="skip the single-gate sweep figures")
     ap.add_argument("--no-tune", action="store_true", help="skip autotuning during warm-up")
+    ap.add_argument("--width-sweep", action="store_true",
+                    help="time both circuit families at every width from 13 to --n qubits and print that line instead")
     return ap.parse_args()
 
 
@@ -144,19 +147,21 @@ def time_mode(torch, s, circ, steps, warmup, fuse_k, tile_m, split_1q=0):
 def adjoint_bench(torch, q, W, dtype: str, reps: int = 5, shift_sample: int = 16):
     """Energy + full gradient of the 20-qubit, 10-layer RY.RZ + CNOT-ladder
     ansatz (400 parameters) with sum Z_iZ_{i+1} + 0.5 sum X_i, by the adjoint
-    method, against the parameter-shift rule on the same GPU (two forward
-    runs and expectations per parameter; timed on a sample, scaled to 400)."""
+    method with fresh parameters every call, against the parameter-shift rule
+    on the same GPU (two forward runs and expectations per parameter; timed
+    on a sample, scaled to 400)."""
     n, layers = 20, 10
     circ = W.ansatz_circuit(n, layers)
     p = W.ansatz_params(n, layers, seed=4)
     H = W.chain_observable(n)
     s = q.State(n, dtype)
-    s.adjoint_grad(circ, p, H)
+    e, g = s.adjoint_grad(circ, p, H)
     torch.cuda.synchronize()
+    # new parameters on every call, as in a training loop (no plan is reused)
     t0 = time.perf_counter()
-    for _ in range(reps):
+    for r in range(reps):
         s.set_basis(0)
-        e, g = s.adjoint_grad(circ, p, H)
+        s.adjoint_grad(circ, p + 1e-3 * (r + 1), H)
     torch.cuda.synchronize()
     adj = (time.perf_counter() - t0) / reps
     # parameter shift, same GPU, same options
@@ -276,6 +281,9 @@ def multiplier_bench(torch, q, W, reps: int = 5):
                  for o in circ.ops)
     dense = len(circ.ops) * 2 * N * amp
     s = q.State(n, "c64")
+    # warm-up: the autotuner picks tile size and fusion width for this circuit
+    best, _ = s.autotune(circ, reps=1)
+    s.set_basis(0)
     s.apply_circuit(circ)
     torch.cuda.synchronize()
     ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -296,11 +304,63 @@ def multiplier_bench(torch, q, W, reps: int = 5):
     s.close()
     return {"workload": f"{n}-qubit multiplier, b = {b}, a in uniform superposition, {len(circ.ops)} gates "
                         f"(H, X, CX, CCX), complex64",
-            "ms": round(ev0.elapsed_time(ev1) / reps, 3), "kernel_ms": round(kms, 3),
+            "options": best, "ms": round(ev0.elapsed_time(ev1) / reps, 3), "kernel_ms": round(kms, 3),
             "gates_per_s": round(len(circ.ops) / (kms / 1e3), 1), "passes": stats,
             "bytes_per_gate_model": sparse, "bytes_dense_model": dense,
             "gbs_per_gate_model": round(sparse / (kms / 1e3) / 1e9, 1),
             "gbs_dense_model": round(dense / (kms / 1e3) / 1e9, 1)}
+
+
+def width_sweep(torch, q, W, lo: int = 13, hi: int = 30, dtype: str = "c64"):
+    """The paper's qubit-by-qubit scaling runs (§II, Figs. 1-4) on this GPU:
+    supremacy-style and multiplier circuits at every width from `lo` to `hi`
+    (intermediate widths by random qubit removal), equal-superposition input.
+    Per width: kernel time of one circuit (HIP events), and the time through
+    Python as a user sees it (state allocation, the circuit, the state vector
+    copied back to host memory, release), averaged over the paper's 10 runs
+    (3 from 26 qubits up).  Plans and compiled passes are built by an untimed
+    first run."""
+    out = {}
+    for family in ("supremacy", "multiplier"):
+        rows = []
+        for n in range(lo, hi + 1):
+            circ = W.width_circuit(family, n)
+            reps = 10 if n < 26 else 3
+            s = q.State(n, dtype)
+            s.apply_circuit(circ)
+            torch.cuda.synchronize()
+            ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            s.profile(True)
+            ev0.record()
+            for _ in range(reps):
+                s.apply_circuit(circ)
+            ev1.record()
+            torch.cuda.synchronize()
+            gpu_ms = ev0.elapsed_time(ev1) / reps
+            passes = {}
+            for cls in ("sweep_dense", "sweep_diag", "tile", "tile_jit", "mfma"):
+                c = s.profile_read(cls)[0]
+                if c:
+                    passes[cls] = c // reps
+            s.close()
+            t0 = time.perf_counter()
+            for _ in range(reps):
+                s = q.State(n, dtype)
+                s.apply_circuit(circ)
+                psi = s.to_numpy()
+                s.close()
+            e2e_ms = (time.perf_counter() - t0) / reps * 1e3
+            del psi
+            rows.append({"n": n, "gates": len(circ.ops), "gpu_ms": round(gpu_ms, 3), "e2e_ms": round(e2e_ms, 2),
+                         "gate_apps_per_s": round(len(circ.ops) / (gpu_ms / 1e3), 1), "passes": passes})
+            print(json.dumps({"progress": family, **rows[-1]}), file=sys.stderr, flush=True)
+        out[family] = rows
+    return {"metric": "width sweep: circuit time by width (kernel, and end to end through Python)",
+            "dtype": "complex64" if dtype == "c64" else "complex128", "data": "synthetic",
+            "config": {"workload": f"supremacy-style grid circuits (depth 20) and shift-and-add multipliers, "
+                                   f"{lo}-{hi} qubits, random qubit removal between standard sizes, "
+                                   f"H on every qubit first"},
+            "results": out}
 
 
 def calib_copy(torch, n: int, dtype: str):
@@ -330,6 +390,9 @@ def main():
         return
     import paper_2106_13995_amd as q
     import workloads as W
+    if a.width_sweep:
+        print(json.dumps(width_sweep(torch, q, W, hi=a.n, dtype=a.dtype)))
+        return
 
     rows = 5
     cols = a.n // rows

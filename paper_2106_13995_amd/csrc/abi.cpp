@@ -146,17 +146,16 @@ static qsim_status upload_plan(qsim_state s, Plan &plan) {
         plan.uploaded = true;
         return QSIM_OK;
     }
-    if (hipMalloc(&plan.dev, total) != hipSuccess) {
+    if (hipMallocAsync(&plan.dev, total, s->stream) != hipSuccess) {
         (void)hipGetLastError();
         plan.dev = nullptr;
         return set_error(QSIM_ERR_OOM, "cannot allocate device memory for the plan");
     }
-    if (hipHostMalloc(&plan.host_pinned, total, hipHostMallocDefault) != hipSuccess) {
-        (void)hipGetLastError();
-        plan.host_pinned = nullptr;
-        return set_error(QSIM_ERR_OOM, "cannot allocate pinned memory for the plan");
-    }
-    char *h = static_cast<char *>(plan.host_pinned);
+    plan.dev_stream = s->stream;
+    // staged through the state's pinned buffer, copied in stream order
+    qsim_status st = ensure_pinned(s, total);
+    if (st != QSIM_OK) return st;
+    char *h = static_cast<char *>(s->pinned);
     if (ops_bytes) std::memcpy(h, plan.tile_ops.data(), ops_bytes);
     if (st_bytes) std::memcpy(h + plan.reg_stages_dev_off, plan.reg_stages.data(), st_bytes);
     if (rop_bytes) std::memcpy(h + plan.reg_ops_dev_off, plan.reg_ops.data(), rop_bytes);
@@ -169,8 +168,8 @@ static qsim_status upload_plan(qsim_state s, Plan &plan) {
         if (!plan.real_pool.empty())
             std::memcpy(h + plan.real_pool_dev_off, plan.real_pool.data(), sizeof(double) * plan.real_pool.size());
     }
-    QSIM_HIP(s, hipMemcpyAsync(plan.dev, plan.host_pinned, total, hipMemcpyHostToDevice, s->stream),
-             "hipMemcpyAsync(plan)");
+    st = upload_staged(s, plan.dev, total);
+    if (st != QSIM_OK) return st;
     plan.dev_bytes = total;
     plan.uploaded = true;
     return QSIM_OK;
@@ -344,10 +343,8 @@ static qsim_status get_plan(qsim_state s, const qsim_circuit *c, const double *p
         }
     }
     if (!cache) {
-        // one transient plan per state; its device buffer may still be read
-        // by queued kernels, so wait before replacing one that has it
-        if (s->transient && s->transient->dev)
-            QSIM_HIP(s, hipStreamSynchronize(s->stream), "hipStreamSynchronize");
+        // one transient plan per state; the one it replaces releases its
+        // device buffer in stream order, after the kernels that read it
         s->transient = std::move(plan);
         *out = s->transient.get();
         return QSIM_OK;
@@ -355,8 +352,7 @@ static qsim_status get_plan(qsim_state s, const qsim_circuit *c, const double *p
     if (s->plans.size() >= kMaxCachedPlans) {
         auto lru = std::min_element(s->plans.begin(), s->plans.end(),
                                     [](const CachedPlan &a, const CachedPlan &b) { return a.last_use < b.last_use; });
-        QSIM_HIP(s, hipStreamSynchronize(s->stream), "hipStreamSynchronize");
-        s->plans.erase(lru);
+        s->plans.erase(lru);   // released in stream order
     }
     CachedPlan cp;
     cp.key = std::move(key);
@@ -449,9 +445,12 @@ qsim_status qsim_free(qsim_state s) {
 qsim_status qsim_set_stream(qsim_state s, void *hip_stream) {
     qsim_status st = check_state(s);
     if (st != QSIM_OK) return st;
-    // order the new stream after everything queued so far on the old one
+    // order the new stream after everything queued so far on the old one;
+    // plans now release their buffers on the new stream
     QSIM_HIP(s, hipStreamSynchronize(s->stream), "hipStreamSynchronize");
     s->stream = static_cast<hipStream_t>(hip_stream);
+    for (auto &cp : s->plans) cp.plan->dev_stream = s->stream;
+    if (s->transient) s->transient->dev_stream = s->stream;
     return QSIM_OK;
 }
 

@@ -40,8 +40,7 @@ PlanOptions resolve_options(const qsim_options *o, int n, int dtype) {
 }
 
 Plan::~Plan() {
-    if (dev) (void)hipFree(dev);
-    if (host_pinned) (void)hipHostFree(host_pinned);
+    if (dev) (void)hipFreeAsync(dev, dev_stream);
 }
 
 // ------------------------------------------------------------ fusion

@@ -181,10 +181,14 @@ struct Plan {
     std::vector<double> real_pool;    // real-embedded block matrices of MFMA passes
     size_t real_pool_dev_off = 0;
     // device copies (tile ops + pool rounded to the state precision)
+    // `dev` comes from the stream-ordered allocator on `dev_stream` (the
+    // owning state's stream; the state updates it when its stream changes) and
+    // is released on that stream, behind every kernel queued there that reads
+    // it, so dropping a plan never waits for the device
     void *dev = nullptr;
+    hipStream_t dev_stream = nullptr;
     size_t dev_bytes = 0;
     size_t pool_dev_off = 0;          // byte offset of the pool inside dev
-    void *host_pinned = nullptr;
     bool uploaded = false;
     // run-time compiled kernels of register-staged passes (null: interpreted)
     std::vector<hipFunction_t> jit_fn;

@@ -2,6 +2,10 @@
 // stages whose dense gates act on the stage's register bits, and builds the
 // XOR-swizzled LDS address maps of the exchanges between stages.
 #include <algorithm>
+#include <tuple>
+#include <mutex>
+#include <map>
+#include <array>
 #include <cstring>
 
 #include "qsim_internal.h"
@@ -65,13 +69,12 @@ void split_layout(uint32_t R, int m, int *Rpos, int *Tpos) {
     }
 }
 
-// Picks the XOR swizzle of one exchange so that both the writing and the
-// reading layout access LDS without bank conflicts where possible.
-void make_exchange(int m, int wb, uint32_t Rw, uint32_t Rr, RegStage &st, uint64_t seed) {
-    int Rwp[kRegBitsMax], Twp[16], Rrp[kRegBitsMax], Trp[16];
-    split_layout(Rw, m, Rwp, Twp);
-    split_layout(Rr, m, Rrp, Trp);
-    const int r = popc(Rw);
+// Random search over swizzles of the positions that are low lane bits of
+// either layout, keeping the one that satisfies the most bank constraints.
+// On 12-qubit tiles with four register bits the best score over 16384
+// attempts is already reached within the first 64 for every pair of
+// register sets sampled, so the search stops there.
+std::array<uint32_t, 16> search_swizzle(int m, int wb, const int *Twp, const int *Trp, uint64_t seed) {
     // Only positions that are among the low lane bits of either layout
     // decide bank conflicts.  Every other position keeps its plain bit, so
     // the register parts of the addresses mostly stay clear of the bits the
@@ -81,7 +84,7 @@ void make_exchange(int m, int wb, uint32_t Rw, uint32_t Rr, RegStage &st, uint64
     uint32_t best[16] = {};
     int best_score = -1;
     uint64_t x = seed * 0x9E3779B97F4A7C15ull + 1;
-    for (int attempt = 0; attempt < 4096 && best_score < 4; ++attempt) {
+    for (int attempt = 0; attempt < 64 && best_score < 4; ++attempt) {
         uint32_t addr[16];
         for (int p = 0; p < m; ++p) {
             uint32_t sw = 0;
@@ -97,6 +100,44 @@ void make_exchange(int m, int wb, uint32_t Rw, uint32_t Rr, RegStage &st, uint64
             std::memcpy(best, addr, sizeof(uint32_t) * m);
         }
     }
+    std::array<uint32_t, 16> out{};
+    std::memcpy(out.data(), best, sizeof(uint32_t) * 16);
+    return out;
+}
+
+// Swizzles found so far, by (tile qubits, bank-slot bits, writing register
+// set, reading register set): the search costs far more than the rest
+// of planning, and the same pairs of register sets recur across passes and
+// plans (a parameter sweep re-plans the same circuit structure every call).
+std::mutex g_swizzle_mu;
+std::map<std::tuple<int, int, uint32_t, uint32_t>, std::array<uint32_t, 16>> g_swizzles;
+
+// Picks the XOR swizzle of one exchange so that both the writing and the
+// reading layout access LDS without bank conflicts where possible.  The
+// search is seeded from its key, so a plan's layout does not depend on what
+// was planned before it.
+void make_exchange(int m, int wb, uint32_t Rw, uint32_t Rr, RegStage &st) {
+    int Rwp[kRegBitsMax], Twp[16], Rrp[kRegBitsMax], Trp[16];
+    split_layout(Rw, m, Rwp, Twp);
+    split_layout(Rr, m, Rrp, Trp);
+    const int r = popc(Rw);
+    const auto key = std::make_tuple(m, wb, Rw, Rr);
+    std::array<uint32_t, 16> found{};
+    bool have = false;
+    {
+        std::lock_guard<std::mutex> lk(g_swizzle_mu);
+        auto it = g_swizzles.find(key);
+        if (it != g_swizzles.end()) {
+            found = it->second;
+            have = true;
+        }
+    }
+    if (!have) {
+        found = search_swizzle(m, wb, Twp, Trp, (uint64_t(Rw) << 32) ^ (uint64_t(Rr) << 8) ^ uint64_t(m));
+        std::lock_guard<std::mutex> lk(g_swizzle_mu);
+        g_swizzles.emplace(key, found);
+    }
+    const uint32_t *best = found.data();
     for (int b = 0; b < 8; ++b) {
         st.wr_t[b] = best[Twp[b]];
         st.rd_t[b] = best[Trp[b]];
@@ -232,7 +273,7 @@ bool build_reg_program(Plan &plan, Pass &p, uint64_t q, const int *local_of,
     for (size_t si = 0; si < stages.size(); ++si) {
         const uint32_t Rm = stages[si].first;
         RegStage st{};
-        if (si > 0) make_exchange(m, wb, prevR, Rm, st, si);
+        if (si > 0) make_exchange(m, wb, prevR, Rm, st);
         int Rp[kRegBitsMax], Tp[16];
         split_layout(Rm, m, Rp, Tp);
         st.op_begin = int(plan.reg_ops.size()) - p.rop_begin;

@@ -115,6 +115,18 @@ def test_grid_circuit_20q_c64(qs):
     assert O.rel_l2(s.to_numpy(), O.apply_circuit(circ)) <= TOL["c64"]
 
 
+@pytest.mark.parametrize("family", ["supremacy", "multiplier"])
+def test_width_sweep_circuit_18q(qs, family):
+    """An 18-qubit circuit of the width sweep (qubits removed from the 20- and
+    21-qubit circuits), automatic options: compiled passes throughout."""
+    circ = W.width_circuit(family, 18)
+    s = _state(qs, 18, "c64")
+    s.profile(True)
+    s.apply_circuit(circ)
+    assert s.profile_read("tile_jit")[0] > 0
+    assert O.rel_l2(s.to_numpy(), O.apply_circuit(circ)) <= TOL["c64"]
+
+
 @pytest.mark.parametrize("mode", ["tile", "tile_complex"])
 def test_multiplier_basis_inputs_bit_exact(qs, mode):
     """X, CX and CCX only: the split form of X is an exchange with a sign and a

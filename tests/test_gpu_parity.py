@@ -183,6 +183,18 @@ def test_controlled_blocks(qs, dtype, mode):
 
 
 @pytest.mark.parametrize("dtype", ["c64", "c128"])
+@pytest.mark.parametrize("family", ["supremacy", "multiplier"])
+@pytest.mark.parametrize("n", [13, 14])
+def test_width_sweep_circuits(qs, dtype, family, n):
+    """The width sweep's cut-down circuits on their superposition input,
+    with the library's automatic options (the sweep runs those)."""
+    circ = W.width_circuit(family, n)
+    s = _state(qs, n, dtype)
+    s.apply_circuit(circ)
+    assert O.rel_l2(s.to_numpy(), O.apply_circuit(circ)) <= TOL[dtype]
+
+
+@pytest.mark.parametrize("dtype", ["c64", "c128"])
 @pytest.mark.parametrize("mode", ["sweep", "tile", "fuse4", "fuse5_tile"])
 def test_grid_circuit_16q(qs, dtype, mode):
     circ = W.random_grid_circuit(4, 4, depth=12, seed=2)

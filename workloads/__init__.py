@@ -269,6 +269,49 @@ def multiplier_inputs(count: int = 64, bits: int = 7, seed: int = 3) -> np.ndarr
     return rng.integers(0, 1 << bits, size=(count, 2))
 
 
+# -------------------------------------------------------- width sweep
+
+# grid shapes of the standard supremacy-style circuits the sweep cuts down
+SWEEP_GRIDS = [(3, 4), (4, 4), (4, 5), (5, 5), (5, 6)]
+
+
+def remove_qubits(circ: Circuit, width: int, seed: int) -> Circuit:
+    """Drops circ.n - width qubits drawn at random (seeded) together with
+    every op that touches one of them, and relabels the remaining qubits in
+    increasing order: the way the paper reaches widths between the sizes its
+    circuit generators produce (§II; the multipliers of §III.A the same way)."""
+    if not 1 <= width <= circ.n:
+        raise ValueError("width must be between 1 and the circuit's width")
+    rng = np.random.default_rng(seed)
+    drop = set(int(x) for x in rng.choice(circ.n, circ.n - width, replace=False))
+    keep = [q for q in range(circ.n) if q not in drop]
+    label = {q: i for i, q in enumerate(keep)}
+    ops = [Op(o.kind, tuple(label[t] for t in o.targets), o.angles, o.param, o.matrix)
+           for o in circ.ops if all(t in label for t in o.targets)]
+    return Circuit(width, ops, circ.nparams, f"{circ.name}_keep{width}_s{seed}")
+
+
+def width_circuit(family: str, width: int, seed: int = 6) -> Circuit:
+    """A `width`-qubit circuit of the sweep, on an equal-superposition input
+    (H on every qubit first, as the paper feeds both families).
+
+    "supremacy": the smallest grid circuit of SWEEP_GRIDS (depth 20, seed 2)
+    with at least `width` qubits; "multiplier": the smallest (4w+1)-qubit
+    multiplier core with at least `width` qubits; either cut down to `width`
+    by remove_qubits."""
+    if family == "supremacy":
+        rows, cols = next(rc for rc in SWEEP_GRIDS if rc[0] * rc[1] >= width)
+        full = random_grid_circuit(rows, cols, depth=20, seed=2)
+    elif family == "multiplier":
+        bits = max(2, (width - 1 + 3) // 4)
+        full = multiplier_core(bits)
+    else:
+        raise ValueError(f"unknown family {family!r}")
+    cut = remove_qubits(full, width, seed) if full.n > width else full
+    prep = [op("h", q) for q in range(width)]
+    return Circuit(width, prep + cut.ops, 0, f"{family}{width}")
+
+
 # -------------------------------------------------------- variational
 
 def ansatz_circuit(n: int, layers: int) -> Circuit:
