@@ -7,10 +7,10 @@
 // source, one kernel per pass (amplitudes as named scalars, register and
 // layout indices as constants, matrices and parameters still read from the
 // uploaded pool), compiled once with hipRTC for gfx950 and kept for the life
-// of the process, keyed by the source text: plans that differ only in gate
-// angles share their code.
+// of the process, keyed by what the source is written from.
 #include <hip/hiprtc.h>
 
+#include <cmath>
 #include <cstdarg>
 #include <cstdio>
 #include <cstdlib>
@@ -383,11 +383,40 @@ double gen_pass(Src &o, const Plan &plan, const Pass &p, const char *name) {
 struct JitModule {
     hipModule_t mod = nullptr;
     std::vector<hipFunction_t> fns;
+    std::vector<double> flops_per_thread;   // per compiled pass
 };
 
 std::mutex g_mu;
-// (device, program text) -> loaded module; modules stay loaded until exit
+// (device, source key) -> loaded module; modules stay loaded until exit
 std::map<std::pair<int, std::string>, std::shared_ptr<JitModule>> g_modules;
+
+// Exact description of everything the generated source depends on: the
+// precision and, for each compiled pass in order, its layout fields and the
+// register stages, register ops and pool entries it reads (all pass-relative).
+// Equal keys give equal source, so a plan whose passes were compiled before
+// finds its module without writing the source out again.
+std::string source_key(const Plan &plan) {
+    std::string k;
+    auto put = [&k](const void *p, size_t n) { k.append(static_cast<const char *>(p), n); };
+    put(&plan.dtype, sizeof plan.dtype);
+    put(&plan.n, sizeof plan.n);
+    for (const Pass &p : plan.passes) {
+        if (p.kind != PASS_TILE || p.reg_r <= 0) continue;
+        const int head[4] = {p.m, p.L, p.reg_r, int(p.hpos.size())};
+        put(head, sizeof head);
+        put(p.hpos.data(), sizeof(int) * p.hpos.size());
+        put(p.ld_t, sizeof p.ld_t);
+        put(p.ld_r, sizeof p.ld_r);
+        put(p.st_t, sizeof p.st_t);
+        put(p.st_r, sizeof p.st_r);
+        const int sizes[3] = {p.stage_end - p.stage_begin, p.rop_end - p.rop_begin, p.pool_end - p.pool_begin};
+        put(sizes, sizeof sizes);
+        put(plan.reg_stages.data() + p.stage_begin, sizeof(RegStage) * size_t(sizes[0]));
+        put(plan.reg_ops.data() + p.rop_begin, sizeof(RegOp) * size_t(sizes[1]));
+        put(plan.tile_pool.data() + p.pool_begin, sizeof(cd) * size_t(sizes[2]));
+    }
+    return k;
+}
 std::string g_last_log;
 
 int env_int(const char *name, int dflt) {
@@ -426,16 +455,18 @@ std::string jit_source(const Plan &plan, std::vector<int> &which, std::vector<do
 qsim_status jit_prepare(qsim_state s, Plan &plan, std::string &err) {
     plan.jit_fn.assign(plan.passes.size(), nullptr);
     std::vector<int> which;
-    std::vector<double> flops;
-    const std::string text = jit_source(plan, which, &flops);
+    for (size_t i = 0; i < plan.passes.size(); ++i)
+        if (plan.passes[i].kind == PASS_TILE && plan.passes[i].reg_r > 0) which.push_back(int(i));
     if (which.empty()) return QSIM_OK;
     std::lock_guard<std::mutex> lk(g_mu);
-    const auto key = std::make_pair(s->device, text);
+    const auto key = std::make_pair(s->device, source_key(plan));
     auto it = g_modules.find(key);
     std::shared_ptr<JitModule> jm;
     if (it != g_modules.end()) {
         jm = it->second;
     } else {
+        std::vector<double> flops;
+        const std::string text = jit_source(plan, which, &flops);
         hiprtcProgram prog;
         if (hiprtcCreateProgram(&prog, text.c_str(), "qsim_tiles.hip", 0, nullptr, nullptr) != HIPRTC_SUCCESS) {
             err = "hiprtcCreateProgram failed";
@@ -475,12 +506,15 @@ qsim_status jit_prepare(qsim_state s, Plan &plan, std::string &err) {
                 return QSIM_ERR_DEVICE;
             }
             jm->fns.push_back(fn);
+            const Pass &p = plan.passes[size_t(which[k])];
+            jm->flops_per_thread.push_back(flops[k] / (256.0 * std::ldexp(1.0, plan.n - p.m)));
         }
         g_modules[key] = jm;
     }
     for (size_t k = 0; k < which.size(); ++k) {
+        Pass &p = plan.passes[size_t(which[k])];
         plan.jit_fn[size_t(which[k])] = jm->fns[k];
-        plan.passes[size_t(which[k])].flops = flops[k];
+        p.flops = jm->flops_per_thread[k] * 256.0 * std::ldexp(1.0, plan.n - p.m);
     }
     return QSIM_OK;
 }
