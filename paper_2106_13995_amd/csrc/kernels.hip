@@ -441,18 +441,124 @@ k_expect_tile(const c2_t<T> *__restrict__ psi, const ExpTilePass p, const ExpTer
     }
 }
 
+// The same sums for tiles of exactly KPT * 256 amplitudes, with each
+// thread's amplitudes and products in registers and the terms as the outer
+// loop (one load of a term per group and tile instead of one per amplitude).
+// Amplitude l = t + 256 k of the tile is thread t's k-th, so the sign parity
+// of a term splits into a thread part and a part known for each k.
+//  * X mask 0: each amplitude's weight D = sum_t w_t (-1)^{|y & z_t|} is
+//    summed first (in double), then D |psi_y|^2 is added.
+//  * X mask x != 0: the pair (y, y ^ x) is visited once, from the member
+//    whose lowest bit of x is 0, and counted twice: for a Hermitian term the
+//    two members' summands are complex conjugates, so their sum is twice the
+//    real part of either.
+template <typename T, int KPT>
+__global__ void __launch_bounds__(kExpThreads)
+k_expect_tile_reg(const c2_t<T> *__restrict__ psi, const ExpTilePass p, const ExpTerm *__restrict__ terms,
+                  uint64_t ntiles, double *__restrict__ partials) {
+    extern __shared__ char lds_raw[];
+    c2_t<T> *lds = reinterpret_cast<c2_t<T> *>(lds_raw);
+    __shared__ double wsum[kExpTileGroups][kExpThreads / 64];
+    const uint32_t t = threadIdx.x;
+    const int wave = t / 64, lane = t % 64;
+    for (int g = t; g < kExpTileGroups * (kExpThreads / 64); g += kExpThreads)
+        wsum[g / (kExpThreads / 64)][g % (kExpThreads / 64)] = 0.0;
+    for (uint64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+        uint64_t base = tile << p.L;
+        for (int i = 0; i < p.H; ++i) {
+            const uint64_t lo = base & ((1ull << p.hpos[i]) - 1ull);
+            base = ((base - lo) << 1) | lo;
+        }
+        __syncthreads();   // the previous tile's readers are done
+#pragma unroll
+        for (int k = 0; k < KPT; ++k) {
+            const uint32_t l = t + uint32_t(k) * kExpThreads;
+            uint64_t gi = base | (l & ((1u << p.L) - 1u));
+            const uint32_t h = l >> p.L;
+            for (int i = 0; i < p.H; ++i) gi |= uint64_t((h >> i) & 1u) << p.hpos[i];
+            lds[l] = psi[gi];
+        }
+        __syncthreads();
+        for (int g = 0; g < p.ngroups; ++g) {
+            const ExpTileGroup gr = p.groups[g];
+            double acc = 0.0;
+            if (gr.xl == 0) {
+                double D[KPT];
+#pragma unroll
+                for (int k = 0; k < KPT; ++k) D[k] = 0.0;
+                for (int tt = gr.first; tt < gr.first + gr.count; ++tt) {
+                    const ExpTerm e = terms[tt];
+                    const uint32_t zl = uint32_t(e.pad_);
+                    const uint32_t par = (uint32_t(__popcll(base & e.z)) ^ uint32_t(__popc(t & zl & 0xffu))) & 1u;
+                    const double w = par ? -e.wr : e.wr;
+#pragma unroll
+                    for (int k = 0; k < KPT; ++k)
+                        D[k] += (__popc(uint32_t(k) & (zl >> 8)) & 1) ? -w : w;
+                }
+#pragma unroll
+                for (int k = 0; k < KPT; ++k) {
+                    const c2_t<T> a = lds[t + uint32_t(k) * kExpThreads];
+                    acc += D[k] * (double(a.x) * double(a.x) + double(a.y) * double(a.y));
+                }
+            } else {
+                const uint32_t lb = gr.xl & (0u - gr.xl);   // lowest bit of x
+                double pr[KPT / 2], pi[KPT / 2];
+                uint32_t ly[KPT / 2];   // y ^ x of each pair (its sign bits)
+#pragma unroll
+                for (int k = 0; k < KPT / 2; ++k) {
+                    const uint32_t j = t + uint32_t(k) * kExpThreads;
+                    const uint32_t l = ((j & ~(lb - 1u)) << 1) | (j & (lb - 1u));
+                    const c2_t<T> a = lds[l], b = lds[l ^ gr.xl];
+                    pr[k] = double(a.x) * double(b.x) + double(a.y) * double(b.y);
+                    pi[k] = double(a.x) * double(b.y) - double(a.y) * double(b.x);
+                    ly[k] = l ^ gr.xl;
+                }
+                for (int tt = gr.first; tt < gr.first + gr.count; ++tt) {
+                    const ExpTerm e = terms[tt];
+                    const uint32_t zo = uint32_t(__popcll(base & e.z));
+                    const uint32_t zl = uint32_t(e.pad_);
+#pragma unroll
+                    for (int k = 0; k < KPT / 2; ++k) {
+                        const double v = e.wr * pr[k] - e.wi * pi[k];
+                        acc += ((uint32_t(__popc(ly[k] & zl)) ^ zo) & 1u) ? -2.0 * v : 2.0 * v;
+                    }
+                }
+            }
+            for (int sft = 32; sft > 0; sft >>= 1) acc += __shfl_xor(acc, sft, 64);
+            if (lane == 0) wsum[g][wave] += acc;
+        }
+    }
+    __syncthreads();
+    if (t < uint32_t(p.ngroups)) {
+        double tot = 0.0;
+        for (int w = 0; w < kExpThreads / 64; ++w) tot += wsum[t][w];
+        partials[size_t(t) * gridDim.x + blockIdx.x] = tot;
+    }
+}
+
 hipError_t launch_expect_tiles(qsim_state s, const ExpTilePass &p, const void *dev_terms, double *partials,
                                int *nwritten) {
     const uint64_t ntiles = 1ull << (s->n - p.m);
     const int grid = int(std::min<uint64_t>(ntiles, 2048));
     const ExpTerm *terms = static_cast<const ExpTerm *>(dev_terms);
     const size_t lds = (s->dtype == QSIM_C64 ? 8u : 16u) << p.m;
-    if (s->dtype == QSIM_C64)
-        hipLaunchKernelGGL((k_expect_tile<float>), dim3(grid), dim3(kExpThreads), lds, s->stream,
-                           static_cast<const c2_t<float> *>(s->data), p, terms, ntiles, partials);
-    else
-        hipLaunchKernelGGL((k_expect_tile<double>), dim3(grid), dim3(kExpThreads), lds, s->stream,
-                           static_cast<const c2_t<double> *>(s->data), p, terms, ntiles, partials);
+    if (s->dtype == QSIM_C64) {
+        const c2_t<float> *psi = static_cast<const c2_t<float> *>(s->data);
+        if (p.m == 12)
+            hipLaunchKernelGGL((k_expect_tile_reg<float, 16>), dim3(grid), dim3(kExpThreads), lds, s->stream, psi,
+                               p, terms, ntiles, partials);
+        else
+            hipLaunchKernelGGL((k_expect_tile<float>), dim3(grid), dim3(kExpThreads), lds, s->stream, psi, p, terms,
+                               ntiles, partials);
+    } else {
+        const c2_t<double> *psi = static_cast<const c2_t<double> *>(s->data);
+        if (p.m == 11)
+            hipLaunchKernelGGL((k_expect_tile_reg<double, 8>), dim3(grid), dim3(kExpThreads), lds, s->stream, psi,
+                               p, terms, ntiles, partials);
+        else
+            hipLaunchKernelGGL((k_expect_tile<double>), dim3(grid), dim3(kExpThreads), lds, s->stream, psi, p, terms,
+                               ntiles, partials);
+    }
     *nwritten = grid * p.ngroups;
     return hipGetLastError();
 }

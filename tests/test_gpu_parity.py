@@ -384,3 +384,28 @@ def test_expectation_tiled_and_wide_groups(qs, dtype):
     got = s.expectation(H)
     ref = O.expectation(psi, H)
     assert abs(got - ref) <= (1e-4 if dtype == "c64" else 1e-11) * max(1.0, abs(ref))
+
+
+def test_plan_cache_eviction_and_stream_switch(qs):
+    """A parameter sweep over 40 settings on one state: more plans than the
+    state keeps, so evicted plans release their device buffers in stream
+    order while later plans are uploaded; half way the state moves to another
+    stream (plans then release on that one).  Results are checked along the
+    way against the oracle."""
+    import torch
+    n, layers = 12, 2
+    circ = W.ansatz_circuit(n, layers)
+    rng = np.random.default_rng(112)
+    s = _state(qs, n, "c128")
+    side = torch.cuda.Stream()
+    for i in range(40):
+        if i == 20:
+            torch.cuda.synchronize()
+            qs.qsim_set_stream(s.handle, side.cuda_stream)
+        p = rng.uniform(0, 2 * np.pi, circ.nparams)
+        s.set_basis(0)
+        s.apply_circuit(circ, params=p)
+        if i % 7 == 0 or i >= 36:
+            assert O.rel_l2(s.to_numpy(), O.apply_circuit(circ, params=p)) <= TOL["c128"]
+    s.close()
+    torch.cuda.synchronize()
