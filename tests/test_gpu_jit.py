@@ -163,3 +163,22 @@ def test_bound_ansatz_and_parametric_form(qs, dtype):
         assert s.profile_read(cls)[0] > 0
         assert O.rel_l2(s.to_numpy(), ref) <= TOL[dtype]
         s.close()
+
+
+def test_same_structure_different_angles(qs):
+    """Two grid circuits with the same gates on the same qubits but other
+    angles, one after the other on one state: the compiled passes are looked
+    up by what their source is written from (angles included), so each gets
+    its own kernels and both match the oracle."""
+    a = W.random_grid_circuit(4, 4, depth=10, seed=21)
+    b = W.random_grid_circuit(4, 4, depth=10, seed=22)
+    assert [(o.kind, o.targets) for o in a.ops] == [(o.kind, o.targets) for o in b.ops]
+    s = _state(qs, 16, "c64")
+    for circ in (a, b, a):
+        s.set_basis(0)
+        s.profile(True)
+        s.apply_circuit(circ, fuse_k=1, tile_m=12)
+        assert s.profile_read("tile_jit")[0] > 0
+        s.profile(False)
+        assert O.rel_l2(s.to_numpy(), O.apply_circuit(circ)) <= TOL["c64"]
+    s.close()
