@@ -1,0 +1,102 @@
+// Host-side planner check, built with AddressSanitizer and UBSan by
+// tests/test_host_sanitize.py: every planning path (sweeps, fusion, tiles,
+// register programs, split form, compiled-pass source, adjoint tiles) runs on
+// the circuits given as files, at both precisions and many options.  Device
+// launchers are stubs that abort: planning must never reach them.
+#include <cstdio>
+#include <cstdlib>
+#include <vector>
+
+#include "batch.h"
+#include "qsim_internal.h"
+
+namespace qsim {
+[[noreturn]] static void no_device(const char *what) {
+    std::fprintf(stderr, "planner reached a device launch: %s\n", what);
+    std::abort();
+}
+hipError_t launch_adjoint_pass(qsim_state, const Plan &, const Pass &, void *, double *) { no_device("adjoint"); }
+hipError_t launch_batch(hipStream_t, int, const BatchDevice &, int) { no_device("batch"); }
+hipError_t launch_dense_sweep(qsim_state, const Pass &) { no_device("dense"); }
+hipError_t launch_diag_sweep(qsim_state, const Pass &) { no_device("diag"); }
+hipError_t launch_expect_group(qsim_state, uint64_t, const void *, int, double *, int *) { no_device("expect"); }
+hipError_t launch_expect_tiles(qsim_state, const ExpTilePass &, const void *, double *, int *) { no_device("expect"); }
+hipError_t launch_mfma_pass(qsim_state, const Plan &, const Pass &) { no_device("mfma"); }
+hipError_t launch_pauli_apply(qsim_state, void *, const void *, int, const void *, double *) { no_device("pauli"); }
+hipError_t launch_reduce(qsim_state, const double *, int, double *) { no_device("reduce"); }
+hipError_t launch_reduce_rows(qsim_state, const double *, int, int, double *) { no_device("reduce"); }
+hipError_t launch_set_basis(qsim_state, uint64_t) { no_device("basis"); }
+hipError_t launch_tile_pass(qsim_state, const Plan &, const Pass &) { no_device("tile"); }
+hipError_t launch_tile_reg_pass(qsim_state, const Plan &, const Pass &) { no_device("tile"); }
+int pauli_apply_grid(uint64_t) { no_device("pauli"); }
+}  // namespace qsim
+
+using namespace qsim;
+
+int main(int argc, char **argv) {
+    long plans = 0, passes = 0;
+    for (int f = 1; f < argc; ++f) {
+        FILE *in = std::fopen(argv[f], "rb");
+        if (!in) return 2;
+        int32_t hdr[3];
+        if (std::fread(hdr, 4, 3, in) != 3) return 2;
+        const int n = hdr[0], nops = hdr[1], nparams = hdr[2];
+        int64_t nmats = 0;
+        if (std::fread(&nmats, 8, 1, in) != 1) return 2;
+        std::vector<qsim_op> ops(static_cast<size_t>(nops));
+        std::vector<double> mats(size_t(2 * nmats + 2)), params(size_t(nparams + 1));
+        if (std::fread(ops.data(), sizeof(qsim_op), ops.size(), in) != ops.size()) return 2;
+        if (std::fread(mats.data(), sizeof(double), size_t(2 * nmats), in) != size_t(2 * nmats)) return 2;
+        if (std::fread(params.data(), sizeof(double), size_t(nparams), in) != size_t(nparams)) return 2;
+        std::fclose(in);
+        qsim_circuit c{};
+        c.n = n;
+        c.nops = nops;
+        c.ops = ops.data();
+        c.mats = mats.data();
+        c.nmats = nmats;
+        // (fuse_k, tile_m, use_mfma, split_1q): automatic; sweeps; matrix-core
+        // blocks; tiles of several sizes, fused or not; complex 2x2 form; LDS tiles
+        const qsim_options opts[] = {{0, 0, 0, 0},  {1, -1, 0, 0}, {2, -1, 0, 0}, {3, -1, 0, 0},  {4, -1, 1, 0},
+                                     {5, -1, 0, 0}, {6, -1, 1, 0}, {1, 12, 0, 0}, {1, 13, 0, 0},  {2, 12, 0, 0},
+                                     {3, 11, 0, 0}, {5, 12, 0, 0}, {2, 0, 0, 0},  {1, 12, 0, -1}, {1, 9, 0, 0}};
+        for (int dt : {QSIM_C64, QSIM_C128}) {
+            if (n > (dt == QSIM_C64 ? 35 : 34)) continue;
+            for (const qsim_options &o : opts) {
+                int64_t counts[QSIM_KCLASS_COUNT_] = {};
+                double by = 0, fl = 0;
+                const qsim_status st = qsim_plan_summary(n, qsim_dtype(dt), &c, nparams ? params.data() : nullptr,
+                                                         nparams, &o, counts, &by, &fl);
+                if (st != QSIM_OK) {
+                    std::fprintf(stderr, "%s: plan_summary status %d: %s\n", argv[f], int(st), qsim_last_error());
+                    return 3;
+                }
+                ++plans;
+                for (int64_t v : counts) passes += v;
+                // the register programs written out as kernel source
+                std::vector<HostGate> gates(static_cast<size_t>(nops));
+                for (int i = 0; i < nops; ++i)
+                    if (make_gate(&c, i, nparams ? params.data() : nullptr, nparams, gates[size_t(i)]) != QSIM_OK)
+                        return 4;
+                Plan plan;
+                plan.n = n;
+                plan.dtype = dt;
+                build_plan(plan, gates, resolve_options(&o, n, dt));
+                std::vector<int> which;
+                std::vector<double> flops;
+                const std::string src = jit_source(plan, which, &flops);
+                if (!which.empty() && src.empty()) return 5;
+            }
+            std::vector<HostGate> gates(static_cast<size_t>(nops));
+            for (int i = 0; i < nops; ++i)
+                if (make_gate(&c, i, nparams ? params.data() : nullptr, nparams, gates[size_t(i)]) != QSIM_OK) return 4;
+            Plan adj;
+            adj.n = n;
+            adj.dtype = dt;
+            build_adjoint_plan(adj, gates, std::min(n, 10));
+            passes += long(adj.passes.size());
+        }
+    }
+    std::printf("planner check: %ld plans, %ld passes\n", plans, passes);
+    return 0;
+}
