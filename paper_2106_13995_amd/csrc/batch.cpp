@@ -207,7 +207,7 @@ qsim_status qsim_batch_create(int ncirc, const qsim_circuit *circs, const int64_
                 bps.op_end = op_base + p.op_end;
                 for (int o = p.op_begin; o < p.op_end; ++o) {
                     TileOp t = plan.tile_ops[size_t(o)];
-                    if (t.type == 0 || t.type == 1) t.moff += pool_base + p.pool_begin;
+                    if (t.type == 0 || t.type == 1 || t.type == 5) t.moff += pool_base + p.pool_begin;
                     ops.push_back(t);
                 }
                 passes.push_back(bps);

@@ -238,6 +238,8 @@ __global__ void __launch_bounds__(kTileThreads) k_tile_pass(const TileArgs<T> a)
         const c2_t<T> *U = spool + op.moff;
         if (op.type == 1) {
             tile_diag<T>(lds, op, U, base, M);
+        } else if (op.type == 5) {
+            tile_controlled<T>(lds, op, U, M);
         } else {
             switch (op.k) {
                 case 1: tile_dense_small<T, 1>(lds, op, U, M); break;

@@ -178,6 +178,9 @@ k_adjoint_tile(const TileArgs<T> a, c2_t<T> *__restrict__ lam, double *__restric
         } else if (op.type == 1) {
             tile_diag<T>(lp, op, U, base, M);
             tile_diag<T>(ll, op, U, base, M);
+        } else if (op.type == 5) {
+            tile_controlled<T>(lp, op, U, M);
+            tile_controlled<T>(ll, op, U, M);
         } else {
             switch (op.k) {
                 case 1: tile_dense_small<T, 1>(lp, op, U, M); tile_dense_small<T, 1>(ll, op, U, M); break;

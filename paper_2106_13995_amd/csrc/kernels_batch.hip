@@ -156,6 +156,10 @@ __device__ void batch_tile_ops(const BatchArgs<T> &a, const BatchPass &ps, c2_t<
             const c2_t<T> *U = a.pool + op.moff;
             tile_diag<T>(lp, op, U, base, M);
             if (both) tile_diag<T>(ll, op, U, base, M);
+        } else if (op.type == 5) {
+            const c2_t<T> *U = a.pool + op.moff;
+            tile_controlled<T>(lp, op, U, M);
+            if (both) tile_controlled<T>(ll, op, U, M);
         } else {
             const c2_t<T> *U = a.pool + op.moff;
             switch (op.k) {

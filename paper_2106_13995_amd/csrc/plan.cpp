@@ -197,16 +197,17 @@ struct TileBuilder {
                     continue;
                 }
                 const int d = 1 << g->k;
-                if (regform && !is_diagonal(*g) && g->k > 1) {
+                if (!is_diagonal(*g) && g->k > 1) {
                     HostGate red;
                     int ctl[QSIM_MAX_K];
                     const int nc = extract_controls(*g, red, ctl);
                     if (red.k == 1) {
                         // a controlled one-qubit block: a complex 2 x 2 product
-                        // where the controls are 1, nothing for a permutation
+                        // where the controls are 1 (register programs move the
+                        // values of a permutation without arithmetic)
                         const bool perm = red.M[0] == cd(0.0) && red.M[3] == cd(0.0) &&
                                           red.M[1] == cd(1.0) && red.M[2] == cd(1.0);
-                        if (!perm) f += 16.0 * std::ldexp(1.0, n - nc);
+                        if (!perm || !regform) f += 16.0 * std::ldexp(1.0, n - nc);
                         continue;
                     }
                 }
@@ -285,10 +286,25 @@ struct TileBuilder {
                 op.kin = nin;
                 for (int j = 0; j < d; ++j) plan.tile_pool.push_back(s.M[j * d + j]);
             } else {
-                op.type = 0;
-                op.kin = s.k;
-                for (int b = 0; b < s.k; ++b) op.pos[b] = local_of[s.targets[b]];
-                plan.tile_pool.insert(plan.tile_pool.end(), s.M.begin(), s.M.end());
+                // a one-qubit block under controls (all inside the tile here)
+                // touches only the pairs where the controls are 1
+                HostGate red;
+                int ctl[QSIM_MAX_K];
+                const int nc = s.k > 1 ? extract_controls(s, red, ctl) : 0;
+                bool controlled = nc > 0 && red.k == 1 && ((q >> red.targets[0]) & 1);
+                for (int c = 0; c < nc && controlled; ++c) controlled = (q >> ctl[c]) & 1;
+                if (controlled) {
+                    op.type = 5;
+                    op.k = 1;
+                    op.pos[0] = local_of[red.targets[0]];
+                    for (int c = 0; c < nc; ++c) op.kin |= 1 << local_of[ctl[c]];
+                    plan.tile_pool.insert(plan.tile_pool.end(), red.M.begin(), red.M.end());
+                } else {
+                    op.type = 0;
+                    op.kin = s.k;
+                    for (int b = 0; b < s.k; ++b) op.pos[b] = local_of[s.targets[b]];
+                    plan.tile_pool.insert(plan.tile_pool.end(), s.M.begin(), s.M.end());
+                }
             }
             plan.tile_ops.push_back(op);
         }

@@ -97,6 +97,9 @@ enum PassKind : int { PASS_DENSE = 0, PASS_DIAG = 1, PASS_TILE = 2, PASS_MFMA = 
 //     diagonal index; the other k - kin lie outside, at global positions
 //     gpos[i], giving bit gbit[i] (constant across a tile).
 struct TileOp {
+    // 0 dense on pos[0..k-1], 1 diagonal (in-tile pos / out-of-tile gpos
+    // bits), 3 adjoint probe, 4 device-formed rotation (batch), 5 one-qubit
+    // block on pos[0] where the in-tile control positions of mask kin are 1
     int32_t type;
     int32_t k;
     int32_t kin;

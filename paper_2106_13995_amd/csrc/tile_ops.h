@@ -41,6 +41,36 @@ __device__ __forceinline__ uint32_t insert_zeros32(uint32_t x, const int *pos, i
 
 // Dense op on k <= 3 local positions: one thread per group of 2^k amplitudes.
 // The matrix is read from LDS (the same address in every lane).
+// 2 x 2 block U on tile position op.pos[0] for the pairs whose control
+// positions (mask op.kin, all inside the tile) are 1: CX, CCX and other
+// one-qubit blocks under controls touch only that part of the tile.
+template <typename T>
+__device__ __forceinline__ void tile_controlled(c2_t<T> *lds, const TileOp &op, const c2_t<T> *U, uint32_t M) {
+    const uint32_t tb = 1u << op.pos[0], cm = uint32_t(op.kin), fixed = tb | cm;
+    const uint32_t npairs = M >> __popc(fixed);
+    const T u0r = U[0].x, u0i = U[0].y, u1r = U[1].x, u1i = U[1].y;
+    const T u2r = U[2].x, u2i = U[2].y, u3r = U[3].x, u3i = U[3].y;
+    for (uint32_t g = threadIdx.x; g < npairs; g += kTileThreads) {
+        // spread g over the free positions (zeros at the fixed ones, lowest first)
+        uint32_t x = g, rest = fixed;
+        while (rest) {
+            const uint32_t bit = rest & (0u - rest);
+            rest ^= bit;
+            const uint32_t low = x & (bit - 1u);
+            x = ((x - low) << 1) | low;
+        }
+        x |= cm;
+        const c2_t<T> a = lds[x], b = lds[x | tb];
+        c2_t<T> y0, y1;
+        y0.x = u0r * a.x - u0i * a.y + u1r * b.x - u1i * b.y;
+        y0.y = u0r * a.y + u0i * a.x + u1r * b.y + u1i * b.x;
+        y1.x = u2r * a.x - u2i * a.y + u3r * b.x - u3i * b.y;
+        y1.y = u2r * a.y + u2i * a.x + u3r * b.y + u3i * b.x;
+        lds[x] = y0;
+        lds[x | tb] = y1;
+    }
+}
+
 template <typename T, int K>
 __device__ __forceinline__ void tile_dense_small(c2_t<T> *lds, const TileOp &op, const c2_t<T> *U, uint32_t M) {
     constexpr int D = 1 << K;
