@@ -169,3 +169,57 @@ def test_autograd_function(q):
     assert abs(E.item() - O.energy(circ, p, H)) < 1e-12
     assert rel(theta.grad.numpy(), 2.0 * O.param_shift_grad(circ, p, H)) < 1e-10
     s.close()
+
+
+def _controlled_circuit(n, rng):
+    """RY/RZ layers with one-qubit blocks under one or two controls: CX and
+    CCX, and controlled random unitaries given as matrices, with the control
+    listed before and after the target (so it sits above and below it)."""
+    ops, npar = [], 0
+    for layer in range(2):
+        for qb in range(n):
+            ops.append(W.op("ry", qb, param=npar)); npar += 1
+            ops.append(W.op("rz", qb, param=npar)); npar += 1
+        for a in range(layer % 2, n - 1, 2):
+            u = W.random_unitary(1, rng)
+            cu = np.eye(4, dtype=np.complex128)
+            if a % 4 == 0:      # control = targets[0] (bit 0 of the matrix index)
+                cu[np.ix_([1, 3], [1, 3])] = u
+                ops.append(W.matrix_op([a, a + 1], cu))
+            else:               # control = targets[1]
+                cu[2:, 2:] = u
+                ops.append(W.matrix_op([a, a + 1], cu))
+        ops.append(W.op("cx", n - 1, 0))
+        ops.append(W.op("cx", 1, n - 2))
+        ops.append(W.op("ccx", 0, n - 1, n // 2))
+        ccu = np.eye(8, dtype=np.complex128)
+        ccu[np.ix_([5, 7], [5, 7])] = W.random_unitary(1, rng)   # controls on bits 0, 2
+        ops.append(W.matrix_op([2, n // 2 + 1, n - 2], ccu))
+    return W.Circuit(n, ops, npar)
+
+
+@pytest.mark.parametrize("n", [7, 13])
+def test_controlled_blocks_in_tiles(q, n):
+    """Controlled one-qubit blocks as masked pair ops in the adjoint's and the
+    batch's LDS tiles: complex128 against the oracle's energy and parameter
+    shift, complex64 against complex128, the batch against the per-circuit
+    path."""
+    rng = np.random.default_rng(60 + n)
+    circ = _controlled_circuit(n, rng)
+    p = rng.uniform(0, 2 * np.pi, circ.nparams)
+    H = W.random_pauli_sum(n, 8, rng)
+    s = q.State(n, "c128")
+    e, g = s.adjoint_grad(circ, p, H)
+    assert abs(e - O.energy(circ, p, H)) < 1e-12
+    assert rel(g, O.param_shift_grad(circ, p, H)) < 1e-10
+    s.close()
+    s = q.State(n, "c64")
+    e32, g32 = s.adjoint_grad(circ, p, H)
+    assert abs(e32 - e) < 1e-5 and rel(g32, g) < 1e-4
+    s.close()
+    for dt, tol in (("c128", 1e-10), ("c64", 1e-4)):
+        b = q.Batch([circ, circ], [H, H], dt)
+        eb, gb = b.run(np.concatenate([p, p]))
+        assert np.max(np.abs(eb - e)) < (1e-11 if dt == "c128" else 1e-5)
+        assert rel(gb[:circ.nparams], g) < tol and rel(gb[circ.nparams:], g) < tol
+        b.close()
