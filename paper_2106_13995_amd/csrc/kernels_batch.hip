@@ -46,6 +46,7 @@ struct BatchArgs {
 // per-wave partial sums of a tile's probes, added to the gradient in a fixed
 // order when the tile is done.
 constexpr int kBatchTrig = 512;
+constexpr int kLoadBatch = 8;   // tile loads a thread keeps in flight
 constexpr int kProbeSlots = 64;
 struct BatchShared {
     double cs[kBatchTrig], sn[kBatchTrig];
@@ -66,21 +67,36 @@ __device__ __forceinline__ void tile_rotation(c2_t<T> *lds, int p, int gen, doub
     } else {               // Z: diag(e^{-i t/2}, e^{i t/2})
         ar = T(cs); ai = T(-sn); br = T(0); bi = T(0); cr = T(0); ci = T(0); dr = T(cs); di = T(sn);
     }
-    const uint32_t bit = 1u << p;
-    for (uint32_t g = threadIdx.x; g < (M >> 1); g += kTileThreads) {
-        const uint32_t lo = g & (bit - 1u);
-        const uint32_t x = ((g - lo) << 1) | lo;
-        const c2_t<T> u = lds[x], v = lds[x | bit];
-        T o0r = T(0), o0i = T(0), o1r = T(0), o1i = T(0);
-        cfma(o0r, o0i, ar, ai, u.x, u.y);
-        cfma(o0r, o0i, br, bi, v.x, v.y);
-        cfma(o1r, o1i, cr, ci, u.x, u.y);
-        cfma(o1r, o1i, dr, di, v.x, v.y);
-        c2_t<T> w0, w1;
-        w0.x = o0r; w0.y = o0i;
-        w1.x = o1r; w1.y = o1i;
-        lds[x] = w0;
-        lds[x | bit] = w1;
+    const uint32_t bit = 1u << p, npairs = M >> 1;
+    // kPairBatch pairs per thread are read before any is written (distinct
+    // pairs never share an address), so their LDS reads overlap
+    for (uint32_t g0 = threadIdx.x; g0 < npairs; g0 += kPairBatch * kTileThreads) {
+        uint32_t xs[kPairBatch];
+        c2_t<T> u[kPairBatch], v[kPairBatch];
+#pragma unroll
+        for (int c = 0; c < kPairBatch; ++c) {
+            const uint32_t g = g0 + uint32_t(c) * kTileThreads;
+            const uint32_t lo = g & (bit - 1u);
+            xs[c] = ((g - lo) << 1) | lo;
+            if (g < npairs) {
+                u[c] = lds[xs[c]];
+                v[c] = lds[xs[c] | bit];
+            }
+        }
+#pragma unroll
+        for (int c = 0; c < kPairBatch; ++c) {
+            if (g0 + uint32_t(c) * kTileThreads >= npairs) break;
+            T o0r = T(0), o0i = T(0), o1r = T(0), o1i = T(0);
+            cfma(o0r, o0i, ar, ai, u[c].x, u[c].y);
+            cfma(o0r, o0i, br, bi, v[c].x, v[c].y);
+            cfma(o1r, o1i, cr, ci, u[c].x, u[c].y);
+            cfma(o1r, o1i, dr, di, v[c].x, v[c].y);
+            c2_t<T> w0, w1;
+            w0.x = o0r; w0.y = o0i;
+            w1.x = o1r; w1.y = o1i;
+            lds[xs[c]] = w0;
+            lds[xs[c] | bit] = w1;
+        }
     }
 }
 
@@ -239,16 +255,27 @@ __global__ void __launch_bounds__(kTileThreads) k_batch(const BatchArgs<T> a) {
                     base = ((base - lo) << 1) | lo;
                 }
                 if (!single) {
-                    for (uint32_t l = threadIdx.x; l < M; l += kTileThreads) {
-                        const uint64_t gi = base | batch_scatter<T>(ps, l);
-                        c2_t<T> w;
-                        if (pi == pg.fwd_begin) {
-                            w.x = (gi == 0) ? T(1) : T(0);
-                            w.y = T(0);
-                        } else {
-                            w = gpsi[gi];
+                    // kLoadBatch loads per thread in flight before the LDS writes
+                    for (uint32_t l0 = threadIdx.x; l0 < M; l0 += kLoadBatch * kTileThreads) {
+                        c2_t<T> w[kLoadBatch];
+#pragma unroll
+                        for (int c = 0; c < kLoadBatch; ++c) {
+                            const uint32_t l = l0 + uint32_t(c) * kTileThreads;
+                            if (l >= M) break;
+                            const uint64_t gi = base | batch_scatter<T>(ps, l);
+                            if (pi == pg.fwd_begin) {
+                                w[c].x = (gi == 0) ? T(1) : T(0);
+                                w[c].y = T(0);
+                            } else {
+                                w[c] = gpsi[gi];
+                            }
                         }
-                        lp[l] = w;
+#pragma unroll
+                        for (int c = 0; c < kLoadBatch; ++c) {
+                            const uint32_t l = l0 + uint32_t(c) * kTileThreads;
+                            if (l >= M) break;
+                            lp[l] = w[c];
+                        }
                     }
                     __syncthreads();
                 }
@@ -305,10 +332,23 @@ __global__ void __launch_bounds__(kTileThreads) k_batch(const BatchArgs<T> a) {
                     base = ((base - lo) << 1) | lo;
                 }
                 if (!single) {
-                    for (uint32_t l = threadIdx.x; l < M; l += kTileThreads) {
-                        const uint64_t gi = base | batch_scatter<T>(ps, l);
-                        lp[l] = gpsi[gi];
-                        ll[l] = glam[gi];
+                    for (uint32_t l0 = threadIdx.x; l0 < M; l0 += kLoadBatch * kTileThreads) {
+                        c2_t<T> wp[kLoadBatch], wl[kLoadBatch];
+#pragma unroll
+                        for (int c = 0; c < kLoadBatch; ++c) {
+                            const uint32_t l = l0 + uint32_t(c) * kTileThreads;
+                            if (l >= M) break;
+                            const uint64_t gi = base | batch_scatter<T>(ps, l);
+                            wp[c] = gpsi[gi];
+                            wl[c] = glam[gi];
+                        }
+#pragma unroll
+                        for (int c = 0; c < kLoadBatch; ++c) {
+                            const uint32_t l = l0 + uint32_t(c) * kTileThreads;
+                            if (l >= M) break;
+                            lp[l] = wp[c];
+                            ll[l] = wl[c];
+                        }
                     }
                     __syncthreads();
                 }

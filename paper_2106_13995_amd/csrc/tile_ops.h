@@ -9,6 +9,7 @@ namespace qsim {
 
 constexpr int kTileThreads = 256;
 constexpr int kMaxTileHigh = 16;
+constexpr int kPairBatch = 4;   // pairs a thread reads ahead in pair ops
 
 template <typename T>
 struct TileArgs {
@@ -50,24 +51,39 @@ __device__ __forceinline__ void tile_controlled(c2_t<T> *lds, const TileOp &op, 
     const uint32_t npairs = M >> __popc(fixed);
     const T u0r = U[0].x, u0i = U[0].y, u1r = U[1].x, u1i = U[1].y;
     const T u2r = U[2].x, u2i = U[2].y, u3r = U[3].x, u3i = U[3].y;
-    for (uint32_t g = threadIdx.x; g < npairs; g += kTileThreads) {
-        // spread g over the free positions (zeros at the fixed ones, lowest first)
-        uint32_t x = g, rest = fixed;
-        while (rest) {
-            const uint32_t bit = rest & (0u - rest);
-            rest ^= bit;
-            const uint32_t low = x & (bit - 1u);
-            x = ((x - low) << 1) | low;
+    // kPairBatch pairs per thread are read before any is written (distinct
+    // pairs never share an address), so their LDS reads overlap
+    for (uint32_t g0 = threadIdx.x; g0 < npairs; g0 += kPairBatch * kTileThreads) {
+        uint32_t xs[kPairBatch];
+        c2_t<T> a[kPairBatch], b[kPairBatch];
+#pragma unroll
+        for (int c = 0; c < kPairBatch; ++c) {
+            // spread g over the free positions (zeros at the fixed ones, lowest first)
+            const uint32_t g = g0 + uint32_t(c) * kTileThreads;
+            uint32_t x = g, rest = fixed;
+            while (rest) {
+                const uint32_t bit = rest & (0u - rest);
+                rest ^= bit;
+                const uint32_t low = x & (bit - 1u);
+                x = ((x - low) << 1) | low;
+            }
+            xs[c] = x | cm;
+            if (g < npairs) {
+                a[c] = lds[xs[c]];
+                b[c] = lds[xs[c] | tb];
+            }
         }
-        x |= cm;
-        const c2_t<T> a = lds[x], b = lds[x | tb];
-        c2_t<T> y0, y1;
-        y0.x = u0r * a.x - u0i * a.y + u1r * b.x - u1i * b.y;
-        y0.y = u0r * a.y + u0i * a.x + u1r * b.y + u1i * b.x;
-        y1.x = u2r * a.x - u2i * a.y + u3r * b.x - u3i * b.y;
-        y1.y = u2r * a.y + u2i * a.x + u3r * b.y + u3i * b.x;
-        lds[x] = y0;
-        lds[x | tb] = y1;
+#pragma unroll
+        for (int c = 0; c < kPairBatch; ++c) {
+            if (g0 + uint32_t(c) * kTileThreads >= npairs) break;
+            c2_t<T> y0, y1;
+            y0.x = u0r * a[c].x - u0i * a[c].y + u1r * b[c].x - u1i * b[c].y;
+            y0.y = u0r * a[c].y + u0i * a[c].x + u1r * b[c].y + u1i * b[c].x;
+            y1.x = u2r * a[c].x - u2i * a[c].y + u3r * b[c].x - u3i * b[c].y;
+            y1.y = u2r * a[c].y + u2i * a[c].x + u3r * b[c].y + u3i * b[c].x;
+            lds[xs[c]] = y0;
+            lds[xs[c] | tb] = y1;
+        }
     }
 }
 
