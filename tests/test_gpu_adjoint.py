@@ -68,6 +68,12 @@ def test_mixed_circuit_with_shared_parameters(q):
     assert rel(g, ps) < 1e-10
     assert g[5] == 0.0 and g[6] == 0.0
     s.close()
+    # the batch path (probes of a shared parameter in one pass, and not)
+    b = q.Batch([circ, circ], [H, H], "c128")
+    eb, gb = b.run(np.concatenate([p, p]))
+    assert np.max(np.abs(eb - e)) < 1e-11
+    assert rel(gb[:7], ps) < 1e-10 and rel(gb[7:], ps) < 1e-10
+    b.close()
 
 
 def test_state_restored_and_nonzero_input(q):
