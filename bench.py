@@ -59,6 +59,9 @@ def parse():
     ap.add_argument("--no-tune", action="store_true", help="skip autotuning during warm-up")
     ap.add_argument("--width-sweep", action="store_true",
                     help="time both circuit families at every width from 13 to --n qubits and print that line instead")
+    ap.add_argument("--batch-circuit", default="",
+                    help="n,layers: time one ansatz circuit through the batched persistent kernel "
+                         "(forward alone, then forward + gradient) and print that line instead")
     return ap.parse_args()
 
 
@@ -384,6 +387,27 @@ def calib_copy(torch, n: int, dtype: str):
                       "gbs": round(2 * nbytes / ms / 1e6, 1), "gbs_best": round(2 * nbytes / min(times) / 1e6, 1)}))
 
 
+def batch_circuit(q, W, n, layers, dtype):
+    """One ansatz circuit alone in the batched kernel: a single workgroup runs
+    it, so this is the time that bounds a batch holding it."""
+    c = W.ansatz_circuit(n, layers)
+    H = W.chain_observable(n)
+    p = W.ansatz_params(n, layers, seed=7)
+    out = {"workload": f"one ansatz circuit, {n} qubits, {layers} layers, {c.nparams} parameters, {dtype}, "
+                       "batched persistent kernel"}
+    for grad, key in ((False, "forward_ms"), (True, "forward_gradient_ms")):
+        b = q.Batch([c], [H], dtype, want_grad=grad)
+        b.run(p)
+        ts = []
+        for _ in range(3):
+            t0 = time.perf_counter()
+            b.run(p)
+            ts.append(time.perf_counter() - t0)
+        b.close()
+        out[key] = round(min(ts) * 1e3, 2)
+    return out
+
+
 def main():
     a = parse()
     if a.gpus != 1:
@@ -397,6 +421,10 @@ def main():
     import workloads as W
     if a.width_sweep:
         print(json.dumps(width_sweep(torch, q, W, hi=a.n, dtype=a.dtype)))
+        return
+    if a.batch_circuit:
+        n, layers = (int(v) for v in a.batch_circuit.split(","))
+        print(json.dumps(batch_circuit(q, W, n, layers, a.dtype)))
         return
 
     rows = 5
