@@ -30,6 +30,7 @@ import workloads as W
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "qsim_oracle.c")
 _LIB_PATH = os.path.join(_HERE, "liboracle.so")
+_LIB_OMP_PATH = os.path.join(_HERE, "liboracle_omp.so")
 
 # The oracle's own gate numbering (must match the enum in qsim_oracle.c).
 CODES: Dict[str, int] = {
@@ -41,27 +42,25 @@ PERMUTATION_GATES = ("x", "cx", "ccx", "swap")
 SHIFTABLE = ("rx", "ry", "rz", "cp")
 
 _lib = None
+_lib_omp = None
 
 
 def build(force: bool = True) -> str:
-    """Compile the oracle with gcc (no GPU headers, no OpenMP)."""
-    if not force and os.path.exists(_LIB_PATH):
-        return _LIB_PATH
-    tmp = _LIB_PATH + ".tmp"
-    cmd = ["gcc", "-O2", "-std=gnu11", "-fPIC", "-shared", "-fcx-limited-range", "-Wall",
-           "-o", tmp, _SRC, "-lm"]
-    subprocess.run(cmd, check=True)
-    os.replace(tmp, _LIB_PATH)
+    """Compile the oracle with gcc (no GPU headers): the single-thread library
+    and a second one built with OpenMP, whose gate loop runs over all host
+    threads with the same per-amplitude arithmetic (bit-identical results)."""
+    for path, extra in ((_LIB_PATH, []), (_LIB_OMP_PATH, ["-fopenmp"])):
+        if not force and os.path.exists(path):
+            continue
+        tmp = path + ".tmp"
+        cmd = ["gcc", "-O2", "-std=gnu11", "-fPIC", "-shared", "-fcx-limited-range", "-Wall",
+               *extra, "-o", tmp, _SRC, "-lm"]
+        subprocess.run(cmd, check=True)
+        os.replace(tmp, path)
     return _LIB_PATH
 
 
-def _load():
-    global _lib
-    if _lib is not None:
-        return _lib
-    if not os.path.exists(_LIB_PATH):
-        build()
-    lib = ctypes.CDLL(_LIB_PATH)
+def _bind(lib):
     P = ctypes.c_void_p
     i32, i64, u64, f64 = ctypes.c_int, ctypes.c_int64, ctypes.c_uint64, ctypes.c_double
     lib.oracle_gate_matrix.argtypes = [i32, P, P]
@@ -80,8 +79,23 @@ def _load():
     lib.oracle_classical_run.restype = i32
     lib.oracle_product_cz_amplitudes.argtypes = [i32, P, i32, P, i64, P, P]
     lib.oracle_product_cz_amplitudes.restype = None
-    _lib = lib
     return lib
+
+
+def _load(threaded: bool = False):
+    """The single-thread library, or (threaded=True) the OpenMP build."""
+    global _lib, _lib_omp
+    if threaded:
+        if _lib_omp is None:
+            if not os.path.exists(_LIB_OMP_PATH):
+                build()
+            _lib_omp = _bind(ctypes.CDLL(_LIB_OMP_PATH))
+        return _lib_omp
+    if _lib is None:
+        if not os.path.exists(_LIB_PATH):
+            build()
+        _lib = _bind(ctypes.CDLL(_LIB_PATH))
+    return _lib
 
 
 def _ptr(a: np.ndarray):
@@ -173,19 +187,28 @@ def basis_state(n: int, index: int = 0) -> np.ndarray:
 
 
 def apply_circuit(circ: W.Circuit, psi: Optional[np.ndarray] = None,
-                  params: Optional[np.ndarray] = None) -> np.ndarray:
+                  params: Optional[np.ndarray] = None, threaded: bool = False) -> np.ndarray:
     """Returns the state after the circuit (|0...0> when psi is None); the
-    input array is not modified."""
-    lib = _load()
+    input array is not modified.  threaded=True runs the gate loop of the
+    OpenMP build (same results, bit for bit)."""
     out = basis_state(circ.n) if psi is None else _c128(psi).copy()
     if out.size != (1 << circ.n):
         raise ValueError("state size does not match the circuit width")
+    return apply_circuit_inplace(out, circ, params, threaded)
+
+
+def apply_circuit_inplace(psi: np.ndarray, circ: W.Circuit, params: Optional[np.ndarray] = None,
+                          threaded: bool = False) -> np.ndarray:
+    """The circuit applied to a complex128 vector in place (no copy); returns it."""
+    lib = _load(threaded)
+    if psi.dtype != np.complex128 or not psi.flags.c_contiguous or psi.size != (1 << circ.n):
+        raise ValueError("need a contiguous complex128 vector of 2^n amplitudes")
     codes, ks, targets, angles, mats, offs = _pack(circ, params)
-    rc = lib.oracle_apply_circuit(_ptr(out), circ.n, len(codes), _ptr(codes), _ptr(ks),
+    rc = lib.oracle_apply_circuit(_ptr(psi), circ.n, len(codes), _ptr(codes), _ptr(ks),
                                   _ptr(targets), _ptr(angles), _ptr(mats), _ptr(offs))
     if rc != 0:
         raise ValueError(f"oracle rejected op {-rc - 1}")
-    return out
+    return psi
 
 
 def circuit_dagger(circ: W.Circuit, params: Optional[np.ndarray] = None) -> W.Circuit:
@@ -223,19 +246,22 @@ def expectation(psi: np.ndarray, H: W.PauliSum) -> float:
     return float(lib.oracle_expectation(_ptr(psi), n, len(c), _ptr(c), _ptr(x), _ptr(z)))
 
 
-def energy(circ: W.Circuit, params: np.ndarray, H: W.PauliSum) -> float:
-    return expectation(apply_circuit(circ, params=params), H)
+def energy(circ: W.Circuit, params: np.ndarray, H: W.PauliSum, threaded: bool = False) -> float:
+    return expectation(apply_circuit(circ, params=params, threaded=threaded), H)
 
 
 # ------------------------------------------------------------ gradients
 
-def param_shift_grad(circ: W.Circuit, params: np.ndarray, H: W.PauliSum) -> np.ndarray:
+def param_shift_grad(circ: W.Circuit, params: np.ndarray, H: W.PauliSum,
+                     indices: Optional[Sequence[int]] = None, threaded: bool = False) -> np.ndarray:
     """dE/dtheta_j by the shift rule, shifting each occurrence of a parameter
-    separately and summing (product rule)."""
+    separately and summing (product rule).  With `indices`, only those
+    parameters are differentiated (the other entries stay 0)."""
     params = np.asarray(params, dtype=np.float64)
     grad = np.zeros_like(params)
+    wanted = None if indices is None else set(int(j) for j in indices)
     for i, o in enumerate(circ.ops):
-        if o.param < 0:
+        if o.param < 0 or (wanted is not None and o.param not in wanted):
             continue
         if o.kind not in SHIFTABLE:
             raise ValueError(f"no shift rule for {o.kind}")
@@ -244,7 +270,7 @@ def param_shift_grad(circ: W.Circuit, params: np.ndarray, H: W.PauliSum) -> np.n
         for s in (+0.5 * np.pi, -0.5 * np.pi):
             ops = list(circ.ops)
             ops[i] = W.Op(o.kind, o.targets, (base + s,), -1)
-            vals.append(energy(W.Circuit(circ.n, ops, circ.nparams), params, H))
+            vals.append(energy(W.Circuit(circ.n, ops, circ.nparams), params, H, threaded))
         grad[o.param] += 0.5 * (vals[0] - vals[1])
     return grad
 

@@ -309,7 +309,6 @@ class State:
         self.tensor = torch.empty(2 << n, dtype=real, device=device)
         self.stream = torch.cuda.current_stream(self.tensor.device).cuda_stream
         self.handle = qsim_wrap(self.tensor.data_ptr(), n, self.dtype, self.stream)
-        self._packed: Dict[int, PackedCircuit] = {}
         if init:
             self.set_basis(0)
 
@@ -334,13 +333,12 @@ class State:
     def apply_gate(self, targets: Sequence[int], U: np.ndarray) -> None:
         qsim_apply_gate(self.handle, targets, U)
 
-    def packed(self, circ) -> PackedCircuit:
-        key = id(circ)
-        pc = self._packed.get(key)
-        if pc is None or pc.nops != len(circ.ops):
-            pc = PackedCircuit(circ)
-            self._packed[key] = pc
-        return pc
+    @staticmethod
+    def packed(circ) -> PackedCircuit:
+        """The circuit in the C structs: a PackedCircuit is used as given,
+        anything else is marshalled afresh (callers that apply one circuit
+        many times pack it once with PackedCircuit(circ))."""
+        return circ if isinstance(circ, PackedCircuit) else PackedCircuit(circ)
 
     def apply_circuit(self, circ, params: Optional[np.ndarray] = None, fuse_k: int = 0, tile_m: int = 0,
                       use_mfma: int = 0, split_1q: int = 0) -> None:

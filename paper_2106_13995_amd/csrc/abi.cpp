@@ -330,7 +330,7 @@ static qsim_status get_plan(qsim_state s, const qsim_circuit *c, const double *p
     if (!plan) return set_error(QSIM_ERR_OOM, "host allocation failed");
     plan->n = s->n;
     plan->dtype = s->dtype;
-    build_plan(*plan, gates, po);
+    if (!build_plan(*plan, gates, po)) return set_error(QSIM_ERR_UNSUPPORTED, "the planner could not place every op");
     // compiled tiles for fixed circuits only: the split form's structure
     // depends on the gate values, so a parameter sweep would recompile
     bool parametric = false;
@@ -703,7 +703,8 @@ qsim_status qsim_plan_summary(int n, qsim_dtype dtype, const qsim_circuit *c, co
     Plan plan;
     plan.n = n;
     plan.dtype = dtype;
-    build_plan(plan, gates, resolve_options(opts, n, dtype));
+    if (!build_plan(plan, gates, resolve_options(opts, n, dtype)))
+        return set_error(QSIM_ERR_UNSUPPORTED, "the planner could not place every op");
     int64_t cnt[QSIM_KCLASS_COUNT_] = {0};
     double by = 0.0, fl = 0.0;
     for (const Pass &p : plan.passes) {
@@ -790,12 +791,12 @@ qsim_status qsim_adjoint_grad(qsim_state s, const qsim_circuit *c, const double 
     rev->dtype = s->dtype;
     // 2^10 amplitudes per state and tile for both precisions: measured on the
     // 20-qubit ansatz, smaller tiles put more workgroups on the chip
-    const int adj_m = 10;
-    build_adjoint_plan(*rev, items, adj_m);
+    // (wider when a gate needs more tile positions)
+    const int mtile = build_adjoint_plan(*rev, items, 10);
+    if (mtile < 0) return set_error(QSIM_ERR_UNSUPPORTED, "the planner could not place every op");
     st = upload_plan(s, *rev);
     if (st != QSIM_OK) return st;
     const int nprobes = int(slot_param.size());
-    const int mtile = std::min(s->n, adj_m);
     const int ntiles = 1 << (s->n - mtile);
     // scratch: [energy partials][groups][terms][probe partials][probe sums + energy]
     struct DevGroup {

@@ -57,6 +57,11 @@ void load_file_locked() {
     unsigned long long h;
     int n, dt, fk, tm, mf;
     while (std::fscanf(f, "%llx %d %d %d %d %d", &h, &n, &dt, &fk, &tm, &mf) == 6) {
+        // the file is outside the library's control: keep only option sets
+        // the ABI would accept from a caller
+        const bool ok = (dt == QSIM_C64 || dt == QSIM_C128) && n >= 1 && n <= 35 && fk >= 0 && fk <= QSIM_MAX_K &&
+                        (tm == -1 || tm == 0 || (tm >= 7 && tm <= 13)) && mf >= -1 && mf <= 1;
+        if (!ok) continue;
         qsim_options o{};
         o.fuse_k = fk;
         o.tile_m = tm;

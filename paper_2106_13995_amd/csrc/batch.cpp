@@ -185,7 +185,11 @@ qsim_status qsim_batch_create(int ncirc, const qsim_circuit *circs, const int64_
             Plan plan;
             plan.n = c.n;
             plan.dtype = dtype;
-            build_tile_plan(plan, dir == 0 ? fwd : rev, bp.m);
+            // batch tiles hold L + 6 qubits, so the planner never widens them
+            if (build_tile_plan(plan, dir == 0 ? fwd : rev, bp.m) != bp.m) {
+                delete b;
+                return fail(QSIM_ERR_UNSUPPORTED, "a batch program: the planner could not place every op");
+            }
             if (dir == 0 && plan.passes.empty()) {
                 // one empty forward pass initialises psi
                 Pass p;

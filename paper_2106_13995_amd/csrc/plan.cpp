@@ -326,7 +326,20 @@ struct TileBuilder {
 // well inside the LDS next to its tile(s).
 static const size_t kMaxOpsPerPass = 128;
 
-static void group_tiles(TileBuilder &tb, const std::vector<HostGate> &gates) {
+// Smallest tile that holds every gate next to the low L qubits: a gate whose
+// qubits lie outside the low L needs L + (those qubits) tile positions.
+static int tile_m_for(const std::vector<HostGate> &gates, int m, int n, int dtype) {
+    const int L = std::min(m, low_tile_qubits(dtype));
+    const uint64_t low = (1ull << L) - 1;
+    int need = m;
+    for (const HostGate &g : gates)
+        if (!is_diagonal(g)) need = std::max(need, L + __builtin_popcountll(qmask(g) & ~low));
+    return std::min(n, need);
+}
+
+// Returns false if some gate could not be placed in any pass (the caller
+// reports an error rather than applying part of the circuit).
+static bool group_tiles(TileBuilder &tb, const std::vector<HostGate> &gates) {
     const uint64_t low = (1ull << tb.L) - 1;
     const int r = tb.m - 8;
     const bool reg_ctl = tb.reg && r >= 3 && r <= kRegBitsMax;
@@ -375,7 +388,7 @@ static void group_tiles(TileBuilder &tb, const std::vector<HostGate> &gates) {
                     blocked |= gm;
                 }
             }
-            if (idx.empty()) return;   // cannot happen: k <= 6 < m - L
+            if (idx.empty()) return false;   // the tile cannot hold the gate at `first`
             std::vector<const HostGate *> chosen;
             for (size_t i : idx) chosen.push_back(&gates[i]);
             if (!tb.emit(q, chosen, any_relaxed)) continue;
@@ -383,22 +396,25 @@ static void group_tiles(TileBuilder &tb, const std::vector<HostGate> &gates) {
             remaining -= idx.size();
             placed = true;
         }
-        if (!placed) return;
+        if (!placed) return false;
     }
+    return true;
 }
 
-void build_tile_plan(Plan &plan, const std::vector<HostGate> &items, int tile_m) {
-    TileBuilder tb(plan, plan.n, plan.dtype, std::min(plan.n, tile_m), false);
-    group_tiles(tb, items);
+int build_tile_plan(Plan &plan, const std::vector<HostGate> &items, int tile_m) {
+    const int m = tile_m_for(items, std::min(plan.n, tile_m), plan.n, plan.dtype);
+    TileBuilder tb(plan, plan.n, plan.dtype, m, false);
+    plan.items = int(items.size());
+    return group_tiles(tb, items) ? m : -1;
 }
 
-void build_adjoint_plan(Plan &plan, const std::vector<HostGate> &items, int tile_m) {
-    TileBuilder tb(plan, plan.n, plan.dtype, std::min(plan.n, tile_m), false);
-    group_tiles(tb, items);
+int build_adjoint_plan(Plan &plan, const std::vector<HostGate> &items, int tile_m) {
+    const int m = build_tile_plan(plan, items, tile_m);
     for (Pass &p : plan.passes) p.bytes *= 2.0;   // two states per pass
+    return m;
 }
 
-void build_plan(Plan &plan, const std::vector<HostGate> &gates_in, const PlanOptions &po) {
+bool build_plan(Plan &plan, const std::vector<HostGate> &gates_in, const PlanOptions &po) {
     const int n = plan.n, dtype = plan.dtype;
     std::vector<HostGate> gates = fuse_gates(gates_in, po.fuse_k);
     const int per_block = int(gates_in.size());
@@ -433,12 +449,16 @@ void build_plan(Plan &plan, const std::vector<HostGate> &gates_in, const PlanOpt
         }
     } else {
         if (po.reg_tiles && po.split_1q) gates = split_single_qubit(gates, n);
-        TileBuilder tb(plan, n, dtype, po.tile_m, po.reg_tiles);
-        group_tiles(tb, gates);
+        TileBuilder tb(plan, n, dtype, tile_m_for(gates, po.tile_m, n, dtype), po.reg_tiles);
+        plan.items = int(gates.size());
+        if (!group_tiles(tb, gates)) return false;
+        return true;
     }
     // logical gate counts for sweep passes
+    plan.items = int(gates.size());
     for (Pass &p : plan.passes)
         if (p.kind != PASS_TILE) p.logical_gates = 1;
+    return true;
 }
 
 }  // namespace qsim

@@ -176,6 +176,7 @@ struct Plan {
     int n = 0;
     int dtype = 0;
     std::vector<Pass> passes;
+    int items = 0;                    // gates handed to the pass grouping
     std::vector<TileOp> tile_ops;
     std::vector<cd> tile_pool;        // matrices / diagonals of tile ops
     std::vector<RegOp> reg_ops;
@@ -224,16 +225,20 @@ PlanOptions resolve_options(const qsim_options *o, int n, int dtype);
 bool tuned_options(const qsim_circuit *c, int n, int dtype, qsim_options *out);
 void remember_tuning(const qsim_circuit *c, int n, int dtype, const qsim_options &o);
 
-// Builds passes from normalised gates.
-void build_plan(Plan &plan, const std::vector<HostGate> &gates, const PlanOptions &po);
+// Builds passes from normalised gates.  Tile passes are widened when a gate
+// would not fit next to the low qubits of a 2^tile_m tile.  Returns false if
+// a gate could not be placed (nothing of the plan may then be run).
+bool build_plan(Plan &plan, const std::vector<HostGate> &gates, const PlanOptions &po);
 
 // Reverse-sweep plan of the adjoint method: tile passes over (psi, lambda)
 // holding, for each op from last to first, its probe (if parametric) and its
-// inverse.
-void build_adjoint_plan(Plan &plan, const std::vector<HostGate> &items, int tile_m);
+// inverse.  Returns the tile width used (tile_m, or more when a gate needs
+// it), or -1 if a gate could not be placed.
+int build_adjoint_plan(Plan &plan, const std::vector<HostGate> &items, int tile_m);
 
-// LDS-resident tile passes (no register staging) over the given ops.
-void build_tile_plan(Plan &plan, const std::vector<HostGate> &items, int tile_m);
+// LDS-resident tile passes (no register staging) over the given ops; returns
+// the tile width used, or -1 as build_adjoint_plan.
+int build_tile_plan(Plan &plan, const std::vector<HostGate> &items, int tile_m);
 
 // Fusion: greedy merge into blocks of at most fuse_k qubits.
 std::vector<HostGate> fuse_gates(const std::vector<HostGate> &gates, int fuse_k);

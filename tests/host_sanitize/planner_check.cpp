@@ -55,11 +55,21 @@ int main(int argc, char **argv) {
         c.ops = ops.data();
         c.mats = mats.data();
         c.nmats = nmats;
+        // the tuning table (read from QSIM_TUNE_CACHE on first use); a loaded
+        // entry must be an option set the ABI accepts
+        {
+            qsim_options tuned{};
+            for (int dt : {QSIM_C64, QSIM_C128})
+                if (tuned_options(&c, n, dt, &tuned) &&
+                    (tuned.fuse_k < 0 || tuned.fuse_k > QSIM_MAX_K || (tuned.tile_m > 0 && tuned.tile_m < 7)))
+                    return 10;
+        }
         // (fuse_k, tile_m, use_mfma, split_1q): automatic; sweeps; matrix-core
         // blocks; tiles of several sizes, fused or not; complex 2x2 form; LDS tiles
         const qsim_options opts[] = {{0, 0, 0, 0},  {1, -1, 0, 0}, {2, -1, 0, 0}, {3, -1, 0, 0},  {4, -1, 1, 0},
                                      {5, -1, 0, 0}, {6, -1, 1, 0}, {1, 12, 0, 0}, {1, 13, 0, 0},  {2, 12, 0, 0},
-                                     {3, 11, 0, 0}, {5, 12, 0, 0}, {2, 0, 0, 0},  {1, 12, 0, -1}, {1, 9, 0, 0}};
+                                     {3, 11, 0, 0}, {5, 12, 0, 0}, {2, 0, 0, 0},  {1, 12, 0, -1}, {1, 9, 0, 0},
+                                     {5, 9, 0, 0},  {1, 7, 0, 0},  {6, 10, 0, 0}, {6, 7, -1, 0}};
         for (int dt : {QSIM_C64, QSIM_C128}) {
             if (n > (dt == QSIM_C64 ? 35 : 34)) continue;
             for (const qsim_options &o : opts) {
@@ -81,7 +91,18 @@ int main(int argc, char **argv) {
                 Plan plan;
                 plan.n = n;
                 plan.dtype = dt;
-                build_plan(plan, gates, resolve_options(&o, n, dt));
+                if (!build_plan(plan, gates, resolve_options(&o, n, dt))) {
+                    std::fprintf(stderr, "%s: build_plan failed\n", argv[f]);
+                    return 6;
+                }
+                // every gate handed to the grouping lands in exactly one pass
+                long placed = 0;
+                for (const Pass &p : plan.passes) placed += p.logical_gates;
+                if (placed != plan.items) {
+                    std::fprintf(stderr, "%s: options (%d,%d,%d,%d): %ld of %d gates placed\n", argv[f], o.fuse_k,
+                                 o.tile_m, o.use_mfma, o.split_1q, placed, plan.items);
+                    return 7;
+                }
                 std::vector<int> which;
                 std::vector<double> flops;
                 const std::string src = jit_source(plan, which, &flops);
@@ -93,7 +114,13 @@ int main(int argc, char **argv) {
             Plan adj;
             adj.n = n;
             adj.dtype = dt;
-            build_adjoint_plan(adj, gates, std::min(n, 10));
+            if (build_adjoint_plan(adj, gates, std::min(n, 10)) < 0) return 8;
+            long placed = 0;
+            for (const Pass &p : adj.passes) placed += p.logical_gates;
+            if (placed != adj.items) {
+                std::fprintf(stderr, "%s: adjoint plan placed %ld of %d gates\n", argv[f], placed, adj.items);
+                return 9;
+            }
             passes += long(adj.passes.size());
         }
     }

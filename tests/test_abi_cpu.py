@@ -207,3 +207,30 @@ def test_plan_summary_rejects_bad_ops_without_device():
     bad = W.Circuit(8, [W.Op("cz", (2, 2))])
     with pytest.raises(q.QsimError):
         _summary(bad)
+
+
+@pytest.mark.parametrize("fuse_k,tile_m", [(1, 7), (1, 8), (1, 9), (5, 9), (3, 7), (6, 10)])
+def test_small_tiles_place_every_gate(fuse_k, tile_m):
+    # A tile of 2^m amplitudes keeps its low 5 (c64) / 4 (c128) qubits for
+    # contiguous HBM runs; a gate on qubits outside them needs more positions
+    # than a small m leaves.  The planner must widen the tile rather than
+    # drop the gate: the arithmetic of the tile plan equals that of one sweep
+    # per (fused) gate.
+    for circ in (W.random_grid_circuit(4, 4, depth=20, seed=2),
+                 W.Circuit(14, [W.op("h", 0), W.op("ccx", 10, 11, 12), W.op("h", 13)])):
+        for dtype in (1, 2):
+            _, _, f_sweep = _summary(circ, dtype=dtype, fuse_k=fuse_k, tile_m=-1, use_mfma=1)
+            c_t, b_t, f_t = _summary(circ, dtype=dtype, fuse_k=fuse_k, tile_m=tile_m, split_1q=-1)
+            assert c_t["tile"] >= 1
+            assert f_t == pytest.approx(f_sweep, rel=1e-12), (dtype, f_t, f_sweep)
+
+
+def test_six_qubit_block_outside_low_qubits_in_small_tiles():
+    rng = np.random.default_rng(11)
+    circ = W.Circuit(14, [W.matrix_op(list(range(8, 14)), W.random_unitary(6, rng))])
+    N = 2 ** 14
+    for dtype in (1, 2):
+        for tile_m in (7, 10):
+            c, b, f = _summary(circ, dtype=dtype, fuse_k=1, tile_m=tile_m)
+            assert c["tile"] == 1 and f == 8 * 64 * N
+

@@ -162,6 +162,49 @@ def test_ansatz20_full_size(q):
     s64.close()
 
 
+@pytest.mark.parametrize("dtype,bar", [("c128", 1e-10), ("c64", 1e-4)])
+def test_ansatz20_sampled_gradient_against_oracle_shift(q, dtype, bar):
+    """Eight seeded entries of the 400-parameter gradient at 20 qubits against
+    the oracle's parameter-shift rule (16 complex128 CPU forward runs), and
+    the energy against the oracle's."""
+    n, layers = 20, 10
+    circ = W.ansatz_circuit(n, layers)
+    p = W.ansatz_params(n, layers, seed=4)
+    H = W.chain_observable(n)
+    s = q.State(n, dtype)
+    e, g = s.adjoint_grad(circ, p, H)
+    s.close()
+    sample = np.random.default_rng(47).choice(p.size, size=8, replace=False)
+    ps = O.param_shift_grad(circ, p, H, indices=sample, threaded=True)
+    assert rel(g[sample], ps[sample]) < bar, (g[sample], ps[sample])
+    assert abs(e - O.energy(circ, p, H, threaded=True)) < (1e-11 if dtype == "c128" else 1e-4)
+
+
+@pytest.mark.parametrize("dtype,bar", [("c128", 1e-10), ("c64", 1e-4)])
+def test_six_qubit_matrix_outside_the_low_qubits(q, dtype, bar):
+    """A dense 6-qubit block on qubits 8..13 of a 14-qubit circuit: the
+    reverse sweep's 2^10 tiles hold only 5 (c64) / 6 (c128) positions beyond
+    the low qubits, so the planner widens them; the gradient must still
+    match the oracle's parameter shift."""
+    n = 14
+    rng = np.random.default_rng(48)
+    ops, npar = [], 0
+    for qb in range(n):
+        ops.append(W.op("ry", qb, param=npar)); npar += 1
+    ops.append(W.matrix_op(list(range(8, 14)), W.random_unitary(6, rng)))
+    for qb in range(0, n, 3):
+        ops.append(W.op("rz", qb, param=npar)); npar += 1
+    ops.append(W.op("cx", 2, 11))
+    circ = W.Circuit(n, ops, npar)
+    p = rng.uniform(0, 2 * np.pi, npar)
+    H = W.chain_observable(n)
+    s = q.State(n, dtype)
+    e, g = s.adjoint_grad(circ, p, H)
+    s.close()
+    assert rel(g, O.param_shift_grad(circ, p, H)) < bar
+    assert abs(e - O.energy(circ, p, H)) < (1e-12 if dtype == "c128" else 1e-5)
+
+
 def test_autograd_function(q):
     torch = pytest.importorskip("torch")
     n, layers = 5, 2

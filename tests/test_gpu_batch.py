@@ -122,4 +122,10 @@ def test_batch_4096_full_size(q):
     for i in small:
         ref = O.energy(circs[i], params[offs[i]:offs[i + 1]], obs[i])
         assert abs(e[i] - ref) < 2e-5 * max(1.0, abs(ref))
+    # whole gradients of four n <= 12 circuits against the oracle's parameter
+    # shift (complex64 adjoint against complex128 shift: the 1e-4 bar)
+    for i in [i for i in range(4096) if circs[i].n <= 12][:4]:
+        p = params[offs[i]:offs[i + 1]]
+        ps = O.param_shift_grad(circs[i], p, obs[i], threaded=True)
+        assert rel(g[offs[i]:offs[i + 1]], ps) < 1e-4, i
     b.close()

@@ -92,7 +92,8 @@ def test_grid30_c64_full_circuit_properties(env):
     assert O.rel_l2(sweep, a128) <= 2e-5
 
 
-@pytest.mark.parametrize("mode", [dict(), dict(fuse_k=1, tile_m=-1)])
+@pytest.mark.parametrize("mode", [dict(), dict(fuse_k=1, tile_m=-1), dict(fuse_k=1, tile_m=12),
+                                  dict(fuse_k=1, tile_m=13)], ids=["auto", "sweeps", "tile12", "tile13"])
 def test_multiplier29_basis_inputs_bit_exact(env, mode):
     """The 29-qubit multiplier (7-bit a, b; 14-bit product; ancilla), complex64,
     on the 64 seed-drawn basis inputs: amplitude exactly 1 at a + 2^7 b + 2^14 ab

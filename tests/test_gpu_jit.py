@@ -20,6 +20,8 @@ TOL = {"c64": 2e-5, "c128": 1e-12}
 MODES = {
     "tile": dict(fuse_k=1, tile_m=0),
     "tile12": dict(fuse_k=1, tile_m=12),
+    "tile13": dict(fuse_k=1, tile_m=13),   # the benchmark's tuned choice (c128 holds 2^12)
+    "tile11": dict(fuse_k=1, tile_m=11),
     "tile_complex": dict(fuse_k=1, tile_m=0, split_1q=-1),
     "fuse2_tile": dict(fuse_k=2, tile_m=0),
     "fuse3_tile": dict(fuse_k=3, tile_m=0),
@@ -78,7 +80,7 @@ def test_random_mixed_circuit(qs, dtype, mode):
 
 
 @pytest.mark.parametrize("dtype", ["c64", "c128"])
-@pytest.mark.parametrize("mode", ["tile", "tile12", "fuse2_tile"])
+@pytest.mark.parametrize("mode", ["tile", "tile12", "tile13", "fuse2_tile"])
 def test_controlled_blocks(qs, dtype, mode):
     """CX, CCX and random 2 x 2 blocks under one or two controls, whose
     controls the compiled passes take as register, lane and block masks."""
@@ -95,7 +97,7 @@ def test_controlled_blocks(qs, dtype, mode):
 
 
 @pytest.mark.parametrize("dtype", ["c64", "c128"])
-@pytest.mark.parametrize("mode", ["tile", "tile12", "tile_complex"])
+@pytest.mark.parametrize("mode", ["tile", "tile11", "tile12", "tile13", "tile_complex"])
 def test_grid_circuit_16q(qs, dtype, mode):
     circ = W.random_grid_circuit(4, 4, depth=12, seed=2)
     s = _state(qs, 16, dtype)
@@ -103,16 +105,18 @@ def test_grid_circuit_16q(qs, dtype, mode):
     assert O.rel_l2(s.to_numpy(), O.apply_circuit(circ)) <= TOL[dtype]
 
 
-def test_grid_circuit_20q_c64(qs):
+@pytest.mark.parametrize("dtype,tile_m", [("c64", 12), ("c64", 13), ("c128", 11), ("c128", 12)])
+def test_grid_circuit_20q(qs, dtype, tile_m):
     """A 5 x 4 grid at the full depth of the benchmark circuit: many passes,
-    each with several register stages."""
+    each with several register stages, at the tile sizes the benchmark's
+    tuner chooses between."""
     circ = W.random_grid_circuit(5, 4, depth=20, seed=2)
-    s = _state(qs, 20, "c64")
+    s = _state(qs, 20, dtype)
     s.profile(True)
-    s.apply_circuit(circ, fuse_k=1, tile_m=12)
+    s.apply_circuit(circ, fuse_k=1, tile_m=tile_m)
     launches, _, _, _ = s.profile_read("tile_jit")
     assert launches > 0 and s.profile_read("tile")[0] == 0   # every tile pass compiled
-    assert O.rel_l2(s.to_numpy(), O.apply_circuit(circ)) <= TOL["c64"]
+    assert O.rel_l2(s.to_numpy(), O.apply_circuit(circ)) <= TOL[dtype]
 
 
 @pytest.mark.parametrize("family", ["supremacy", "multiplier"])

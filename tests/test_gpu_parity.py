@@ -28,6 +28,12 @@ MODES = {
     "tile_complex": dict(fuse_k=1, tile_m=0, split_1q=-1),
     "tile12_split": dict(fuse_k=1, tile_m=12, split_1q=1),
     "fuse2_tile": dict(fuse_k=2, tile_m=0),
+    "tile13": dict(fuse_k=1, tile_m=13),
+    # tiles narrower than the low qubits plus the widest gate: widened by the
+    # planner (gates outside the low 5 / 4 qubits need more positions)
+    "tile7": dict(fuse_k=1, tile_m=7),
+    "fuse5_tile9": dict(fuse_k=5, tile_m=9),
+    "fuse6_tile10": dict(fuse_k=6, tile_m=10),
 }
 
 
@@ -382,8 +388,47 @@ def test_expectation_tiled_and_wide_groups(qs, dtype):
     H = W.PauliSum(n, coeffs, xs, zs)
     s = _state(qs, n, dtype, psi)
     got = s.expectation(H)
+    # the device reads the same (rounded) amplitudes the oracle is given and
+    # accumulates in double: only summation order separates the two
     ref = O.expectation(psi, H)
-    assert abs(got - ref) <= (1e-4 if dtype == "c64" else 1e-11) * max(1.0, abs(ref))
+    scale = sum(abs(c) for c in H.coeffs)
+    assert abs(got - ref) <= 1e-10 * scale, (got, ref)
+    s.close()
+
+
+@pytest.mark.parametrize("dtype", ["c64", "c128"])
+def test_expectation_product_state_terms_of_order_one(qs, dtype):
+    """A product state where every term of the chain observable and of single
+    Y terms is O(1), so a dropped, doubled or sign-flipped term moves the sum
+    by O(1): against the oracle on the rounded input and the product closed
+    form (<Z_i Z_j> = <Z_i><Z_j>, <X_i>, <Y_i> from each qubit's Bloch vector)."""
+    n = 20
+    rng = np.random.default_rng(113)
+    ops = [W.op("u3", qb, angles=(0.3 + 0.1 * (qb % 7), 0.2 * qb, 0.0)) for qb in range(n)]
+    circ = W.Circuit(n, ops)
+    s = _state(qs, n, dtype)
+    s.apply_circuit(circ, fuse_k=1, tile_m=-1)
+    psi = s.to_numpy().astype(np.complex128)
+    coeffs, xs, zs = [], [], []
+    for i in range(n - 1):
+        coeffs.append(1.0 + 0.05 * i); xs.append(0); zs.append((1 << i) | (1 << (i + 1)))
+    for i in range(n):
+        coeffs.append(0.5); xs.append(1 << i); zs.append(0)
+        coeffs.append(-0.25); xs.append(1 << i); zs.append(1 << i)
+    H = W.PauliSum(n, coeffs, xs, zs)
+    got = s.expectation(H)
+    assert abs(got - O.expectation(psi, H)) <= 1e-10 * sum(abs(c) for c in coeffs)
+    # closed form from the single-qubit states u3|0>
+    bloch = []
+    for o in ops:
+        v = O.gate_matrix("u3", o.angles)[:, 0]
+        bloch.append((2 * (np.conj(v[0]) * v[1]).real, 2 * (np.conj(v[0]) * v[1]).imag,
+                      abs(v[0]) ** 2 - abs(v[1]) ** 2))
+    closed = sum(c * bloch[i][2] * bloch[i + 1][2] for i, c in zip(range(n - 1), coeffs))
+    closed += sum(0.5 * bloch[i][0] - 0.25 * bloch[i][1] for i in range(n))
+    assert abs(got - closed) <= (1e-5 if dtype == "c64" else 1e-12) * sum(abs(c) for c in coeffs)
+    assert min(abs(b[2]) for b in bloch) > 0.2        # every ZZ term is O(1)
+    s.close()
 
 
 def test_plan_cache_eviction_and_stream_switch(qs):

@@ -78,6 +78,9 @@ def test_planner_under_sanitizers(tmp_path):
         (controlled_blocks(14, 200, rng), None),
         (W.ansatz_circuit(20, 10), W.ansatz_params(20, 10, seed=4)),
         (W.random_line_circuit(5, 8, seed=1), None),
+        # gates wider than a small tile's free positions (the tile is widened)
+        (W.Circuit(14, [W.op("h", 0), W.op("ccx", 10, 11, 12)]), None),
+        (W.Circuit(14, [W.matrix_op(list(range(8, 14)), W.random_unitary(6, rng)), W.op("h", 3)]), None),
     ]
     files = []
     for i, (c, p) in enumerate(circuits):
@@ -93,8 +96,11 @@ def test_planner_under_sanitizers(tmp_path):
     build = subprocess.run(["g++", *flags, *srcs, "-o", exe, "-L/opt/rocm/lib", "-lamdhip64", "-lhiprtc",
                             "-Wl,-rpath,/opt/rocm/lib"], capture_output=True, text=True)
     assert build.returncode == 0, build.stderr[-3000:]
+    # a tuning cache with lines outside the accepted option ranges and junk
+    cache = tmp_path / "tune.txt"
+    cache.write_text("deadbeef 12 1 9 7 0\nabc 12 1 1 99 0\n1 14 2 2 3 0\n12 oops\n")
     env = dict(os.environ, ASAN_OPTIONS="detect_leaks=0:abort_on_error=1",
-               UBSAN_OPTIONS="halt_on_error=1:print_stacktrace=1", QSIM_JIT="0")
+               UBSAN_OPTIONS="halt_on_error=1:print_stacktrace=1", QSIM_JIT="0", QSIM_TUNE_CACHE=str(cache))
     run = subprocess.run([exe, *files], capture_output=True, text=True, env=env, timeout=600)
     assert run.returncode == 0, (run.stdout[-2000:], run.stderr[-4000:])
     assert "planner check:" in run.stdout

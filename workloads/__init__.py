@@ -421,3 +421,28 @@ def random_state(n: int, rng: np.random.Generator, normalise: bool = True) -> np
     if normalise:
         v /= np.sqrt(np.vdot(v, v).real)
     return v
+
+
+def sample_indices(n: int, count: int, seed: int) -> np.ndarray:
+    """Sorted distinct amplitude indices drawn uniformly from [0, 2^n)
+    (numpy PCG64 seeded by `seed`); used to compare states too large to
+    copy whole."""
+    rng = np.random.default_rng(seed)
+    idx = np.unique(rng.integers(0, 1 << n, size=count, dtype=np.uint64))
+    return idx
+
+
+def circuit_digest(circ: Circuit) -> str:
+    """SHA-256 over the op list (kinds, qubits, angles, parameter slots,
+    matrices): identifies a generated workload in stored reference files."""
+    import hashlib
+    h = hashlib.sha256()
+    h.update(f"{circ.n}:{circ.nparams}".encode())
+    for o in circ.ops:
+        h.update(o.kind.encode())
+        h.update(np.asarray(o.targets, dtype=np.int64).tobytes())
+        h.update(np.asarray(o.angles, dtype=np.float64).tobytes())
+        h.update(np.int64(o.param).tobytes())
+        if o.matrix is not None:
+            h.update(np.ascontiguousarray(o.matrix, dtype=np.complex128).tobytes())
+    return h.hexdigest()
