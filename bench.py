@@ -49,7 +49,10 @@ def parse():
     ap.add_argument("--fuse-k", type=int, default=0)
     ap.add_argument("--tile-m", type=int, default=0)
     ap.add_argument("--modes", default="", help="comma list of extra fuse_k:tile_m[:split_1q] variants to time")
-    ap.add_argument("--cpu-gates", type=int, default=4, help="gates of the circuit the oracle times")
+    ap.add_argument("--cpu-gates", type=int, default=2, help="gates of the circuit the oracle times on one thread")
+    ap.add_argument("--cpu-threaded-gates", type=int, default=12,
+                    help="further gates the oracle's OpenMP build times on every host thread")
+    ap.add_argument("--no-interp", action="store_true", help="skip the interpreted (QSIM_JIT=0) variant")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--calib-copy", action="store_true", help="run a plain device copy of the state size")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the 20-qubit adjoint-gradient figure")
@@ -86,20 +89,79 @@ def measured_traffic(cls: str, config_key: str):
     return rec.get("bytes_per_launch")
 
 
-def cpu_baseline(circ, ngates: int):
-    """The CPU oracle (complex128, one thread) on the first `ngates` gates of
-    the same circuit at full width."""
+def host_info() -> dict:
+    """CPU model, logical CPUs and memory of the host the oracle runs on."""
+    info = {"nproc": os.cpu_count()}
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    info["cpu_model"] = line.split(":", 1)[1].strip()
+                    break
+        with open("/proc/meminfo") as f:
+            for line in f:
+                if line.startswith("MemTotal"):
+                    info["mem_gib"] = round(int(line.split()[1]) / 2 ** 20, 1)
+                    break
+    except OSError:
+        pass
+    return info
+
+
+def cpu_baseline(circ, single_gates: int, threaded_gates: int):
+    """The CPU oracle (complex128) on the first gates of the same circuit at
+    full width, gate loop only (the 2^n-amplitude state is allocated and its
+    pages touched before the clock starts): `single_gates` on one thread,
+    then the next `threaded_gates` with the oracle's OpenMP build on every
+    host thread (same per-amplitude arithmetic)."""
     import oracle as O
     import workloads as W
-    sub = W.Circuit(circ.n, circ.ops[:ngates], 0, circ.name + f"_first{ngates}")
-    psi = O.basis_state(circ.n)
+    psi = np.zeros(1 << circ.n, dtype=np.complex128)
+    psi.view(np.float64)[::512] = 0.0          # touch every page before timing
+    psi[0] = 1.0
+    ops = circ.ops
+    one = W.Circuit(circ.n, ops[:single_gates], 0)
     t0 = time.perf_counter()
-    O.apply_circuit(sub, psi)
-    dt = time.perf_counter() - t0
+    O.apply_circuit_inplace(psi, one)
+    dt1 = time.perf_counter() - t0
+    many = W.Circuit(circ.n, ops[single_gates:single_gates + threaded_gates], 0)
+    threads = int(os.environ.get("OMP_NUM_THREADS") or os.cpu_count() or 1)
+    t0 = time.perf_counter()
+    O.apply_circuit_inplace(psi, many, threaded=True)
+    dtn = time.perf_counter() - t0
     del psi
-    return {"value": round(ngates / dt, 4), "unit": "gate-apps/s", "cores": 1, "kind": "oracle",
-            "sample": f"first {ngates} gates (U3) of the same {circ.n}-qubit circuit, complex128 oracle, "
-                      f"1 thread, {dt:.1f} s (includes one copy of the 2^{circ.n}-amplitude input)"}
+    kinds = sorted({o.kind for o in ops[:single_gates + threaded_gates]})
+    return {"value": round(threaded_gates / dtn, 4), "unit": "gate-apps/s", "cores": threads, "kind": "oracle",
+            "sample": f"gates {single_gates + 1}-{single_gates + threaded_gates} ({'/'.join(kinds)}) of the same "
+                      f"{circ.n}-qubit circuit, complex128 oracle, OpenMP build on {threads} threads, "
+                      f"{dtn:.1f} s, gate loop only",
+            "single_thread": {"value": round(single_gates / dt1, 4), "unit": "gate-apps/s", "cores": 1,
+                              "sample": f"gates 1-{single_gates}, one thread, {dt1:.1f} s"},
+            "host": host_info()}
+
+
+def oracle_check(torch, q, W, circ, dtype, opts):
+    """The circuit applied once to |0...0> with the benchmark's options,
+    against the stored complex128 oracle output of the same circuit (65 536
+    seeded amplitudes and the chain-observable energy)."""
+    path = os.path.join(ROOT, "tests", "golden", "grid30_d20_s2.npz")
+    if circ.n != 30 or not os.path.exists(path):
+        return None
+    z = np.load(path, allow_pickle=False)
+    if str(z["digest"]) != W.circuit_digest(circ):
+        return None
+    idx = W.sample_indices(30, int(z["sample_count"]), int(z["sample_seed"])).astype(np.int64)
+    s = q.State(30, dtype)
+    s.apply_circuit(circ, **opts)
+    t = s.tensor.view(-1, 2)
+    sel = t[torch.as_tensor(idx, device=t.device)].double().cpu().numpy()
+    got = sel[:, 0] + 1j * sel[:, 1]
+    ref = z["amps"]
+    energy = s.expectation(W.chain_observable(30))
+    s.close()
+    return {"rel_l2_samples": float(np.linalg.norm(got - ref) / np.linalg.norm(ref)),
+            "energy_abs_err": abs(energy - float(z["energy"])), "samples": int(idx.size),
+            "reference": "tests/golden/grid30_d20_s2.npz (complex128 oracle)"}
 
 
 def expectation_bench(torch, q, W, s, reps: int = 5):
@@ -147,44 +209,62 @@ def time_mode(torch, s, circ, steps, warmup, fuse_k, tile_m, split_1q=0):
     return wall, ev_ms, stats
 
 
-def adjoint_bench(torch, q, W, dtype: str, reps: int = 5, shift_sample: int = 16):
+def adjoint_bench(torch, q, W, dtype: str, reps: int = 10, shift_sample: int = 16):
     """Energy + full gradient of the 20-qubit, 10-layer RY.RZ + CNOT-ladder
     ansatz (400 parameters) with sum Z_iZ_{i+1} + 0.5 sum X_i, by the adjoint
-    method with fresh parameters every call, against the parameter-shift rule
-    on the same GPU (two forward runs and expectations per parameter; timed
-    on a sample, scaled to 400)."""
+    method with fresh parameters every call, all on the device (parameters,
+    energy and gradient stay there; no host wait inside the loop), against the
+    parameter-shift rule on the same GPU (two forward runs and expectations
+    per parameter; timed on a sample, scaled to 400).  Bytes: every pass's
+    algorithmic state traffic (the forward tiles, lambda = H psi, the reverse
+    tiles over psi and lambda); the 8-16 MiB states stay in the 256 MB
+    Infinity Cache, so the rate is quoted against HBM only for scale."""
     n, layers = 20, 10
-    circ = W.ansatz_circuit(n, layers)
+    circ = q.PackedCircuit(W.ansatz_circuit(n, layers))
     p = W.ansatz_params(n, layers, seed=4)
     H = W.chain_observable(n)
     s = q.State(n, dtype)
-    e, g = s.adjoint_grad(circ, p, H)
+    p_dev = torch.as_tensor(p, dtype=torch.float64, device="cuda")
+    e, g = s.adjoint_grad_device(circ, p_dev, H)
     torch.cuda.synchronize()
-    # new parameters on every call, as in a training loop (no plan is reused)
+    energy = float(e.cpu()[0])
+    # new parameters on every call, as in a training loop
+    steps = [p_dev + 1e-3 * (r + 1) for r in range(reps)]
+    torch.cuda.synchronize()
+    s.profile(True)
     t0 = time.perf_counter()
     for r in range(reps):
         s.set_basis(0)
-        s.adjoint_grad(circ, p + 1e-3 * (r + 1), H)
+        s.adjoint_grad_device(circ, steps[r], H)
     torch.cuda.synchronize()
     adj = (time.perf_counter() - t0) / reps
+    kms, kbytes = 0.0, 0.0
+    for cls in ("tile", "expect", "adjoint"):
+        cnt, ms, by, fl = s.profile_read(cls)
+        kms += ms
+        kbytes += by
+    s.profile(False)
     # parameter shift, same GPU, same options
-    def energy(pp):
+    def energy_at(pp):
         s.set_basis(0)
         s.apply_circuit(circ, params=pp)
         return s.expectation(H)
-    energy(p)
+    energy_at(p)
     idx = list(range(0, p.size, max(1, p.size // shift_sample)))[:shift_sample]
     t0 = time.perf_counter()
     for j in idx:
         for sh in (0.5 * np.pi, -0.5 * np.pi):
             pp = p.copy()
             pp[j] += sh
-            energy(pp)
+            energy_at(pp)
     shift = (time.perf_counter() - t0) / len(idx) * p.size
     s.close()
+    gbs = kbytes / reps / (kms / reps / 1e3) / 1e9 if kms > 0 else 0.0
     return {"workload": f"ansatz {n} qubits, {layers} layers, {p.size} parameters, {dtype}",
             "grads_per_s": round(1.0 / adj, 2), "ms_per_gradient": round(adj * 1e3, 3),
-            "energy": e, "param_shift_ms_same_gpu": round(shift * 1e3, 1),
+            "kernel_ms_per_gradient": round(kms / reps, 3), "bytes_per_gradient": kbytes / reps,
+            "gbs": round(gbs, 1), "hbm_frac": round(gbs / HBM_PEAK_GBS, 4), "memory": "MALL-resident",
+            "energy": energy, "param_shift_ms_same_gpu": round(shift * 1e3, 1),
             "speedup_vs_param_shift": round(shift / adj, 1)}
 
 
@@ -198,13 +278,24 @@ def batch_bench(torch, q, W, dtype: str = "c64", reps: int = 3, loop_sample: int
     obs = [W.chain_observable(int(n)) for n in spec.ns]
     params = np.concatenate(spec.params)
     b = q.Batch(circs, obs, dtype)
-    b.run(params)
+    p_dev = torch.as_tensor(params, dtype=torch.float64, device="cuda")
+    e_dev, g_dev = b.run_device(p_dev)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(reps):
-        b.run(params)
+        b.run_device(p_dev, e_dev, g_dev)
     torch.cuda.synchronize()
     t_batch = (time.perf_counter() - t0) / reps
+    # LDS traffic of the kernel's op-by-op tile updates (each op reads and
+    # writes its state's tile once; the reverse sweep does it for psi and
+    # lambda and each probe reads both): the bound of a persistent kernel
+    # that applies one op per barrier
+    amp = 8 if dtype == "c64" else 16
+    lds_bytes = 0.0
+    for c in circs:
+        nops, nprobe = len(c.ops), c.nparams
+        lds_bytes += (2.0 * nops + 2.0 * 2.0 * nops + 2.0 * nprobe) * (1 << c.n) * amp
+    lds_peak = 256 * 128 * 2.4e9 / 1e9
     grid, programs, _ = b.info()
     b.close()
     offs = np.concatenate([[0], np.cumsum([c.nparams for c in circs])])
@@ -229,6 +320,10 @@ def batch_bench(torch, q, W, dtype: str = "c64", reps: int = 3, loop_sample: int
                         f"{dtype}, forward + adjoint gradient",
             "circuits_per_s": round(len(circs) / t_batch, 1), "ms_per_batch": round(t_batch * 1e3, 2),
             "persistent_workgroups": grid, "programs": programs,
+            "lds_bytes_per_batch": lds_bytes, "lds_gbs": round(lds_bytes / t_batch / 1e9, 1),
+            "roofline": {"bound": "lds", "achieved": round(lds_bytes / t_batch / 1e9, 1), "peak": round(lds_peak, 1),
+                         "unit": "GB/s", "frac": round(lds_bytes / t_batch / 1e9 / lds_peak, 4),
+                         "note": "256 CUs x 128 B/clock x 2.4 GHz of LDS bandwidth"},
             "loop_ms_same_gpu": round(t_loop * 1e3, 1), "speedup_vs_loop": round(t_loop / t_batch, 1),
             "loop_sample": len(sample)}
 
@@ -431,7 +526,18 @@ def main():
     cols = a.n // rows
     circ = W.random_grid_circuit(rows, cols, depth=20, seed=2)
     ngates = len(circ.ops)
+    packed = q.PackedCircuit(circ)
     s = q.State(circ.n, a.dtype)
+    # first call in the process: planning, run-time compilation of the tile
+    # passes and one application (what a user waits for once per circuit)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    s.apply_circuit(packed, fuse_k=a.fuse_k, tile_m=a.tile_m)
+    torch.cuda.synchronize()
+    first_call_s = time.perf_counter() - t0
+    s.set_basis(0)
+    circ_arg = circ
+    circ = packed
     tuned = None
     if not a.no_tune and a.fuse_k == 0 and a.tile_m == 0:
         # warm-up: the library's autotuner picks tile size and fusion width for
@@ -445,32 +551,30 @@ def main():
     ms_per_step = ev_ms / a.steps
     value = ngates * a.steps / (ev_ms / 1e3)
 
-    # dominant kernel class by total time, and what bounds it
+    # dominant kernel class by total time.  Its bound is HBM: every pass reads
+    # and writes the whole state once (2 * 2^n * bytes per amplitude); the
+    # vector-ALU figures of the arithmetic it performs sit beside it.
     dname, (dn, dms, dby, dfl) = max(stats.items(), key=lambda kv: kv[1][1])
     sec = dms / 1e3
     hbm_gbs = dby / sec / 1e9
     alu_tfs = dfl / sec / 1e12
-    t_hbm = dby / (HBM_PEAK_GBS * 1e9)
-    t_alu = dfl / (ALU_PEAK_TFLOPS * 1e12)
-    config_key = f"grid{rows}x{cols}_d20_{a.dtype}_fuse{a.fuse_k}_tile{a.tile_m}"
+    ran = tuned["options"] if tuned else {"fuse_k": a.fuse_k, "tile_m": a.tile_m}
+    config_key = f"grid{rows}x{cols}_d20_{a.dtype}_fuse{ran['fuse_k']}_tile{ran['tile_m']}"
     traffic = measured_traffic(dname, config_key)
-    if t_alu > t_hbm:
-        roofline = {"bound": "alu", "achieved": round(alu_tfs, 2), "peak": round(ALU_PEAK_TFLOPS, 1),
-                    "unit": "TFLOP/s", "frac": round(alu_tfs / ALU_PEAK_TFLOPS, 4)}
-    else:
-        roofline = {"bound": "hbm", "achieved": round(hbm_gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                    "frac": round(hbm_gbs / HBM_PEAK_GBS, 4)}
-    roofline.update({
-        "traffic": traffic,
-        "kernel": dname, "launches": dn, "avg_launch_ms": round(dms / dn, 4),
-        "bytes_per_launch": dby / dn, "flops_per_launch": dfl / dn,
-        "hbm_gbs": round(hbm_gbs, 1), "hbm_frac": round(hbm_gbs / HBM_PEAK_GBS, 4),
-        "alu_tflops": round(alu_tfs, 2), "alu_frac": round(alu_tfs / ALU_PEAK_TFLOPS, 4),
-    })
+    roofline = {"bound": "hbm", "achieved": round(hbm_gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(hbm_gbs / HBM_PEAK_GBS, 4), "traffic": traffic,
+                "kernel": dname, "launches": dn, "avg_launch_ms": round(dms / dn, 4),
+                "bytes_per_launch": dby / dn, "flops_per_launch": dfl / dn, "counters_config": config_key,
+                "alu": {"tflops": round(alu_tfs, 2),
+                        "frac_of_78.6": round(alu_tfs / ALU_PEAK_TFLOPS, 4),
+                        "frac_of_157.3": round(alu_tfs / 157.3, 4),
+                        "note": "flops of the arithmetic the compiled passes perform; 78.6 TFLOP/s is the "
+                                "vector FP32 rate without packed instructions (kept off in this build), "
+                                "157.3 the published FP32 vector peak"}}
     total_bytes = sum(v[2] for v in stats.values())
 
     # <psi|psi> after the timed steps (unitary circuit from |0...0>)
-    norm = s.expectation(W.PauliSum(circ.n, [1.0], [0], [0]))
+    norm = s.expectation(W.PauliSum(circ_arg.n, [1.0], [0], [0]))
 
     extra = {}
     for m in [x for x in a.modes.split(",") if x]:
@@ -485,6 +589,27 @@ def main():
     s.close()
     del s
     torch.cuda.empty_cache()
+
+    # the same options once more from |0...0>, against the oracle's output
+    check = oracle_check(torch, q, W, circ_arg, a.dtype,
+                         dict(fuse_k=ran["fuse_k"], tile_m=ran["tile_m"])) if a.dtype == "c64" else None
+    torch.cuda.empty_cache()
+
+    interp = None
+    if not a.no_interp:
+        # the same options with the tile passes interpreted (no run-time
+        # compilation), on a fresh state so that no compiled plan is reused
+        os.environ["QSIM_JIT"] = "0"
+        si = q.State(circ_arg.n, a.dtype)
+        k = max(1, a.steps // 2)
+        _, e_i, st_i = time_mode(torch, si, circ, k, 1, ran["fuse_k"], ran["tile_m"])
+        si.close()
+        del si
+        os.environ.pop("QSIM_JIT")
+        torch.cuda.empty_cache()
+        interp = {"ms_per_step": round(e_i / k, 3), "gate_apps_per_s": round(ngates * k / (e_i / 1e3), 1),
+                  "passes_per_step": sum(v[0] for v in st_i.values()) // k,
+                  "kernels": sorted(st_i), "options": ran}
 
     adjoint = None
     if not a.no_adjoint:
@@ -501,7 +626,7 @@ def main():
 
     cpu = None
     if not a.no_cpu:
-        cpu = cpu_baseline(circ, a.cpu_gates)
+        cpu = cpu_baseline(circ_arg, a.cpu_gates, a.cpu_threaded_gates)
 
     out = {
         "metric": METRIC,
@@ -516,10 +641,13 @@ def main():
         "vs_baseline": None,
         "dtype": "complex64" if a.dtype == "c64" else "complex128",
         "data": "synthetic",
-        "config": {"workload": f"random supremacy-style circuit, {rows}x{cols} grid, {circ.n} qubits, depth 20, "
+        "config": {"workload": f"random supremacy-style circuit, {rows}x{cols} grid, {circ_arg.n} qubits, depth 20, "
                                f"{ngates} gates (U3 + CZ), |0...0> input, state resident in HBM",
-                   "n": circ.n, "gates": ngates, "fuse_k": a.fuse_k, "tile_m": a.tile_m,
-                   "autotuned": tuned},
+                   "n": circ_arg.n, "gates": ngates, "fuse_k": a.fuse_k, "tile_m": a.tile_m,
+                   "options_run": ran, "autotuned": tuned},
+        "first_call_s": round(first_call_s, 2),
+        "c64_vs_oracle": check,
+        "interpreted": interp,
         "hbm_gbs_algorithmic": round(total_bytes / (ev_ms / 1e3) / 1e9, 1),
         "passes_per_step": sum(v[0] for v in stats.values()) // a.steps,
         "wall_s": round(wall, 3),

@@ -25,9 +25,11 @@
  * except qsim_free returns QSIM_ERR_STATE.
  *
  * Streams and synchronisation: each state carries a HIP stream (the null
- * stream by default).  Gate and circuit calls are stream-ordered and return
- * without waiting for the device; calls that deliver a value to host memory
- * (qsim_copy_to_host, qsim_expectation) synchronise the state's stream.
+ * stream by default).  Gate, circuit and gradient calls (qsim_apply_gate,
+ * qsim_apply_circuit, qsim_adjoint_grad) and qsim_batch_run are
+ * stream-ordered and return without waiting for the device; calls that
+ * deliver a value to host memory (qsim_copy_to_host, qsim_expectation)
+ * synchronise the state's stream.
  *
  * Threads: calls on different states may run concurrently from different host
  * threads; calls on one state must be serialised by the caller.
@@ -120,50 +122,69 @@ typedef struct {
  *            on at most fuse_k qubits (products formed in double precision and
  *            rounded once); 0 = automatic.
  *   tile_m:  -1 = every gate / block is its own sweep over the state;
- *            m in [4, 13] (c64) / [4, 12] (c128) = group gates into passes
- *            that hold 2^m-amplitude tiles in LDS; 0 = automatic.
+ *            m in [7, 13] (c64) / [7, 12] (c128) = group gates into passes
+ *            that hold 2^m-amplitude tiles in LDS (larger m is clamped; a
+ *            tile is widened when a gate needs more positions next to the
+ *            low 5 (c64) / 4 (c128) qubits every tile keeps); 0 = automatic.
  *   use_mfma: -1 never, 1 whenever a fused block has k >= 4, 0 automatic.
  *   split_1q: single-qubit unitaries in tile passes.  1 (and 0, automatic):
  *            each is written as g diag(1, b) O diag(1, a) with O a real
  *            rotation; O runs as three in-place multiply-adds per amplitude
  *            component and the phases travel, merged, to the next gate that
  *            does not commute with them.  -1: every gate is applied as its
- *            complex 2 x 2 matrix.  Both are exact up to rounding. */
+ *            complex 2 x 2 matrix.  Both are exact up to rounding.
+ *   deterministic: 1 = automatic choices never consult the autotuner's table
+ *            (whose entries come from timing), so the passes, and with them
+ *            the rounding of every result, depend on the inputs alone; every
+ *            reduction already runs in a fixed order, so repeated calls give
+ *            bitwise identical results.  0 = the table is used when present. */
 typedef struct {
     int32_t fuse_k;
     int32_t tile_m;
     int32_t use_mfma;
     int32_t split_1q;
+    int32_t deterministic;
 } qsim_options;
 
 typedef struct qsim_state_s *qsim_state;
 
 /* Allocates a state of n qubits on the current HIP device, owned by the
  * library, initialised to |0...0>.  1 <= n <= 35 (c64) or 34 (c128).
- * QSIM_ERR_OOM if the device memory cannot be allocated. */
+ * QSIM_ERR_OOM if the device memory cannot be allocated.
+ * (paper, Sec. I.A: a Schroedinger-type simulator holds all 2^n amplitudes
+ * at once; its memory doubles with every qubit.) */
 qsim_status qsim_alloc(int n, qsim_dtype dtype, qsim_state *out);
 
 /* Wraps caller-owned device memory (e.g. a PyTorch tensor) holding 2^n
  * amplitudes of `dtype`, 256-byte aligned, without copying or initialising
  * it.  `hip_stream` (a hipStream_t, may be NULL) becomes the state's stream.
- * The caller keeps ownership and must keep the memory alive until qsim_free. */
+ * The caller keeps ownership and must keep the memory alive until qsim_free.
+ * (paper, Sec. I.A, Sec. II: the state vector the gates act on, here kept in
+ * device memory between gates rather than moved per operation.) */
 qsim_status qsim_wrap(void *dev_ptr, int n, qsim_dtype dtype, void *hip_stream, qsim_state *out);
 
 /* Releases the handle and, for qsim_alloc'd states, the device memory (after
- * synchronising the state's stream).  NULL is accepted. */
+ * synchronising the state's stream).  NULL is accepted.  (Sec. I.A: the
+ * state vector's lifetime.) */
 qsim_status qsim_free(qsim_state s);
 
+/* Makes `hip_stream` (a hipStream_t, may be NULL) the state's stream after
+ * waiting for the work queued on the previous one.  (Sec. II: the chain of
+ * matrix-vector products runs in order; the stream carries that order.) */
 qsim_status qsim_set_stream(qsim_state s, void *hip_stream);
 
 /* Reports the width, dtype and device address of a state (any out pointer
- * may be NULL). */
+ * may be NULL).  (Sec. I.A: n qubits, 2^n amplitudes.) */
 qsim_status qsim_state_info(qsim_state s, int *n, int *dtype, void **dev_ptr);
 
-/* Sets the state to the basis state |index> (index < 2^n). Stream-ordered. */
+/* Sets the state to the basis state |index> (index < 2^n). Stream-ordered.
+ * (Sec. III: circuits start from basis inputs, e.g. the multiplier's.) */
 qsim_status qsim_set_basis(qsim_state s, uint64_t index);
 
 /* Copies the whole state to / from host memory; `bytes` must equal
- * 2^n * bytes-per-amplitude.  Synchronous with respect to the host. */
+ * 2^n * bytes-per-amplitude.  Synchronous with respect to the host.
+ * (Sec. III: host-device transfers, which the paper finds dominate small
+ * circuits, happen only here.) */
 qsim_status qsim_copy_to_host(qsim_state s, void *host, size_t bytes);
 qsim_status qsim_copy_from_host(qsim_state s, const void *host, size_t bytes);
 
@@ -185,7 +206,10 @@ qsim_status qsim_apply_circuit(qsim_state s, const qsim_circuit *c, const double
 
 /* Writes <psi|H|psi> (no renormalisation) to *out_host, accumulated in double
  * precision with a fixed-order reduction (bitwise reproducible run to run).
- * Synchronises the state's stream.  Qubit masks must lie below 2^n. */
+ * Synchronises the state's stream.  Qubit masks must lie below 2^n.
+ * (Sec. I: expectation values of simulated circuits are what a variational
+ * model is trained on; Sec. III evaluates circuits through the simulator's
+ * Python interface for that use.) */
 qsim_status qsim_expectation(qsim_state s, const qsim_pauli_sum *H, double *out_host);
 
 /* Energy and gradient of a variational circuit by the adjoint method.
@@ -199,14 +223,22 @@ qsim_status qsim_expectation(qsim_state s, const qsim_pauli_sum *H, double *out_
  * differentiation is not in the paper, whose motivating use is training
  * variational models with simulated expectation values (Sec. I).
  *
- * params: host, nparams doubles; energy: host double; grad: host, nparams
- * doubles (overwritten; entries no op uses are 0).  Parametric ops of other
- * kinds return QSIM_ERR_UNSUPPORTED before any device work.  On return the
- * state holds psi_0 again, up to rounding.  Uses one extra state-sized
- * device buffer per state (allocated on first use, kept until qsim_free).
- * Synchronises the state's stream. */
-qsim_status qsim_adjoint_grad(qsim_state s, const qsim_circuit *c, const double *params, int64_t nparams,
-                              const qsim_pauli_sum *H, const qsim_options *opts, double *energy, double *grad);
+ * params_dev: device memory, nparams doubles; energy_dev: device memory, one
+ * double; grad_dev: device memory, nparams doubles (overwritten; entries no op
+ * uses are 0).  All on the state's device.  Stream-ordered: the call queues
+ * its work on the state's stream and returns without waiting (the caller
+ * orders reads of energy_dev / grad_dev after it on that stream).  Plans
+ * depend on the circuit's structure only (the rotations read their angles
+ * from params_dev on the device), so repeated calls with new parameters do
+ * no planning.  opts: tile_m > 0 sets the forward tile width; other fields
+ * are ignored.  Parametric ops of other kinds return QSIM_ERR_UNSUPPORTED and
+ * pointers that are not device memory QSIM_ERR_ARG, before any device work.
+ * On return the state holds psi_0 again, up to rounding.  Uses one extra
+ * state-sized device buffer per state (allocated on first use, kept until
+ * qsim_free). */
+qsim_status qsim_adjoint_grad(qsim_state s, const qsim_circuit *c, const double *params_dev, int64_t nparams,
+                              const qsim_pauli_sum *H, const qsim_options *opts, double *energy_dev,
+                              double *grad_dev);
 
 /* Batched forward + adjoint runs of many independent circuits, for callers
  * that evaluate thousands of small variational circuits (paper, Sec. I: the
@@ -216,28 +248,34 @@ qsim_status qsim_adjoint_grad(qsim_state s, const qsim_circuit *c, const double 
  * qsim_batch_create validates every circuit (1 <= n <= 26; parametric ops
  * must be RX, RY or RZ), builds one device program per distinct structure
  * (circuit ops, fixed angles and matrices, observable), allocates device
- * memory (programs, outputs, and for circuits wider than one LDS tile a
- * psi/lambda slot per workgroup) and captures the whole run -- parameter
- * upload, one persistent kernel, result download -- in a HIP graph.
- * Circuit i reads its parameters from params[param_offsets[i] ..
- * param_offsets[i+1]) (param indices in its ops are relative to that block),
- * is applied to |0...0>, and yields energies[i] = <psi|Hs[i]|psi> and, when
- * want_grad, grads over the same block.  `opts` is reserved (may be NULL).
+ * memory (programs, parameters, outputs, and for circuits wider than one LDS
+ * tile a psi/lambda slot per workgroup) and captures the persistent kernel
+ * in a HIP graph.  Circuit i reads its parameters from params[param_offsets[i]
+ * .. param_offsets[i+1]) (param indices in its ops are relative to that
+ * block), is applied to |0...0>, and yields energies[i] = <psi|Hs[i]|psi>
+ * and, when want_grad, grads over the same block.  `opts` is reserved (may
+ * be NULL).
  *
- * qsim_batch_run copies params (host) in, replays the graph on `hip_stream`,
- * waits, and copies energies (ncirc doubles) and grads (host) out.  Calls on
- * one batch must be serialised.  qsim_batch_info reports the persistent grid
- * size, the number of distinct programs and the widest circuit. */
+ * qsim_batch_run: params_dev (device, nparams doubles), energies_dev (device,
+ * ncirc doubles) and grads_dev (device, nparams doubles; may be NULL when the
+ * batch was created without gradients).  Stream-ordered on `hip_stream`: a
+ * device-to-device copy of the parameters in, the graph, copies of the
+ * results out; returns without waiting.  Calls on one batch must be
+ * serialised on one stream.  qsim_batch_info reports the persistent grid
+ * size, the number of distinct programs and the widest circuit; qsim_batch_free
+ * waits for the batch's work and releases it. */
 typedef struct qsim_batch_s *qsim_batch;
 
 qsim_status qsim_batch_create(int ncirc, const qsim_circuit *circs, const int64_t *param_offsets,
                               const qsim_pauli_sum *Hs, qsim_dtype dtype, int want_grad, const qsim_options *opts,
                               qsim_batch *out);
-qsim_status qsim_batch_run(qsim_batch b, const double *params, double *energies, double *grads, void *hip_stream);
+qsim_status qsim_batch_run(qsim_batch b, const double *params_dev, double *energies_dev, double *grads_dev,
+                           void *hip_stream);
 qsim_status qsim_batch_info(qsim_batch b, int *grid, int *programs, int *max_n);
 qsim_status qsim_batch_free(qsim_batch b);
 
-/* Autotuner: applies the circuit with each candidate option set (plain
+/* Autotuner (Sec. IV: the paper leaves kernel-level tuning to future work):
+ * applies the circuit with each candidate option set (plain
  * sweeps; LDS tile passes of three tile sizes with fusion widths 1..3;
  * matrix-core blocks of 4..6 qubits), once to warm up and `reps` times timed
  * with HIP events, and writes the fastest set to *best and its mean time per
@@ -252,7 +290,9 @@ qsim_status qsim_autotune(qsim_state s, const qsim_circuit *c, const double *par
                           qsim_options *best, double *best_ms);
 
 /* Plans a circuit for an n-qubit state of `dtype` without touching any
- * device (host-only): validates the ops as qsim_apply_circuit does and
+ * device (host-only; Sec. II: the cost of a circuit is its chain of
+ * matrix-vector products, reported here pass by pass): validates the ops as
+ * qsim_apply_circuit does and
  * reports how many passes of each kind (QSIM_KCLASS_*, `counts` has
  * QSIM_KCLASS_COUNT_ entries) the circuit would take, the algorithmic HBM
  * bytes they move and the floating-point operations their gate arithmetic
@@ -262,10 +302,13 @@ qsim_status qsim_plan_summary(int n, qsim_dtype dtype, const qsim_circuit *c, co
                               int64_t nparams, const qsim_options *opts, int64_t *counts, double *bytes,
                               double *flops);
 
-/* Thread-local description of the last error on this thread ("" if none). */
+/* Thread-local description of the last error on this thread ("" if none).
+ * (Not a step of the method: error reporting of this interface.) */
 const char *qsim_last_error(void);
 
-/* Per-kernel-class timing of this library's launches on a state, measured
+/* Per-kernel-class timing of this library's launches on a state (Sec. III:
+ * the paper measures wall-clock time per circuit; these events break it down
+ * by kernel), measured
  * with HIP events recorded on the state's stream around every launch while
  * enabled.  qsim_profile_enable(s, 1) clears and starts; 0 stops.
  * qsim_profile_read synchronises the stream and reports, for class `cls`

@@ -80,7 +80,7 @@ class QsimPauliSum(ctypes.Structure):
 
 class QsimOptions(ctypes.Structure):
     _fields_ = [("fuse_k", ctypes.c_int32), ("tile_m", ctypes.c_int32), ("use_mfma", ctypes.c_int32),
-                ("split_1q", ctypes.c_int32)]
+                ("split_1q", ctypes.c_int32), ("deterministic", ctypes.c_int32)]
 
 
 def _hip_runtimes() -> set:
@@ -117,9 +117,8 @@ def _load() -> ctypes.CDLL:
         "qsim_apply_circuit": ([P, ctypes.POINTER(QsimCircuit), ctypes.POINTER(ctypes.c_double), i64,
                                 ctypes.POINTER(QsimOptions)], S),
         "qsim_expectation": ([P, ctypes.POINTER(QsimPauliSum), ctypes.POINTER(ctypes.c_double)], S),
-        "qsim_adjoint_grad": ([P, ctypes.POINTER(QsimCircuit), ctypes.POINTER(ctypes.c_double), i64,
-                               ctypes.POINTER(QsimPauliSum), ctypes.POINTER(QsimOptions),
-                               ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)], S),
+        "qsim_adjoint_grad": ([P, ctypes.POINTER(QsimCircuit), P, i64, ctypes.POINTER(QsimPauliSum),
+                               ctypes.POINTER(QsimOptions), P, P], S),
         "qsim_last_error": ([], ctypes.c_char_p),
         "qsim_plan_summary": ([i32, i32, ctypes.POINTER(QsimCircuit), ctypes.POINTER(ctypes.c_double), i64,
                                ctypes.POINTER(QsimOptions), ctypes.POINTER(i64), ctypes.POINTER(ctypes.c_double),
@@ -127,8 +126,7 @@ def _load() -> ctypes.CDLL:
         "qsim_profile_enable": ([P, i32], S),
         "qsim_batch_create": ([i32, ctypes.POINTER(QsimCircuit), ctypes.POINTER(i64), ctypes.POINTER(QsimPauliSum),
                                i32, i32, ctypes.POINTER(QsimOptions), ctypes.POINTER(P)], S),
-        "qsim_batch_run": ([P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double),
-                            ctypes.POINTER(ctypes.c_double), P], S),
+        "qsim_batch_run": ([P, P, P, P, P], S),
         "qsim_batch_info": ([P, ctypes.POINTER(i32), ctypes.POINTER(i32), ctypes.POINTER(i32)], S),
         "qsim_batch_free": ([P], S),
         "qsim_autotune": ([P, ctypes.POINTER(QsimCircuit), ctypes.POINTER(ctypes.c_double), i64, i32,
@@ -233,8 +231,9 @@ class PackedCircuit:
         self.nops = len(circ.ops)
 
 
-def make_options(fuse_k: int = 0, tile_m: int = 0, use_mfma: int = 0, split_1q: int = 0) -> QsimOptions:
-    return QsimOptions(fuse_k, tile_m, use_mfma, split_1q)
+def make_options(fuse_k: int = 0, tile_m: int = 0, use_mfma: int = 0, split_1q: int = 0,
+                 deterministic: int = 0) -> QsimOptions:
+    return QsimOptions(fuse_k, tile_m, use_mfma, split_1q, deterministic)
 
 
 def qsim_apply_circuit(h: int, packed: PackedCircuit, params: Optional[np.ndarray] = None,
@@ -272,15 +271,22 @@ def qsim_plan_summary(n: int, dtype: int, circ, params: Optional[np.ndarray] = N
     return {name: counts[i] for name, i in KCLASS.items()}, by.value, fl.value
 
 
-def qsim_adjoint_grad(h: int, packed: PackedCircuit, params: np.ndarray, packedH: PackedPauliSum,
-                      opts: Optional[QsimOptions] = None) -> Tuple[float, np.ndarray]:
-    p = np.ascontiguousarray(params, dtype=np.float64)
-    grad = np.zeros(p.size)
-    e = ctypes.c_double()
-    _check(_lib.qsim_adjoint_grad(ctypes.c_void_p(h), ctypes.byref(packed.c), _dptr(p), p.size,
-                                  ctypes.byref(packedH.h), ctypes.byref(opts) if opts is not None else None,
-                                  ctypes.byref(e), _dptr(grad)))
-    return e.value, grad
+def _device_f64(t, name: str):
+    """A contiguous float64 torch tensor on a GPU (device memory for the ABI)."""
+    import torch
+    if not isinstance(t, torch.Tensor) or not t.is_cuda or t.dtype != torch.float64 or not t.is_contiguous():
+        raise TypeError(f"{name} must be a contiguous float64 torch tensor on a GPU")
+    return ctypes.c_void_p(t.data_ptr() if t.numel() else 0)
+
+
+def qsim_adjoint_grad(h: int, packed: PackedCircuit, params_dev, packedH: PackedPauliSum,
+                      opts: Optional[QsimOptions], energy_dev, grad_dev) -> None:
+    """Queues the adjoint gradient on the state's stream: params_dev (nparams),
+    energy_dev (1) and grad_dev (nparams) are float64 device tensors."""
+    _check(_lib.qsim_adjoint_grad(ctypes.c_void_p(h), ctypes.byref(packed.c), _device_f64(params_dev, "params"),
+                                  params_dev.numel(), ctypes.byref(packedH.h),
+                                  ctypes.byref(opts) if opts is not None else None,
+                                  _device_f64(energy_dev, "energy"), _device_f64(grad_dev, "grad")))
 
 
 def qsim_profile_enable(h: int, on: bool) -> None:
@@ -347,11 +353,27 @@ class State:
     def expectation(self, H) -> float:
         return qsim_expectation(self.handle, PackedPauliSum(H))
 
-    def adjoint_grad(self, circ, params: np.ndarray, H, fuse_k: int = 0, tile_m: int = 0):
-        """(energy, gradient) of <psi|C^dag H C|psi> for the state's current
-        content psi; the state is returned to psi (up to rounding)."""
-        return qsim_adjoint_grad(self.handle, self.packed(circ), params, PackedPauliSum(H),
-                                 make_options(fuse_k, tile_m, 0))
+    def adjoint_grad_device(self, circ, params, H, tile_m: int = 0):
+        """Energy (a one-element tensor) and gradient of <psi|C^dag H C|psi>
+        for the state's current content psi, as float64 tensors on the
+        state's device, queued on its stream without waiting; `params` is a
+        float64 device tensor.  The state is returned to psi (up to
+        rounding)."""
+        import torch
+        dev = self.tensor.device
+        energy = torch.empty(1, dtype=torch.float64, device=dev)
+        grad = torch.empty(params.numel(), dtype=torch.float64, device=dev)
+        qsim_adjoint_grad(self.handle, self.packed(circ), params, PackedPauliSum(H),
+                          make_options(tile_m=tile_m), energy, grad)
+        return energy, grad
+
+    def adjoint_grad(self, circ, params, H, tile_m: int = 0):
+        """(energy, gradient) as a float and a numpy array: the parameters
+        are copied to the device, the gradient back after the call."""
+        import torch
+        p = torch.as_tensor(np.ascontiguousarray(params, dtype=np.float64)).to(self.tensor.device)
+        e, g = self.adjoint_grad_device(circ, p, H, tile_m=tile_m)
+        return float(e.cpu()[0]), g.cpu().numpy()
 
     def autotune(self, circ, params: Optional[np.ndarray] = None, reps: int = 2):
         """Times the candidate options for `circ` on this state (overwriting it)
@@ -409,18 +431,32 @@ class Batch:
         _check(_lib.qsim_batch_info(ctypes.c_void_p(self.handle), ctypes.byref(g), ctypes.byref(p), ctypes.byref(m)))
         return g.value, p.value, m.value
 
-    def run(self, params: np.ndarray, stream: int = 0):
-        p = np.ascontiguousarray(params, dtype=np.float64)
-        if p.size != self.nparams:
-            raise ValueError(f"expected {self.nparams} parameters, got {p.size}")
-        energies = np.zeros(self.ncirc)
-        grads = np.zeros(max(1, self.nparams))
-        if not stream:
-            import torch
-            stream = torch.cuda.current_stream().cuda_stream
-        _check(_lib.qsim_batch_run(ctypes.c_void_p(self.handle), _dptr(p), _dptr(energies), _dptr(grads),
+    def run_device(self, params, energies=None, grads=None):
+        """Queues one batch run on torch's current stream: `params` is a
+        float64 device tensor of all parameter blocks; returns the energies
+        and (with gradients) the gradient tensors, without waiting."""
+        import torch
+        if params.numel() != self.nparams:
+            raise ValueError(f"expected {self.nparams} parameters, got {params.numel()}")
+        dev = params.device
+        if energies is None:
+            energies = torch.empty(self.ncirc, dtype=torch.float64, device=dev)
+        if grads is None and self.want_grad:
+            grads = torch.empty(max(1, self.nparams), dtype=torch.float64, device=dev)
+        stream = torch.cuda.current_stream(dev).cuda_stream
+        _check(_lib.qsim_batch_run(ctypes.c_void_p(self.handle), _device_f64(params, "params"),
+                                   _device_f64(energies, "energies"),
+                                   _device_f64(grads, "grads") if grads is not None else None,
                                    ctypes.c_void_p(stream)))
-        return energies, (grads[:self.nparams] if self.want_grad else None)
+        return energies, grads
+
+    def run(self, params):
+        """Host convenience: numpy (or tensor) parameters in, numpy energies
+        and gradients out (copies to and from the device, then a wait)."""
+        import torch
+        p = torch.as_tensor(np.ascontiguousarray(params, dtype=np.float64)).to("cuda")
+        e, g = self.run_device(p)
+        return e.cpu().numpy(), (g[:self.nparams].cpu().numpy() if self.want_grad else None)
 
     def close(self) -> None:
         if getattr(self, "handle", None):
@@ -446,11 +482,13 @@ def _expectation_function():
 
         @staticmethod
         def forward(ctx, params, state, circ, H):
-            p = params.detach().to("cpu", torch.float64).numpy()
+            # everything stays on the device and in stream order: the
+            # parameters are read there, energy and gradient written there
+            p = params.detach().to(state.tensor.device, torch.float64).contiguous()
             state.set_basis(0)
-            e, g = state.adjoint_grad(circ, p, H)
-            ctx.save_for_backward(torch.as_tensor(g, dtype=params.dtype, device=params.device))
-            return torch.as_tensor(e, dtype=params.dtype, device=params.device)
+            e, g = state.adjoint_grad_device(circ, p, H)
+            ctx.save_for_backward(g.to(params.dtype).to(params.device))
+            return e[0].to(params.dtype).to(params.device)
 
         @staticmethod
         def backward(ctx, grad_out):

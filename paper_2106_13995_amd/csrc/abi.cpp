@@ -309,7 +309,8 @@ static qsim_status get_plan(qsim_state s, const qsim_circuit *c, const double *p
     qsim_options tuned{};
     const bool automatic =
         !opts || (opts->fuse_k == 0 && opts->tile_m == 0 && opts->use_mfma == 0 && opts->split_1q == 0);
-    if (automatic && tuned_options(c, s->n, s->dtype, &tuned)) opts = &tuned;
+    const bool deterministic = opts && opts->deterministic;
+    if (automatic && !deterministic && tuned_options(c, s->n, s->dtype, &tuned)) opts = &tuned;
     const PlanOptions po = resolve_options(opts, s->n, s->dtype);
     std::string key;
     if (cache) {
@@ -430,7 +431,9 @@ qsim_status qsim_free(qsim_state s) {
     if (!s) return QSIM_OK;
     (void)hipStreamSynchronize(s->stream);
     s->plans.clear();
+    s->adj_plans.clear();
     s->transient.reset();
+    if (s->adj_h) (void)hipFree(s->adj_h);
     if (s->adj_lam) (void)hipFree(s->adj_lam);
     prof_clear(s);
     for (hipEvent_t e : s->prof.pool) (void)hipEventDestroy(e);
@@ -450,6 +453,10 @@ qsim_status qsim_set_stream(qsim_state s, void *hip_stream) {
     QSIM_HIP(s, hipStreamSynchronize(s->stream), "hipStreamSynchronize");
     s->stream = static_cast<hipStream_t>(hip_stream);
     for (auto &cp : s->plans) cp.plan->dev_stream = s->stream;
+    for (auto &ap : s->adj_plans) {
+        ap->fwd.dev_stream = ap->rev.dev_stream = s->stream;
+        ap->dev_stream = s->stream;
+    }
     if (s->transient) s->transient->dev_stream = s->stream;
     return QSIM_OK;
 }
@@ -525,6 +532,9 @@ static qsim_status check_options(const qsim_options *opts) {
     if (opts->fuse_k < 0 || opts->fuse_k > QSIM_MAX_K) return set_error(QSIM_ERR_ARG, "fuse_k outside [0, 6]");
     if (opts->tile_m > 0 && opts->tile_m < 7) return set_error(QSIM_ERR_ARG, "tile_m must be -1, 0 or at least 7");
     if (opts->split_1q < -1 || opts->split_1q > 1) return set_error(QSIM_ERR_ARG, "split_1q outside [-1, 1]");
+    if (opts->use_mfma < -1 || opts->use_mfma > 1) return set_error(QSIM_ERR_ARG, "use_mfma outside [-1, 1]");
+    if (opts->deterministic < 0 || opts->deterministic > 1)
+        return set_error(QSIM_ERR_ARG, "deterministic must be 0 or 1");
     return QSIM_OK;
 }
 
@@ -591,11 +601,17 @@ qsim_status qsim_expectation(qsim_state s, const qsim_pauli_sum *H, double *out_
     // evaluated several to a pass over the state; the rest one pass each.
     const int mt = std::min(s->n, s->dtype == QSIM_C128 ? 11 : 12);
     const int Lt = std::min(mt, s->dtype == QSIM_C128 ? 4 : 5);
+    const bool reg_kernel = (s->dtype == QSIM_C64 && mt == 12) || (s->dtype == QSIM_C128 && mt == 11);
+    const int kpt_bits = s->dtype == QSIM_C128 ? 3 : 4;
     std::vector<ExpTilePass> tpasses;
     std::vector<uint64_t> tmask;           // tile qubits of each pass
     std::vector<size_t> single;            // groups evaluated alone
     {
+        // passes from the groups with X bits above the low L qubits (greedy,
+        // in X-mask order); the groups inside the low L qubits (the diagonal
+        // group among them) then go to the passes with the least work
         std::vector<std::vector<size_t>> members;
+        std::vector<size_t> low_only;
         uint64_t hm = 0;
         for (size_t gi = 0; gi < spans.size(); ++gi) {
             const uint64_t hx = spans[gi].first >> Lt << Lt;
@@ -603,15 +619,40 @@ qsim_status qsim_expectation(qsim_state s, const qsim_pauli_sum *H, double *out_
                 single.push_back(gi);
                 continue;
             }
+            if (hx == 0) {
+                low_only.push_back(gi);
+                continue;
+            }
             if (members.empty() || __builtin_popcountll(hm | hx) > mt - Lt ||
                 members.back().size() == size_t(kExpTileGroups)) {
                 members.emplace_back();
+                tmask.push_back(0);
                 hm = 0;
             }
             hm |= hx;
             members.back().push_back(gi);
-            if (tmask.size() < members.size()) tmask.push_back(0);
             tmask.back() = hm;
+        }
+        auto group_terms = [&](size_t gi) {
+            return (gi + 1 < spans.size() ? spans[gi + 1].second : slot) - spans[gi].second;
+        };
+        for (size_t gi : low_only) {
+            // work of a pass: its groups' terms, the diagonal group's counted
+            // once per KPT amplitudes plus its transform
+            size_t best = members.size();
+            double best_w = 1e300;
+            for (size_t pi = 0; pi < members.size(); ++pi) {
+                if (members[pi].size() == size_t(kExpTileGroups)) continue;
+                double w = 0.0;
+                for (size_t g2 : members[pi]) w += spans[g2].first ? 1.0 : 2.0;
+                if (w < best_w) { best_w = w; best = pi; }
+            }
+            if (best == members.size()) {
+                members.emplace_back();
+                tmask.push_back(0);
+            }
+            members[best].push_back(gi);
+            (void)group_terms;
         }
         for (size_t pi = 0; pi < members.size(); ++pi) {
             ExpTilePass tp{};
@@ -633,14 +674,41 @@ qsim_status qsim_expectation(qsim_state s, const qsim_pauli_sum *H, double *out_
                     if (((v & tmask[pi]) >> q) & 1) o |= 1u << local_of[q];
                 return o;
             };
+            for (int mu = 0; mu <= 32; ++mu) tp.dmu[mu] = 0;
             for (size_t gi : members[pi]) {
+                const uint64_t x = spans[gi].first;
                 const int first = spans[gi].second;
-                const int cnt = (gi + 1 < spans.size() ? spans[gi + 1].second : slot) - first;
+                const int cnt = group_terms(gi);
                 ExpTileGroup &g = tp.groups[tp.ngroups++];
-                g.xl = to_local(spans[gi].first);
+                g.xl = to_local(x);
                 g.first = first;
                 g.count = cnt;
+                g.flags = 0;
+                g.A = g.B = 0.0;
                 for (int t = first; t < first + cnt; ++t) ht[t].pad = to_local(ht[t].z);
+                if (__builtin_popcountll(x) == 1) {
+                    bool simple = true;
+                    for (int t = first; t < first + cnt; ++t) {
+                        if (ht[t].z == 0) g.A += ht[t].wr;
+                        else if (ht[t].z == x) g.B += ht[t].wi;
+                        else simple = false;
+                    }
+                    if (simple) g.flags = kExpGroupSimple;
+                }
+                if (x == 0) {
+                    // order the diagonal terms by the register part of their
+                    // local Z mask (local bits 8 and up) for the register kernel
+                    std::stable_sort(ht + first, ht + first + cnt, [&](const DevTerm &a, const DevTerm &b) {
+                        return (a.pad >> 8) < (b.pad >> 8);
+                    });
+                    const int kpt = 1 << kpt_bits;
+                    int t = first;
+                    for (int mu = 0; mu <= kpt; ++mu) {
+                        while (t < first + cnt && mu < kpt && int(ht[t].pad >> 8) < mu) ++t;
+                        tp.dmu[mu] = mu == kpt ? first + cnt : t;
+                    }
+                    (void)reg_kernel;
+                }
             }
             tpasses.push_back(tp);
         }
@@ -723,58 +791,158 @@ qsim_status qsim_plan_summary(int n, qsim_dtype dtype, const qsim_circuit *c, co
     return QSIM_OK;
 }
 
-qsim_status qsim_adjoint_grad(qsim_state s, const qsim_circuit *c, const double *params, int64_t nparams,
-                              const qsim_pauli_sum *H, const qsim_options *opts, double *energy, double *grad) {
-    qsim_status st = check_state(s);
-    if (st != QSIM_OK) return st;
-    if (!c || !H || !energy) return set_error(QSIM_ERR_ARG, "NULL argument");
-    if (c->n != s->n) return set_error(QSIM_ERR_ARG, "circuit width does not match the state");
-    if (c->nops < 0 || (c->nops > 0 && !c->ops)) return set_error(QSIM_ERR_ARG, "bad op array");
-    if (nparams < 0 || (nparams > 0 && (!params || !grad))) return set_error(QSIM_ERR_ARG, "bad parameter arrays");
-    if (H->nterms < 0 || (H->nterms > 0 && !H->terms)) return set_error(QSIM_ERR_ARG, "bad Pauli sum");
-    const uint64_t lim = (1ull << s->n) - 1;
-    for (int t = 0; t < H->nterms; ++t)
-        if ((H->terms[t].xmask & ~lim) || (H->terms[t].zmask & ~lim))
-            return set_error(QSIM_ERR_ARG, "Pauli mask has a bit at or above n");
-    // validate every op and collect the reverse sweep: probe, then inverse
+// Adjoint plans depend on the circuit's structure only: parametric
+// rotations read (cos, sin) of their half angle from a table the call fills
+// on the device from the caller's parameters, so a training loop plans once.
+static const size_t kMaxAdjointPlans = 8;
+
+static int rotation_kind_generator(int kind) {
+    return kind == QSIM_GATE_RX ? 1 : kind == QSIM_GATE_RY ? 2 : kind == QSIM_GATE_RZ ? 3 : 0;
+}
+
+static qsim_status get_adjoint_plan(qsim_state s, const qsim_circuit *c, int64_t nparams, const qsim_options *opts,
+                                    AdjointPlan **out) {
+    const int fwd_m = (opts && opts->tile_m > 0) ? opts->tile_m : (s->dtype == QSIM_C128 ? 11 : 12);
+    std::string key;
+    auto put = [&key](const void *p, size_t n) { key.append(static_cast<const char *>(p), n); };
+    put(&nparams, sizeof nparams);
+    put(&fwd_m, sizeof fwd_m);
+    for (int i = 0; i < c->nops; ++i) {
+        qsim_op op = c->ops[i];
+        if (op.param >= 0) op.angles[0] = op.angles[1] = op.angles[2] = 0.0;
+        put(&op, sizeof op);
+    }
+    if (c->mats && c->nmats > 0) put(c->mats, sizeof(double) * 2 * size_t(c->nmats));
+    for (auto &ap : s->adj_plans)
+        if (ap->key == key) {
+            ap->last_use = ++s->use_clock;
+            *out = ap.get();
+            return QSIM_OK;
+        }
+    std::unique_ptr<AdjointPlan> ap(new (std::nothrow) AdjointPlan());
+    if (!ap) return set_error(QSIM_ERR_OOM, "host allocation failed");
+    // gates with placeholder angles; parametric rotations become device-formed ops
+    std::vector<double> zeros(size_t(std::max<int64_t>(nparams, 1)), 0.0);
     std::vector<HostGate> gates(size_t(c->nops));
     for (int i = 0; i < c->nops; ++i) {
-        st = make_gate(c, i, params, nparams, gates[size_t(i)]);
+        qsim_status st = make_gate(c, i, zeros.data(), nparams, gates[size_t(i)]);
         if (st != QSIM_OK) return st;
+        if (c->ops[i].param >= 0) {
+            const int gen = rotation_kind_generator(c->ops[i].kind);
+            if (!gen)
+                return set_error(QSIM_ERR_UNSUPPORTED,
+                                 "op " + std::to_string(i) + ": gradients need RX, RY or RZ for parametric ops");
+            gates[size_t(i)].rot_gen = gen;
+            gates[size_t(i)].rot_param = c->ops[i].param;
+        }
     }
+    // reverse sweep, last op first: its probe (if parametric), then its inverse
     std::vector<HostGate> items;
     std::vector<int> slot_param;
     items.reserve(2 * gates.size());
     for (int i = c->nops - 1; i >= 0; --i) {
-        const qsim_op &op = c->ops[i];
-        if (op.param >= 0) {
-            int gen = 0;
-            if (op.kind == QSIM_GATE_RX) gen = 1;
-            else if (op.kind == QSIM_GATE_RY) gen = 2;
-            else if (op.kind == QSIM_GATE_RZ) gen = 3;
-            else
-                return set_error(QSIM_ERR_UNSUPPORTED,
-                                 "op " + std::to_string(i) + ": gradients need RX, RY or RZ for parametric ops");
+        const HostGate &g = gates[size_t(i)];
+        if (g.rot_gen) {
             HostGate pr;
             pr.k = 1;
-            pr.targets[0] = op.targets[0];
-            pr.probe_gen = gen;
+            pr.targets[0] = g.targets[0];
+            pr.probe_gen = g.rot_gen;
             pr.probe_slot = int(slot_param.size());
-            slot_param.push_back(op.param);
+            slot_param.push_back(g.rot_param);
             items.push_back(pr);
+            HostGate inv = g;
+            inv.rot_inv = 1;
+            items.push_back(std::move(inv));
+        } else {
+            HostGate inv = g;
+            const int d = 1 << g.k;
+            for (int r = 0; r < d; ++r)
+                for (int cc = 0; cc < d; ++cc) inv.M[size_t(r) * d + cc] = std::conj(g.M[size_t(cc) * d + r]);
+            items.push_back(std::move(inv));
         }
-        const HostGate &g = gates[size_t(i)];
-        HostGate inv = g;
-        const int d = 1 << g.k;
-        for (int r = 0; r < d; ++r)
-            for (int cc = 0; cc < d; ++cc) inv.M[size_t(r) * d + cc] = std::conj(g.M[size_t(cc) * d + r]);
-        items.push_back(std::move(inv));
     }
-    // forward: psi <- C psi
-    Plan *fwd = nullptr;
-    st = get_plan(s, c, params, nparams, opts, &fwd);
+    ap->fwd.n = ap->rev.n = s->n;
+    ap->fwd.dtype = ap->rev.dtype = s->dtype;
+    if (build_tile_plan(ap->fwd, gates, std::min(s->n, fwd_m)) < 0)
+        return set_error(QSIM_ERR_UNSUPPORTED, "the planner could not place every op");
+    // reverse tiles of 2^10 amplitudes per state (wider when a gate needs
+    // it): measured on the 20-qubit ansatz, smaller tiles put more
+    // workgroups on the chip
+    ap->mtile = build_adjoint_plan(ap->rev, items, 10);
+    if (ap->mtile < 0) return set_error(QSIM_ERR_UNSUPPORTED, "the planner could not place every op");
+    ap->nprobes = int(slot_param.size());
+    ap->nparams = nparams;
+    qsim_status st = upload_plan(s, ap->fwd);
     if (st != QSIM_OK) return st;
-    st = run_plan(s, *fwd);
+    st = upload_plan(s, ap->rev);
+    if (st != QSIM_OK) return st;
+    // probes of each parameter, in sweep order: row[j] .. row[j + 1] of idx
+    std::vector<int32_t> row(size_t(nparams) + 1, 0), idx(size_t(std::max(1, ap->nprobes)), 0);
+    for (int k = 0; k < ap->nprobes; ++k) ++row[size_t(slot_param[size_t(k)]) + 1];
+    for (int64_t j = 0; j < nparams; ++j) row[size_t(j) + 1] += row[size_t(j)];
+    {
+        std::vector<int32_t> fill(row.begin(), row.end() - 1);
+        for (int k = 0; k < ap->nprobes; ++k) idx[size_t(fill[size_t(slot_param[size_t(k)])]++)] = k;
+    }
+    ap->idx_off = (sizeof(int32_t) * row.size() + 255) & ~size_t(255);
+    const size_t bytes = ap->idx_off + sizeof(int32_t) * idx.size();
+    if (hipMallocAsync(&ap->dev, bytes, s->stream) != hipSuccess) {
+        (void)hipGetLastError();
+        ap->dev = nullptr;
+        return set_error(QSIM_ERR_OOM, "cannot allocate device memory for the adjoint plan");
+    }
+    ap->dev_stream = s->stream;
+    st = ensure_pinned(s, bytes);
+    if (st != QSIM_OK) return st;
+    char *h = static_cast<char *>(s->pinned);
+    std::memcpy(h, row.data(), sizeof(int32_t) * row.size());
+    std::memcpy(h + ap->idx_off, idx.data(), sizeof(int32_t) * idx.size());
+    st = upload_staged(s, ap->dev, bytes);
+    if (st != QSIM_OK) return st;
+    if (s->adj_plans.size() >= kMaxAdjointPlans) {
+        auto lru = std::min_element(s->adj_plans.begin(), s->adj_plans.end(),
+                                    [](const std::unique_ptr<AdjointPlan> &a, const std::unique_ptr<AdjointPlan> &b) {
+                                        return a->last_use < b->last_use;
+                                    });
+        s->adj_plans.erase(lru);   // released in stream order
+    }
+    ap->key = std::move(key);
+    ap->last_use = ++s->use_clock;
+    *out = ap.get();
+    s->adj_plans.push_back(std::move(ap));
+    return QSIM_OK;
+}
+
+static bool on_device(const void *p) {
+    hipPointerAttribute_t attr;
+    if (hipPointerGetAttributes(&attr, p) != hipSuccess) {
+        (void)hipGetLastError();
+        return false;
+    }
+    return attr.type == hipMemoryTypeDevice || attr.type == hipMemoryTypeManaged;
+}
+
+qsim_status qsim_adjoint_grad(qsim_state s, const qsim_circuit *c, const double *params_dev, int64_t nparams,
+                              const qsim_pauli_sum *H, const qsim_options *opts, double *energy_dev,
+                              double *grad_dev) {
+    qsim_status st = check_state(s);
+    if (st != QSIM_OK) return st;
+    if (!c || !H || !energy_dev) return set_error(QSIM_ERR_ARG, "NULL argument");
+    if (c->n != s->n) return set_error(QSIM_ERR_ARG, "circuit width does not match the state");
+    if (c->nops < 0 || (c->nops > 0 && !c->ops)) return set_error(QSIM_ERR_ARG, "bad op array");
+    if (nparams < 0 || nparams > (int64_t(1) << 30) || (nparams > 0 && (!params_dev || !grad_dev)))
+        return set_error(QSIM_ERR_ARG, "bad parameter arrays");
+    if (H->nterms < 0 || (H->nterms > 0 && !H->terms)) return set_error(QSIM_ERR_ARG, "bad Pauli sum");
+    st = check_options(opts);
+    if (st != QSIM_OK) return st;
+    const uint64_t lim = (1ull << s->n) - 1;
+    for (int t = 0; t < H->nterms; ++t)
+        if ((H->terms[t].xmask & ~lim) || (H->terms[t].zmask & ~lim))
+            return set_error(QSIM_ERR_ARG, "Pauli mask has a bit at or above n");
+    if (!on_device(energy_dev) || (nparams > 0 && (!on_device(params_dev) || !on_device(grad_dev))))
+        return set_error(QSIM_ERR_ARG, "params, energy and grad must be device memory");
+    AdjointPlan *ap = nullptr;
+    st = get_adjoint_plan(s, c, nparams, opts, &ap);
     if (st != QSIM_OK) return st;
     const size_t sbytes = amp_bytes(s->dtype) << s->n;
     if (!s->adj_lam) {
@@ -784,21 +952,7 @@ qsim_status qsim_adjoint_grad(qsim_state s, const qsim_circuit *c, const double 
             return set_error(QSIM_ERR_OOM, "cannot allocate the adjoint state");
         }
     }
-    // reverse plan
-    std::unique_ptr<Plan> rev(new (std::nothrow) Plan());
-    if (!rev) return set_error(QSIM_ERR_OOM, "host allocation failed");
-    rev->n = s->n;
-    rev->dtype = s->dtype;
-    // 2^10 amplitudes per state and tile for both precisions: measured on the
-    // 20-qubit ansatz, smaller tiles put more workgroups on the chip
-    // (wider when a gate needs more tile positions)
-    const int mtile = build_adjoint_plan(*rev, items, 10);
-    if (mtile < 0) return set_error(QSIM_ERR_UNSUPPORTED, "the planner could not place every op");
-    st = upload_plan(s, *rev);
-    if (st != QSIM_OK) return st;
-    const int nprobes = int(slot_param.size());
-    const int ntiles = 1 << (s->n - mtile);
-    // scratch: [energy partials][groups][terms][probe partials][probe sums + energy]
+    // the Pauli sum on the device, grouped by X mask (kept while it is unchanged)
     struct DevGroup {
         uint64_t x;
         int32_t first, count;
@@ -809,66 +963,89 @@ qsim_status qsim_adjoint_grad(qsim_state s, const qsim_circuit *c, const double 
     };
     std::map<uint64_t, std::vector<int>> bygroup;
     for (int t = 0; t < H->nterms; ++t) bygroup[H->terms[t].xmask].push_back(t);
-    const int egrid = pauli_apply_grid(1ull << s->n);
+    const int ng = int(bygroup.size());
     auto align = [](size_t v) { return (v + 255) & ~size_t(255); };
-    const size_t off_groups = align(sizeof(double) * size_t(egrid));
-    const size_t gbytes = sizeof(DevGroup) * std::max<size_t>(1, bygroup.size());
-    const size_t off_terms = align(off_groups + gbytes);
-    const size_t tbytes = sizeof(DevTerm) * size_t(std::max(1, H->nterms));
-    const size_t off_pp = align(off_terms + tbytes);
+    const size_t hterms_off = align(sizeof(DevGroup) * size_t(std::max(1, ng)));
+    const size_t hbytes = hterms_off + sizeof(DevTerm) * size_t(std::max(1, H->nterms));
+    const std::string hkey(reinterpret_cast<const char *>(H->terms), sizeof(qsim_pauli_term) * size_t(H->nterms));
+    if (!s->adj_h || s->adj_h_key != hkey || s->adj_h_bytes < hbytes) {
+        if (s->adj_h_bytes < hbytes) {
+            if (s->adj_h) (void)hipFreeAsync(s->adj_h, s->stream);
+            s->adj_h = nullptr;
+            s->adj_h_bytes = 0;
+            if (hipMallocAsync(&s->adj_h, hbytes, s->stream) != hipSuccess) {
+                (void)hipGetLastError();
+                s->adj_h = nullptr;
+                return set_error(QSIM_ERR_OOM, "cannot allocate device memory for the Pauli sum");
+            }
+            s->adj_h_bytes = hbytes;
+        }
+        st = ensure_pinned(s, hbytes);
+        if (st != QSIM_OK) return st;
+        char *hp = static_cast<char *>(s->pinned);
+        DevGroup *hg = reinterpret_cast<DevGroup *>(hp);
+        DevTerm *ht = reinterpret_cast<DevTerm *>(hp + hterms_off);
+        int gi = 0, slot = 0;
+        for (auto &kv : bygroup) {
+            hg[gi].x = kv.first;
+            hg[gi].first = slot;
+            hg[gi].count = int(kv.second.size());
+            ++gi;
+            for (int t : kv.second) {
+                const qsim_pauli_term &pt = H->terms[t];
+                const int ny = __builtin_popcountll(pt.xmask & pt.zmask) & 3;
+                const double re[4] = {1, 0, -1, 0}, im[4] = {0, 1, 0, -1};
+                ht[slot].wr = pt.coeff * re[ny];
+                ht[slot].wi = pt.coeff * im[ny];
+                ht[slot].z = pt.zmask;
+                ht[slot].pad = 0;
+                ++slot;
+            }
+        }
+        st = upload_staged(s, s->adj_h, hbytes);
+        if (st != QSIM_OK) return st;
+        s->adj_h_key = hkey;
+    }
+    const int nprobes = ap->nprobes;
+    const int ntiles = 1 << (s->n - ap->mtile);
+    // scratch: [trig][energy partials][probe partials][probe sums + energy]
+    const int egrid = pauli_apply_grid(1ull << s->n);
+    const size_t off_epart = align(sizeof(double) * 2 * size_t(std::max<int64_t>(nparams, 1)));
+    const size_t off_pp = align(off_epart + sizeof(double) * size_t(egrid));
     const size_t off_sums = align(off_pp + sizeof(double) * size_t(nprobes) * size_t(ntiles));
     const size_t total = off_sums + sizeof(double) * size_t(nprobes + 1);
     st = ensure_scratch(s, total);
     if (st != QSIM_OK) return st;
-    st = ensure_pinned(s, off_terms - off_groups + tbytes);
-    if (st != QSIM_OK) return st;
-    char *hp = static_cast<char *>(s->pinned);
-    DevGroup *hg = reinterpret_cast<DevGroup *>(hp);
-    DevTerm *ht = reinterpret_cast<DevTerm *>(hp + (off_terms - off_groups));
-    int ng = 0, slot = 0;
-    for (auto &kv : bygroup) {
-        hg[ng].x = kv.first;
-        hg[ng].first = slot;
-        hg[ng].count = int(kv.second.size());
-        ++ng;
-        for (int t : kv.second) {
-            const qsim_pauli_term &pt = H->terms[t];
-            const int ny = __builtin_popcountll(pt.xmask & pt.zmask) & 3;
-            const double re[4] = {1, 0, -1, 0}, im[4] = {0, 1, 0, -1};
-            ht[slot].wr = pt.coeff * re[ny];
-            ht[slot].wi = pt.coeff * im[ny];
-            ht[slot].z = pt.zmask;
-            ht[slot].pad = 0;
-            ++slot;
-        }
-    }
     char *scr = static_cast<char *>(s->scratch);
-    st = upload_staged(s, scr + off_groups, off_terms - off_groups + tbytes);
-    if (st != QSIM_OK) return st;
-    double *epart = reinterpret_cast<double *>(scr);
+    double *trig = reinterpret_cast<double *>(scr);
+    double *epart = reinterpret_cast<double *>(scr + off_epart);
     double *pp = reinterpret_cast<double *>(scr + off_pp);
     double *sums = reinterpret_cast<double *>(scr + off_sums);
+    QSIM_HIP(s, launch_half_angle_trig(s, params_dev, nparams, trig), "trig launch");
+    // forward: psi <- C(theta) psi
+    for (const Pass &p : ap->fwd.passes) {
+        prof_begin(s, QSIM_KCLASS_TILE, p.bytes, p.flops);
+        hipError_t e = launch_tile_pass(s, ap->fwd, p, trig);
+        prof_end(s);
+        if (e != hipSuccess) return device_error(s, e, "forward pass");
+    }
     // lambda <- H psi, energy partials
     prof_begin(s, QSIM_KCLASS_EXPECT, 2.0 * double(sbytes) * double(std::max(1, ng)));
-    QSIM_HIP(s, launch_pauli_apply(s, s->adj_lam, scr + off_groups, ng, scr + off_terms, epart), "pauli apply");
+    QSIM_HIP(s, launch_pauli_apply(s, s->adj_lam, s->adj_h, ng, static_cast<char *>(s->adj_h) + hterms_off, epart),
+             "pauli apply");
     prof_end(s);
     QSIM_HIP(s, launch_reduce(s, epart, egrid, sums + nprobes), "reduce");
     // reverse sweep over (psi, lambda)
-    for (const Pass &p : rev->passes) {
+    for (const Pass &p : ap->rev.passes) {
         prof_begin(s, QSIM_KCLASS_ADJOINT, p.bytes, 2.0 * p.flops);
-        hipError_t e = launch_adjoint_pass(s, *rev, p, s->adj_lam, pp);
+        hipError_t e = launch_adjoint_pass(s, ap->rev, p, s->adj_lam, pp, trig);
         prof_end(s);
         if (e != hipSuccess) return device_error(s, e, "adjoint pass");
     }
     QSIM_HIP(s, launch_reduce_rows(s, pp, nprobes, ntiles, sums), "reduce rows");
-    std::vector<double> hs(size_t(nprobes) + 1);
-    QSIM_HIP(s, hipMemcpyAsync(hs.data(), sums, sizeof(double) * hs.size(), hipMemcpyDeviceToHost, s->stream),
-             "hipMemcpyAsync");
-    QSIM_HIP(s, hipStreamSynchronize(s->stream), "hipStreamSynchronize");
-    s->pinned_ev_pending = false;
-    *energy = hs[size_t(nprobes)];
-    for (int64_t j = 0; j < nparams; ++j) grad[j] = 0.0;
-    for (int k = 0; k < nprobes; ++k) grad[slot_param[size_t(k)]] += hs[size_t(k)];
+    const int32_t *row = static_cast<const int32_t *>(ap->dev);
+    const int32_t *idx = reinterpret_cast<const int32_t *>(static_cast<const char *>(ap->dev) + ap->idx_off);
+    QSIM_HIP(s, launch_gather_gradient(s, sums, row, idx, nparams, nprobes, grad_dev, energy_dev), "gradient gather");
     return QSIM_OK;
 }
 

@@ -27,8 +27,9 @@ struct qsim_batch_s {
     void *dev = nullptr;          // programs, circuits, params, outputs, counter
     size_t dev_bytes = 0;
     void *arena = nullptr;        // per-workgroup psi / lambda slots
-    void *pinned = nullptr;       // params in, energies + grads out
-    size_t off_params = 0, off_energy = 0, off_grads = 0;
+    double *d_params = nullptr, *d_energy = nullptr, *d_grads = nullptr;   // inside dev
+    hipStream_t last_stream = nullptr;   // stream of the last run
+    bool ran = false;
     hipStream_t cap_stream = nullptr;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
@@ -47,7 +48,6 @@ void destroy(qsim_batch b) {
     if (b->cap_stream) (void)hipStreamDestroy(b->cap_stream);
     if (b->dev) (void)hipFree(b->dev);
     if (b->arena) (void)hipFree(b->arena);
-    if (b->pinned) (void)hipHostFree(b->pinned);
     delete b;
 }
 
@@ -316,19 +316,12 @@ qsim_status qsim_batch_create(int ncirc, const qsim_circuit *circs, const int64_
         destroy(b);
         return fail(QSIM_ERR_DEVICE, "uploading the batch programs failed");
     }
-    // pinned staging: params in, energies and grads out
-    b->off_params = 0;
-    b->off_energy = al(sizeof(double) * size_t(std::max<int64_t>(b->nparams, 1)));
-    b->off_grads = al(b->off_energy + sizeof(double) * size_t(ncirc));
-    const size_t pinned_bytes = b->off_grads + sizeof(double) * size_t(std::max<int64_t>(b->nparams, 1));
-    if (hipHostMalloc(&b->pinned, pinned_bytes, hipHostMallocDefault) != hipSuccess) {
-        (void)hipGetLastError();
-        destroy(b);
-        return fail(QSIM_ERR_OOM, "cannot allocate pinned batch memory");
-    }
-    // capture: params in, counter reset + persistent kernel, results out
+    // capture: counter reset + persistent kernel (parameters and results
+    // move device to device around the graph, in stream order)
     char *d = static_cast<char *>(b->dev);
-    char *h = static_cast<char *>(b->pinned);
+    b->d_params = reinterpret_cast<double *>(d + o_params);
+    b->d_energy = reinterpret_cast<double *>(d + o_energy);
+    b->d_grads = reinterpret_cast<double *>(d + o_grads);
     BatchDevice bd{};
     bd.circs = reinterpret_cast<const BatchCircuit *>(d + o_circs);
     bd.order = reinterpret_cast<const int32_t *>(d + o_order);
@@ -349,16 +342,7 @@ qsim_status qsim_batch_create(int ncirc, const qsim_circuit *circs, const int64_
     bd.mmax = batch_tile_max(dtype);
     hipError_t e = hipStreamCreateWithFlags(&b->cap_stream, hipStreamNonBlocking);
     if (e == hipSuccess) e = hipStreamBeginCapture(b->cap_stream, hipStreamCaptureModeThreadLocal);
-    if (e == hipSuccess && b->nparams > 0)
-        e = hipMemcpyAsync(d + o_params, h + b->off_params, sizeof(double) * size_t(b->nparams),
-                           hipMemcpyHostToDevice, b->cap_stream);
     if (e == hipSuccess) e = launch_batch(b->cap_stream, dtype, bd, b->grid);
-    if (e == hipSuccess)
-        e = hipMemcpyAsync(h + b->off_energy, d + o_energy, sizeof(double) * size_t(ncirc), hipMemcpyDeviceToHost,
-                           b->cap_stream);
-    if (e == hipSuccess && b->want_grad && b->nparams > 0)
-        e = hipMemcpyAsync(h + b->off_grads, d + o_grads, sizeof(double) * size_t(b->nparams),
-                           hipMemcpyDeviceToHost, b->cap_stream);
     hipGraph_t g = nullptr;
     const hipError_t ec = hipStreamEndCapture(b->cap_stream, &g);
     if (e == hipSuccess) e = ec;
@@ -373,19 +357,36 @@ qsim_status qsim_batch_create(int ncirc, const qsim_circuit *circs, const int64_
     return QSIM_OK;
 }
 
-qsim_status qsim_batch_run(qsim_batch b, const double *params, double *energies, double *grads,
+static bool device_memory(const void *p) {
+    hipPointerAttribute_t attr;
+    if (hipPointerGetAttributes(&attr, p) != hipSuccess) {
+        (void)hipGetLastError();
+        return false;
+    }
+    return attr.type == hipMemoryTypeDevice || attr.type == hipMemoryTypeManaged;
+}
+
+qsim_status qsim_batch_run(qsim_batch b, const double *params_dev, double *energies_dev, double *grads_dev,
                            void *hip_stream) {
     if (!b) return fail(QSIM_ERR_ARG, "batch handle is NULL");
-    if (!energies || (b->nparams > 0 && !params) || (b->want_grad && b->nparams > 0 && !grads))
+    clear_error();
+    if (!energies_dev || (b->nparams > 0 && !params_dev) || (b->want_grad && b->nparams > 0 && !grads_dev))
         return fail(QSIM_ERR_ARG, "NULL argument");
+    if (!device_memory(energies_dev) || (b->nparams > 0 && !device_memory(params_dev)) ||
+        (b->want_grad && b->nparams > 0 && !device_memory(grads_dev)))
+        return fail(QSIM_ERR_ARG, "params, energies and grads must be device memory");
     hipStream_t st = static_cast<hipStream_t>(hip_stream);
-    char *h = static_cast<char *>(b->pinned);
-    if (b->nparams > 0) std::memcpy(h + b->off_params, params, sizeof(double) * size_t(b->nparams));
-    hipError_t e = hipGraphLaunch(b->exec, st);
-    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    const size_t pbytes = sizeof(double) * size_t(b->nparams);
+    hipError_t e = hipSuccess;
+    if (b->nparams > 0) e = hipMemcpyAsync(b->d_params, params_dev, pbytes, hipMemcpyDeviceToDevice, st);
+    if (e == hipSuccess) e = hipGraphLaunch(b->exec, st);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(energies_dev, b->d_energy, sizeof(double) * size_t(b->ncirc), hipMemcpyDeviceToDevice, st);
+    if (e == hipSuccess && b->want_grad && b->nparams > 0)
+        e = hipMemcpyAsync(grads_dev, b->d_grads, pbytes, hipMemcpyDeviceToDevice, st);
     if (e != hipSuccess) return fail(QSIM_ERR_DEVICE, std::string("batch run failed: ") + hipGetErrorString(e));
-    std::memcpy(energies, h + b->off_energy, sizeof(double) * size_t(b->ncirc));
-    if (b->want_grad && b->nparams > 0) std::memcpy(grads, h + b->off_grads, sizeof(double) * size_t(b->nparams));
+    b->last_stream = st;
+    b->ran = true;
     return QSIM_OK;
 }
 
@@ -398,6 +399,7 @@ qsim_status qsim_batch_info(qsim_batch b, int *grid, int *programs, int *max_n) 
 }
 
 qsim_status qsim_batch_free(qsim_batch b) {
+    if (b && b->ran) (void)hipStreamSynchronize(b->last_stream);
     if (b && b->cap_stream) (void)hipStreamSynchronize(b->cap_stream);
     destroy(b);
     return QSIM_OK;

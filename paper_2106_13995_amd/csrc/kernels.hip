@@ -238,6 +238,11 @@ __global__ void __launch_bounds__(kTileThreads) k_tile_pass(const TileArgs<T> a)
         const c2_t<T> *U = spool + op.moff;
         if (op.type == 1) {
             tile_diag<T>(lds, op, U, base, M);
+        } else if (op.type == 4) {
+            // rotation by a parameter held on the device: (cos, sin) of its half angle
+            const double cs = a.trig[2 * op.moff];
+            const double sn = op.jbit[0] ? -a.trig[2 * op.moff + 1] : a.trig[2 * op.moff + 1];
+            tile_rotation<T>(lds, op.pos[0], op.kin, cs, sn, M);
         } else if (op.type == 5) {
             tile_controlled<T>(lds, op, U, M);
         } else {
@@ -263,9 +268,10 @@ __global__ void __launch_bounds__(kTileThreads) k_tile_pass(const TileArgs<T> a)
 }
 
 template <typename T>
-static hipError_t tile_pass_t(qsim_state s, const Plan &plan, const Pass &p) {
+static hipError_t tile_pass_t(qsim_state s, const Plan &plan, const Pass &p, const double *trig) {
     TileArgs<T> a{};
     a.psi = static_cast<c2_t<T> *>(s->data);
+    a.trig = trig;
     a.ops = reinterpret_cast<const TileOp *>(plan.dev) + p.op_begin;
     a.pool = reinterpret_cast<const c2_t<T> *>(static_cast<const char *>(plan.dev) + plan.pool_dev_off) +
              p.pool_begin;
@@ -296,8 +302,8 @@ static hipError_t tile_pass_t(qsim_state s, const Plan &plan, const Pass &p) {
     return hipGetLastError();
 }
 
-hipError_t launch_tile_pass(qsim_state s, const Plan &plan, const Pass &p) {
-    return s->dtype == QSIM_C64 ? tile_pass_t<float>(s, plan, p) : tile_pass_t<double>(s, plan, p);
+hipError_t launch_tile_pass(qsim_state s, const Plan &plan, const Pass &p, const double *trig) {
+    return s->dtype == QSIM_C64 ? tile_pass_t<float>(s, plan, p, trig) : tile_pass_t<double>(s, plan, p, trig);
 }
 
 // ------------------------------------------------------------ basis state
@@ -444,20 +450,44 @@ k_expect_tile(const c2_t<T> *__restrict__ psi, const ExpTilePass p, const ExpTer
 }
 
 // The same sums for tiles of exactly KPT * 256 amplitudes, with each
-// thread's amplitudes and products in registers and the terms as the outer
-// loop (one load of a term per group and tile instead of one per amplitude).
-// Amplitude l = t + 256 k of the tile is thread t's k-th, so the sign parity
-// of a term splits into a thread part and a part known for each k.
-//  * X mask 0: each amplitude's weight D = sum_t w_t (-1)^{|y & z_t|} is
-//    summed first (in double), then D |psi_y|^2 is added.
-//  * X mask x != 0: the pair (y, y ^ x) is visited once, from the member
-//    whose lowest bit of x is 0, and counted twice: for a Hermitian term the
-//    two members' summands are complex conjugates, so their sum is twice the
-//    real part of either.
+// thread's amplitudes in registers and the terms as the outer loop.
+// Amplitude l = t + 256 k of the tile is thread t's k-th, so the local bits
+// 0..7 of l are the thread's and bits 8.. the register index k.
+//  * X mask 0: for amplitude y = (thread part) + (register part k),
+//    (-1)^{|y & z|} = (-1)^{|y_t & z|} (-1)^{|k & mu(z)|} with mu(z) the
+//    register part of z.  The thread sums C_mu = sum of w (-1)^{|y_t & z|}
+//    over the terms with register part mu (terms arrive ordered by mu), and
+//    the weights of all its amplitudes, D_k = sum_mu C_mu (-1)^{|k & mu|},
+//    follow by a Walsh-Hadamard transform over the register bits; then
+//    D_k |psi_k|^2 is added.  Cost per amplitude: about one term-sign per
+//    KPT amplitudes per term, instead of one per amplitude per term.
+//  * simple groups (X_h / Y_h terms only): the pair (y, y ^ x) is visited
+//    once, from the member with y_h = 0, and adds 2 (A Re + B Im) of
+//    conj(psi_y) psi_{y^x}; when h is a register bit both members are in
+//    the thread's registers.
+//  * other X masks: the pair is visited once and counted twice: for a
+//    Hermitian term the two members' summands are complex conjugates, so
+//    their sum is twice the real part of either.
+template <typename T, int KPT, int KX>
+__device__ __forceinline__ void pairs_in_registers(const c2_t<T> (&a)[KPT], double A, double B, bool use_b,
+                                                   double &acc) {
+    double sr = 0.0, si = 0.0;
+#pragma unroll
+    for (int k = 0; k < KPT; ++k) {
+        if (k & KX) continue;
+        const double ar = double(a[k].x), ai = double(a[k].y);
+        const double br = double(a[k ^ KX].x), bi = double(a[k ^ KX].y);
+        sr += ar * br + ai * bi;
+        if (use_b) si += ar * bi - ai * br;
+    }
+    acc += 2.0 * (A * sr + B * si);
+}
+
 template <typename T, int KPT>
 __global__ void __launch_bounds__(kExpThreads)
 k_expect_tile_reg(const c2_t<T> *__restrict__ psi, const ExpTilePass p, const ExpTerm *__restrict__ terms,
                   uint64_t ntiles, double *__restrict__ partials) {
+    static_assert(KPT == 8 || KPT == 16, "register tiles of 8 or 16 amplitudes per thread");
     extern __shared__ char lds_raw[];
     c2_t<T> *lds = reinterpret_cast<c2_t<T> *>(lds_raw);
     __shared__ double wsum[kExpTileGroups][kExpThreads / 64];
@@ -481,26 +511,65 @@ k_expect_tile_reg(const c2_t<T> *__restrict__ psi, const ExpTilePass p, const Ex
             lds[l] = psi[gi];
         }
         __syncthreads();
+        c2_t<T> a[KPT];
+#pragma unroll
+        for (int k = 0; k < KPT; ++k) a[k] = lds[t + uint32_t(k) * kExpThreads];
         for (int g = 0; g < p.ngroups; ++g) {
             const ExpTileGroup gr = p.groups[g];
             double acc = 0.0;
             if (gr.xl == 0) {
-                double D[KPT];
+                double C[KPT];
 #pragma unroll
-                for (int k = 0; k < KPT; ++k) D[k] = 0.0;
-                for (int tt = gr.first; tt < gr.first + gr.count; ++tt) {
-                    const ExpTerm e = terms[tt];
-                    const uint32_t zl = uint32_t(e.pad_);
-                    const uint32_t par = (uint32_t(__popcll(base & e.z)) ^ uint32_t(__popc(t & zl & 0xffu))) & 1u;
-                    const double w = par ? -e.wr : e.wr;
+                for (int k = 0; k < KPT; ++k) C[k] = 0.0;
 #pragma unroll
-                    for (int k = 0; k < KPT; ++k)
-                        D[k] += (__popc(uint32_t(k) & (zl >> 8)) & 1) ? -w : w;
+                for (int mu = 0; mu < KPT; ++mu) {
+                    for (int tt = p.dmu[mu]; tt < p.dmu[mu + 1]; ++tt) {
+                        const ExpTerm e = terms[tt];
+                        const uint32_t par =
+                            (uint32_t(__popcll(base & e.z)) ^ uint32_t(__popc(t & uint32_t(e.pad_) & 0xffu))) & 1u;
+                        C[mu] += par ? -e.wr : e.wr;
+                    }
+                }
+#pragma unroll
+                for (int bit = 1; bit < KPT; bit <<= 1) {
+#pragma unroll
+                    for (int k = 0; k < KPT; ++k) {
+                        if (k & bit) continue;
+                        const double u = C[k], v = C[k | bit];
+                        C[k] = u + v;
+                        C[k | bit] = u - v;
+                    }
                 }
 #pragma unroll
                 for (int k = 0; k < KPT; ++k) {
-                    const c2_t<T> a = lds[t + uint32_t(k) * kExpThreads];
-                    acc += D[k] * (double(a.x) * double(a.x) + double(a.y) * double(a.y));
+                    const double ar = double(a[k].x), ai = double(a[k].y);
+                    acc += C[k] * (ar * ar + ai * ai);
+                }
+            } else if ((gr.flags & kExpGroupSimple) && (gr.xl & 0xffu) == 0) {
+                // one register bit: both members of every pair are in registers
+                const bool use_b = gr.B != 0.0;
+                switch (gr.xl >> 8) {
+                case 1: pairs_in_registers<T, KPT, 1>(a, gr.A, gr.B, use_b, acc); break;
+                case 2: pairs_in_registers<T, KPT, 2>(a, gr.A, gr.B, use_b, acc); break;
+                case 4: pairs_in_registers<T, KPT, 4>(a, gr.A, gr.B, use_b, acc); break;
+                default:
+                    if constexpr (KPT == 16) pairs_in_registers<T, KPT, 8>(a, gr.A, gr.B, use_b, acc);
+                    break;
+                }
+            } else if (gr.flags & kExpGroupSimple) {
+                // one thread bit: the member with bit 0 reads its partner from LDS
+                const uint32_t xb = gr.xl;
+                if ((t & xb) == 0) {
+                    const bool use_b = gr.B != 0.0;
+                    double sr = 0.0, si = 0.0;
+#pragma unroll
+                    for (int k = 0; k < KPT; ++k) {
+                        const c2_t<T> b = lds[(t ^ xb) + uint32_t(k) * kExpThreads];
+                        const double ar = double(a[k].x), ai = double(a[k].y), br = double(b.x), bi = double(b.y);
+                        sr += ar * br + ai * bi;
+                        if (use_b) si += ar * bi - ai * br;
+                    }
+                    acc += 2.0 * (gr.A * sr + gr.B * si);
                 }
             } else {
                 const uint32_t lb = gr.xl & (0u - gr.xl);   // lowest bit of x
@@ -510,9 +579,9 @@ k_expect_tile_reg(const c2_t<T> *__restrict__ psi, const ExpTilePass p, const Ex
                 for (int k = 0; k < KPT / 2; ++k) {
                     const uint32_t j = t + uint32_t(k) * kExpThreads;
                     const uint32_t l = ((j & ~(lb - 1u)) << 1) | (j & (lb - 1u));
-                    const c2_t<T> a = lds[l], b = lds[l ^ gr.xl];
-                    pr[k] = double(a.x) * double(b.x) + double(a.y) * double(b.y);
-                    pi[k] = double(a.x) * double(b.y) - double(a.y) * double(b.x);
+                    const c2_t<T> av = lds[l], bv = lds[l ^ gr.xl];
+                    pr[k] = double(av.x) * double(bv.x) + double(av.y) * double(bv.y);
+                    pi[k] = double(av.x) * double(bv.y) - double(av.y) * double(bv.x);
                     ly[k] = l ^ gr.xl;
                 }
                 for (int tt = gr.first; tt < gr.first + gr.count; ++tt) {

@@ -178,6 +178,11 @@ k_adjoint_tile(const TileArgs<T> a, c2_t<T> *__restrict__ lam, double *__restric
         } else if (op.type == 1) {
             tile_diag<T>(lp, op, U, base, M);
             tile_diag<T>(ll, op, U, base, M);
+        } else if (op.type == 4) {
+            const double cs = a.trig[2 * op.moff];
+            const double sn = op.jbit[0] ? -a.trig[2 * op.moff + 1] : a.trig[2 * op.moff + 1];
+            tile_rotation<T>(lp, op.pos[0], op.kin, cs, sn, M);
+            tile_rotation<T>(ll, op.pos[0], op.kin, cs, sn, M);
         } else if (op.type == 5) {
             tile_controlled<T>(lp, op, U, M);
             tile_controlled<T>(ll, op, U, M);
@@ -209,9 +214,11 @@ k_adjoint_tile(const TileArgs<T> a, c2_t<T> *__restrict__ lam, double *__restric
 }
 
 template <typename T>
-static hipError_t adjoint_pass_t(qsim_state s, const Plan &plan, const Pass &p, void *lam, double *probe_partials) {
+static hipError_t adjoint_pass_t(qsim_state s, const Plan &plan, const Pass &p, void *lam, double *probe_partials,
+                                 const double *trig) {
     TileArgs<T> a{};
     a.psi = static_cast<c2_t<T> *>(s->data);
+    a.trig = trig;
     a.ops = reinterpret_cast<const TileOp *>(plan.dev) + p.op_begin;
     a.pool = reinterpret_cast<const c2_t<T> *>(static_cast<const char *>(plan.dev) + plan.pool_dev_off) +
              p.pool_begin;
@@ -245,9 +252,50 @@ static hipError_t adjoint_pass_t(qsim_state s, const Plan &plan, const Pass &p, 
     return hipGetLastError();
 }
 
-hipError_t launch_adjoint_pass(qsim_state s, const Plan &plan, const Pass &p, void *lam, double *probe_partials) {
-    return s->dtype == QSIM_C64 ? adjoint_pass_t<float>(s, plan, p, lam, probe_partials)
-                                : adjoint_pass_t<double>(s, plan, p, lam, probe_partials);
+hipError_t launch_adjoint_pass(qsim_state s, const Plan &plan, const Pass &p, void *lam, double *probe_partials,
+                               const double *trig) {
+    return s->dtype == QSIM_C64 ? adjoint_pass_t<float>(s, plan, p, lam, probe_partials, trig)
+                                : adjoint_pass_t<double>(s, plan, p, lam, probe_partials, trig);
+}
+
+// (cos, sin) of theta_j / 2 for every parameter, read from device memory.
+__global__ void __launch_bounds__(kBlockThreads) k_half_angle_trig(const double *__restrict__ params, int64_t n,
+                                                                   double *__restrict__ trig) {
+    for (int64_t j = int64_t(blockIdx.x) * kBlockThreads + threadIdx.x; j < n; j += int64_t(gridDim.x) * kBlockThreads) {
+        double sn, cs;
+        sincos(0.5 * params[j], &sn, &cs);
+        trig[2 * j] = cs;
+        trig[2 * j + 1] = sn;
+    }
+}
+
+hipError_t launch_half_angle_trig(qsim_state s, const double *params, int64_t n, double *trig) {
+    if (n <= 0) return hipSuccess;
+    const int grid = int(std::min<int64_t>((n + kBlockThreads - 1) / kBlockThreads, 1024));
+    hipLaunchKernelGGL(k_half_angle_trig, dim3(grid), dim3(kBlockThreads), 0, s->stream, params, n, trig);
+    return hipGetLastError();
+}
+
+// grad[j] = sum of probe sums sums[idx[k]] for k in [row[j], row[j + 1]) in
+// that order (the ops that use parameter j, last op first); energy = sums[nprobes].
+__global__ void __launch_bounds__(kBlockThreads)
+k_gather_gradient(const double *__restrict__ sums, const int32_t *__restrict__ row, const int32_t *__restrict__ idx,
+                  int64_t nparams, int nprobes, double *__restrict__ grad, double *__restrict__ energy) {
+    for (int64_t j = int64_t(blockIdx.x) * kBlockThreads + threadIdx.x; j < nparams;
+         j += int64_t(gridDim.x) * kBlockThreads) {
+        double g = 0.0;
+        for (int k = row[j]; k < row[j + 1]; ++k) g += sums[idx[k]];
+        grad[j] = g;
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) energy[0] = sums[nprobes];
+}
+
+hipError_t launch_gather_gradient(qsim_state s, const double *sums, const int32_t *row, const int32_t *idx,
+                                  int64_t nparams, int nprobes, double *grad, double *energy) {
+    const int grid = int(std::max<int64_t>(1, std::min<int64_t>((nparams + kBlockThreads - 1) / kBlockThreads, 1024)));
+    hipLaunchKernelGGL(k_gather_gradient, dim3(grid), dim3(kBlockThreads), 0, s->stream, sums, row, idx, nparams,
+                       nprobes, grad, energy);
+    return hipGetLastError();
 }
 
 // out[r] = sum of row r (`cols` doubles), one block per row, fixed order.

@@ -54,51 +54,6 @@ struct BatchShared {
     int probe_param[kProbeSlots];
 };
 
-// Rotation exp(-i theta G / 2) (or its inverse) on local position p, given
-// cs = cos(theta / 2) and sn = sin(theta / 2).
-template <typename T>
-__device__ __forceinline__ void tile_rotation(c2_t<T> *lds, int p, int gen, double cs, double sn, uint32_t M) {
-    // [[a, b], [c, d]] as (re, im)
-    T ar, ai, br, bi, cr, ci, dr, di;
-    if (gen == 1) {        // X: [[c, -is], [-is, c]]
-        ar = T(cs); ai = T(0); br = T(0); bi = T(-sn); cr = T(0); ci = T(-sn); dr = T(cs); di = T(0);
-    } else if (gen == 2) { // Y: [[c, -s], [s, c]]
-        ar = T(cs); ai = T(0); br = T(-sn); bi = T(0); cr = T(sn); ci = T(0); dr = T(cs); di = T(0);
-    } else {               // Z: diag(e^{-i t/2}, e^{i t/2})
-        ar = T(cs); ai = T(-sn); br = T(0); bi = T(0); cr = T(0); ci = T(0); dr = T(cs); di = T(sn);
-    }
-    const uint32_t bit = 1u << p, npairs = M >> 1;
-    // kPairBatch pairs per thread are read before any is written (distinct
-    // pairs never share an address), so their LDS reads overlap
-    for (uint32_t g0 = threadIdx.x; g0 < npairs; g0 += kPairBatch * kTileThreads) {
-        uint32_t xs[kPairBatch];
-        c2_t<T> u[kPairBatch], v[kPairBatch];
-#pragma unroll
-        for (int c = 0; c < kPairBatch; ++c) {
-            const uint32_t g = g0 + uint32_t(c) * kTileThreads;
-            const uint32_t lo = g & (bit - 1u);
-            xs[c] = ((g - lo) << 1) | lo;
-            if (g < npairs) {
-                u[c] = lds[xs[c]];
-                v[c] = lds[xs[c] | bit];
-            }
-        }
-#pragma unroll
-        for (int c = 0; c < kPairBatch; ++c) {
-            if (g0 + uint32_t(c) * kTileThreads >= npairs) break;
-            T o0r = T(0), o0i = T(0), o1r = T(0), o1i = T(0);
-            cfma(o0r, o0i, ar, ai, u[c].x, u[c].y);
-            cfma(o0r, o0i, br, bi, v[c].x, v[c].y);
-            cfma(o1r, o1i, cr, ci, u[c].x, u[c].y);
-            cfma(o1r, o1i, dr, di, v[c].x, v[c].y);
-            c2_t<T> w0, w1;
-            w0.x = o0r; w0.y = o0i;
-            w1.x = o1r; w1.y = o1i;
-            lds[xs[c]] = w0;
-            lds[xs[c] | bit] = w1;
-        }
-    }
-}
 
 template <typename T>
 __device__ __forceinline__ double batch_probe(const c2_t<T> *lp, const c2_t<T> *ll, int p, int gen, uint32_t M) {

@@ -262,6 +262,25 @@ struct CachedPlan {
     uint64_t last_use = 0;
 };
 
+// Plans of the adjoint method for one circuit structure: forward and reverse
+// tile passes whose parametric rotations take (cos, sin) of their half angle
+// from a device table, and the probes of each parameter (device, CSR:
+// int32 row[nparams + 1] at offset 0, int32 idx[nprobes] at idx_off).
+struct AdjointPlan {
+    std::string key;
+    Plan fwd, rev;
+    int mtile = 0;        // reverse tile width
+    int nprobes = 0;
+    int64_t nparams = 0;
+    void *dev = nullptr;
+    size_t idx_off = 0;
+    hipStream_t dev_stream = nullptr;
+    uint64_t last_use = 0;
+    ~AdjointPlan() {
+        if (dev) (void)hipFreeAsync(dev, dev_stream);
+    }
+};
+
 }  // namespace qsim
 
 struct qsim_state_s {
@@ -283,6 +302,10 @@ struct qsim_state_s {
     std::vector<qsim::CachedPlan> plans;
     std::unique_ptr<qsim::Plan> transient;   // last uncached plan (single gates)
     void *adj_lam = nullptr;                 // second state of the adjoint method
+    std::vector<std::unique_ptr<qsim::AdjointPlan>> adj_plans;
+    void *adj_h = nullptr;                   // the adjoint's Pauli sum on the device
+    size_t adj_h_bytes = 0;
+    std::string adj_h_key;                   // ... and the terms it was written from
     uint64_t use_clock = 0;
 };
 
@@ -293,7 +316,9 @@ size_t amp_bytes(int dtype);
 // Launchers (kernels_*.hip).  All return hipSuccess or the launch error.
 hipError_t launch_dense_sweep(qsim_state s, const Pass &p);
 hipError_t launch_diag_sweep(qsim_state s, const Pass &p);
-hipError_t launch_tile_pass(qsim_state s, const Plan &plan, const Pass &p);
+// trig: (cos, sin) of each parameter's half angle, for passes with
+// device-parameter rotations (TileOp type 4); may be NULL otherwise.
+hipError_t launch_tile_pass(qsim_state s, const Plan &plan, const Pass &p, const double *trig = nullptr);
 hipError_t launch_tile_reg_pass(qsim_state s, const Plan &plan, const Pass &p);
 hipError_t launch_mfma_pass(qsim_state s, const Plan &plan, const Pass &p);
 hipError_t launch_set_basis(qsim_state s, uint64_t index);
@@ -310,14 +335,24 @@ hipError_t launch_reduce(qsim_state s, const double *partials, int count, double
 // field, the local image of their Z mask.  Writes ngroups * grid partials
 // (group-major) and returns the count.
 constexpr int kExpTileGroups = 64;
+// A group is "simple" when its X mask is one qubit h and every term's Z mask
+// is 0 (X_h, weight A = sum of their coefficients) or h itself (Y_h, weight
+// B); the pair (y, y ^ x) then contributes 2 (A Re + B Im)(conj(psi_y)
+// psi_{y^x}) from the member with y_h = 0.
+constexpr uint32_t kExpGroupSimple = 1;
 struct ExpTileGroup {
     uint32_t xl;          // X mask in tile-local bits
     int32_t first, count; // term range
-    int32_t pad_;
+    uint32_t flags;       // kExpGroupSimple
+    double A, B;          // weights of a simple group
 };
+// The group with X mask 0 (at most one per sum) keeps its terms ordered by
+// the register part of their local Z mask (local bits 8 and up for the
+// register-staged kernel); dmu[mu] .. dmu[mu + 1] is the range with part mu.
 struct ExpTilePass {
     int32_t m, L, H, ngroups;
     int32_t hpos[16];
+    int32_t dmu[33];
     ExpTileGroup groups[kExpTileGroups];
 };
 hipError_t launch_expect_tiles(qsim_state s, const ExpTilePass &p, const void *dev_terms, double *partials,
@@ -327,7 +362,11 @@ hipError_t launch_expect_tiles(qsim_state s, const ExpTilePass &p, const void *d
 int pauli_apply_grid(uint64_t N);
 hipError_t launch_pauli_apply(qsim_state s, void *lam, const void *groups, int ngroups, const void *terms,
                               double *partials);
-hipError_t launch_adjoint_pass(qsim_state s, const Plan &plan, const Pass &p, void *lam, double *probe_partials);
+hipError_t launch_adjoint_pass(qsim_state s, const Plan &plan, const Pass &p, void *lam, double *probe_partials,
+                               const double *trig);
+hipError_t launch_half_angle_trig(qsim_state s, const double *params, int64_t n, double *trig);
+hipError_t launch_gather_gradient(qsim_state s, const double *sums, const int32_t *row, const int32_t *idx,
+                                  int64_t nparams, int nprobes, double *grad, double *energy);
 hipError_t launch_reduce_rows(qsim_state s, const double *in, int rows, int cols, double *out);
 
 // Profiling hooks around launches.

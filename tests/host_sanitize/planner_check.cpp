@@ -15,7 +15,14 @@ namespace qsim {
     std::fprintf(stderr, "planner reached a device launch: %s\n", what);
     std::abort();
 }
-hipError_t launch_adjoint_pass(qsim_state, const Plan &, const Pass &, void *, double *) { no_device("adjoint"); }
+hipError_t launch_adjoint_pass(qsim_state, const Plan &, const Pass &, void *, double *, const double *) {
+    no_device("adjoint");
+}
+hipError_t launch_half_angle_trig(qsim_state, const double *, int64_t, double *) { no_device("trig"); }
+hipError_t launch_gather_gradient(qsim_state, const double *, const int32_t *, const int32_t *, int64_t, int, double *,
+                                  double *) {
+    no_device("gather");
+}
 hipError_t launch_batch(hipStream_t, int, const BatchDevice &, int) { no_device("batch"); }
 hipError_t launch_dense_sweep(qsim_state, const Pass &) { no_device("dense"); }
 hipError_t launch_diag_sweep(qsim_state, const Pass &) { no_device("diag"); }
@@ -26,7 +33,7 @@ hipError_t launch_pauli_apply(qsim_state, void *, const void *, int, const void 
 hipError_t launch_reduce(qsim_state, const double *, int, double *) { no_device("reduce"); }
 hipError_t launch_reduce_rows(qsim_state, const double *, int, int, double *) { no_device("reduce"); }
 hipError_t launch_set_basis(qsim_state, uint64_t) { no_device("basis"); }
-hipError_t launch_tile_pass(qsim_state, const Plan &, const Pass &) { no_device("tile"); }
+hipError_t launch_tile_pass(qsim_state, const Plan &, const Pass &, const double *) { no_device("tile"); }
 hipError_t launch_tile_reg_pass(qsim_state, const Plan &, const Pass &) { no_device("tile"); }
 int pauli_apply_grid(uint64_t) { no_device("pauli"); }
 }  // namespace qsim

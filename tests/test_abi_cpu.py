@@ -35,11 +35,19 @@ def test_header_declarations_all_exported():
         assert hasattr(lib, name), name
 
 
-def test_struct_layouts_match_header_sizes():
-    # qsim_op: 2 + 6 + 2 int32, 3 doubles, 1 int64 = 72 bytes
-    assert ctypes.sizeof(q.QsimOp) == 72
-    assert ctypes.sizeof(q.QsimPauliTerm) == 24
-    assert ctypes.sizeof(q.QsimOptions) == 16
+def test_struct_layouts_match_header_sizes(tmp_path):
+    # the binding's ctypes structs against what a C compiler makes of the header
+    import subprocess
+    src = tmp_path / "sizes.c"
+    src.write_text('#include <stdio.h>\n#include <stddef.h>\n#include "qsim.h"\n'
+                   'int main(void) { printf("%zu %zu %zu %zu %zu %zu\\n", sizeof(qsim_op), sizeof(qsim_circuit), '
+                   'sizeof(qsim_pauli_term), sizeof(qsim_pauli_sum), sizeof(qsim_options), '
+                   'offsetof(qsim_options, deterministic)); return 0; }\n')
+    exe = tmp_path / "sizes"
+    subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    got = [int(v) for v in subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.split()]
+    assert got == [ctypes.sizeof(q.QsimOp), ctypes.sizeof(q.QsimCircuit), ctypes.sizeof(q.QsimPauliTerm),
+                   ctypes.sizeof(q.QsimPauliSum), ctypes.sizeof(q.QsimOptions), q.QsimOptions.deterministic.offset]
 
 
 def test_wrap_validation():
