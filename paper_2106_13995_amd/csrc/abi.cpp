@@ -1,6 +1,8 @@
 // C ABI of the qsim library: argument validation, state lifetime, plan cache
 // and dispatch of passes to the HIP kernels.
 #include <algorithm>
+#include <mutex>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <new>
@@ -28,6 +30,28 @@ static qsim_status device_error(qsim_state s, hipError_t e, const char *what) {
         hipError_t e_ = (call);                                   \
         if (e_ != hipSuccess) return device_error((s), e_, what); \
     } while (0)
+
+// Failure injection for tests of the error paths: with QSIM_FAULT=launch
+// every launch point fails as a failed kernel launch would (the call returns
+// QSIM_ERR_DEVICE and the state becomes invalid); with QSIM_FAULT=launch:N
+// only the N-th launch point reached since the variable took its value.
+// Nothing is launched at an injected failure.
+static std::mutex g_fault_mu;
+static std::string g_fault_spec;
+static long g_launch_points = 0;
+
+static hipError_t injected_fault() {
+    const char *v = std::getenv("QSIM_FAULT");
+    if (!v || std::strncmp(v, "launch", 6) != 0) return hipSuccess;
+    std::lock_guard<std::mutex> lk(g_fault_mu);
+    if (g_fault_spec != v) {
+        g_fault_spec = v;
+        g_launch_points = 0;
+    }
+    const long k = ++g_launch_points;
+    if (v[6] == ':') return std::atol(v + 7) == k ? hipErrorLaunchFailure : hipSuccess;
+    return v[6] == 0 ? hipErrorLaunchFailure : hipSuccess;
+}
 
 static qsim_status check_state(qsim_state s) {
     if (!s) return set_error(QSIM_ERR_ARG, "state handle is NULL");
@@ -176,6 +200,7 @@ static qsim_status upload_plan(qsim_state s, Plan &plan) {
 }
 
 static qsim_status run_plan(qsim_state s, Plan &plan) {
+    QSIM_HIP(s, injected_fault(), "injected fault (QSIM_FAULT)");
     qsim_status st = upload_plan(s, plan);
     if (st != QSIM_OK) return st;
     for (size_t i = 0; i < plan.passes.size(); ++i) {
@@ -474,6 +499,7 @@ qsim_status qsim_set_basis(qsim_state s, uint64_t index) {
     qsim_status st = check_state(s);
     if (st != QSIM_OK) return st;
     if (index >= (1ull << s->n)) return set_error(QSIM_ERR_ARG, "basis index outside [0, 2^n)");
+    QSIM_HIP(s, injected_fault(), "injected fault (QSIM_FAULT)");
     QSIM_HIP(s, launch_set_basis(s, index), "set_basis launch");
     return QSIM_OK;
 }
@@ -555,7 +581,16 @@ qsim_status qsim_apply_circuit(qsim_state s, const qsim_circuit *c, const double
     return run_plan(s, *plan);
 }
 
-qsim_status qsim_expectation(qsim_state s, const qsim_pauli_sum *H, double *out_host) {
+}  // extern "C"
+
+namespace qsim {
+
+// <psi|H|psi> into *out_host.  Device scratch: the state's own (grown on
+// demand, host staging pinned) when fixed_dev is NULL, else the caller's
+// fixed_bytes at fixed_dev (nothing allocated; terms copied from host
+// memory; sums that need more than fixed_bytes are rejected).
+qsim_status expectation_with(qsim_state s, const qsim_pauli_sum *H, double *out_host, void *fixed_dev,
+                             size_t fixed_bytes) {
     qsim_status st = check_state(s);
     if (st != QSIM_OK) return st;
     if (!H || !out_host || (H->nterms > 0 && !H->terms)) return set_error(QSIM_ERR_ARG, "NULL argument");
@@ -576,11 +611,25 @@ qsim_status qsim_expectation(qsim_state s, const qsim_pauli_sum *H, double *out_
     const size_t terms_off = ngroups * maxp * sizeof(double) + 256;
     const size_t terms_bytes = sizeof(DevTerm) * size_t(std::max(H->nterms, 1));
     const size_t out_off = (terms_off + terms_bytes + 255) & ~size_t(255);
-    st = ensure_scratch(s, out_off + 256);
-    if (st != QSIM_OK) return st;
-    st = ensure_pinned(s, std::max(terms_bytes, size_t(64)));
-    if (st != QSIM_OK) return st;
-    DevTerm *ht = static_cast<DevTerm *>(s->pinned);
+    std::vector<DevTerm> host_terms;
+    DevTerm *ht = nullptr;
+    char *scr = nullptr;
+    if (fixed_dev) {
+        if (out_off + 256 > fixed_bytes)
+            return set_error(QSIM_ERR_ARG, "the Pauli sum needs " + std::to_string(out_off + 256) +
+                                               " bytes of scratch; the fixed buffer holds " +
+                                               std::to_string(fixed_bytes));
+        host_terms.resize(size_t(std::max(H->nterms, 1)));
+        ht = host_terms.data();
+        scr = static_cast<char *>(fixed_dev);
+    } else {
+        st = ensure_scratch(s, out_off + 256);
+        if (st != QSIM_OK) return st;
+        st = ensure_pinned(s, std::max(terms_bytes, size_t(64)));
+        if (st != QSIM_OK) return st;
+        ht = static_cast<DevTerm *>(s->pinned);
+        scr = static_cast<char *>(s->scratch);
+    }
     std::vector<std::pair<uint64_t, int>> spans;   // (x, first term slot)
     int slot = 0;
     for (auto &kv : groups) {
@@ -713,14 +762,20 @@ qsim_status qsim_expectation(qsim_state s, const qsim_pauli_sum *H, double *out_
             tpasses.push_back(tp);
         }
     }
-    char *scr = static_cast<char *>(s->scratch);
     double *partials = reinterpret_cast<double *>(scr);
     DevTerm *dterms = reinterpret_cast<DevTerm *>(scr + terms_off);
     double *dout = reinterpret_cast<double *>(scr + out_off);
     if (H->nterms > 0) {
-        st = upload_staged(s, dterms, terms_bytes);
-        if (st != QSIM_OK) return st;
+        if (fixed_dev) {
+            // from pageable host memory: the copy has read it when the call
+            // returns, and the stream is synchronised below in any case
+            QSIM_HIP(s, hipMemcpyAsync(dterms, ht, terms_bytes, hipMemcpyHostToDevice, s->stream), "hipMemcpyAsync");
+        } else {
+            st = upload_staged(s, dterms, terms_bytes);
+            if (st != QSIM_OK) return st;
+        }
     }
+    QSIM_HIP(s, injected_fault(), "injected fault (QSIM_FAULT)");
     int total = 0;
     for (const ExpTilePass &tp : tpasses) {
         int wrote = 0;
@@ -746,12 +801,18 @@ qsim_status qsim_expectation(qsim_state s, const qsim_pauli_sum *H, double *out_
         return QSIM_OK;
     }
     QSIM_HIP(s, launch_reduce(s, partials, total, dout), "reduce launch");
-    double *hout = static_cast<double *>(s->pinned) + (terms_bytes + 7) / 8;
-    (void)hout;
     QSIM_HIP(s, hipMemcpyAsync(out_host, dout, sizeof(double), hipMemcpyDeviceToHost, s->stream), "hipMemcpyAsync");
     QSIM_HIP(s, hipStreamSynchronize(s->stream), "hipStreamSynchronize");
     s->pinned_ev_pending = false;
     return QSIM_OK;
+}
+
+}  // namespace qsim
+
+extern "C" {
+
+qsim_status qsim_expectation(qsim_state s, const qsim_pauli_sum *H, double *out_host) {
+    return expectation_with(s, H, out_host, nullptr, 0);
 }
 
 qsim_status qsim_plan_summary(int n, qsim_dtype dtype, const qsim_circuit *c, const double *params,
@@ -1021,6 +1082,7 @@ qsim_status qsim_adjoint_grad(qsim_state s, const qsim_circuit *c, const double 
     double *epart = reinterpret_cast<double *>(scr + off_epart);
     double *pp = reinterpret_cast<double *>(scr + off_pp);
     double *sums = reinterpret_cast<double *>(scr + off_sums);
+    QSIM_HIP(s, injected_fault(), "injected fault (QSIM_FAULT)");
     QSIM_HIP(s, launch_half_angle_trig(s, params_dev, nparams, trig), "trig launch");
     // forward: psi <- C(theta) psi
     for (const Pass &p : ap->fwd.passes) {

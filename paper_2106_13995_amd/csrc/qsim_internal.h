@@ -329,6 +329,11 @@ hipError_t launch_expect_group(qsim_state s, uint64_t xmask, const void *dev_ter
                                double *partials, int *nwritten);
 hipError_t launch_reduce(qsim_state s, const double *partials, int count, double *out);
 
+// <psi|H|psi> with the state's scratch (fixed_dev NULL) or a caller's fixed
+// device buffer of fixed_bytes (no allocation).
+qsim_status expectation_with(qsim_state s, const qsim_pauli_sum *H, double *out_host, void *fixed_dev,
+                             size_t fixed_bytes);
+
 // Several term groups in one pass over the state: tiles of 2^m amplitudes
 // (the low L qubits and the H qubits hpos[]) in LDS, every group whose X mask
 // lies inside the tile evaluated from there.  Terms carry, in their pad

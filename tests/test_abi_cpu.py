@@ -242,3 +242,34 @@ def test_six_qubit_block_outside_low_qubits_in_small_tiles():
             c, b, f = _summary(circ, dtype=dtype, fuse_k=1, tile_m=tile_m)
             assert c["tile"] == 1 and f == 8 * 64 * N
 
+
+
+# ------------------------------------------------------------ failure paths
+
+def test_injected_launch_fault_invalidates_the_state(monkeypatch):
+    """QSIM_FAULT=launch fails the next launch point as a failed kernel launch
+    would (nothing is launched): the call returns QSIM_ERR_DEVICE, and every
+    later call on that state QSIM_ERR_STATE until it is freed."""
+    h = q.qsim_wrap(FAKE_PTR, 8, q.QSIM_C64)
+    monkeypatch.setenv("QSIM_FAULT", "launch")
+    assert q._lib.qsim_set_basis(ctypes.c_void_p(h), 0) == q.QSIM_ERR_DEVICE
+    assert "QSIM_FAULT" in q._lib.qsim_last_error().decode()
+    monkeypatch.delenv("QSIM_FAULT")
+    assert q._lib.qsim_set_basis(ctypes.c_void_p(h), 0) == q.QSIM_ERR_STATE
+    assert _circuit_status(h, W.ghz_circuit(8)) == q.QSIM_ERR_STATE
+    out = ctypes.c_double()
+    H = q.PackedPauliSum(W.chain_observable(8))
+    assert q._lib.qsim_expectation(ctypes.c_void_p(h), ctypes.byref(H.h), ctypes.byref(out)) == q.QSIM_ERR_STATE
+    assert q._lib.qsim_free(ctypes.c_void_p(h)) == q.QSIM_OK
+
+
+def test_injected_fault_at_the_nth_launch_point(monkeypatch):
+    """launch:N fails only the N-th launch point: validation errors before it
+    still return QSIM_ERR_ARG and leave the state valid."""
+    h = q.qsim_wrap(FAKE_PTR, 6, q.QSIM_C64)
+    monkeypatch.setenv("QSIM_FAULT", "launch:1")
+    assert q._lib.qsim_set_basis(ctypes.c_void_p(h), 1 << 6) == q.QSIM_ERR_ARG   # rejected before any launch
+    assert q._lib.qsim_set_basis(ctypes.c_void_p(h), 3) == q.QSIM_ERR_DEVICE
+    assert "QSIM_FAULT" in q._lib.qsim_last_error().decode()
+    assert q._lib.qsim_set_basis(ctypes.c_void_p(h), 3) == q.QSIM_ERR_STATE
+    q.qsim_free(h)

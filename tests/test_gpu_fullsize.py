@@ -184,3 +184,21 @@ def test_max_width_state(env, dtype, n, targets, tol):
     s.close()
     del s
     torch.cuda.empty_cache()
+
+
+def test_out_of_memory_is_reported(env):
+    """Two 34-qubit complex128 states (256 GiB each) do not fit in one
+    MI355X's 288 GB: the second qsim_alloc returns QSIM_ERR_OOM, and the
+    first state stays usable."""
+    q, torch = env
+    torch.cuda.empty_cache()
+    h1 = q.qsim_alloc(34, q.QSIM_C128)
+    try:
+        with pytest.raises(q.QsimError) as e:
+            q.qsim_alloc(34, q.QSIM_C128)
+        assert e.value.status == q.QSIM_ERR_OOM
+        q.qsim_set_basis(h1, (1 << 34) - 1)
+        H = q.PackedPauliSum(W.PauliSum(34, [1.0, 1.0], [0, 0], [0, 1 << 33]))   # 1 + Z_33
+        assert q.qsim_expectation(h1, H) == 0.0
+    finally:
+        q.qsim_free(h1)

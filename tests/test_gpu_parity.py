@@ -454,3 +454,25 @@ def test_plan_cache_eviction_and_stream_switch(qs):
             assert O.rel_l2(s.to_numpy(), O.apply_circuit(circ, params=p)) <= TOL["c128"]
     s.close()
     torch.cuda.synchronize()
+
+
+def test_injected_launch_fault_on_a_live_state(qs, monkeypatch):
+    """QSIM_FAULT=launch:2: the first launch point (set_basis) runs, the second
+    (the circuit) fails before launching anything; the state then reports
+    QSIM_ERR_STATE, and a fresh state on the same device works."""
+    n = 10
+    s = _state(qs, n, "c64", None)
+    monkeypatch.setenv("QSIM_FAULT", "launch:2")
+    s.set_basis(0)
+    with pytest.raises(qs.QsimError) as e:
+        s.apply_circuit(W.ghz_circuit(n))
+    assert e.value.status == qs.QSIM_ERR_DEVICE
+    monkeypatch.delenv("QSIM_FAULT")
+    with pytest.raises(qs.QsimError) as e:
+        s.expectation(W.chain_observable(n))
+    assert e.value.status == qs.QSIM_ERR_STATE
+    s.close()
+    s2 = _state(qs, n, "c64")
+    s2.apply_circuit(W.ghz_circuit(n))
+    assert O.rel_l2(s2.to_numpy(), O.apply_circuit(W.ghz_circuit(n))) <= TOL["c64"]
+    s2.close()

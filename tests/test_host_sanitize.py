@@ -104,3 +104,22 @@ def test_planner_under_sanitizers(tmp_path):
     run = subprocess.run([exe, *files], capture_output=True, text=True, env=env, timeout=600)
     assert run.returncode == 0, (run.stdout[-2000:], run.stderr[-4000:])
     assert "planner check:" in run.stdout
+
+
+@pytest.mark.skipif(shutil.which("gcc") is None, reason="needs gcc")
+def test_oracle_under_sanitizers(tmp_path):
+    """The CPU oracle built with AddressSanitizer and UBSan, driven through
+    every entry point (all gate codes, a dense 6-qubit matrix, rejected
+    arguments)."""
+    exe = str(tmp_path / "oracle_check")
+    build = subprocess.run(["gcc", "-std=gnu11", "-O1", "-g", "-fno-omit-frame-pointer", "-fcx-limited-range",
+                            "-fsanitize=address,undefined", "-fno-sanitize-recover=all",
+                            os.path.join(ROOT, "oracle", "qsim_oracle.c"),
+                            os.path.join(ROOT, "tests", "host_sanitize", "oracle_check.c"), "-lm", "-o", exe],
+                           capture_output=True, text=True)
+    assert build.returncode == 0, build.stderr[-3000:]
+    run = subprocess.run([exe], capture_output=True, text=True, timeout=300,
+                         env=dict(os.environ, ASAN_OPTIONS="detect_leaks=1:abort_on_error=1",
+                                  UBSAN_OPTIONS="halt_on_error=1:print_stacktrace=1"))
+    assert run.returncode == 0, (run.stdout[-2000:], run.stderr[-4000:])
+    assert "oracle check:" in run.stdout
