@@ -158,6 +158,7 @@ static Pass mfma_pass(Plan &plan, const HostGate &g) {
 struct TileBuilder {
     int n, dtype, m, L;
     bool reg;
+    int tiles = 1;   // state tiles a pass keeps in LDS (2 in adjoint passes)
     Plan &plan;
     TileBuilder(Plan &p, int n_, int dt, int m_, bool reg_) : n(n_), dtype(dt), m(m_), L(0), reg(reg_), plan(p) {
         L = std::min(m, low_tile_qubits(dt));
@@ -346,19 +347,36 @@ static bool group_tiles(TileBuilder &tb, const std::vector<HostGate> &gates) {
     const size_t ng = gates.size();
     std::vector<uint64_t> full(ng), target(ng);
     std::vector<char> diag(ng), wide(ng);
+    // matrix entries a gate adds to the pass pool when the pass runs from
+    // LDS (diagonal: 2^k; one-qubit block under controls: 4; dense: 4^k)
+    std::vector<size_t> pool(ng);
     for (size_t i = 0; i < ng; ++i) {
         const HostGate &g = gates[i];
         full[i] = target[i] = qmask(g);
         diag[i] = is_diagonal(g);
-        if (!diag[i] && reg_ctl && g.k > 1) {
+        const size_t d = size_t(1) << g.k;
+        pool[i] = diag[i] ? d : d * d;
+        if (!diag[i] && g.k > 1) {
             HostGate red;
             int ctl[QSIM_MAX_K];
             extract_controls(g, red, ctl);
-            if (red.k == 1) target[i] = 1ull << red.targets[0];
+            if (red.k == 1) {
+                pool[i] = 4;
+                if (reg_ctl) target[i] = 1ull << red.targets[0];
+            }
         }
+        if (g.probe_gen || g.rot_gen) pool[i] = 0;
         // dense on more than three qubits: no register program holds it
         wide[i] = !diag[i] && target[i] == full[i] && g.k > 3;
     }
+    // An LDS pass holds its tile(s), op list and pool in one workgroup's LDS
+    // (160 KiB on gfx950): the ops and matrices a pass takes are bounded by
+    // what is left next to the tile(s).
+    const size_t lds_cap = size_t(160) * 1024;
+    const size_t tile_lds = size_t(tb.tiles) * (amp_bytes(tb.dtype) << tb.m);
+    const size_t pool_cap = lds_cap > tile_lds + kMaxOpsPerPass * sizeof(TileOp)
+                                ? (lds_cap - tile_lds - kMaxOpsPerPass * sizeof(TileOp)) / amp_bytes(tb.dtype)
+                                : 0;
     std::vector<char> done(ng, 0);
     size_t remaining = ng;
     size_t first = 0;
@@ -371,8 +389,13 @@ static bool group_tiles(TileBuilder &tb, const std::vector<HostGate> &gates) {
             uint64_t blocked = 0;
             bool any_relaxed = false, any_wide = false;
             std::vector<size_t> idx;
+            size_t pooled = 0;
             for (size_t i = first; i < ng && idx.size() < kMaxOpsPerPass; ++i) {
                 if (done[i]) continue;
+                // the pass's matrices would outgrow the LDS next to its tile:
+                // the gates from here on go to later passes (the first gate
+                // of a pass is always taken; its launch checks the limit)
+                if (!idx.empty() && pooled + pool[i] > pool_cap) break;
                 const uint64_t gm = full[i];
                 if ((gm & blocked) || (wide[i] && any_relaxed)) {
                     blocked |= gm;
@@ -382,6 +405,7 @@ static bool group_tiles(TileBuilder &tb, const std::vector<HostGate> &gates) {
                 if (diag[i] || __builtin_popcountll(q | need) <= tb.m) {
                     q |= need;
                     idx.push_back(i);
+                    pooled += pool[i];
                     any_relaxed |= !diag[i] && need != gm;
                     any_wide |= bool(wide[i]);
                 } else {
@@ -401,15 +425,16 @@ static bool group_tiles(TileBuilder &tb, const std::vector<HostGate> &gates) {
     return true;
 }
 
-int build_tile_plan(Plan &plan, const std::vector<HostGate> &items, int tile_m) {
+int build_tile_plan(Plan &plan, const std::vector<HostGate> &items, int tile_m, int tiles) {
     const int m = tile_m_for(items, std::min(plan.n, tile_m), plan.n, plan.dtype);
     TileBuilder tb(plan, plan.n, plan.dtype, m, false);
+    tb.tiles = tiles;
     plan.items = int(items.size());
     return group_tiles(tb, items) ? m : -1;
 }
 
 int build_adjoint_plan(Plan &plan, const std::vector<HostGate> &items, int tile_m) {
-    const int m = build_tile_plan(plan, items, tile_m);
+    const int m = build_tile_plan(plan, items, tile_m, 2);
     for (Pass &p : plan.passes) p.bytes *= 2.0;   // two states per pass
     return m;
 }

@@ -238,7 +238,8 @@ int build_adjoint_plan(Plan &plan, const std::vector<HostGate> &items, int tile_
 
 // LDS-resident tile passes (no register staging) over the given ops; returns
 // the tile width used, or -1 as build_adjoint_plan.
-int build_tile_plan(Plan &plan, const std::vector<HostGate> &items, int tile_m);
+// `tiles`: state tiles each pass keeps in LDS next to its ops and matrices.
+int build_tile_plan(Plan &plan, const std::vector<HostGate> &items, int tile_m, int tiles = 1);
 
 // Fusion: greedy merge into blocks of at most fuse_k qubits.
 std::vector<HostGate> fuse_gates(const std::vector<HostGate> &gates, int fuse_k);

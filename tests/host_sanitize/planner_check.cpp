@@ -40,6 +40,16 @@ int pauli_apply_grid(uint64_t) { no_device("pauli"); }
 
 using namespace qsim;
 
+// LDS a tile pass takes when it runs from LDS (not as a register program):
+// `tiles` state tiles, its op list and its matrix pool.
+static bool lds_fits(const Pass &p, int dtype, int tiles) {
+    if (p.kind != PASS_TILE || p.reg_r > 0) return true;
+    const size_t amp = amp_bytes(dtype);
+    const size_t lds = size_t(tiles) * (amp << p.m) + sizeof(TileOp) * size_t(p.op_end - p.op_begin) +
+                       amp * size_t(p.pool_end - p.pool_begin);
+    return lds <= size_t(160) * 1024;
+}
+
 int main(int argc, char **argv) {
     long plans = 0, passes = 0;
     for (int f = 1; f < argc; ++f) {
@@ -110,6 +120,14 @@ int main(int argc, char **argv) {
                                  o.tile_m, o.use_mfma, o.split_1q, placed, plan.items);
                     return 7;
                 }
+                // an LDS pass's tile, op list and matrices fit the 160 KiB a
+                // workgroup may hold
+                for (const Pass &p : plan.passes)
+                    if (!lds_fits(p, dt, 1)) {
+                        std::fprintf(stderr, "%s: options (%d,%d,%d,%d): an LDS pass needs more than 160 KiB\n",
+                                     argv[f], o.fuse_k, o.tile_m, o.use_mfma, o.split_1q);
+                        return 11;
+                    }
                 std::vector<int> which;
                 std::vector<double> flops;
                 const std::string src = jit_source(plan, which, &flops);
@@ -128,6 +146,11 @@ int main(int argc, char **argv) {
                 std::fprintf(stderr, "%s: adjoint plan placed %ld of %d gates\n", argv[f], placed, adj.items);
                 return 9;
             }
+            for (const Pass &p : adj.passes)
+                if (!lds_fits(p, dt, 2)) {
+                    std::fprintf(stderr, "%s: an adjoint pass needs more than 160 KiB of LDS\n", argv[f]);
+                    return 12;
+                }
             passes += long(adj.passes.size());
         }
     }
