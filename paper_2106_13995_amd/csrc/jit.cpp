@@ -14,9 +14,11 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstdlib>
+#include <cstring>
 #include <map>
 #include <memory>
 #include <mutex>
+#include <set>
 #include <string>
 #include <vector>
 
@@ -34,7 +36,16 @@ struct Src {
         va_start(ap, fmt);
         const int n = vsnprintf(buf, sizeof buf, fmt, ap);
         va_end(ap);
-        if (n > 0) s.append(buf, size_t(std::min(n, int(sizeof buf) - 1)));
+        if (n >= int(sizeof buf)) {
+            // a long line: format again into a buffer of its size
+            std::vector<char> big(size_t(n) + 1);
+            va_start(ap, fmt);
+            vsnprintf(big.data(), big.size(), fmt, ap);
+            va_end(ap);
+            s.append(big.data(), size_t(n));
+        } else if (n > 0) {
+            s.append(buf, size_t(n));
+        }
         s.push_back('\n');
     }
 };
@@ -49,6 +60,25 @@ int deposit_bits(int j, int mask) {
             ++b;
         }
     return out;
+}
+
+// x with its sign flipped where the unsigned 0/1 expression `e` is 1, as a
+// C expression: the sign bit is XORed into x's bit pattern, so a condition
+// that is uniform across the block stays on the scalar unit.
+std::string signed_by(double x, const std::string &e, bool f) {
+    char buf[96];
+    if (f) {
+        const float v = float(x);
+        uint32_t u;
+        std::memcpy(&u, &v, 4);
+        snprintf(buf, sizeof buf, "__builtin_bit_cast(float, 0x%08xu ^ ((", u);
+        return buf + e + ") << 31))";
+    }
+    uint64_t u;
+    std::memcpy(&u, &x, 8);
+    snprintf(buf, sizeof buf, "__builtin_bit_cast(double, 0x%016llxull ^ ((unsigned long long)(",
+             (unsigned long long)u);
+    return buf + e + ") << 63))";
 }
 
 // Exact literal of x in the kernel's precision.
@@ -107,11 +137,199 @@ double emit_factor(Src &o, bool f, int i, std::complex<double> v, const char *on
     return 6.0;
 }
 
+// A diagonal that the compiled passes owe the amplitudes they store: the
+// stored value times (-1)^F(y) times `scale` is the amplitude of index y.
+// F is the XOR of the monomials in `mono`, each a product of qubit bits kept
+// as the mask of its qubits (mask 0: the constant 1).  Sign changes of
+// diagonal gates (CZ, CCZ, Z under controls) join F instead of being applied:
+// F commutes with every diagonal op, a real rotation on qubit b takes it
+// through by flipping the sign of its off-diagonal constant where dF/dy_b is
+// 1, and an exchange on b (a signed swap, a controlled X) reflects F in b.
+// The factors the scaled rotations leave out accumulate in `scale`.  Both are
+// applied at a store: F when the next pass is not compiled in the same chain,
+// the scale then or once it leaves [2^-40, 1].
+struct Owed {
+    std::set<uint64_t> mono;
+    double scale = 1.0;
+    void toggle(uint64_t m) {
+        if (!mono.erase(m)) mono.insert(m);
+    }
+    bool depends_on(uint64_t qmask) const {
+        for (uint64_t m : mono)
+            if (m & qmask) return true;
+        return false;
+    }
+    // F(y with bit q flipped where the monomial c is 1) = F + c dF/dy_q
+    void reflect(int q, uint64_t c) {
+        const uint64_t qb = 1ull << q;
+        std::vector<uint64_t> add;
+        for (uint64_t m : mono)
+            if (m & qb) add.push_back((m & ~qb) | c);
+        for (uint64_t m : add) toggle(m);
+    }
+};
+
+// Qubit on each register / thread bit of a register stage; qubits outside the
+// tile are the block's (bits of `base`).
+struct Layout {
+    int R = 0;
+    int qr[kRegBitsMax] = {};
+    int qt[8] = {};
+};
+
+// Sign of register i under F in layout ly: a constant part and the XOR of
+// monomials over thread and block qubits (evaluated at run time).
+struct RegSign {
+    bool c = false;
+    std::set<uint64_t> rt;
+    void add(const RegSign &o) {
+        c ^= o.c;
+        for (uint64_t m : o.rt)
+            if (!rt.erase(m)) rt.insert(m);
+    }
+};
+
+RegSign sign_of(const Owed &ow, const Layout &ly, int i) {
+    RegSign s;
+    for (uint64_t m : ow.mono) {
+        uint64_t rest = m;
+        bool hit = true;
+        for (int b = 0; b < ly.R && hit; ++b) {
+            const uint64_t qb = 1ull << ly.qr[b];
+            if (rest & qb) {
+                hit = (i >> b) & 1;
+                rest &= ~qb;
+            }
+        }
+        if (!hit) continue;
+        if (!rest)
+            s.c = !s.c;
+        else if (!s.rt.erase(rest))
+            s.rt.insert(rest);
+    }
+    return s;
+}
+
+// Run-time parity of a set of monomials over thread and block qubits, as a
+// C expression (thread bits from t, block bits from base): single-bit terms
+// by one population count over thread bits and one over block bits (uniform
+// across the block), products term by term.
+std::string rt_expr(const std::set<uint64_t> &rt, const Layout &ly) {
+    std::string e;
+    uint32_t lin_t = 0;
+    uint64_t lin_g = 0;
+    char buf[160];
+    auto add = [&e](const char *term) {
+        if (!e.empty()) e += " ^ ";
+        e += term;
+    };
+    for (uint64_t m : rt) {
+        uint32_t tm = 0;
+        uint64_t gm = m;
+        for (int b = 0; b < 8; ++b)
+            if ((m >> ly.qt[b]) & 1) {
+                tm |= 1u << b;
+                gm &= ~(1ull << ly.qt[b]);
+            }
+        if (__builtin_popcountll(m) == 1) {
+            if (tm)
+                lin_t ^= tm;
+            else
+                lin_g ^= gm;
+            continue;
+        }
+        if (tm && gm)
+            snprintf(buf, sizeof buf, "(unsigned)(((t & %uu) == %uu) && ((base & 0x%llxull) == 0x%llxull))", tm, tm,
+                     (unsigned long long)gm, (unsigned long long)gm);
+        else if (tm)
+            snprintf(buf, sizeof buf, "(unsigned)((t & %uu) == %uu)", tm, tm);
+        else
+            snprintf(buf, sizeof buf, "(unsigned)((base & 0x%llxull) == 0x%llxull)", (unsigned long long)gm,
+                     (unsigned long long)gm);
+        add(buf);
+    }
+    if (lin_t) {
+        snprintf(buf, sizeof buf, "(__builtin_popcount(t & %uu) & 1u)", lin_t);
+        add(buf);
+    }
+    if (lin_g) {
+        snprintf(buf, sizeof buf, "(unsigned)(__builtin_popcountll(base & 0x%llxull) & 1)", (unsigned long long)lin_g);
+        add(buf);
+    }
+    return e.empty() ? std::string("0u") : e;
+}
+
+// Sign of every register under F, as C expressions: F splits by the
+// register qubits of its monomials, F = XOR over register subsets S of
+// [S all 1] * R_S (R_S over thread and block qubits); each R_S is computed
+// once and register i XORs those with S inside its bits.  Returns, per
+// register, a constant part and the names to XOR (none: constant sign).
+struct SignTable {
+    std::vector<bool> c;
+    std::vector<std::string> e;
+};
+SignTable emit_sign_table(Src &o, const Owed &ow, const Layout &ly, int NA, const char *pre) {
+    std::map<uint32_t, std::set<uint64_t>> parts;   // register subset -> runtime monomials
+    std::map<uint32_t, bool> cparts;                 // register subset -> constant term
+    for (uint64_t m : ow.mono) {
+        uint32_t S = 0;
+        uint64_t rest = m;
+        for (int b = 0; b < ly.R; ++b)
+            if ((rest >> ly.qr[b]) & 1) {
+                S |= 1u << b;
+                rest &= ~(1ull << ly.qr[b]);
+            }
+        if (!rest)
+            cparts[S] = !cparts[S];
+        else if (!parts[S].erase(rest))
+            parts[S].insert(rest);
+    }
+    std::map<uint32_t, std::string> name;
+    for (auto &kv : parts) {
+        if (kv.second.empty()) continue;
+        const std::string nm = std::string(pre) + std::to_string(name.size());
+        o("    const unsigned %s = %s;", nm.c_str(), rt_expr(kv.second, ly).c_str());
+        name[kv.first] = nm;
+    }
+    SignTable tb;
+    tb.c.assign(size_t(NA), false);
+    tb.e.assign(size_t(NA), std::string());
+    for (int i = 0; i < NA; ++i) {
+        bool c = false;
+        for (auto &kv : cparts)
+            if (kv.second && (kv.first & ~uint32_t(i)) == 0) c = !c;
+        std::string e;
+        for (auto &kv : name)
+            if ((kv.first & ~uint32_t(i)) == 0) e += (e.empty() ? "" : " ^ ") + kv.second;
+        tb.c[size_t(i)] = c;
+        tb.e[size_t(i)] = e;
+    }
+    return tb;
+}
+
+// Applies F to every register of the layout (values change sign where F is
+// 1) and clears it.
+void settle_signs(Src &o, Owed &ow, const Layout &ly, int NA) {
+    if (ow.mono.empty()) return;
+    o("  {");
+    const SignTable tb = emit_sign_table(o, ow, ly, NA, "sgn");
+    for (int i = 0; i < NA; ++i) {
+        if (tb.e[size_t(i)].empty()) {
+            if (tb.c[size_t(i)]) o("    ar%d = -ar%d; ai%d = -ai%d;", i, i, i, i);
+            continue;
+        }
+        o("    { const unsigned e = %s%s;", tb.e[size_t(i)].c_str(), tb.c[size_t(i)] ? " ^ 1u" : "");
+        o("      ar%d = e ? -ar%d : ar%d; ai%d = e ? -ai%d : ai%d; }", i, i, i, i, i, i);
+    }
+    o("  }");
+    ow.mono.clear();
+}
+
 // Emits one pass as kernel `name`; returns the arithmetic it performs per
-// thread (flops; a multiply-add counts 2).
-double gen_pass(Src &o, const Plan &plan, const Pass &p, const char *name) {
+// thread (flops; a multiply-add counts 2).  `ow` is what earlier passes of
+// the chain left owed; with `settle` the pass stores true amplitudes.
+double gen_pass(Src &o, const Plan &plan, const Pass &p, const char *name, Owed &ow, bool settle) {
     double fl = 0.0;
-    double scale = 1.0;   // product of the factors the scaled rotations leave out
     const bool f = plan.dtype == QSIM_C64;
     const char *T = f ? "float" : "double";
     const char *V = f ? "f2" : "d2";
@@ -139,8 +357,14 @@ double gen_pass(Src &o, const Plan &plan, const Pass &p, const char *name) {
           i, i);
     }
     o("  }");
+    Layout ly;
+    ly.R = R;
     for (int si = p.stage_begin; si < p.stage_end; ++si) {
         const RegStage &st = plan.reg_stages[size_t(si)];
+        // the owed signs are a function of the qubits: they cross the
+        // exchange unchanged and are read in the new layout from here on
+        for (int b = 0; b < R; ++b) ly.qr[b] = st.q_r[b];
+        for (int b = 0; b < 8; ++b) ly.qt[b] = st.q_t[b];
         if (si > p.stage_begin) {
             // The swizzled slot of register i is (thread part) ^ c_i.  Bits of
             // c_i where the thread part is always zero add instead of mixing,
@@ -195,6 +419,10 @@ double gen_pass(Src &o, const Plan &plan, const Pass &p, const char *name) {
             const int m2 = 2 * op.moff;
             switch (op.type) {
                 case 0: {   // dense on register mask, complex matrix
+                    uint64_t qm = 0;
+                    for (int b = 0; b < R; ++b)
+                        if ((op.rmask >> b) & 1) qm |= 1ull << ly.qr[b];
+                    if (ow.depends_on(qm)) settle_signs(o, ow, ly, NA);
                     const int K = popc32(uint32_t(op.rmask)), D = 1 << K;
                     fl += 8.0 * D * NA;   // a complex multiply-add per matrix entry and amplitude
                     o("  {");
@@ -228,31 +456,52 @@ double gen_pass(Src &o, const Plan &plan, const Pass &p, const char *name) {
                     // As c [[1, -t], [t, 1]] (t = s / c, when c >= s) or
                     // s [[v, -1], [1, v]] (v = c / s): two multiply-adds per
                     // component and pair.  The factor c or s is the same for
-                    // every amplitude; the pass multiplies these factors on
-                    // the host and applies their product once, at the store.
+                    // every amplitude and joins the owed scale.  Owed signs
+                    // that differ between the members of a pair flip the
+                    // sign of t or v (a constant here, or chosen per lane or
+                    // block at run time); the first form keeps each member's
+                    // sign, the second swaps them (F reflected in the bit).
                     // (The pool entry holds the lifting form p = -s / (1 + c),
                     // u = s, used by the interpreted kernel.)
                     const int B = op.rb[0];
                     const cd pu = pool_at(op.moff);
                     const double sv = pu.imag(), cv = -sv / pu.real() - 1.0;
                     const bool tform = cv >= sv;
-                    const std::string q = lit(tform ? sv / cv : cv / sv, f), mq = lit(tform ? -sv / cv : 0.0, f);
-                    scale *= tform ? cv : sv;
+                    const double kv = tform ? sv / cv : cv / sv;
+                    ow.scale *= tform ? cv : sv;
                     fl += 4.0 * NA;
                     o("  {");
+                    std::map<std::set<uint64_t>, std::string> kvar;
                     for (int g = 0; g < NA; ++g) {
                         if (g & (1 << B)) continue;
                         const int h = g | (1 << B);
+                        RegSign sig = sign_of(ow, ly, g);
+                        sig.add(sign_of(ow, ly, h));
+                        std::string K, NK;   // the constant and its negation
+                        if (sig.rt.empty()) {
+                            K = lit(sig.c ? -kv : kv, f);
+                            NK = lit(sig.c ? kv : -kv, f);
+                        } else {
+                            auto it = kvar.find(sig.rt);
+                            if (it == kvar.end()) {
+                                const std::string nm = "k" + std::to_string(kvar.size());
+                                o("    const %s %s = %s;", T, nm.c_str(), signed_by(kv, rt_expr(sig.rt, ly), f).c_str());
+                                it = kvar.emplace(sig.rt, nm).first;
+                            }
+                            K = (sig.c ? "-" : "") + it->second;
+                            NK = (sig.c ? "" : "-") + it->second;
+                        }
                         for (const char *c : {"ar", "ai"}) {
                             if (tform)
                                 o("    { const %s y = %s(%s, %s%d, %s%d); %s%d = %s(%s, %s%d, %s%d); %s%d = y; }", T, FMA,
-                                  mq.c_str(), c, h, c, g, c, h, FMA, q.c_str(), c, g, c, h, c, g);
+                                  NK.c_str(), c, h, c, g, c, h, FMA, K.c_str(), c, g, c, h, c, g);
                             else
                                 o("    { const %s y = %s(%s, %s%d, -%s%d); %s%d = %s(%s, %s%d, %s%d); %s%d = y; }", T, FMA,
-                                  q.c_str(), c, g, c, h, c, h, FMA, q.c_str(), c, h, c, g, c, g);
+                                  K.c_str(), c, g, c, h, c, h, FMA, K.c_str(), c, h, c, g, c, g);
                         }
                     }
                     o("  }");
+                    if (!tform) ow.reflect(ly.qr[B], 0);
                     break;
                 }
                 case 5: {   // (x0, x1) <- (-x1, x0)
@@ -265,6 +514,7 @@ double gen_pass(Src &o, const Plan &plan, const Pass &p, const char *name) {
                           g, g, h, g, h, h, h);
                     }
                     o("  }");
+                    ow.reflect(ly.qr[B], 0);   // the members trade their owed signs
                     break;
                 }
                 case 4: {   // phase table over the register bits (entry 0 is 1)
@@ -277,6 +527,16 @@ double gen_pass(Src &o, const Plan &plan, const Pass &p, const char *name) {
                 case 6: {   // factor on the all-ones amplitudes of the op's bits
                     const uint64_t gmask = uint64_t(uint32_t(op.gp[0])) | (uint64_t(uint32_t(op.gp[1])) << 32);
                     const uint32_t tmask = uint32_t(op.tb[0]);
+                    if (pool_at(op.moff) == cd(-1.0)) {
+                        // a sign change (CZ, CCZ, ...): owed, not applied
+                        uint64_t mono = gmask;
+                        for (int b = 0; b < R; ++b)
+                            if ((op.rmask >> b) & 1) mono |= 1ull << ly.qr[b];
+                        for (int b = 0; b < 8; ++b)
+                            if ((tmask >> b) & 1u) mono |= 1ull << ly.qt[b];
+                        ow.toggle(mono);
+                        break;
+                    }
                     // A condition on out-of-tile bits only holds for whole
                     // blocks: a uniform branch, taken by the blocks it holds
                     // in, in place of a select on every lane of every block.
@@ -306,6 +566,12 @@ double gen_pass(Src &o, const Plan &plan, const Pass &p, const char *name) {
                                      pool_at(op.moff + 3)};
                     // an exchange (X under controls: CX, CCX) moves values only
                     const bool perm = u[0] == cd(0.0) && u[3] == cd(0.0) && u[1] == cd(1.0) && u[2] == cd(1.0);
+                    uint64_t cmono = gmask;   // product of the controls
+                    for (int b = 0; b < R; ++b)
+                        if ((rc >> b) & 1) cmono |= 1ull << ly.qr[b];
+                    for (int b = 0; b < 8; ++b)
+                        if ((tmask >> b) & 1u) cmono |= 1ull << ly.qt[b];
+                    if (!perm && ow.depends_on(1ull << ly.qr[B])) settle_signs(o, ow, ly, NA);
                     o("  {");
                     if (cond)
                         o("    const bool on = ((base & 0x%llxull) == 0x%llxull) && ((t & %uu) == %uu);",
@@ -337,6 +603,7 @@ double gen_pass(Src &o, const Plan &plan, const Pass &p, const char *name) {
                     }
                     if (block_cond) o("    }");
                     o("  }");
+                    if (perm) ow.reflect(ly.qr[B], cmono);   // values moved where the controls are 1
                     break;
                 }
                 default: {   // any other diagonal: index from out-of-tile, thread and register bits
@@ -360,12 +627,35 @@ double gen_pass(Src &o, const Plan &plan, const Pass &p, const char *name) {
             }
         }
     }
-    // store (with the product of the rotations' factors)
+    // store: owed signs (end of a chain) and the owed scale (end of a chain,
+    // or once it leaves [2^-40, 1]) are applied here, one multiply per
+    // component
     o("  {");
-    if (scale != 1.0) {
-        const std::string sc = lit(scale, f);
+    if (!settle && ow.scale < std::ldexp(1.0, -40)) {
+        const std::string sc = lit(ow.scale, f);
         for (int i = 0; i < NA; ++i) o("    ar%d *= %s; ai%d *= %s;", i, sc.c_str(), i, sc.c_str());
         fl += 2.0 * NA;
+        ow.scale = 1.0;
+    } else if (settle && (ow.scale != 1.0 || !ow.mono.empty())) {
+        const double scv = ow.scale;
+        const SignTable tb = emit_sign_table(o, ow, ly, NA, "sgn");
+        const std::string P = lit(scv, f), N = lit(-scv, f);
+        for (int i = 0; i < NA; ++i) {
+            const bool c = tb.c[size_t(i)];
+            if (tb.e[size_t(i)].empty()) {
+                if (scv == 1.0) {
+                    if (c) o("    ar%d = -ar%d; ai%d = -ai%d;", i, i, i, i);
+                    continue;
+                }
+                o("    ar%d *= %s; ai%d *= %s;", i, (c ? N : P).c_str(), i, (c ? N : P).c_str());
+                continue;
+            }
+            o("    { const %s g = %s; ar%d *= g; ai%d *= g; }", T, signed_by(c ? -scv : scv, tb.e[size_t(i)], f).c_str(),
+              i, i);
+        }
+        fl += 2.0 * NA;
+        ow.mono.clear();
+        ow.scale = 1.0;
     }
     o("    unsigned long long gt = base;");
     for (int b = 0; b < 8; ++b) o("    gt |= (unsigned long long)((t >> %d) & 1u) << %d;", b, int(p.st_t[b]));
@@ -440,12 +730,15 @@ std::string jit_source(const Plan &plan, std::vector<int> &which, std::vector<do
     o("typedef double d2 __attribute__((ext_vector_type(2)));");
     o("#define QC __attribute__((address_space(4)))");
     which.clear();
+    auto compiled = [&](size_t i) { return plan.passes[i].kind == PASS_TILE && plan.passes[i].reg_r > 0; };
+    Owed ow;   // carried from pass to pass while the next one is compiled too
     for (size_t i = 0; i < plan.passes.size(); ++i) {
         const Pass &p = plan.passes[i];
-        if (p.kind != PASS_TILE || p.reg_r <= 0) continue;
+        if (!compiled(i)) continue;
         char name[48];
         snprintf(name, sizeof name, "qsim_tile_jit_%zu", which.size());
-        const double fpt = gen_pass(o, plan, p, name);
+        const bool settle = i + 1 == plan.passes.size() || !compiled(i + 1);
+        const double fpt = gen_pass(o, plan, p, name, ow, settle);
         if (flops) flops->push_back(fpt * 256.0 * std::ldexp(1.0, plan.n - p.m));
         which.push_back(int(i));
     }

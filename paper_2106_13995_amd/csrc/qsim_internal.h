@@ -144,6 +144,9 @@ struct RegStage {
     // address, in amplitudes, contributed by each thread / register bit of
     // the previous layout (write) and of this stage's layout (read)
     uint32_t wr_t[8], wr_r[kRegBitsMax], rd_t[8], rd_r[kRegBitsMax];
+    // global qubit on each thread / register bit of this stage's layout
+    int8_t q_t[8], q_r[kRegBitsMax];
+    int8_t pad_[3];
 };
 
 struct Pass {

@@ -276,6 +276,8 @@ bool build_reg_program(Plan &plan, Pass &p, uint64_t q, const int *local_of,
         if (si > 0) make_exchange(m, wb, prevR, Rm, st);
         int Rp[kRegBitsMax], Tp[16];
         split_layout(Rm, m, Rp, Tp);
+        for (int b = 0; b < 8; ++b) st.q_t[b] = int8_t(gpos_of_local[Tp[b]]);
+        for (int b = 0; b < kRegBitsMax; ++b) st.q_r[b] = int8_t(b < r ? gpos_of_local[Rp[b]] : -1);
         st.op_begin = int(plan.reg_ops.size()) - p.rop_begin;
         // input phases of split rotations whose register bit no earlier op of
         // the stage changes commute to the stage's start, where they merge
