@@ -16,31 +16,11 @@ import numpy as np
 import pytest
 
 import workloads as W
+from circuit_io import write_circuit
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 CSRC = os.path.join(ROOT, "paper_2106_13995_amd", "csrc")
 HOST_SOURCES = ["abi.cpp", "plan.cpp", "stages.cpp", "gates.cpp", "jit.cpp", "autotune.cpp", "batch.cpp"]
-GATE_CODES = None
-
-
-def _codes():
-    import paper_2106_13995_amd as q
-    return q.GATE_CODES
-
-
-def write_circuit(path, circ, params=None):
-    """Header (n, nops, nparams, nmats), qsim_op records, matrices, parameters."""
-    import paper_2106_13995_amd as q
-    pc = q.PackedCircuit(circ)
-    import ctypes
-    raw = ctypes.string_at(ctypes.addressof(pc.ops), ctypes.sizeof(q.QsimOp) * len(circ.ops))
-    mats = pc.mats.view(np.float64) if pc.c.nmats else np.zeros(0)
-    p = np.zeros(0) if params is None else np.ascontiguousarray(params, dtype=np.float64)
-    with open(path, "wb") as f:
-        f.write(struct.pack("<iiiq", circ.n, len(circ.ops), p.size, int(pc.c.nmats)))
-        f.write(raw)
-        f.write(np.ascontiguousarray(mats[:2 * int(pc.c.nmats)]).tobytes())
-        f.write(p.tobytes())
 
 
 def controlled_blocks(n, nops, rng):

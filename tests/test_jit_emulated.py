@@ -21,7 +21,7 @@ import pytest
 import oracle as O
 import workloads as W
 
-from test_host_sanitize import write_circuit
+from circuit_io import write_circuit
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 CSRC = os.path.join(ROOT, "paper_2106_13995_amd", "csrc")
