@@ -212,6 +212,23 @@ qsim_status qsim_apply_circuit(qsim_state s, const qsim_circuit *c, const double
  * Python interface for that use.) */
 qsim_status qsim_expectation(qsim_state s, const qsim_pauli_sum *H, double *out_host);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * value as qsim_expectation, from the same kernels in the same order (so
+ * bitwise equal to it), with the partial sums, the uploaded term table and the
+ * result in a fixed device array of QSIM_NOALLOC_SCRATCH_BYTES that the
+ * library defines once per GPU (held from the library's load until the
+ * process ends) instead of memory allocated per state.  The call allocates no
+ * device memory and no pinned host memory; the terms are copied from host
+ * memory in stream order.  A Pauli sum whose partial sums and terms need more
+ * than the array (about 16 KiB per distinct X mask plus 32 bytes per term)
+ * returns QSIM_ERR_ARG before any device work.  Synchronises the state's
+ * stream.  Every call on one GPU shares that GPU's array: calls that overlap
+ * on one GPU (other streams or other host threads) race and must be
+ * serialised by the caller. */
+#define QSIM_NOALLOC_SCRATCH_BYTES (4u << 20)
+qsim_status qsim_expectation_noalloc(qsim_state s, const qsim_pauli_sum *H, double *out_host);
+
 /* Energy and gradient of a variational circuit by the adjoint method.
  *
  * E(theta) = <psi_L|H|psi_L> with psi_L = C(theta) psi_0, where psi_0 is the

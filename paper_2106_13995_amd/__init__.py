@@ -49,7 +49,7 @@ EXPORTS = (
     "qsim_set_basis", "qsim_copy_to_host", "qsim_copy_from_host", "qsim_apply_gate",
     "qsim_apply_circuit", "qsim_expectation", "qsim_last_error", "qsim_profile_enable",
     "qsim_profile_read", "qsim_plan_summary", "qsim_adjoint_grad", "qsim_batch_create", "qsim_batch_run",
-    "qsim_batch_info", "qsim_batch_free", "qsim_autotune",
+    "qsim_batch_info", "qsim_batch_free", "qsim_autotune", "qsim_expectation_noalloc",
 )
 
 
@@ -117,6 +117,7 @@ def _load() -> ctypes.CDLL:
         "qsim_apply_circuit": ([P, ctypes.POINTER(QsimCircuit), ctypes.POINTER(ctypes.c_double), i64,
                                 ctypes.POINTER(QsimOptions)], S),
         "qsim_expectation": ([P, ctypes.POINTER(QsimPauliSum), ctypes.POINTER(ctypes.c_double)], S),
+        "qsim_expectation_noalloc": ([P, ctypes.POINTER(QsimPauliSum), ctypes.POINTER(ctypes.c_double)], S),
         "qsim_adjoint_grad": ([P, ctypes.POINTER(QsimCircuit), P, i64, ctypes.POINTER(QsimPauliSum),
                                ctypes.POINTER(QsimOptions), P, P], S),
         "qsim_last_error": ([], ctypes.c_char_p),
@@ -255,6 +256,14 @@ class PackedPauliSum:
 def qsim_expectation(h: int, packedH: PackedPauliSum) -> float:
     out = ctypes.c_double()
     _check(_lib.qsim_expectation(ctypes.c_void_p(h), ctypes.byref(packedH.h), ctypes.byref(out)))
+    return out.value
+
+
+def qsim_expectation_noalloc(h: int, packedH: PackedPauliSum) -> float:
+    """qsim_expectation with its scratch in the library's fixed per-GPU array
+    (no device allocation)."""
+    out = ctypes.c_double()
+    _check(_lib.qsim_expectation_noalloc(ctypes.c_void_p(h), ctypes.byref(packedH.h), ctypes.byref(out)))
     return out.value
 
 
