@@ -125,7 +125,8 @@ typedef struct {
  *            m in [7, 13] (c64) / [7, 12] (c128) = group gates into passes
  *            that hold 2^m-amplitude tiles in LDS (larger m is clamped; a
  *            tile is widened when a gate needs more positions next to the
- *            low 5 (c64) / 4 (c128) qubits every tile keeps); 0 = automatic.
+ *            low qubits every tile keeps: 5 or 6 (c64), 4 or 5 (c128), the
+ *            planner takes whichever gives fewer passes); 0 = automatic.
  *   use_mfma: -1 never, 1 whenever a fused block has k >= 4, 0 automatic.
  *   split_1q: single-qubit unitaries in tile passes.  1 (and 0, automatic):
  *            each is written as g diag(1, b) O diag(1, a) with O a real
@@ -221,7 +222,7 @@ qsim_status qsim_expectation(qsim_state s, const qsim_pauli_sum *H, double *out_
  * process ends) instead of memory allocated per state.  The call allocates no
  * device memory and no pinned host memory; the terms are copied from host
  * memory in stream order.  A Pauli sum whose partial sums and terms need more
- * than the array (about 16 KiB per distinct X mask plus 32 bytes per term)
+ * than the array (up to 16 KiB per pass over the state, 32 bytes per term)
  * returns QSIM_ERR_ARG before any device work.  Synchronises the state's
  * stream.  Every call on one GPU shares that GPU's array: calls that overlap
  * on one GPU (other streams or other host threads) race and must be

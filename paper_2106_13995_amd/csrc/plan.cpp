@@ -160,8 +160,10 @@ struct TileBuilder {
     bool reg;
     int tiles = 1;   // state tiles a pass keeps in LDS (2 in adjoint passes)
     Plan &plan;
-    TileBuilder(Plan &p, int n_, int dt, int m_, bool reg_) : n(n_), dtype(dt), m(m_), L(0), reg(reg_), plan(p) {
-        L = std::min(m, low_tile_qubits(dt));
+    // `low`: qubits 0 .. low - 1 are in every tile (0: the precision's default)
+    TileBuilder(Plan &p, int n_, int dt, int m_, bool reg_, int low = 0)
+        : n(n_), dtype(dt), m(m_), L(0), reg(reg_), plan(p) {
+        L = std::min(m, low > 0 ? low : low_tile_qubits(dt));
     }
 
     // Adds a tile pass over qubit set `q` (must contain the low L qubits)
@@ -329,8 +331,8 @@ static const size_t kMaxOpsPerPass = 128;
 
 // Smallest tile that holds every gate next to the low L qubits: a gate whose
 // qubits lie outside the low L needs L + (those qubits) tile positions.
-static int tile_m_for(const std::vector<HostGate> &gates, int m, int n, int dtype) {
-    const int L = std::min(m, low_tile_qubits(dtype));
+static int tile_m_for(const std::vector<HostGate> &gates, int m, int n, int dtype, int nlow = 0) {
+    const int L = std::min(m, nlow > 0 ? nlow : low_tile_qubits(dtype));
     const uint64_t low = (1ull << L) - 1;
     int need = m;
     for (const HostGate &g : gates)
@@ -474,10 +476,27 @@ bool build_plan(Plan &plan, const std::vector<HostGate> &gates_in, const PlanOpt
         }
     } else {
         if (po.reg_tiles && po.split_1q) gates = split_single_qubit(gates, n);
-        TileBuilder tb(plan, n, dtype, tile_m_for(gates, po.tile_m, n, dtype), po.reg_tiles);
-        plan.items = int(gates.size());
-        if (!group_tiles(tb, gates)) return false;
-        return true;
+        // Every tile holds the low qubits, so every HBM access runs over
+        // 2^low consecutive amplitudes.  The default width (256 bytes) and
+        // one more qubit (512 bytes) are both planned; the plan with fewer
+        // passes is kept (the wider one on a tie).  Which is fewer depends
+        // on the circuit: on the 5 x 6 grid the wider block is the grid's
+        // first row, and 2^12 tiles take 17 passes instead of 21.
+        // (plans are copied here before any upload: no device buffer yet)
+        if (plan.dev) return false;
+        const Plan shell = plan;
+        bool have = false;
+        for (int low : {low_tile_qubits(dtype) + 1, low_tile_qubits(dtype)}) {
+            Plan trial = shell;
+            TileBuilder tb(trial, n, dtype, tile_m_for(gates, po.tile_m, n, dtype, low), po.reg_tiles, low);
+            trial.items = int(gates.size());
+            if (!group_tiles(tb, gates)) continue;
+            if (!have || trial.passes.size() < plan.passes.size()) {
+                plan = std::move(trial);
+                have = true;
+            }
+        }
+        return have;
     }
     // logical gate counts for sweep passes
     plan.items = int(gates.size());

@@ -57,13 +57,16 @@ def test_noalloc_matches_expectation_on_two_calls(q, dtype):
 
 
 def test_noalloc_rejects_a_sum_beyond_the_array(q):
-    n = 20
+    n = 24
     s, _ = _prepared(q, n, "c64", 3)
-    # one term per distinct X mask: each group needs 2048 partials (16 KiB),
-    # so 300 groups exceed the 4 MiB array
+    # one term per distinct X mask, each mask too wide for a tile: at 24
+    # qubits a group evaluated alone writes 2048 partials (16 KiB), so 300
+    # groups exceed the 4 MiB array
     rng = np.random.default_rng(9)
-    xs = rng.choice(np.arange(1, 1 << n), size=300, replace=False)
-    H = W.PauliSum(n, [1.0] * 300, [int(x) for x in xs], [0] * 300)
+    xs = rng.choice(np.arange(1, 1 << n), size=300, replace=False) | (0xFF << 12)
+    xs = np.unique(xs)
+    assert len(xs) > 260
+    H = W.PauliSum(n, [1.0] * len(xs), [int(x) for x in xs], [0] * len(xs))
     P = q.PackedPauliSum(H)
     out = ctypes.c_double()
     st = q._lib.qsim_expectation_noalloc(ctypes.c_void_p(s.handle), ctypes.byref(P.h), ctypes.byref(out))
