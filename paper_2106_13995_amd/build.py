@@ -13,7 +13,7 @@ OBJ = os.path.join(ROOT, "_build", "qsim")
 LIB = os.path.join(HERE, "libqsim.so")
 SOURCES = ["abi.cpp", "gates.cpp", "plan.cpp", "stages.cpp", "kernels.hip", "kernels_reg.hip",
            "kernels_adjoint.hip", "batch.cpp", "kernels_batch.hip",
-           "kernels_mfma.hip", "autotune.cpp", "jit.cpp", "noalloc.cpp"]
+           "kernels_mfma.hip", "autotune.cpp", "jit.cpp", "noalloc.cpp", "kernels_expect.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"

@@ -589,6 +589,11 @@ namespace qsim {
 // demand, host staging pinned) when fixed_dev is NULL, else the caller's
 // fixed_bytes at fixed_dev (nothing allocated; terms copied from host
 // memory; sums that need more than fixed_bytes are rejected).
+//
+// Terms are grouped by X mask.  When every group is the diagonal one or a
+// single-qubit X_h / Y_h group, the sum runs as register passes without LDS
+// (launch_expect_simple); otherwise groups whose X mask fits a tile share LDS
+// tile passes and the rest take one pass each.
 qsim_status expectation_with(qsim_state s, const qsim_pauli_sum *H, double *out_host, void *fixed_dev,
                              size_t fixed_bytes) {
     qsim_status st = check_state(s);
@@ -606,30 +611,7 @@ qsim_status expectation_with(qsim_state s, const qsim_pauli_sum *H, double *out_
         double wr, wi;
         uint64_t z, pad;
     };
-    const int maxp = 2048;
-    const size_t ngroups = groups.size();
-    const size_t terms_off = ngroups * maxp * sizeof(double) + 256;
-    const size_t terms_bytes = sizeof(DevTerm) * size_t(std::max(H->nterms, 1));
-    const size_t out_off = (terms_off + terms_bytes + 255) & ~size_t(255);
-    std::vector<DevTerm> host_terms;
-    DevTerm *ht = nullptr;
-    char *scr = nullptr;
-    if (fixed_dev) {
-        if (out_off + 256 > fixed_bytes)
-            return set_error(QSIM_ERR_ARG, "the Pauli sum needs " + std::to_string(out_off + 256) +
-                                               " bytes of scratch; the fixed buffer holds " +
-                                               std::to_string(fixed_bytes));
-        host_terms.resize(size_t(std::max(H->nterms, 1)));
-        ht = host_terms.data();
-        scr = static_cast<char *>(fixed_dev);
-    } else {
-        st = ensure_scratch(s, out_off + 256);
-        if (st != QSIM_OK) return st;
-        st = ensure_pinned(s, std::max(terms_bytes, size_t(64)));
-        if (st != QSIM_OK) return st;
-        ht = static_cast<DevTerm *>(s->pinned);
-        scr = static_cast<char *>(s->scratch);
-    }
+    std::vector<DevTerm> ht(size_t(std::max(H->nterms, 1)));
     std::vector<std::pair<uint64_t, int>> spans;   // (x, first term slot)
     int slot = 0;
     for (auto &kv : groups) {
@@ -639,26 +621,132 @@ qsim_status expectation_with(qsim_state s, const qsim_pauli_sum *H, double *out_
             const int ny = __builtin_popcountll(pt.xmask & pt.zmask) & 3;
             // coeff * i^ny
             const double re[4] = {1, 0, -1, 0}, im[4] = {0, 1, 0, -1};
-            ht[slot].wr = pt.coeff * re[ny];
-            ht[slot].wi = pt.coeff * im[ny];
-            ht[slot].z = pt.zmask;
-            ht[slot].pad = 0;
+            ht[size_t(slot)].wr = pt.coeff * re[ny];
+            ht[size_t(slot)].wi = pt.coeff * im[ny];
+            ht[size_t(slot)].z = pt.zmask;
+            ht[size_t(slot)].pad = 0;
             ++slot;
         }
     }
-    // Groups whose X mask fits a tile (the low L qubits and m - L others) are
-    // evaluated several to a pass over the state; the rest one pass each.
-    const int mt = std::min(s->n, s->dtype == QSIM_C128 ? 11 : 12);
-    const int Lt = std::min(mt, s->dtype == QSIM_C128 ? 4 : 5);
-    const bool reg_kernel = (s->dtype == QSIM_C64 && mt == 12) || (s->dtype == QSIM_C128 && mt == 11);
-    const int kpt_bits = s->dtype == QSIM_C128 ? 3 : 4;
-    std::vector<ExpTilePass> tpasses;
-    std::vector<uint64_t> tmask;           // tile qubits of each pass
-    std::vector<size_t> single;            // groups evaluated alone
+    auto group_terms = [&](size_t gi) {
+        return (gi + 1 < spans.size() ? spans[gi + 1].second : slot) - spans[gi].second;
+    };
+    const uint64_t N = 1ull << s->n;
+    const bool c64 = s->dtype == QSIM_C64;
+
+    // ---- register passes for diagonal + single-qubit X / Y groups
+    std::vector<ExpSimplePass> spasses;
     {
+        const int R = kExpSimpleR, L = c64 ? 5 : 4, F = 6 - L;
+        bool ok = s->n >= 6 + R && !spans.empty();
+        int diag_gi = -1;
+        std::vector<size_t> hi, lo;   // single-qubit groups above / within the low L qubits
+        std::vector<double> A(spans.size(), 0.0), B(spans.size(), 0.0);
+        for (size_t gi = 0; gi < spans.size() && ok; ++gi) {
+            const uint64_t x = spans[gi].first;
+            if (x == 0) {
+                diag_gi = int(gi);
+                continue;
+            }
+            if (__builtin_popcountll(x) != 1) {
+                ok = false;
+                break;
+            }
+            for (int t = spans[gi].second; t < spans[gi].second + group_terms(gi); ++t) {
+                if (ht[size_t(t)].z == 0)
+                    A[gi] += ht[size_t(t)].wr;
+                else if (ht[size_t(t)].z == x)
+                    B[gi] += ht[size_t(t)].wi;
+                else
+                    ok = false;
+            }
+            (x >> L ? hi : lo).push_back(gi);
+        }
+        if (ok) {
+            const size_t per = size_t(F + R);
+            const size_t np = std::max<size_t>(1, (hi.size() + per - 1) / per);
+            for (size_t pi = 0; pi < np; ++pi) {
+                ExpSimplePass sp{};
+                sp.R = R;
+                uint64_t used = (1ull << L) - 1;
+                for (int b = 0; b < L; ++b) sp.lane_q[b] = b;
+                std::vector<size_t> mine;
+                for (size_t j = pi * per; j < std::min(hi.size(), (pi + 1) * per); ++j) mine.push_back(hi[j]);
+                // the first F on free lane bits, the rest on register bits
+                int nl = L, nr = 0;
+                for (size_t j = 0; j < mine.size(); ++j) {
+                    const size_t gi = mine[j];
+                    const int h = __builtin_ctzll(spans[gi].first);
+                    used |= 1ull << h;
+                    if (nl < 6) {
+                        sp.lane_bit[sp.nlane_g] = nl;
+                        sp.lane_A[sp.nlane_g] = A[gi];
+                        sp.lane_B[sp.nlane_g] = B[gi];
+                        ++sp.nlane_g;
+                        sp.lane_q[nl++] = h;
+                    } else {
+                        sp.reg_bit[sp.nreg_g] = nr;
+                        sp.reg_A[sp.nreg_g] = A[gi];
+                        sp.reg_B[sp.nreg_g] = B[gi];
+                        ++sp.nreg_g;
+                        sp.reg_q[nr++] = h;
+                    }
+                }
+                // remaining slots: the lowest qubits not used yet
+                for (int q = L; q < s->n && (nl < 6 || nr < R); ++q) {
+                    if ((used >> q) & 1) continue;
+                    used |= 1ull << q;
+                    if (nl < 6)
+                        sp.lane_q[nl++] = q;
+                    else
+                        sp.reg_q[nr++] = q;
+                }
+                sp.ntile_q = 0;
+                for (int q = 0; q < s->n; ++q)
+                    if ((used >> q) & 1) sp.tile_q[sp.ntile_q++] = q;
+                spasses.push_back(sp);
+            }
+            // groups on the low qubits: spread over the passes, on their lane bit
+            for (size_t j = 0; j < lo.size(); ++j) {
+                ExpSimplePass &sp = spasses[j % spasses.size()];
+                const size_t gi = lo[j];
+                sp.lane_bit[sp.nlane_g] = __builtin_ctzll(spans[gi].first);
+                sp.lane_A[sp.nlane_g] = A[gi];
+                sp.lane_B[sp.nlane_g] = B[gi];
+                ++sp.nlane_g;
+            }
+            if (diag_gi >= 0) {
+                // the last pass (the fewest groups): terms ordered by the
+                // register part of their Z mask
+                ExpSimplePass &sp = spasses.back();
+                sp.diag = 1;
+                const int first = spans[size_t(diag_gi)].second, cnt = group_terms(size_t(diag_gi));
+                for (int t = first; t < first + cnt; ++t) {
+                    uint32_t mu = 0;
+                    for (int b = 0; b < R; ++b)
+                        if ((ht[size_t(t)].z >> sp.reg_q[b]) & 1) mu |= 1u << b;
+                    ht[size_t(t)].pad = mu;
+                }
+                std::stable_sort(ht.begin() + first, ht.begin() + first + cnt,
+                                 [](const DevTerm &a, const DevTerm &b) { return a.pad < b.pad; });
+                sp.diag_first = first;
+                sp.diag_end = first + cnt;
+            }
+        }
+    }
+
+    // ---- otherwise LDS tile passes (groups whose X mask fits a tile: the low
+    // L qubits and m - L others) and one pass per remaining group
+    const int mt = std::min(s->n, c64 ? 12 : 11);
+    const int Lt = std::min(mt, c64 ? 5 : 4);
+    const int kpt_bits = c64 ? 4 : 3;
+    std::vector<ExpTilePass> tpasses;
+    std::vector<size_t> single;            // groups evaluated alone
+    if (spasses.empty()) {
         // passes from the groups with X bits above the low L qubits (greedy,
         // in X-mask order); the groups inside the low L qubits (the diagonal
         // group among them) then go to the passes with the least work
+        std::vector<uint64_t> tmask;
         std::vector<std::vector<size_t>> members;
         std::vector<size_t> low_only;
         uint64_t hm = 0;
@@ -682,9 +770,6 @@ qsim_status expectation_with(qsim_state s, const qsim_pauli_sum *H, double *out_
             members.back().push_back(gi);
             tmask.back() = hm;
         }
-        auto group_terms = [&](size_t gi) {
-            return (gi + 1 < spans.size() ? spans[gi + 1].second : slot) - spans[gi].second;
-        };
         for (size_t gi : low_only) {
             // work of a pass: its groups' terms, the diagonal group's counted
             // once per KPT amplitudes plus its transform
@@ -701,7 +786,6 @@ qsim_status expectation_with(qsim_state s, const qsim_pauli_sum *H, double *out_
                 tmask.push_back(0);
             }
             members[best].push_back(gi);
-            (void)group_terms;
         }
         for (size_t pi = 0; pi < members.size(); ++pi) {
             ExpTilePass tp{};
@@ -734,12 +818,12 @@ qsim_status expectation_with(qsim_state s, const qsim_pauli_sum *H, double *out_
                 g.count = cnt;
                 g.flags = 0;
                 g.A = g.B = 0.0;
-                for (int t = first; t < first + cnt; ++t) ht[t].pad = to_local(ht[t].z);
+                for (int t = first; t < first + cnt; ++t) ht[size_t(t)].pad = to_local(ht[size_t(t)].z);
                 if (__builtin_popcountll(x) == 1) {
                     bool simple = true;
                     for (int t = first; t < first + cnt; ++t) {
-                        if (ht[t].z == 0) g.A += ht[t].wr;
-                        else if (ht[t].z == x) g.B += ht[t].wi;
+                        if (ht[size_t(t)].z == 0) g.A += ht[size_t(t)].wr;
+                        else if (ht[size_t(t)].z == x) g.B += ht[size_t(t)].wi;
                         else simple = false;
                     }
                     if (simple) g.flags = kExpGroupSimple;
@@ -747,20 +831,41 @@ qsim_status expectation_with(qsim_state s, const qsim_pauli_sum *H, double *out_
                 if (x == 0) {
                     // order the diagonal terms by the register part of their
                     // local Z mask (local bits 8 and up) for the register kernel
-                    std::stable_sort(ht + first, ht + first + cnt, [&](const DevTerm &a, const DevTerm &b) {
-                        return (a.pad >> 8) < (b.pad >> 8);
-                    });
+                    std::stable_sort(ht.begin() + first, ht.begin() + first + cnt,
+                                     [&](const DevTerm &a, const DevTerm &b) { return (a.pad >> 8) < (b.pad >> 8); });
                     const int kpt = 1 << kpt_bits;
                     int t = first;
                     for (int mu = 0; mu <= kpt; ++mu) {
-                        while (t < first + cnt && mu < kpt && int(ht[t].pad >> 8) < mu) ++t;
+                        while (t < first + cnt && mu < kpt && int(ht[size_t(t)].pad >> 8) < mu) ++t;
                         tp.dmu[mu] = mu == kpt ? first + cnt : t;
                     }
-                    (void)reg_kernel;
                 }
             }
             tpasses.push_back(tp);
         }
+    }
+
+    // ---- scratch: [partials][terms][result]
+    // partials: one per workgroup of each register pass, groups x workgroups
+    // of each tile pass, workgroups of each single-group pass
+    size_t npart = 0;
+    for (const ExpSimplePass &sp : spasses) npart += size_t(expect_simple_grid(N >> (6 + sp.R)));
+    for (const ExpTilePass &tp : tpasses) npart += size_t(tp.ngroups) * size_t(std::min<uint64_t>(N >> tp.m, 2048));
+    npart += single.size() * size_t(expect_group_grid(N));
+    const size_t terms_off = (npart * sizeof(double) + 255) & ~size_t(255);
+    const size_t terms_bytes = sizeof(DevTerm) * ht.size();
+    const size_t out_off = (terms_off + terms_bytes + 255) & ~size_t(255);
+    char *scr = nullptr;
+    if (fixed_dev) {
+        if (out_off + 256 > fixed_bytes)
+            return set_error(QSIM_ERR_ARG, "the Pauli sum needs " + std::to_string(out_off + 256) +
+                                               " bytes of scratch; the fixed buffer holds " +
+                                               std::to_string(fixed_bytes));
+        scr = static_cast<char *>(fixed_dev);
+    } else {
+        st = ensure_scratch(s, out_off + 256);
+        if (st != QSIM_OK) return st;
+        scr = static_cast<char *>(s->scratch);
     }
     double *partials = reinterpret_cast<double *>(scr);
     DevTerm *dterms = reinterpret_cast<DevTerm *>(scr + terms_off);
@@ -769,38 +874,50 @@ qsim_status expectation_with(qsim_state s, const qsim_pauli_sum *H, double *out_
         if (fixed_dev) {
             // from pageable host memory: the copy has read it when the call
             // returns, and the stream is synchronised below in any case
-            QSIM_HIP(s, hipMemcpyAsync(dterms, ht, terms_bytes, hipMemcpyHostToDevice, s->stream), "hipMemcpyAsync");
+            QSIM_HIP(s, hipMemcpyAsync(dterms, ht.data(), terms_bytes, hipMemcpyHostToDevice, s->stream),
+                     "hipMemcpyAsync");
         } else {
+            st = ensure_pinned(s, terms_bytes);
+            if (st != QSIM_OK) return st;
+            std::memcpy(s->pinned, ht.data(), terms_bytes);
             st = upload_staged(s, dterms, terms_bytes);
             if (st != QSIM_OK) return st;
         }
     }
     QSIM_HIP(s, injected_fault(), "injected fault (QSIM_FAULT)");
-    int total = 0;
+    size_t total = 0;
+    for (const ExpSimplePass &sp : spasses) {
+        int wrote = 0;
+        prof_begin(s, QSIM_KCLASS_EXPECT, double(amp_bytes(s->dtype) << s->n));
+        hipError_t e = launch_expect_simple(s, sp, dterms, partials + total, &wrote);
+        prof_end(s);
+        if (e != hipSuccess) return device_error(s, e, "expectation launch");
+        total += size_t(wrote);
+    }
     for (const ExpTilePass &tp : tpasses) {
         int wrote = 0;
         prof_begin(s, QSIM_KCLASS_EXPECT, double(amp_bytes(s->dtype) << s->n));
         hipError_t e = launch_expect_tiles(s, tp, dterms, partials + total, &wrote);
         prof_end(s);
         if (e != hipSuccess) return device_error(s, e, "expectation launch");
-        total += wrote;
+        total += size_t(wrote);
     }
     for (size_t gi : single) {
         const int first = spans[gi].second;
-        const int cnt = (gi + 1 < spans.size() ? spans[gi + 1].second : slot) - first;
+        const int cnt = group_terms(gi);
         int wrote = 0;
         const double bytes = double(amp_bytes(s->dtype) << s->n) * (spans[gi].first ? 2.0 : 1.0);
         prof_begin(s, QSIM_KCLASS_EXPECT, bytes);
         hipError_t e = launch_expect_group(s, spans[gi].first, dterms + first, cnt, partials + total, &wrote);
         prof_end(s);
         if (e != hipSuccess) return device_error(s, e, "expectation launch");
-        total += wrote;
+        total += size_t(wrote);
     }
     if (total == 0) {
         *out_host = 0.0;
         return QSIM_OK;
     }
-    QSIM_HIP(s, launch_reduce(s, partials, total, dout), "reduce launch");
+    QSIM_HIP(s, launch_reduce(s, partials, int(total), dout), "reduce launch");
     QSIM_HIP(s, hipMemcpyAsync(out_host, dout, sizeof(double), hipMemcpyDeviceToHost, s->stream), "hipMemcpyAsync");
     QSIM_HIP(s, hipStreamSynchronize(s->stream), "hipStreamSynchronize");
     s->pinned_ev_pending = false;

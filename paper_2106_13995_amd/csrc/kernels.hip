@@ -369,7 +369,7 @@ k_expect(const c2_t<T> *__restrict__ psi, uint64_t N, uint64_t x, const ExpTerm 
     if (threadIdx.x == 0) partials[blockIdx.x] = tot;
 }
 
-static int expect_grid(uint64_t N) {
+int expect_group_grid(uint64_t N) {
     const uint64_t want = (N + kExpThreads * 8 - 1) / (kExpThreads * 8);
     return int(std::max<uint64_t>(1, std::min<uint64_t>(want, 2048)));
 }
@@ -377,7 +377,7 @@ static int expect_grid(uint64_t N) {
 hipError_t launch_expect_group(qsim_state s, uint64_t xmask, const void *dev_terms, int nterms,
                                double *partials, int *nwritten) {
     const uint64_t N = 1ull << s->n;
-    const int grid = expect_grid(N);
+    const int grid = expect_group_grid(N);
     const ExpTerm *terms = static_cast<const ExpTerm *>(dev_terms);
     if (s->dtype == QSIM_C64)
         hipLaunchKernelGGL((k_expect<float>), dim3(grid), dim3(kExpThreads), 0, s->stream,

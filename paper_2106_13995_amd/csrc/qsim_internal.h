@@ -367,6 +367,32 @@ struct ExpTilePass {
 hipError_t launch_expect_tiles(qsim_state s, const ExpTilePass &p, const void *dev_terms, double *partials,
                                int *nwritten);
 
+// Sums whose X masks are all 0 or one qubit (the diagonal group and X_h / Y_h
+// groups): passes of 64-lane wavefronts with 2^R amplitudes per lane in
+// registers (R = kExpSimpleR) and no LDS.  Lane bit b is qubit
+// lane_q[b] (the low 5 / 4 qubits first), register bit b qubit reg_q[b];
+// tile_q lists the 6 + R tile qubits ascending.  Groups on register qubits
+// pair registers (reg_bit, weights A of the X_h terms, B of the Y_h terms);
+// groups on lane qubits exchange across lanes (lane_bit).  With diag set the
+// pass also evaluates the diagonal group: terms diag_first .. diag_end - 1,
+// ordered by the register part mu of their Z mask (kept in each term's pad
+// field).  Each launch writes one partial per workgroup.
+constexpr int kExpSimpleMaxR = 6;
+constexpr int kExpSimpleR = 4;
+struct ExpSimplePass {
+    int32_t R, ntile_q, nreg_g, nlane_g, diag;
+    int32_t lane_q[6];
+    int32_t reg_q[kExpSimpleMaxR];
+    int32_t tile_q[6 + kExpSimpleMaxR];
+    int32_t reg_bit[kExpSimpleMaxR], lane_bit[6];
+    double reg_A[kExpSimpleMaxR], reg_B[kExpSimpleMaxR], lane_A[6], lane_B[6];
+    int32_t diag_first, diag_end;
+};
+int expect_simple_grid(uint64_t ntiles);
+hipError_t launch_expect_simple(qsim_state s, const ExpSimplePass &p, const void *dev_terms, double *partials,
+                                int *nwritten);
+int expect_group_grid(uint64_t N);
+
 // Adjoint differentiation.
 int pauli_apply_grid(uint64_t N);
 hipError_t launch_pauli_apply(qsim_state s, void *lam, const void *groups, int ngroups, const void *terms,

@@ -28,6 +28,9 @@ hipError_t launch_dense_sweep(qsim_state, const Pass &) { no_device("dense"); }
 hipError_t launch_diag_sweep(qsim_state, const Pass &) { no_device("diag"); }
 hipError_t launch_expect_group(qsim_state, uint64_t, const void *, int, double *, int *) { no_device("expect"); }
 hipError_t launch_expect_tiles(qsim_state, const ExpTilePass &, const void *, double *, int *) { no_device("expect"); }
+hipError_t launch_expect_simple(qsim_state, const ExpSimplePass &, const void *, double *, int *) { no_device("expect"); }
+int expect_simple_grid(uint64_t) { no_device("expect"); }
+int expect_group_grid(uint64_t) { no_device("expect"); }
 hipError_t launch_mfma_pass(qsim_state, const Plan &, const Pass &) { no_device("mfma"); }
 hipError_t launch_pauli_apply(qsim_state, void *, const void *, int, const void *, double *) { no_device("pauli"); }
 hipError_t launch_reduce(qsim_state, const double *, int, double *) { no_device("reduce"); }

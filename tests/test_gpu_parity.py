@@ -369,6 +369,44 @@ def test_autotune_choice_is_used_and_correct(qs, tmp_path, monkeypatch):
     s.close()
 
 
+def _simple_sum(n, rng, diag=True, xs_on=True, ys_on=True, low_only=False):
+    """Diagonal terms with random Z masks (register, lane and block qubits
+    alike) and X_h / Y_h terms: the sums the register passes take."""
+    coeffs, xs, zs = [], [], []
+    if diag:
+        for _ in range(12):
+            coeffs.append(float(rng.normal())); xs.append(0); zs.append(int(rng.integers(0, 1 << n)))
+        for i in range(n - 1):
+            coeffs.append(float(rng.normal())); xs.append(0); zs.append((1 << i) | (1 << (i + 1)))
+    qubits = range(min(n, 4)) if low_only else range(n)
+    for h in qubits:
+        if xs_on:
+            coeffs.append(float(rng.normal())); xs.append(1 << h); zs.append(0)
+        if ys_on and rng.random() < 0.6:
+            coeffs.append(float(rng.normal())); xs.append(1 << h); zs.append(1 << h)
+    return W.PauliSum(n, coeffs, xs, zs)
+
+
+@pytest.mark.parametrize("dtype", ["c64", "c128"])
+@pytest.mark.parametrize("n", [10, 11, 13, 17])
+def test_expectation_register_passes(qs, dtype, n):
+    """Sums of diagonal terms and single-qubit X / Y terms (the register
+    passes, one or more per sum, from the smallest width they take): against
+    the oracle on the device's rounded amplitudes, with parts left out."""
+    rng = np.random.default_rng(1200 + n)
+    psi = _rounded(W.random_state(n, rng), dtype)
+    s = _state(qs, n, dtype, psi)
+    cases = [_simple_sum(n, rng), _simple_sum(n, rng, diag=False), _simple_sum(n, rng, xs_on=False),
+             _simple_sum(n, rng, xs_on=False, ys_on=False), _simple_sum(n, rng, diag=False, low_only=True)]
+    for H in cases:
+        got = s.expectation(H)
+        ref = O.expectation(psi, H)
+        scale = sum(abs(c) for c in H.coeffs)
+        assert abs(got - ref) <= 1e-12 * scale, (len(H.coeffs), got, ref)
+        assert s.expectation(H) == got
+    s.close()
+
+
 @pytest.mark.parametrize("dtype", ["c64", "c128"])
 def test_expectation_tiled_and_wide_groups(qs, dtype):
     """Several X-mask groups per pass over the state (single X and Y terms,
