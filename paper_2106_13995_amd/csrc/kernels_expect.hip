@@ -66,18 +66,47 @@ __device__ __forceinline__ void register_group(const f64x2 (&a)[NA], int b, doub
     }
 }
 
+// One 32-bit word of lane (lane ^ 2^B): a quad permutation (DPP, a vector
+// ALU move) for B = 0, 1, a swizzle within 32 lanes for B = 2..4, a
+// permutation through the LDS crossbar for B = 5.
+template <int B>
+__device__ __forceinline__ int xor_lane(int v) {
+    if constexpr (B == 0)
+        return __builtin_amdgcn_mov_dpp(v, 0xB1, 0xF, 0xF, false);   // quad lanes 1,0,3,2
+    else if constexpr (B == 1)
+        return __builtin_amdgcn_mov_dpp(v, 0x4E, 0xF, 0xF, false);   // quad lanes 2,3,0,1
+    else if constexpr (B < 5)
+        return __builtin_amdgcn_ds_swizzle(v, 0x1F | ((1 << B) << 10));   // and 31, xor 2^B
+    else
+        return __builtin_amdgcn_ds_bpermute(int((threadIdx.x ^ 32u) << 2), v);
+}
+
+// The partner's double across lane bit B.  With FROM_FLOAT the value is a
+// converted float (complex64 amplitudes): off the quad permutations it
+// travels as that float (one word instead of two; both conversions exact).
+template <int B, bool FROM_FLOAT>
+__device__ __forceinline__ double xor_lane_d(double v) {
+    if constexpr (FROM_FLOAT && B >= 2) {
+        return double(__builtin_bit_cast(float, xor_lane<B>(__builtin_bit_cast(int, float(v)))));
+    } else {
+        const uint64_t u = __builtin_bit_cast(uint64_t, v);
+        const uint32_t lo = uint32_t(xor_lane<B>(int(uint32_t(u)))), hi = uint32_t(xor_lane<B>(int(uint32_t(u >> 32))));
+        return __builtin_bit_cast(double, (uint64_t(hi) << 32) | lo);
+    }
+}
+
 // Every lane adds Re / (+-)Im of conj(a_k) times its partner's a_k across lane
-// bit `mask`: summed over all lanes this is twice the sum over pairs (the
-// Y part with the sign of the lower member).
-template <int NA, bool WITH_B>
-__device__ __forceinline__ void lane_group(const f64x2 (&a)[NA], unsigned mask, double &sr, double &si) {
+// bit B: summed over all lanes this is twice the sum over pairs (the Y part
+// with the sign of the lower member).
+template <int NA, bool WITH_B, int B, bool FROM_FLOAT>
+__device__ __forceinline__ void lane_pairs(const f64x2 (&a)[NA], double &sr, double &si) {
 #pragma unroll
     for (int k = 0; k < NA; ++k) {
         // chunks of eight: the scheduler would otherwise hoist every
         // exchange ahead of the products, holding 2 x 2^R doubles at once
         if (k % 8 == 0) __builtin_amdgcn_sched_barrier(0);
-        const double pr = __shfl_xor(a[k].x, int(mask), 64);
-        const double pi = __shfl_xor(a[k].y, int(mask), 64);
+        const double pr = xor_lane_d<B, FROM_FLOAT>(a[k].x);
+        const double pi = xor_lane_d<B, FROM_FLOAT>(a[k].y);
         sr = fma(a[k].x, pr, sr);
         sr = fma(a[k].y, pi, sr);
         if (WITH_B) {
@@ -87,15 +116,34 @@ __device__ __forceinline__ void lane_group(const f64x2 (&a)[NA], unsigned mask, 
     }
 }
 
-// w[mu] for a mu that is the same on every lane, without indexing the
-// register array at run time (which would place it in scratch memory).
+template <int NA, bool WITH_B, bool FROM_FLOAT>
+__device__ __forceinline__ void lane_group(const f64x2 (&a)[NA], int b, double &sr, double &si) {
+    switch (b) {
+        case 0: lane_pairs<NA, WITH_B, 0, FROM_FLOAT>(a, sr, si); break;
+        case 1: lane_pairs<NA, WITH_B, 1, FROM_FLOAT>(a, sr, si); break;
+        case 2: lane_pairs<NA, WITH_B, 2, FROM_FLOAT>(a, sr, si); break;
+        case 3: lane_pairs<NA, WITH_B, 3, FROM_FLOAT>(a, sr, si); break;
+        case 4: lane_pairs<NA, WITH_B, 4, FROM_FLOAT>(a, sr, si); break;
+        default: lane_pairs<NA, WITH_B, 5, FROM_FLOAT>(a, sr, si); break;
+    }
+}
+
+// acc += c w[mu] for a mu that is the same on every lane: a uniform branch
+// per value, so the register array is never indexed at run time (which
+// would place it in scratch memory).
 template <int NA>
-__device__ __forceinline__ double pick(const double (&w)[NA], int mu) {
-    double r = 0.0;
-#pragma unroll
-    for (int k = 0; k < NA; ++k)
-        if (k == mu) r = w[k];
-    return r;
+__device__ __forceinline__ void add_at(const double (&w)[NA], int mu, double c, double &acc) {
+    switch (mu) {
+#define QSIM_CASE(K) \
+    case K:          \
+        if constexpr (K < NA) acc = fma(c, w[K], acc); \
+        break;
+        QSIM_CASE(0) QSIM_CASE(1) QSIM_CASE(2) QSIM_CASE(3) QSIM_CASE(4) QSIM_CASE(5) QSIM_CASE(6) QSIM_CASE(7)
+        QSIM_CASE(8) QSIM_CASE(9) QSIM_CASE(10) QSIM_CASE(11) QSIM_CASE(12) QSIM_CASE(13) QSIM_CASE(14)
+        QSIM_CASE(15)
+#undef QSIM_CASE
+        default: break;
+    }
 }
 
 template <typename T, int R>
@@ -109,6 +157,11 @@ k_expect_simple(const c2_t<T> *__restrict__ psi, const ExpSimplePass p, const Si
     uint64_t roff[R];
 #pragma unroll
     for (int b = 0; b < R; ++b) roff[b] = 1ull << p.reg_q[b];
+    // lane-bit parity of the first 64 diagonal terms' Z masks
+    uint64_t lpar = 0;
+    if (p.diag)
+        for (int j = 0; j < 64 && p.diag_first + j < p.diag_end; ++j)
+            lpar |= uint64_t(__popcll(terms[p.diag_first + j].z & toff) & 1) << j;
     double acc = 0.0;
     for (uint64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
         // the tile's out-of-tile bits: zeros inserted at the tile qubits
@@ -142,10 +195,11 @@ k_expect_simple(const c2_t<T> *__restrict__ psi, const ExpSimplePass p, const Si
         for (int g = 0; g < p.nlane_g; ++g) {
             const unsigned mask = 1u << p.lane_bit[g];
             double sr = 0.0, si = 0.0;
+            constexpr bool FF = sizeof(T) == 4;
             if (p.lane_B[g] != 0.0)
-                lane_group<NA, true>(a, mask, sr, si);
+                lane_group<NA, true, FF>(a, p.lane_bit[g], sr, si);
             else
-                lane_group<NA, false>(a, mask, sr, si);
+                lane_group<NA, false, FF>(a, p.lane_bit[g], sr, si);
             // Im part: the lower member of each pair carries it with +, the
             // upper with - (its product is the conjugate)
             acc += p.lane_A[g] * sr + ((lane & mask) ? -p.lane_B[g] : p.lane_B[g]) * si;
@@ -165,16 +219,21 @@ k_expect_simple(const c2_t<T> *__restrict__ psi, const ExpSimplePass p, const Si
                 }
             }
             // terms in order of their register part mu (in pad_): the signed
-            // weights of a run of equal mu multiply w[mu] once
+            // weights of a run of equal mu multiply w[mu] once.  A term's
+            // sign is the parity of its Z mask on the lane bits (fixed per
+            // lane: lpar) and on the block bits (the same on every lane).
             int t = p.diag_first;
             while (t < p.diag_end) {
                 const int mu = int(terms[t].pad_);
                 double c = 0.0;
                 for (; t < p.diag_end && int(terms[t].pad_) == mu; ++t) {
                     const SimpleTerm e = terms[t];
-                    c += (__popcll(e.z & bt) & 1) ? -e.wr : e.wr;
+                    const int j = t - p.diag_first;
+                    const unsigned lb = j < 64 ? unsigned(lpar >> j) & 1u : unsigned(__popcll(e.z & toff) & 1);
+                    const unsigned ub = unsigned(__popcll(e.z & base) & 1);
+                    c += (lb ^ ub) ? -e.wr : e.wr;
                 }
-                acc = fma(c, pick<NA>(w, mu), acc);
+                add_at<NA>(w, mu, c, acc);
             }
         }
     }
