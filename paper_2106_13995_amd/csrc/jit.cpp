@@ -357,6 +357,19 @@ double gen_pass(Src &o, const Plan &plan, const Pass &p, const char *name, Owed 
           i, i);
     }
     o("  }");
+    // A tile that is zero everywhere stays zero (every op is linear; owed
+    // signs and factors multiply zeros): the block skips its ops and store.
+    // Sparse states (basis inputs, few superposed values) then cost the
+    // reads and little else.
+    {
+        std::string nz;
+        for (int i = 0; i < NA; ++i) {
+            char b[64];
+            snprintf(b, sizeof b, "%s(ar%d != %s(0)) | (ai%d != %s(0))", i ? " | " : "", i, T, i, T);
+            nz += b;
+        }
+        o("  if (!__syncthreads_or(int(%s))) return;", nz.c_str());
+    }
     Layout ly;
     ly.R = R;
     for (int si = p.stage_begin; si < p.stage_end; ++si) {

@@ -13,6 +13,22 @@ static thread_local EmuDim threadIdx;
 static EmuDim blockIdx;
 static pthread_barrier_t g_bar;
 static inline void __syncthreads() { pthread_barrier_wait(&g_bar); }
+// block-wide OR of one predicate per thread (barrier, sum, barrier)
+static int g_or_acc;
+static pthread_mutex_t g_or_mu = PTHREAD_MUTEX_INITIALIZER;
+static inline int __syncthreads_or(int v) {
+    if (threadIdx.x == 0) g_or_acc = 0;
+    pthread_barrier_wait(&g_bar);
+    if (v) {
+        pthread_mutex_lock(&g_or_mu);
+        g_or_acc = 1;
+        pthread_mutex_unlock(&g_or_mu);
+    }
+    pthread_barrier_wait(&g_bar);
+    const int r = g_or_acc;
+    pthread_barrier_wait(&g_bar);
+    return r;
+}
 #define __global__
 #define __launch_bounds__(x)
 #define __shared__ static
