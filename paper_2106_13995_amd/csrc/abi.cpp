@@ -203,9 +203,22 @@ static qsim_status run_plan(qsim_state s, Plan &plan) {
     QSIM_HIP(s, injected_fault(), "injected fault (QSIM_FAULT)");
     qsim_status st = upload_plan(s, plan);
     if (st != QSIM_OK) return st;
+    // occupancy maps of the compiled passes (sparse states), in the state's
+    // scratch; zeroed before each chain of compiled passes
+    void *maps = nullptr;
+    size_t map_bytes = 0;
+    if (plan.jit_map_shift > 0 && !plan.jit_fn.empty()) {
+        map_bytes = size_t(3) << (s->n - plan.jit_map_shift);
+        st = ensure_scratch(s, map_bytes);
+        if (st != QSIM_OK) return st;
+        maps = s->scratch;
+    }
     for (size_t i = 0; i < plan.passes.size(); ++i) {
         const Pass &p = plan.passes[i];
         hipError_t e = hipSuccess;
+        const bool jit = p.kind == PASS_TILE && p.reg_r > 0 && i < plan.jit_fn.size() && plan.jit_fn[i];
+        if (jit && maps && (i == 0 || !plan.jit_fn[i - 1]))
+            QSIM_HIP(s, launch_fill_zero(s, maps, map_bytes), "map clear launch");
         switch (p.kind) {
             case PASS_DENSE:
                 prof_begin(s, QSIM_KCLASS_SWEEP_DENSE, p.bytes, p.flops);
@@ -216,9 +229,9 @@ static qsim_status run_plan(qsim_state s, Plan &plan) {
                 e = launch_diag_sweep(s, p);
                 break;
             case PASS_TILE:
-                if (p.reg_r > 0 && i < plan.jit_fn.size() && plan.jit_fn[i]) {
+                if (jit) {
                     prof_begin(s, QSIM_KCLASS_TILE_JIT, p.bytes, p.flops);
-                    e = launch_jit_pass(s, plan, p, plan.jit_fn[i]);
+                    e = launch_jit_pass(s, plan, p, plan.jit_fn[i], maps);
                 } else {
                     prof_begin(s, QSIM_KCLASS_TILE, p.bytes, p.flops);
                     e = p.reg_r > 0 ? launch_tile_reg_pass(s, plan, p) : launch_tile_pass(s, plan, p);

@@ -325,10 +325,50 @@ void settle_signs(Src &o, Owed &ow, const Layout &ly, int NA) {
     ow.mono.clear();
 }
 
+bool perm_block(const Plan &plan, const Pass &p, const RegOp &op) {
+    const cd *u = plan.tile_pool.data() + p.pool_begin + op.moff;
+    return u[0] == cd(0.0) && u[3] == cd(0.0) && u[1] == cd(1.0) && u[2] == cd(1.0);
+}
+
+}  // namespace
+
+// Occupancy maps for compiled passes on sparse states.  Ops that can spread
+// a basis state over several (rotations, dense blocks, controlled blocks that
+// are not exchanges) are counted over the compiled passes; with few of them
+// a state that starts sparse (a basis state, a few superposed values) stays
+// sparse, and the passes keep one byte per chunk of 2^shift amplitudes
+// saying whether the chunk may hold a nonzero value.  Returns shift, or 0
+// for no maps.
+int jit_map_shift(const Plan &plan) {
+    // QSIM_MAP_SHIFT (4..13) sets another chunk width (tests use narrow
+    // chunks to reach the maps on small states)
+    int shift = plan.dtype == QSIM_C128 ? 11 : 12;
+    if (const char *e = std::getenv("QSIM_MAP_SHIFT")) {
+        const int v = std::atoi(e);
+        if (v >= 4 && v <= 13) shift = v;
+    }
+    int spreading = 0;
+    bool any = false;
+    for (const Pass &p : plan.passes) {
+        if (p.kind != PASS_TILE || p.reg_r <= 0) continue;
+        any = true;
+        if (p.m < shift) return 0;
+        for (int oi = p.rop_begin; oi < p.rop_end; ++oi) {
+            const RegOp &op = plan.reg_ops[size_t(oi)];
+            if (op.type == 0 || op.type == 3 || (op.type == 7 && !perm_block(plan, p, op))) ++spreading;
+        }
+    }
+    if (!any || spreading > 24 || plan.n < shift + 6) return 0;
+    return shift;
+}
+
+namespace {
+
 // Emits one pass as kernel `name`; returns the arithmetic it performs per
 // thread (flops; a multiply-add counts 2).  `ow` is what earlier passes of
 // the chain left owed; with `settle` the pass stores true amplitudes.
-double gen_pass(Src &o, const Plan &plan, const Pass &p, const char *name, Owed &ow, bool settle) {
+double gen_pass(Src &o, const Plan &plan, const Pass &p, const char *name, Owed &ow, bool settle, int map_shift,
+                int chain_pos) {
     double fl = 0.0;
     const bool f = plan.dtype == QSIM_C64;
     const char *T = f ? "float" : "double";
@@ -336,7 +376,8 @@ double gen_pass(Src &o, const Plan &plan, const Pass &p, const char *name, Owed 
     const char *FMA = f ? "__builtin_fmaf" : "__builtin_fma";
     const int R = p.reg_r, NA = 1 << R;
     auto pool_at = [&](int rel) { return plan.tile_pool[size_t(p.pool_begin + rel)]; };
-    o("extern \"C\" __global__ void __launch_bounds__(256) %s(%s *psi, const %s *Pg) {", name, V, T);
+    o("extern \"C\" __global__ void __launch_bounds__(256) %s(%s *psi, const %s *Pg, unsigned char *maps) {", name,
+      V, T);
     o("  const QC %s *P = (const QC %s *)Pg;", T, T);
     // A static tile: its address is a link-time constant that folds into
     // the LDS instructions' offsets (a dynamic array costs an add per access).
@@ -344,6 +385,27 @@ double gen_pass(Src &o, const Plan &plan, const Pass &p, const char *name, Owed 
     o("  const unsigned t = threadIdx.x;");
     o("  unsigned long long base = (unsigned long long)blockIdx.x << %d;", p.L);
     for (int h : p.hpos) o("  base = ((base >> %d) << %d) | (base & 0x%llxull);", h, h + 1, (1ull << h) - 1ull);
+    // Occupancy maps (three in rotation, one byte per chunk of 2^shift
+    // amplitudes): this pass reads the previous pass's map (not the first
+    // pass of a chain), marks the chunks of the tiles it processes in the
+    // next one, and clears its share of the third.  A tile's chunks are
+    // fixed by its qubits at or above shift.
+    std::vector<int> hq;
+    if (map_shift > 0) {
+        for (int h : p.hpos)
+            if (h >= map_shift) hq.push_back(h);
+        const unsigned long long C = 1ull << (plan.n - map_shift);
+        const unsigned long long share = 1ull << (p.m - map_shift);   // C / number of tiles
+        const int R_ = chain_pos % 3, W_ = (chain_pos + 1) % 3, X_ = (chain_pos + 2) % 3;
+        o("  unsigned char *const mw = maps + %lluull, *const mx = maps + %lluull;", W_ * C, X_ * C);
+        o("  for (unsigned j = t; j < %lluu; j += 256u) mx[(unsigned long long)blockIdx.x * %lluull + j] = 0;", share,
+          share);
+        o("  unsigned long long ck = base >> %d;", map_shift);
+        for (size_t j = 0; j < hq.size(); ++j)
+            o("  ck |= (unsigned long long)((t >> %zu) & 1u) << %d;", j, hq[j] - map_shift);
+        if (chain_pos > 0)
+            o("  if (!__syncthreads_or(t < %uu ? int(maps[%lluull + ck]) : 0)) return;", 1u << hq.size(), R_ * C);
+    }
     for (int i = 0; i < NA; ++i) o("  %s ar%d, ai%d;", T, i, i);
     // load
     o("  {");
@@ -640,6 +702,7 @@ double gen_pass(Src &o, const Plan &plan, const Pass &p, const char *name, Owed 
             }
         }
     }
+    if (map_shift > 0) o("  if (t < %uu) mw[ck] = 1;", 1u << hq.size());
     // store: owed signs (end of a chain) and the owed scale (end of a chain,
     // or once it leaves [2^-40, 1]) are applied here, one multiply per
     // component
@@ -703,6 +766,8 @@ std::string source_key(const Plan &plan) {
     auto put = [&k](const void *p, size_t n) { k.append(static_cast<const char *>(p), n); };
     put(&plan.dtype, sizeof plan.dtype);
     put(&plan.n, sizeof plan.n);
+    const int map_shift = jit_map_shift(plan);
+    put(&map_shift, sizeof map_shift);
     for (const Pass &p : plan.passes) {
         if (p.kind != PASS_TILE || p.reg_r <= 0) continue;
         const int head[4] = {p.m, p.L, p.reg_r, int(p.hpos.size())};
@@ -745,13 +810,16 @@ std::string jit_source(const Plan &plan, std::vector<int> &which, std::vector<do
     which.clear();
     auto compiled = [&](size_t i) { return plan.passes[i].kind == PASS_TILE && plan.passes[i].reg_r > 0; };
     Owed ow;   // carried from pass to pass while the next one is compiled too
+    const int map_shift = jit_map_shift(plan);
+    int chain_pos = 0;
     for (size_t i = 0; i < plan.passes.size(); ++i) {
         const Pass &p = plan.passes[i];
         if (!compiled(i)) continue;
+        chain_pos = (i > 0 && compiled(i - 1)) ? chain_pos + 1 : 0;
         char name[48];
         snprintf(name, sizeof name, "qsim_tile_jit_%zu", which.size());
         const bool settle = i + 1 == plan.passes.size() || !compiled(i + 1);
-        const double fpt = gen_pass(o, plan, p, name, ow, settle);
+        const double fpt = gen_pass(o, plan, p, name, ow, settle, map_shift, chain_pos);
         if (flops) flops->push_back(fpt * 256.0 * std::ldexp(1.0, plan.n - p.m));
         which.push_back(int(i));
     }
@@ -822,16 +890,17 @@ qsim_status jit_prepare(qsim_state s, Plan &plan, std::string &err) {
         plan.jit_fn[size_t(which[k])] = jm->fns[k];
         p.flops = jm->flops_per_thread[k] * 256.0 * std::ldexp(1.0, plan.n - p.m);
     }
+    plan.jit_map_shift = jit_map_shift(plan);
     return QSIM_OK;
 }
 
-hipError_t launch_jit_pass(qsim_state s, const Plan &plan, const Pass &p, hipFunction_t fn) {
+hipError_t launch_jit_pass(qsim_state s, const Plan &plan, const Pass &p, hipFunction_t fn, void *maps) {
     const bool f = s->dtype == QSIM_C64;
     const size_t amp = f ? 8 : 16;
     void *psi = s->data;
     const char *pool = static_cast<const char *>(plan.dev) + plan.pool_dev_off + size_t(p.pool_begin) * amp;
     const void *pool_arg = pool;
-    void *args[] = {&psi, &pool_arg};
+    void *args[] = {&psi, &pool_arg, &maps};
     const uint64_t ntiles = 1ull << (s->n - p.m);
     // the tile is a static LDS array of the kernel (at most 64 KiB)
     return hipModuleLaunchKernel(fn, unsigned(ntiles), 1, 1, 256, 1, 1, 0u, s->stream, args, nullptr);

@@ -330,6 +330,21 @@ hipError_t launch_set_basis(qsim_state s, uint64_t index) {
     return hipGetLastError();
 }
 
+// ------------------------------------------------------------ fill
+
+__global__ void __launch_bounds__(256) k_fill_zero(uint32_t *dst, uint64_t words) {
+    for (uint64_t i = uint64_t(blockIdx.x) * 256 + threadIdx.x; i < words; i += uint64_t(gridDim.x) * 256) dst[i] = 0u;
+}
+
+// Zeroes `bytes` (a multiple of 4) at dst, stream-ordered.  A kernel rather
+// than a memset node, so that a caller may capture it in a graph.
+hipError_t launch_fill_zero(qsim_state s, void *dst, size_t bytes) {
+    const uint64_t words = bytes / 4;
+    const unsigned grid = unsigned(std::max<uint64_t>(1, std::min<uint64_t>((words + 255) / 256, 4096)));
+    hipLaunchKernelGGL(k_fill_zero, dim3(grid), dim3(256), 0, s->stream, static_cast<uint32_t *>(dst), words);
+    return hipGetLastError();
+}
+
 // ------------------------------------------------------------ expectation
 
 // Device form of one Pauli term inside a group sharing the X mask:

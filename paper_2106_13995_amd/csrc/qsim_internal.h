@@ -199,6 +199,7 @@ struct Plan {
     bool uploaded = false;
     // run-time compiled kernels of register-staged passes (null: interpreted)
     std::vector<hipFunction_t> jit_fn;
+    int jit_map_shift = 0;            // occupancy-map chunk width of the compiled passes (0: none)
     ~Plan();
 };
 
@@ -211,7 +212,12 @@ bool jit_wanted(int n);
 // HIP source of the compiled passes; `flops` receives each one's arithmetic
 std::string jit_source(const Plan &plan, std::vector<int> &which, std::vector<double> *flops = nullptr);
 qsim_status jit_prepare(qsim_state s, Plan &plan, std::string &err);
-hipError_t launch_jit_pass(qsim_state s, const Plan &plan, const Pass &p, hipFunction_t fn);
+// Occupancy maps of compiled passes on sparse states: the chunk width (one
+// byte per 2^shift amplitudes, three maps in rotation), or 0 for none.
+int jit_map_shift(const Plan &plan);
+// `maps`: 3 x 2^(n - shift) bytes of device memory when the plan keeps maps.
+hipError_t launch_jit_pass(qsim_state s, const Plan &plan, const Pass &p, hipFunction_t fn, void *maps);
+hipError_t launch_fill_zero(qsim_state s, void *dst, size_t bytes);
 
 struct PlanOptions {
     int fuse_k = 1;

@@ -37,6 +37,7 @@ hipError_t launch_pauli_apply(qsim_state, void *, const void *, int, const void 
 hipError_t launch_reduce(qsim_state, const double *, int, double *) { no_device("reduce"); }
 hipError_t launch_reduce_rows(qsim_state, const double *, int, int, double *) { no_device("reduce"); }
 hipError_t launch_set_basis(qsim_state, uint64_t) { no_device("basis"); }
+hipError_t launch_fill_zero(qsim_state, void *, size_t) { no_device("fill"); }
 hipError_t launch_tile_pass(qsim_state, const Plan &, const Pass &, const double *) { no_device("tile"); }
 hipError_t launch_tile_reg_pass(qsim_state, const Plan &, const Pass &) { no_device("tile"); }
 int pauli_apply_grid(uint64_t) { no_device("pauli"); }
@@ -79,7 +80,7 @@ int main(int argc, char **argv) {
     for (size_t k = 0; k < which.size(); ++k) std::fprintf(out, "qsim_tile_jit_%zu,\n", k);
     std::fclose(out);
     out = std::fopen((dir + "/plan.txt").c_str(), "w");
-    std::fprintf(out, "%d %d %zu\n", n, dt, which.size());
+    std::fprintf(out, "%d %d %zu %d\n", n, dt, which.size(), jit_map_shift(plan));
     for (int i : which) {
         const Pass &p = plan.passes[size_t(i)];
         std::fprintf(out, "%llu %d\n", 1ull << (n - p.m), p.pool_begin);

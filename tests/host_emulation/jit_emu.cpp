@@ -38,15 +38,15 @@ typedef f2 VT; typedef float ST;
 #else
 typedef d2 VT; typedef double ST;
 #endif
-typedef void (*Kern)(VT *, const ST *);
+typedef void (*Kern)(VT *, const ST *, unsigned char *);
 static Kern kernels[] = {
 #include "table.inc"
 };
-struct Arg { Kern k; VT *psi; const ST *pool; unsigned t; };
+struct Arg { Kern k; VT *psi; const ST *pool; unsigned char *maps; unsigned t; };
 static void *run(void *a_) {
     Arg *a = static_cast<Arg *>(a_);
     threadIdx.x = a->t;
-    a->k(a->psi, a->pool);
+    a->k(a->psi, a->pool, a->maps);
     return nullptr;
 }
 int main(int argc, char **argv) {
@@ -54,8 +54,8 @@ int main(int argc, char **argv) {
     char path[512];
     snprintf(path, sizeof path, "%s/plan.txt", dir);
     FILE *f = fopen(path, "r");
-    int n, dt; size_t np;
-    if (fscanf(f, "%d %d %zu", &n, &dt, &np) != 3) return 2;
+    int n, dt, shift; size_t np;
+    if (fscanf(f, "%d %d %zu %d", &n, &dt, &np, &shift) != 4) return 2;
     std::vector<unsigned long long> ntiles(np); std::vector<int> pb(np);
     for (size_t i = 0; i < np; ++i) if (fscanf(f, "%llu %d", &ntiles[i], &pb[i]) != 2) return 2;
     fclose(f);
@@ -68,13 +68,15 @@ int main(int argc, char **argv) {
     f = fopen(argv[2], "rb");
     if (fread(psi.data(), sizeof(VT), psi.size(), f) != psi.size()) return 3;
     fclose(f);
+    // occupancy maps, zeroed before the chain of passes as the library does
+    std::vector<unsigned char> maps(shift > 0 ? size_t(3) << (n - shift) : 1, 0);
     pthread_barrier_init(&g_bar, nullptr, 256);
     std::vector<pthread_t> th(256); std::vector<Arg> args(256);
     for (size_t k = 0; k < np; ++k) {
         for (unsigned long long b = 0; b < ntiles[k]; ++b) {
             blockIdx.x = unsigned(b);
             for (unsigned t = 0; t < 256; ++t) {
-                args[t] = Arg{kernels[k], psi.data(), pool.data() + 2 * size_t(pb[k]), t};
+                args[t] = Arg{kernels[k], psi.data(), pool.data() + 2 * size_t(pb[k]), maps.data(), t};
                 pthread_create(&th[t], nullptr, run, &args[t]);
             }
             for (unsigned t = 0; t < 256; ++t) pthread_join(th[t], nullptr);

@@ -36,6 +36,7 @@ hipError_t launch_pauli_apply(qsim_state, void *, const void *, int, const void 
 hipError_t launch_reduce(qsim_state, const double *, int, double *) { no_device("reduce"); }
 hipError_t launch_reduce_rows(qsim_state, const double *, int, int, double *) { no_device("reduce"); }
 hipError_t launch_set_basis(qsim_state, uint64_t) { no_device("basis"); }
+hipError_t launch_fill_zero(qsim_state, void *, size_t) { no_device("fill"); }
 hipError_t launch_tile_pass(qsim_state, const Plan &, const Pass &, const double *) { no_device("tile"); }
 hipError_t launch_tile_reg_pass(qsim_state, const Plan &, const Pass &) { no_device("tile"); }
 int pauli_apply_grid(uint64_t) { no_device("pauli"); }

@@ -48,20 +48,26 @@ def emitter(tmp_path_factory):
     return exe
 
 
-def run_emulated(emitter, tmp, circ, tile_m, dtype):
+def run_emulated(emitter, tmp, circ, tile_m, dtype, map_shift=None, psi0=None):
     d = str(tmp)
     cf = os.path.join(d, "c.bin")
     write_circuit(cf, circ)
     dt = 1 if dtype == "c64" else 2
-    r = subprocess.run([emitter, cf, str(tile_m), str(dt), d], capture_output=True, text=True)
+    env = dict(os.environ)
+    if map_shift is not None:
+        env["QSIM_MAP_SHIFT"] = str(map_shift)
+    r = subprocess.run([emitter, cf, str(tile_m), str(dt), d], capture_output=True, text=True, env=env)
     assert r.returncode == 0, r.stderr
     exe = os.path.join(d, "emu")
     flags = ["-O1", "-std=c++17", "-I", d, "-pthread"] + (["-DEMU_DOUBLE"] if dt == 2 else [])
     r = subprocess.run([CLANG, *flags, os.path.join(EMU, "jit_emu.cpp"), "-o", exe], capture_output=True, text=True)
     assert r.returncode == 0, r.stderr[-3000:]
     npdt = np.complex64 if dt == 1 else np.complex128
-    psi = np.zeros(1 << circ.n, dtype=npdt)
-    psi[0] = 1
+    if psi0 is None:
+        psi = np.zeros(1 << circ.n, dtype=npdt)
+        psi[0] = 1
+    else:
+        psi = np.asarray(psi0, dtype=npdt)
     psi.tofile(os.path.join(d, "in.bin"))
     r = subprocess.run([exe, d, os.path.join(d, "in.bin"), os.path.join(d, "out.bin")], capture_output=True,
                        text=True, timeout=600)
@@ -120,3 +126,32 @@ def test_compiled_passes_on_the_host_match_the_oracle(emitter, tmp_path, name, m
         out = run_emulated(emitter, sub, circ, tile_m, dtype)
         err = O.rel_l2(out, ref)
         assert err <= TOL[dtype], (name, dtype, tile_m, err)
+
+
+@pytest.mark.parametrize("dtype", ["c64", "c128"])
+def test_occupancy_maps_on_sparse_states(emitter, tmp_path, dtype):
+    """Multiplier circuits (few spreading gates: the passes keep occupancy
+    maps, here with 2^6-amplitude chunks so that small states have many) on
+    a basis input, a superposed input and a dense random input: the maps may
+    only skip tiles that are zero."""
+    bits = 4
+    L = W.MultiplierLayout(bits)
+    core = W.multiplier_core(bits)
+    rng = np.random.default_rng(31)
+    for k, kind in enumerate(("basis", "superposed", "dense")):
+        if kind == "basis":
+            psi0 = np.zeros(1 << L.n, dtype=np.complex128)
+            psi0[L.basis_index(11, 13)] = 1
+        elif kind == "superposed":
+            psi0 = np.zeros(1 << L.n, dtype=np.complex128)
+            for a in range(16):
+                psi0[L.basis_index(a, 9)] = 0.25
+        else:
+            psi0 = W.random_state(L.n, rng)
+        ref = O.apply_circuit(core, psi0)
+        sub = tmp_path / kind
+        sub.mkdir()
+        out = run_emulated(emitter, sub, core, 12, dtype, map_shift=6, psi0=psi0)
+        assert O.rel_l2(out, ref) <= TOL[dtype], (kind, O.rel_l2(out, ref))
+        if kind == "basis":
+            assert np.count_nonzero(out) == 1
