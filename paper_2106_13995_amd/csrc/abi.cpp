@@ -734,11 +734,15 @@ qsim_status expectation_with(qsim_state s, const qsim_pauli_sum *H, double *out_
                 ExpSimplePass &sp = spasses.back();
                 sp.diag = 1;
                 const int first = spans[size_t(diag_gi)].second, cnt = group_terms(size_t(diag_gi));
+                // pad = mu | zl << 8: the register part of the Z mask (bit b:
+                // register bit b) and its lane part (bit b: lane bit b)
                 for (int t = first; t < first + cnt; ++t) {
-                    uint32_t mu = 0;
+                    uint32_t mu = 0, zl = 0;
                     for (int b = 0; b < R; ++b)
                         if ((ht[size_t(t)].z >> sp.reg_q[b]) & 1) mu |= 1u << b;
-                    ht[size_t(t)].pad = mu;
+                    for (int b = 0; b < 6; ++b)
+                        if ((ht[size_t(t)].z >> sp.lane_q[b]) & 1) zl |= 1u << b;
+                    ht[size_t(t)].pad = uint64_t(mu) | (uint64_t(zl) << 8);
                 }
                 std::stable_sort(ht.begin() + first, ht.begin() + first + cnt,
                                  [](const DevTerm &a, const DevTerm &b) { return a.pad < b.pad; });

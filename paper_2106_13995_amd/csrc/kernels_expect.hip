@@ -13,7 +13,8 @@
 // w_t (-1)^{|y & z_t|} |psi_y|^2: the sign splits into the lane/block part of
 // z_t (one parity per term and tile) and its register part mu_t, and
 // sum_k (-1)^{|mu & k|} |a_k|^2 over a lane's registers is the Walsh-Hadamard
-// transform of |a|^2, computed in place.  Everything after the amplitudes'
+// transform of |a|^2, computed in place; terms sharing mu and their lane part
+// share one multiply by it.  Everything after the amplitudes'
 // conversion is double precision; each lane accumulates its tiles in order,
 // and a fixed-order wave sum gives one partial per workgroup.
 #include <hip/hip_runtime.h>
@@ -157,11 +158,6 @@ k_expect_simple(const c2_t<T> *__restrict__ psi, const ExpSimplePass p, const Si
     uint64_t roff[R];
 #pragma unroll
     for (int b = 0; b < R; ++b) roff[b] = 1ull << p.reg_q[b];
-    // lane-bit parity of the first 64 diagonal terms' Z masks
-    uint64_t lpar = 0;
-    if (p.diag)
-        for (int j = 0; j < 64 && p.diag_first + j < p.diag_end; ++j)
-            lpar |= uint64_t(__popcll(terms[p.diag_first + j].z & toff) & 1) << j;
     double acc = 0.0;
     for (uint64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
         // the tile's out-of-tile bits: zeros inserted at the tile qubits
@@ -218,22 +214,19 @@ k_expect_simple(const c2_t<T> *__restrict__ psi, const ExpSimplePass p, const Si
                     w[k | bit] = u - v;
                 }
             }
-            // terms in order of their register part mu (in pad_): the signed
-            // weights of a run of equal mu multiply w[mu] once.  A term's
-            // sign is the parity of its Z mask on the lane bits (fixed per
-            // lane: lpar) and on the block bits (the same on every lane).
-            int t = p.diag_first;
-            while (t < p.diag_end) {
-                const int mu = int(terms[t].pad_);
-                double c = 0.0;
-                for (; t < p.diag_end && int(terms[t].pad_) == mu; ++t) {
-                    const SimpleTerm e = terms[t];
-                    const int j = t - p.diag_first;
-                    const unsigned lb = j < 64 ? unsigned(lpar >> j) & 1u : unsigned(__popcll(e.z & toff) & 1);
-                    const unsigned ub = unsigned(__popcll(e.z & base) & 1);
-                    c += (lb ^ ub) ? -e.wr : e.wr;
-                }
-                add_at<NA>(w, mu, c, acc);
+            // Each term's sign is the parity of its Z mask over the block bits
+            // (the same on every lane: a scalar choice of +-1), its lane part
+            // zl and its register part mu (pad_ holds mu | zl << 8); the
+            // register part selects the transform entry.  The trip count is
+            // known at the loop's start, so unrolled iterations issue their
+            // term loads together.
+#pragma unroll 8
+            for (int t = p.diag_first; t < p.diag_end; ++t) {
+                const SimpleTerm e = terms[t];
+                const double sg = (__popcll(e.z & base) & 1) ? -1.0 : 1.0;
+                const uint32_t zl = uint32_t(e.pad_ >> 8);
+                const double c = (__popc(zl & lane) & 1) ? -sg * e.wr : sg * e.wr;
+                add_at<NA>(w, int(e.pad_ & 0xffu), c, acc);
             }
         }
     }

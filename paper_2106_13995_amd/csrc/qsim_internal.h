@@ -381,8 +381,8 @@ hipError_t launch_expect_tiles(qsim_state s, const ExpTilePass &p, const void *d
 // pair registers (reg_bit, weights A of the X_h terms, B of the Y_h terms);
 // groups on lane qubits exchange across lanes (lane_bit).  With diag set the
 // pass also evaluates the diagonal group: terms diag_first .. diag_end - 1,
-// ordered by the register part mu of their Z mask (kept in each term's pad
-// field).  Each launch writes one partial per workgroup.
+// ordered by the register part mu of their Z mask and then its lane part zl
+// (each term's pad field holds mu | zl << 8).  Each launch writes one partial per workgroup.
 constexpr int kExpSimpleMaxR = 6;
 constexpr int kExpSimpleR = 4;
 struct ExpSimplePass {
