@@ -266,9 +266,14 @@ qsim_status qsim_adjoint_grad(qsim_state s, const qsim_circuit *c, const double 
  * qsim_batch_create validates every circuit (1 <= n <= 26; parametric ops
  * must be RX, RY or RZ), builds one device program per distinct structure
  * (circuit ops, fixed angles and matrices, observable), allocates device
- * memory (programs, parameters, outputs, and for circuits wider than one LDS
- * tile a psi/lambda slot per workgroup) and captures the persistent kernel
- * in a HIP graph.  Circuit i reads its parameters from params[param_offsets[i]
+ * memory and captures the whole run in a HIP graph.  Circuits that fill
+ * whole tiles (n >= 12 complex64, n >= 11 complex128) and whose ops all fit
+ * register-staged passes run layered: one launch per pass index applies
+ * that pass of every such circuit to all of its tiles at once, each circuit
+ * with psi/lambda slots of its own (2 x 2^n amplitudes, in groups that fit
+ * half the free device memory).  The others run in a persistent kernel, one
+ * workgroup per circuit from LDS (a psi/lambda slot per workgroup for
+ * circuits wider than one tile).  Circuit i reads its parameters from params[param_offsets[i]
  * .. param_offsets[i+1]) (param indices in its ops are relative to that
  * block), is applied to |0...0>, and yields energies[i] = <psi|Hs[i]|psi>
  * and, when want_grad, grads over the same block.  `opts` is reserved (may
@@ -280,8 +285,10 @@ qsim_status qsim_adjoint_grad(qsim_state s, const qsim_circuit *c, const double 
  * device-to-device copy of the parameters in, the graph, copies of the
  * results out; returns without waiting.  Calls on one batch must be
  * serialised on one stream.  qsim_batch_info reports the persistent grid
- * size, the number of distinct programs and the widest circuit; qsim_batch_free
- * waits for the batch's work and releases it. */
+ * size, the number of distinct programs and the widest circuit;
+ * qsim_batch_layout how many circuits run layered and how many in the
+ * persistent kernel; qsim_batch_free waits for the batch's work and releases
+ * it. */
 typedef struct qsim_batch_s *qsim_batch;
 
 qsim_status qsim_batch_create(int ncirc, const qsim_circuit *circs, const int64_t *param_offsets,
@@ -290,6 +297,7 @@ qsim_status qsim_batch_create(int ncirc, const qsim_circuit *circs, const int64_
 qsim_status qsim_batch_run(qsim_batch b, const double *params_dev, double *energies_dev, double *grads_dev,
                            void *hip_stream);
 qsim_status qsim_batch_info(qsim_batch b, int *grid, int *programs, int *max_n);
+qsim_status qsim_batch_layout(qsim_batch b, int *layered, int *persistent);
 qsim_status qsim_batch_free(qsim_batch b);
 
 /* Autotuner (Sec. IV: the paper leaves kernel-level tuning to future work):

@@ -49,7 +49,7 @@ EXPORTS = (
     "qsim_set_basis", "qsim_copy_to_host", "qsim_copy_from_host", "qsim_apply_gate",
     "qsim_apply_circuit", "qsim_expectation", "qsim_last_error", "qsim_profile_enable",
     "qsim_profile_read", "qsim_plan_summary", "qsim_adjoint_grad", "qsim_batch_create", "qsim_batch_run",
-    "qsim_batch_info", "qsim_batch_free", "qsim_autotune", "qsim_expectation_noalloc",
+    "qsim_batch_info", "qsim_batch_layout", "qsim_batch_free", "qsim_autotune", "qsim_expectation_noalloc",
 )
 
 
@@ -129,6 +129,7 @@ def _load() -> ctypes.CDLL:
                                i32, i32, ctypes.POINTER(QsimOptions), ctypes.POINTER(P)], S),
         "qsim_batch_run": ([P, P, P, P, P], S),
         "qsim_batch_info": ([P, ctypes.POINTER(i32), ctypes.POINTER(i32), ctypes.POINTER(i32)], S),
+        "qsim_batch_layout": ([P, ctypes.POINTER(i32), ctypes.POINTER(i32)], S),
         "qsim_batch_free": ([P], S),
         "qsim_autotune": ([P, ctypes.POINTER(QsimCircuit), ctypes.POINTER(ctypes.c_double), i64, i32,
                            ctypes.POINTER(QsimOptions), ctypes.POINTER(ctypes.c_double)], S),
@@ -439,6 +440,12 @@ class Batch:
         g, p, m = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
         _check(_lib.qsim_batch_info(ctypes.c_void_p(self.handle), ctypes.byref(g), ctypes.byref(p), ctypes.byref(m)))
         return g.value, p.value, m.value
+
+    def layout(self) -> Tuple[int, int]:
+        """(circuits run layered, circuits run in the persistent kernel)."""
+        lay, per = ctypes.c_int(), ctypes.c_int()
+        _check(_lib.qsim_batch_layout(ctypes.c_void_p(self.handle), ctypes.byref(lay), ctypes.byref(per)))
+        return lay.value, per.value
 
     def run_device(self, params, energies=None, grads=None):
         """Queues one batch run on torch's current stream: `params` is a

@@ -12,7 +12,7 @@ CSRC = os.path.join(HERE, "csrc")
 OBJ = os.path.join(ROOT, "_build", "qsim")
 LIB = os.path.join(HERE, "libqsim.so")
 SOURCES = ["abi.cpp", "gates.cpp", "plan.cpp", "stages.cpp", "kernels.hip", "kernels_reg.hip",
-           "kernels_adjoint.hip", "batch.cpp", "kernels_batch.hip",
+           "kernels_adjoint.hip", "batch.cpp", "kernels_batch.hip", "kernels_batch_layer.hip",
            "kernels_mfma.hip", "autotune.cpp", "jit.cpp", "noalloc.cpp", "kernels_expect.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
@@ -29,6 +29,7 @@ FLAGS = [
 # pointer phis, which demotes them to scratch memory; keep them in VGPRs.
 EXTRA = {
     "kernels_reg.hip": ["-mllvm", "-simplifycfg-sink-common=false"],
+    "kernels_batch_layer.hip": ["-mllvm", "-simplifycfg-sink-common=false"],
 }
 
 

@@ -3,6 +3,7 @@
 // largest-first work order, device buffers and the captured HIP graph that
 // runs a whole batch as one replay.
 #include <algorithm>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <new>
@@ -26,7 +27,9 @@ struct qsim_batch_s {
     int grid = 0;
     void *dev = nullptr;          // programs, circuits, params, outputs, counter
     size_t dev_bytes = 0;
-    void *arena = nullptr;        // per-workgroup psi / lambda slots
+    void *arena = nullptr;        // per-workgroup psi / lambda slots (persistent kernel)
+    void *larena = nullptr;       // per-circuit psi / lambda slots (layered circuits)
+    int nlayered = 0;
     double *d_params = nullptr, *d_energy = nullptr, *d_grads = nullptr;   // inside dev
     hipStream_t last_stream = nullptr;   // stream of the last run
     bool ran = false;
@@ -48,6 +51,7 @@ void destroy(qsim_batch b) {
     if (b->cap_stream) (void)hipStreamDestroy(b->cap_stream);
     if (b->dev) (void)hipFree(b->dev);
     if (b->arena) (void)hipFree(b->arena);
+    if (b->larena) (void)hipFree(b->larena);
     delete b;
 }
 
@@ -137,9 +141,12 @@ qsim_status qsim_batch_create(int ncirc, const qsim_circuit *circs, const int64_
     std::vector<BatchProgram> progs;
     std::vector<BatchPass> passes;
     std::vector<TileOp> ops;
+    std::vector<RegStage> stages;
+    std::vector<RegOp> rops;
     std::vector<cd> pool;
     std::vector<BatchHGroup> hgroups;
     std::vector<BatchHTerm> hterms;
+    std::vector<int32_t> probe_row, probe_idx;
     int nonsingle_max_n = 0;
     for (size_t pi = 0; pi < prog_circ.size(); ++pi) {
         const qsim_circuit &c = *prog_circ[pi];
@@ -179,17 +186,43 @@ qsim_status qsim_batch_create(int ncirc, const qsim_circuit *circs, const int64_
         BatchProgram bp{};
         bp.n = c.n;
         bp.m = std::min(c.n, batch_tile_max(dtype));
-        if (bp.m < c.n) nonsingle_max_n = std::max(nonsingle_max_n, c.n);
         b->max_n = std::max(b->max_n, c.n);
-        for (int dir = 0; dir < 2; ++dir) {
-            Plan plan;
-            plan.n = c.n;
-            plan.dtype = dtype;
-            // batch tiles hold L + 6 qubits, so the planner never widens them
-            if (build_tile_plan(plan, dir == 0 ? fwd : rev, bp.m) != bp.m) {
-                delete b;
-                return fail(QSIM_ERR_UNSUPPORTED, "a batch program: the planner could not place every op");
+        // Circuits that fill whole tiles run layered, register-staged
+        // throughout; a program with a pass that cannot be staged (a dense
+        // block on more than three qubits) and smaller circuits run in the
+        // persistent kernel, from LDS.
+        bool layered = bp.m == batch_tile_max(dtype);
+        Plan plans[2];
+        for (int attempt = 0; attempt < 2; ++attempt) {
+            bool ok = true;
+            for (int dir = 0; dir < 2; ++dir) {
+                plans[dir] = Plan();
+                plans[dir].n = c.n;
+                plans[dir].dtype = dtype;
+                std::vector<HostGate> items = dir == 0 ? fwd : rev;
+                if (dir == 0 && items.empty() && layered) {
+                    // an identity on qubit 0 gives the forward sweep the pass
+                    // that starts psi at |0...0>
+                    HostGate id;
+                    id.k = 1;
+                    id.M = {cd(1.0), cd(0.0), cd(0.0), cd(1.0)};
+                    items.push_back(id);
+                }
+                // batch tiles hold L + 6 qubits, so the planner never widens them
+                if (build_tile_plan(plans[dir], items, bp.m, 1, layered) != bp.m) {
+                    delete b;
+                    return fail(QSIM_ERR_UNSUPPORTED, "a batch program: the planner could not place every op");
+                }
+                if (layered)
+                    for (const Pass &p : plans[dir].passes) ok = ok && p.reg_r == batch_reg_bits(dtype);
             }
+            if (ok) break;
+            layered = false;
+        }
+        if (!layered && bp.m < c.n) nonsingle_max_n = std::max(nonsingle_max_n, c.n);
+        bp.layered = layered ? 1 : 0;
+        for (int dir = 0; dir < 2; ++dir) {
+            Plan &plan = plans[dir];
             if (dir == 0 && plan.passes.empty()) {
                 // one empty forward pass initialises psi
                 Pass p;
@@ -214,6 +247,36 @@ qsim_status qsim_batch_create(int ncirc, const qsim_circuit *circs, const int64_
                     if (t.type == 0 || t.type == 1 || t.type == 5) t.moff += pool_base + p.pool_begin;
                     ops.push_back(t);
                 }
+                if (layered) {
+                    bps.reg_r = p.reg_r;
+                    const int rop0 = int(rops.size());
+                    for (int o = p.rop_begin; o < p.rop_end; ++o) {
+                        RegOp r = plan.reg_ops[size_t(o)];
+                        // rotations and probes name a parameter, not a pool
+                        // entry; a probe's jmatch is its index in the sweep
+                        if (r.type == 9)
+                            r.jmatch = bp.nprobes++;
+                        else if (r.type != 8)
+                            r.moff += pool_base + p.pool_begin;
+                        rops.push_back(r);
+                    }
+                    bps.stage_begin = int(stages.size());
+                    for (int si = p.stage_begin; si < p.stage_end; ++si) {
+                        RegStage st = plan.reg_stages[size_t(si)];
+                        st.op_begin += rop0;
+                        st.op_end += rop0;
+                        stages.push_back(st);
+                    }
+                    bps.stage_end = int(stages.size());
+                    for (int i = 0; i < 8; ++i) {
+                        bps.ld_t[i] = p.ld_t[i];
+                        bps.st_t[i] = p.st_t[i];
+                    }
+                    for (int i = 0; i < kRegBitsMax; ++i) {
+                        bps.ld_r[i] = p.ld_r[i];
+                        bps.st_r[i] = p.st_r[i];
+                    }
+                }
                 passes.push_back(bps);
             }
             pool.insert(pool.end(), plan.tile_pool.begin(), plan.tile_pool.end());
@@ -224,6 +287,23 @@ qsim_status qsim_batch_create(int ncirc, const qsim_circuit *circs, const int64_
                 bp.rev_begin = first;
                 bp.rev_end = int(passes.size());
             }
+        }
+        if (layered) {
+            // parameter -> its probes (CSR), in sweep order
+            bp.nparams = int(np);
+            bp.row_off = int(probe_row.size());
+            std::vector<std::vector<int32_t>> of(static_cast<size_t>(np));
+            for (int pi2 = bp.rev_begin; pi2 < bp.rev_end; ++pi2)
+                for (int si = passes[size_t(pi2)].stage_begin; si < passes[size_t(pi2)].stage_end; ++si)
+                    for (int o = stages[size_t(si)].op_begin; o < stages[size_t(si)].op_end; ++o)
+                        if (rops[size_t(o)].type == 9) of[size_t(rops[size_t(o)].moff)].push_back(rops[size_t(o)].jmatch);
+            int32_t at = int32_t(probe_idx.size());
+            for (int64_t j = 0; j < np; ++j) {
+                probe_row.push_back(at);
+                for (int32_t k : of[size_t(j)]) probe_idx.push_back(k);
+                at = int32_t(probe_idx.size());
+            }
+            probe_row.push_back(at);
         }
         std::map<uint64_t, std::vector<int>> byx;
         for (int t = 0; t < H.nterms; ++t) byx[H.terms[t].xmask].push_back(t);
@@ -248,7 +328,8 @@ qsim_status qsim_batch_create(int ncirc, const qsim_circuit *circs, const int64_
         bp.hg_end = int(hgroups.size());
         progs.push_back(bp);
     }
-    // circuits, largest (2^n x ops) first
+    // circuits, largest (2^n x ops) first; persistent ones in `order`, the
+    // layered ones in `lcircs`
     std::vector<BatchCircuit> bc(static_cast<size_t>(ncirc));
     std::vector<double> cost(static_cast<size_t>(ncirc));
     for (int i = 0; i < ncirc; ++i) {
@@ -257,12 +338,124 @@ qsim_status qsim_batch_create(int ncirc, const qsim_circuit *circs, const int64_
         bc[size_t(i)].param_off = param_offsets[i];
         cost[size_t(i)] = std::ldexp(1.0, circs[i].n) * double(circs[i].nops + 1);
     }
-    std::vector<int32_t> order(static_cast<size_t>(ncirc));
-    std::iota(order.begin(), order.end(), 0);
-    std::stable_sort(order.begin(), order.end(), [&](int a, int c) { return cost[size_t(a)] > cost[size_t(c)]; });
+    std::vector<int32_t> all(static_cast<size_t>(ncirc));
+    std::iota(all.begin(), all.end(), 0);
+    std::stable_sort(all.begin(), all.end(), [&](int a, int c) { return cost[size_t(a)] > cost[size_t(c)]; });
+    std::vector<int32_t> order;
+    std::vector<BatchLCirc> lcircs;
+    const size_t s = amp_bytes(dtype);
+    for (int32_t i : all) {
+        const BatchProgram &pg = progs[size_t(bc[size_t(i)].prog)];
+        if (!pg.layered) {
+            order.push_back(i);
+            continue;
+        }
+        BatchLCirc l{};
+        l.circ = i;
+        l.prog = bc[size_t(i)].prog;
+        l.ntiles = 1 << (pg.n - pg.m);
+        l.nchunks = int(std::max<int64_t>(1, (int64_t(1) << pg.n) / kBatchChunk));
+        l.param_off = bc[size_t(i)].param_off;
+        l.nparams = bc[size_t(i)].nparams;
+        lcircs.push_back(l);
+    }
+    b->nlayered = int(lcircs.size());
+    // Layered circuits go in groups whose slots fit the budget; each group
+    // runs its forward layers, energies and reverse layers before the next,
+    // in slots at the start of the arena.
+    size_t free_b = 0, total_b = 0;
+    if (hipMemGetInfo(&free_b, &total_b) != hipSuccess) {
+        (void)hipGetLastError();
+        free_b = 0;
+    }
+    size_t budget = std::max<size_t>(size_t(1) << 30, free_b / 2);
+    if (const char *ev = std::getenv("QSIM_BATCH_SLOT_BUDGET")) {
+        // bytes of layered slots per group (tests: several groups on small batches)
+        const long long v = std::atoll(ev);
+        if (v > 0) budget = size_t(v);
+    }
+    std::vector<BatchWork> works;
+    std::vector<BatchStep> steps;
+    size_t larena_amps = 0;
+    uint64_t pp_total = 0, ep_total = 0;
+    int64_t gw_total = 0;
+    for (size_t g0 = 0; g0 < lcircs.size();) {
+        size_t g1 = g0;
+        uint64_t amps = 0;
+        const uint64_t per = b->want_grad ? 2 : 1;
+        while (g1 < lcircs.size()) {
+            const uint64_t need = per * (uint64_t(1) << progs[size_t(lcircs[g1].prog)].n);
+            if (g1 > g0 && (amps + need) * s > budget) break;
+            amps += need;
+            ++g1;
+        }
+        uint64_t at = 0;
+        int max_fwd = 0, max_rev = 0;
+        const int64_t gw0 = gw_total;
+        for (size_t k = g0; k < g1; ++k) {
+            BatchLCirc &l = lcircs[k];
+            const BatchProgram &pg = progs[size_t(l.prog)];
+            const uint64_t N = uint64_t(1) << pg.n;
+            l.psi_off = at;
+            at += N;
+            l.lam_off = b->want_grad ? at : l.psi_off;
+            if (b->want_grad) at += N;
+            l.pp_off = pp_total;
+            if (b->want_grad) pp_total += uint64_t(pg.nprobes) * uint64_t(l.ntiles);
+            l.ep_off = ep_total;
+            ep_total += uint64_t(l.nchunks);
+            l.gfirst = gw_total;
+            gw_total += l.nparams;
+            max_fwd = std::max(max_fwd, pg.fwd_end - pg.fwd_begin);
+            max_rev = std::max(max_rev, pg.rev_end - pg.rev_begin);
+        }
+        larena_amps = std::max<size_t>(larena_amps, size_t(at));
+        auto layer = [&](int kind, int sidx) {
+            BatchStep st{};
+            st.kind = kind;
+            st.init = kind == 0 && sidx == 0;
+            st.wbegin = int(works.size());
+            uint32_t wgs = 0;
+            for (size_t k = g0; k < g1; ++k) {
+                const BatchLCirc &l = lcircs[k];
+                const BatchProgram &pg = progs[size_t(l.prog)];
+                BatchWork w{};
+                w.lc = int(k);
+                if (kind == 2) {
+                    w.pass = -1;
+                    w.count = uint32_t(l.nchunks);
+                } else {
+                    const int b0 = kind == 0 ? pg.fwd_begin : pg.rev_begin, b1 = kind == 0 ? pg.fwd_end : pg.rev_end;
+                    if (b0 + sidx >= b1) continue;
+                    w.pass = b0 + sidx;
+                    w.count = uint32_t(l.ntiles);
+                }
+                w.first = wgs;
+                wgs += w.count;
+                works.push_back(w);
+            }
+            st.wend = int(works.size());
+            st.wgs = wgs;
+            st.lc_begin = int(g0);
+            st.lc_end = int(g1);
+            steps.push_back(st);
+        };
+        for (int k = 0; k < max_fwd; ++k) layer(0, k);
+        layer(2, 0);
+        if (b->want_grad) {
+            for (int k = 0; k < max_rev; ++k) layer(1, k);
+            BatchStep gr{};
+            gr.kind = 3;
+            gr.lc_begin = int(g0);
+            gr.lc_end = int(g1);
+            gr.gw_begin = gw0;
+            gr.gw_end = gw_total;
+            steps.push_back(gr);
+        }
+        g0 = g1;
+    }
 
     // device layout
-    const size_t s = amp_bytes(dtype);
     auto al = [](size_t v) { return (v + 255) & ~size_t(255); };
     size_t off = 0;
     auto place = [&](size_t bytes) {
@@ -275,13 +468,22 @@ qsim_status qsim_batch_create(int ncirc, const qsim_circuit *circs, const int64_
     const size_t o_progs = place(sizeof(BatchProgram) * progs.size());
     const size_t o_passes = place(sizeof(BatchPass) * passes.size());
     const size_t o_ops = place(sizeof(TileOp) * ops.size());
+    const size_t o_stages = place(sizeof(RegStage) * stages.size());
+    const size_t o_rops = place(sizeof(RegOp) * rops.size());
     const size_t o_pool = place(s * pool.size());
     const size_t o_hg = place(sizeof(BatchHGroup) * hgroups.size());
     const size_t o_ht = place(sizeof(BatchHTerm) * hterms.size());
+    const size_t o_lc = place(sizeof(BatchLCirc) * lcircs.size());
+    const size_t o_works = place(sizeof(BatchWork) * works.size());
+    const size_t o_prow = place(sizeof(int32_t) * probe_row.size());
+    const size_t o_pidx = place(sizeof(int32_t) * probe_idx.size());
     const size_t o_params = place(sizeof(double) * size_t(b->nparams));
     const size_t o_energy = place(sizeof(double) * size_t(ncirc));
     const size_t o_grads = place(sizeof(double) * size_t(b->nparams));
     const size_t o_counter = place(sizeof(int));
+    const size_t o_trig = place(2 * sizeof(double) * size_t(b->nparams));
+    const size_t o_ppart = place(sizeof(double) * size_t(pp_total));
+    const size_t o_epart = place(sizeof(double) * size_t(ep_total));
     b->dev_bytes = off;
     hipDeviceProp_t prop;
     int dev = 0;
@@ -291,10 +493,11 @@ qsim_status qsim_batch_create(int ncirc, const qsim_circuit *circs, const int64_
         return fail(QSIM_ERR_DEVICE, "hipGetDeviceProperties failed");
     }
     const int per_cu = 4;
-    b->grid = std::max(1, std::min(ncirc, prop.multiProcessorCount * per_cu));
+    b->grid = std::max(1, std::min(int(order.size()), prop.multiProcessorCount * per_cu));
     const uint64_t slot_amps = nonsingle_max_n ? (1ull << nonsingle_max_n) : 0ull;
     if (hipMalloc(&b->dev, b->dev_bytes) != hipSuccess ||
-        (slot_amps && hipMalloc(&b->arena, size_t(b->grid) * 2 * slot_amps * s) != hipSuccess)) {
+        (slot_amps && !order.empty() && hipMalloc(&b->arena, size_t(b->grid) * 2 * slot_amps * s) != hipSuccess) ||
+        (larena_amps && hipMalloc(&b->larena, larena_amps * s) != hipSuccess)) {
         (void)hipGetLastError();
         destroy(b);
         return fail(QSIM_ERR_OOM, "cannot allocate batch device memory");
@@ -302,22 +505,29 @@ qsim_status qsim_batch_create(int ncirc, const qsim_circuit *circs, const int64_
     // static part uploaded once, synchronously
     std::vector<char> host(o_params, 0);
     std::memcpy(host.data() + o_circs, bc.data(), sizeof(BatchCircuit) * bc.size());
-    std::memcpy(host.data() + o_order, order.data(), sizeof(int32_t) * order.size());
+    if (!order.empty()) std::memcpy(host.data() + o_order, order.data(), sizeof(int32_t) * order.size());
     std::memcpy(host.data() + o_progs, progs.data(), sizeof(BatchProgram) * progs.size());
     if (!passes.empty()) std::memcpy(host.data() + o_passes, passes.data(), sizeof(BatchPass) * passes.size());
     if (!ops.empty()) std::memcpy(host.data() + o_ops, ops.data(), sizeof(TileOp) * ops.size());
+    if (!stages.empty()) std::memcpy(host.data() + o_stages, stages.data(), sizeof(RegStage) * stages.size());
+    if (!rops.empty()) std::memcpy(host.data() + o_rops, rops.data(), sizeof(RegOp) * rops.size());
     if (dtype == QSIM_C64)
         pack_pool<float>(pool, host.data() + o_pool);
     else
         pack_pool<double>(pool, host.data() + o_pool);
     if (!hgroups.empty()) std::memcpy(host.data() + o_hg, hgroups.data(), sizeof(BatchHGroup) * hgroups.size());
     if (!hterms.empty()) std::memcpy(host.data() + o_ht, hterms.data(), sizeof(BatchHTerm) * hterms.size());
+    if (!lcircs.empty()) std::memcpy(host.data() + o_lc, lcircs.data(), sizeof(BatchLCirc) * lcircs.size());
+    if (!works.empty()) std::memcpy(host.data() + o_works, works.data(), sizeof(BatchWork) * works.size());
+    if (!probe_row.empty()) std::memcpy(host.data() + o_prow, probe_row.data(), sizeof(int32_t) * probe_row.size());
+    if (!probe_idx.empty()) std::memcpy(host.data() + o_pidx, probe_idx.data(), sizeof(int32_t) * probe_idx.size());
     if (hipMemcpy(b->dev, host.data(), o_params, hipMemcpyHostToDevice) != hipSuccess) {
         destroy(b);
         return fail(QSIM_ERR_DEVICE, "uploading the batch programs failed");
     }
-    // capture: counter reset + persistent kernel (parameters and results
-    // move device to device around the graph, in stream order)
+    // capture: the layered launches, then the counter reset and the
+    // persistent kernel (parameters and results move device to device around
+    // the graph, in stream order)
     char *d = static_cast<char *>(b->dev);
     b->d_params = reinterpret_cast<double *>(d + o_params);
     b->d_energy = reinterpret_cast<double *>(d + o_energy);
@@ -328,6 +538,8 @@ qsim_status qsim_batch_create(int ncirc, const qsim_circuit *circs, const int64_
     bd.progs = reinterpret_cast<const BatchProgram *>(d + o_progs);
     bd.passes = reinterpret_cast<const BatchPass *>(d + o_passes);
     bd.ops = reinterpret_cast<const TileOp *>(d + o_ops);
+    bd.stages = reinterpret_cast<const RegStage *>(d + o_stages);
+    bd.rops = reinterpret_cast<const RegOp *>(d + o_rops);
     bd.pool = d + o_pool;
     bd.hgroups = reinterpret_cast<const BatchHGroup *>(d + o_hg);
     bd.hterms = reinterpret_cast<const BatchHTerm *>(d + o_ht);
@@ -337,12 +549,37 @@ qsim_status qsim_batch_create(int ncirc, const qsim_circuit *circs, const int64_
     bd.arena = b->arena;
     bd.slot_amps = slot_amps;
     bd.counter = reinterpret_cast<int *>(d + o_counter);
-    bd.ncirc = ncirc;
+    bd.ncirc = int(order.size());
     bd.want_grad = b->want_grad;
     bd.mmax = batch_tile_max(dtype);
-    hipError_t e = hipStreamCreateWithFlags(&b->cap_stream, hipStreamNonBlocking);
+    BatchLayerDevice ld{};
+    ld.lc = reinterpret_cast<const BatchLCirc *>(d + o_lc);
+    ld.nlc = int(lcircs.size());
+    ld.works = reinterpret_cast<const BatchWork *>(d + o_works);
+    ld.progs = bd.progs;
+    ld.passes = bd.passes;
+    ld.stages = bd.stages;
+    ld.rops = bd.rops;
+    ld.pool = bd.pool;
+    ld.hgroups = bd.hgroups;
+    ld.hterms = bd.hterms;
+    ld.probe_row = reinterpret_cast<const int32_t *>(d + o_prow);
+    ld.probe_idx = reinterpret_cast<const int32_t *>(d + o_pidx);
+    ld.params = bd.params;
+    ld.trig = reinterpret_cast<double *>(d + o_trig);
+    ld.nparams = b->nparams;
+    ld.energies = bd.energies;
+    ld.grads = bd.grads;
+    ld.arena = b->larena;
+    ld.ppart = reinterpret_cast<double *>(d + o_ppart);
+    ld.epart = reinterpret_cast<double *>(d + o_epart);
+    ld.want_grad = b->want_grad;
+    ld.steps = steps;
+    hipError_t e = lcircs.empty() ? hipSuccess : batch_layer_setup(dtype);
+    if (e == hipSuccess) e = hipStreamCreateWithFlags(&b->cap_stream, hipStreamNonBlocking);
     if (e == hipSuccess) e = hipStreamBeginCapture(b->cap_stream, hipStreamCaptureModeThreadLocal);
-    if (e == hipSuccess) e = launch_batch(b->cap_stream, dtype, bd, b->grid);
+    if (e == hipSuccess && !lcircs.empty()) e = launch_batch_layered(b->cap_stream, dtype, ld);
+    if (e == hipSuccess && !order.empty()) e = launch_batch(b->cap_stream, dtype, bd, b->grid);
     hipGraph_t g = nullptr;
     const hipError_t ec = hipStreamEndCapture(b->cap_stream, &g);
     if (e == hipSuccess) e = ec;
@@ -395,6 +632,13 @@ qsim_status qsim_batch_info(qsim_batch b, int *grid, int *programs, int *max_n) 
     if (grid) *grid = b->grid;
     if (programs) *programs = b->programs;
     if (max_n) *max_n = b->max_n;
+    return QSIM_OK;
+}
+
+qsim_status qsim_batch_layout(qsim_batch b, int *layered, int *persistent) {
+    if (!b) return fail(QSIM_ERR_ARG, "batch handle is NULL");
+    if (layered) *layered = b->nlayered;
+    if (persistent) *persistent = b->ncirc - b->nlayered;
     return QSIM_OK;
 }
 

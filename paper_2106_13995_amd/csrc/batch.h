@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <vector>
 
 #include "qsim_internal.h"
 
@@ -26,12 +27,25 @@ struct BatchProgram {
     int32_t n, m;        // qubits, tile qubits (m = n when the state is one tile)
     int32_t fwd_begin, fwd_end, rev_begin, rev_end;   // pass ranges
     int32_t hg_begin, hg_end;                         // observable term groups
+    // layered programs (all passes register-staged): probes of the reverse
+    // sweep, and for each parameter j < nparams the probes that feed it,
+    // probe_idx[probe_row[row_off + j] .. probe_row[row_off + j + 1])
+    int32_t layered, nprobes, nparams, row_off;
 };
+
+// Register bits of a batch thread in register-staged passes (256 threads,
+// full tiles of batch_tile_max qubits).
+inline int batch_reg_bits(int dtype) { return batch_tile_max(dtype) - 8; }
 
 struct BatchPass {
     int32_t L, H;
     int32_t hpos[16];
-    int32_t op_begin, op_end;
+    int32_t op_begin, op_end;   // LDS form: TileOps
+    // register-staged form (reg_r > 0): stages [stage_begin, stage_end) of
+    // the batch's stage table, whose op ranges index its RegOp table; global
+    // qubit of each thread / register bit at the load and at the store
+    int32_t reg_r, stage_begin, stage_end;
+    int32_t ld_t[8], ld_r[kRegBitsMax], st_t[8], st_r[kRegBitsMax];
 };
 
 struct BatchHGroup {
@@ -50,6 +64,8 @@ struct BatchDevice {
     const BatchProgram *progs;
     const BatchPass *passes;
     const TileOp *ops;
+    const RegStage *stages;
+    const RegOp *rops;
     const void *pool;
     const BatchHGroup *hgroups;
     const BatchHTerm *hterms;
@@ -65,5 +81,76 @@ struct BatchDevice {
 };
 
 hipError_t launch_batch(hipStream_t stream, int dtype, const BatchDevice &d, int grid);
+
+// ------------------------------------------------------------ layered circuits
+//
+// Circuits whose programs are register-staged throughout run as layers: one
+// launch applies pass s of every such circuit to all of its tiles at once
+// (one workgroup per tile), so a large circuit spreads over the whole device
+// and small and large ones share each launch.  Each circuit keeps psi and
+// lambda in a slot of its own.  Probes leave one partial per (probe, tile)
+// and the energy one per chunk of amplitudes; fixed-order reductions turn
+// them into the gradient and the energies.
+
+struct BatchLCirc {
+    int32_t circ;            // index in the batch (its energy)
+    int32_t prog;
+    int32_t ntiles;          // tiles of a pass (2^(n - m))
+    int32_t nchunks;         // energy chunks (2^n / kBatchChunk, at least 1)
+    int64_t param_off;       // its parameters and gradient entries
+    int32_t nparams;         // the circuit's parameter count
+    int32_t pad_;
+    int64_t gfirst;          // first gradient wave (prefix of nparams)
+    uint64_t psi_off, lam_off;   // slots in the arena (amplitudes)
+    uint64_t pp_off;         // probe partials, [probe][tile]
+    uint64_t ep_off;         // energy partials, [chunk]
+};
+
+// One circuit's share of a launch: workgroups [first, first + count) take
+// its tiles (or chunks) in order.
+struct BatchWork {
+    int32_t lc;              // layered circuit
+    int32_t pass;            // global pass index (-1: energy)
+    uint32_t first, count;
+};
+
+constexpr int kBatchChunk = 4096;   // amplitudes per energy workgroup
+
+struct BatchStep {
+    // 0 forward layer (init: the first), 1 reverse layer, 2 energies,
+    // 3 gradient reduction; each over the layered circuits [lc_begin, lc_end)
+    int kind;
+    int init;
+    int wbegin, wend;        // works
+    uint32_t wgs;            // workgroups of the launch
+    int lc_begin, lc_end;
+    int64_t gw_begin, gw_end;   // gradient waves (kind 3)
+};
+
+struct BatchLayerDevice {
+    const BatchLCirc *lc;
+    int nlc;
+    const BatchWork *works;
+    const BatchProgram *progs;
+    const BatchPass *passes;
+    const RegStage *stages;
+    const RegOp *rops;
+    const void *pool;
+    const BatchHGroup *hgroups;
+    const BatchHTerm *hterms;
+    const int32_t *probe_row, *probe_idx;
+    const double *params;
+    double *trig;            // (cos, sin) of each parameter's half angle
+    int64_t nparams;
+    double *energies, *grads;
+    void *arena;
+    double *ppart, *epart;
+    int want_grad;
+    std::vector<BatchStep> steps;
+};
+
+// Raises the layered kernels' LDS limits (before any capture).
+hipError_t batch_layer_setup(int dtype);
+hipError_t launch_batch_layered(hipStream_t stream, int dtype, const BatchLayerDevice &d);
 
 }  // namespace qsim

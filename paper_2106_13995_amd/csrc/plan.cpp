@@ -427,9 +427,9 @@ static bool group_tiles(TileBuilder &tb, const std::vector<HostGate> &gates) {
     return true;
 }
 
-int build_tile_plan(Plan &plan, const std::vector<HostGate> &items, int tile_m, int tiles) {
+int build_tile_plan(Plan &plan, const std::vector<HostGate> &items, int tile_m, int tiles, bool reg) {
     const int m = tile_m_for(items, std::min(plan.n, tile_m), plan.n, plan.dtype);
-    TileBuilder tb(plan, plan.n, plan.dtype, m, false);
+    TileBuilder tb(plan, plan.n, plan.dtype, m, reg);
     tb.tiles = tiles;
     plan.items = int(items.size());
     return group_tiles(tb, items) ? m : -1;

@@ -124,14 +124,20 @@ struct RegOp {
     // 5 signed exchange on one register bit (x0, x1) <- (-x1, x0), 6 one
     // factor (pool entry moff) on the amplitudes whose target bits are all
     // 1: register bits rmask, thread bits tb[0] (a mask of thread-id bits),
-    // out-of-tile qubits gp[0] | gp[1] << 32 (a mask of global qubits)
+    // out-of-tile qubits gp[0] | gp[1] << 32 (a mask of global qubits),
+    // 7 one-qubit block on register bit rb[0] under controls (masks as in 6),
+    // 8 batched rotation exp(-i theta G / 2), theta the circuit's parameter
+    // moff, G = X, Y, Z for rj[0] = 1, 2, 3, inverse when jmatch is 1,
+    // 9 batched probe Im <lambda|G|psi> into gradient slot moff (G as in 8);
+    // X and Y act on register bit rb[0], Z on the bit that rmask, tb[0] or
+    // gp[0..1] names
     int32_t type;
     int32_t code;     // kernel dispatch code (set from the fields below by op_code)
     int32_t k;
     int32_t rmask;    // dense: register bits of the targets (ascending = matrix bit order)
     int32_t moff;     // pool offset of the matrix / diagonal (complex entries)
     int32_t nreg, nthr, nout;
-    int32_t jmatch;   // type 2: index of the non-unit diagonal entry
+    int32_t jmatch;   // type 2: index of the non-unit diagonal entry; type 7: 1 when the block is X
     // (32-bit fields throughout: the kernel reads them with scalar loads)
     int32_t rb[QSIM_MAX_K], rj[QSIM_MAX_K];   // targets in register bits: bit, diagonal-index bit
     int32_t tb[QSIM_MAX_K], tj[QSIM_MAX_K];   // targets in thread bits
@@ -248,7 +254,7 @@ int build_adjoint_plan(Plan &plan, const std::vector<HostGate> &items, int tile_
 // LDS-resident tile passes (no register staging) over the given ops; returns
 // the tile width used, or -1 as build_adjoint_plan.
 // `tiles`: state tiles each pass keeps in LDS next to its ops and matrices.
-int build_tile_plan(Plan &plan, const std::vector<HostGate> &items, int tile_m, int tiles = 1);
+int build_tile_plan(Plan &plan, const std::vector<HostGate> &items, int tile_m, int tiles = 1, bool reg = false);
 
 // Fusion: greedy merge into blocks of at most fuse_k qubits.
 std::vector<HostGate> fuse_gates(const std::vector<HostGate> &gates, int fuse_k);

@@ -197,9 +197,13 @@ bool build_reg_program(Plan &plan, Pass &p, uint64_t q, const int *local_of,
     sorted.reserve(gates.size());
     reduced.reserve(gates.size());
     std::vector<LocalGate> gs;
-    for (const HostGate *g : gates) sorted.push_back(sorted_targets(*g));
+    // (rotations formed on the device and gradient probes act on one qubit
+    // and carry no matrix: kept as they are)
+    for (const HostGate *g : gates) sorted.push_back(g->rot_gen || g->probe_gen ? *g : sorted_targets(*g));
     for (const HostGate &s : sorted) {
         LocalGate lg{&s, is_diagonal(s), 0u, 0ull};
+        // Z rotations and Z probes are diagonal: any position will do
+        if (s.rot_gen == 3 || s.probe_gen == 3) lg.diag = true;
         for (int b = 0; b < s.k; ++b) {
             lg.qmask |= 1ull << s.targets[b];
             if ((q >> s.targets[b]) & 1) lg.lmask |= 1u << local_of[s.targets[b]];
@@ -306,6 +310,41 @@ bool build_reg_program(Plan &plan, Pass &p, uint64_t q, const int *local_of,
             const int gi = sg[pos];
             const LocalGate &lg = gs[size_t(gi)];
             const HostGate &s = *lg.g;
+            if (s.rot_gen || s.probe_gen) {
+                // batched circuits: rotation exp(-i theta G / 2) with theta
+                // the circuit's parameter moff (type 8), or the probe
+                // Im <lambda|G|psi> into gradient slot moff (type 9); G = X,
+                // Y, Z for rj[0] = 1, 2, 3; jmatch 1 inverts the rotation.
+                // X and Y act on a register bit, Z on a register, thread or
+                // out-of-tile bit.
+                RegOp op{};
+                op.type = s.rot_gen ? 8 : 9;
+                op.k = 1;
+                op.moff = s.rot_gen ? s.rot_param : s.probe_slot;
+                op.rj[0] = s.rot_gen ? s.rot_gen : s.probe_gen;
+                op.jmatch = s.rot_inv;
+                const int t = s.targets[0];
+                if ((q >> t) & 1) {
+                    const int lp = local_of[t];
+                    const int ri = index_in(Rp, r, lp);
+                    if (ri >= 0) {
+                        op.rb[0] = ri;
+                        op.rmask = 1 << ri;
+                        op.nreg = 1;
+                    } else {
+                        op.tb[0] = int32_t(1u << index_in(Tp, 8, lp));
+                        op.nthr = 1;
+                    }
+                } else {
+                    op.gp[0] = int32_t(uint32_t(1ull << t));
+                    op.gp[1] = int32_t(uint32_t((1ull << t) >> 32));
+                    op.nout = 1;
+                }
+                if (op.rj[0] != 3 && op.nreg != 1) return false;
+                if (op.nreg) touched |= uint32_t(op.rmask);
+                sops.push_back(op);
+                continue;
+            }
             if (!lg.diag && s.rot_real) {
                 const int ri = index_in(Rp, r, local_of[s.targets[0]]);
                 if (s.phase_in != cd(1.0) && !phase_done[pos]) {
@@ -380,6 +419,9 @@ bool build_reg_program(Plan &plan, Pass &p, uint64_t q, const int *local_of,
                 op.type = 7;
                 op.k = 1;
                 op.rb[0] = index_in(Rp, r, local_of[lg.red->targets[0]]);
+                // jmatch 1: the block is X, an exchange without arithmetic
+                const std::vector<cd> &B = lg.red->M;
+                op.jmatch = B[0] == cd(0.0) && B[1] == cd(1.0) && B[2] == cd(1.0) && B[3] == cd(0.0);
                 op.moff = pool_off();
                 plan.tile_pool.insert(plan.tile_pool.end(), lg.red->M.begin(), lg.red->M.end());
                 uint32_t tmask = 0;
@@ -485,7 +527,9 @@ bool build_reg_program(Plan &plan, Pass &p, uint64_t q, const int *local_of,
             case 5: op.code = 72 + op.rb[0]; break;
             case 6: op.code = 128 + op.rmask; break;
             case 4: op.code = 200; break;
-            case 7: op.code = 210 + op.rb[0]; break;
+            case 7: op.code = (op.jmatch ? 160 : 210) + op.rb[0]; break;
+            case 8: op.code = op.rj[0] == 3 ? 236 : (op.rj[0] == 1 ? 220 : 228) + op.rb[0]; break;
+            case 9: op.code = op.rj[0] == 3 ? 256 : (op.rj[0] == 1 ? 240 : 248) + op.rb[0]; break;
             default: op.code = 201; break;
         }
     }
