@@ -67,67 +67,6 @@ __device__ __forceinline__ uint64_t layer_tile_base(CBatchPass &ps, uint32_t t) 
     return base;
 }
 
-// Rotation exp(-i theta G / 2) on register bit B (G = X for GEN 1, Y for
-// GEN 2) with c = cos(theta / 2), s = sin(theta / 2).
-template <typename T, int RA, int B, int GEN>
-__device__ __forceinline__ void brot_bit(T *vr, T *vi, T c, T s) {
-#pragma unroll
-    for (int g = 0; g < (1 << RA); ++g) {
-        if (g & (1 << B)) continue;
-        const int h = g | (1 << B);
-        const T x0r = vr[g], x0i = vi[g], x1r = vr[h], x1i = vi[h];
-        if constexpr (GEN == 1) {   // [[c, -is], [-is, c]]
-            vr[g] = fma(c, x0r, s * x1i);
-            vi[g] = fma(c, x0i, -s * x1r);
-            vr[h] = fma(c, x1r, s * x0i);
-            vi[h] = fma(c, x1i, -s * x0r);
-        } else {                    // [[c, -s], [s, c]]
-            vr[g] = fma(c, x0r, -s * x1r);
-            vi[g] = fma(c, x0i, -s * x1i);
-            vr[h] = fma(c, x1r, s * x0r);
-            vi[h] = fma(c, x1i, s * x0i);
-        }
-    }
-}
-
-// Whether the one bit an op names outside the registers (a thread bit in
-// tb[0] or an out-of-tile qubit in gp) is 1 for this thread and tile.
-__device__ __forceinline__ bool outer_bit(CRegOp &op, uint64_t base, uint32_t t) {
-    const uint64_t gmask = uint64_t(uint32_t(op.gp[0])) | (uint64_t(uint32_t(op.gp[1])) << 32);
-    return ((base & gmask) != 0) || ((t & uint32_t(op.tb[0])) != 0u);
-}
-
-// exp(-i theta Z / 2) = diag(c - is, c + is) on the bit the op names: a
-// register bit (rmask), a thread bit or an out-of-tile bit.
-template <typename T, int RA>
-__device__ __forceinline__ void brot_z(T *vr, T *vi, CRegOp &op, T c, T s, uint64_t base, uint32_t t) {
-    const bool up = outer_bit(op, base, t);
-    const int rm = op.rmask;
-#pragma unroll
-    for (int i = 0; i < (1 << RA); ++i) {
-        const bool one = up || ((i & rm) != 0);
-        const T sg = one ? s : -s;
-        const T xr = vr[i], xi = vi[i];
-        vr[i] = fma(c, xr, -sg * xi);
-        vi[i] = fma(c, xi, sg * xr);
-    }
-}
-
-template <typename T, int R, int RA, int B>
-__device__ __forceinline__ void brot_dispatch(int code, T *vr, T *vi, T c, T s) {
-    if constexpr (B < R) {
-        if (code == 220 + B) {
-            brot_bit<T, RA, B, 1>(vr, vi, c, s);
-            return;
-        }
-        if (code == 228 + B) {
-            brot_bit<T, RA, B, 2>(vr, vi, c, s);
-            return;
-        }
-        brot_dispatch<T, R, RA, B + 1>(code, vr, vi, c, s);
-    }
-}
-
 // Probe Im <lambda|G|psi> over the thread's amplitudes (psi at [0, 2^R),
 // lambda at [2^R, 2^(R+1))), G = X (GEN 1) or Y (GEN 2) on register bit B:
 // each pair's terms in the state precision, the pairs summed in double.
@@ -277,16 +216,11 @@ __global__ void __launch_bounds__(kLayerThreads) k_batch_layer(const LayerArgs<T
         for (int o = st.op_begin; o < st.op_end; ++o) {
             CRegOp &op = sop[o];
             const int code = op.code;
-            if (code < 220) {
-                run_op<T, R, 0, RA>(code, vr, vi, op, spool + 2 * op.moff, base, t);
-            } else if (code <= 236) {
-                const T cs = T(trig[2 * op.moff]);
-                const T sn = op.jmatch ? T(-trig[2 * op.moff + 1]) : T(trig[2 * op.moff + 1]);
-                if (code == 236)
-                    brot_z<T, RA>(vr, vi, op, cs, sn, base, t);
-                else
-                    brot_dispatch<T, R, RA, 0>(code, vr, vi, cs, sn);
-            } else if constexpr (BOTH) {
+            if (code < 240) {
+                run_op<T, R, 0, RA, true>(code, vr, vi, op, spool + 2 * op.moff, base, t, trig);
+            } else if constexpr (!BOTH) {
+                __builtin_unreachable();   // forward passes hold no probes
+            } else {
                 double v = code == 256 ? bprobe_z<T, R>(vr, vi, op, base, t) : bprobe_dispatch<T, R, 0>(code, vr, vi);
                 for (int sft = 32; sft > 0; sft >>= 1) v += __shfl_xor(v, sft, 64);
                 if (t % 64 == 0) probe[np][t / 64] = v;

@@ -284,8 +284,6 @@ __device__ __forceinline__ void controlled_bit(T *vr, T *vi, CRegOp &op, CT<T> *
     }
 }
 
-// Op `code` (valid for R register bits) on an amplitude array of RA >= R
-// register bits.
 // X on register bit B under controls (masks as controlled_bit): the pair
 // is exchanged where every control is 1 (selects only).
 template <typename T, int R, int B>
@@ -307,12 +305,125 @@ __device__ __forceinline__ void controlled_x_bit(T *vr, T *vi, CRegOp &op, uint6
     }
 }
 
-template <typename T, int R, int C, int RA = R>
-__device__ __forceinline__ void run_op(int code, T *vr, T *vi, CRegOp &op, CT<T> *U, uint64_t base, uint32_t t) {
-    if constexpr (C <= 217) {
-        if constexpr (code_valid<C, R>()) {
+// Plane rotation [[c, -s], [s, c]] of (a, b) as three lifting steps, each
+// one multiply-add in place: for c >= 0, with P = -s / (1 + c),
+//   a += P b;  b += s a;  a += P b;
+// for c < 0 it is minus the rotation by (-c, -s), with P = s / (1 - c),
+//   a += P b;  b = s a - b;  a = P b - a
+// (|P| <= 1 either way).  `neg` selects the second form.
+template <typename T>
+__device__ __forceinline__ void lift3(T &a, T &b, T P, T s, bool neg) {
+    if (!neg) {
+        a = fma(P, b, a);
+        b = fma(s, a, b);
+        a = fma(P, b, a);
+    } else {
+        a = fma(P, b, a);
+        b = fma(s, a, -b);
+        a = fma(P, b, -a);
+    }
+}
+
+// Rotation exp(-i theta G / 2) on register bit B (G = X for GEN 1, Y for
+// GEN 2) given c = cos(theta / 2), s = sin(theta / 2):
+//   Y: [[c, -s], [s, c]] on the real parts and on the imaginary parts;
+//   X: [[c, -is], [-is, c]] is [[c, s], [-s, c]] on (re x0, im x1) and
+//      [[c, -s], [s, c]] on (im x0, re x1).
+template <typename T, int RA, int B, int GEN, bool NEG>
+__device__ __forceinline__ void brot_bit_lift(T *vr, T *vi, T Pp, T sp, T Pm, T sm) {
+#pragma unroll
+    for (int g = 0; g < (1 << RA); ++g) {
+        if (g & (1 << B)) continue;
+        const int h = g | (1 << B);
+        if constexpr (GEN == 2) {
+            lift3(vr[g], vr[h], Pp, sp, NEG);
+            lift3(vi[g], vi[h], Pp, sp, NEG);
+        } else {
+            lift3(vr[g], vi[h], Pm, sm, NEG);
+            lift3(vi[g], vr[h], Pp, sp, NEG);
+        }
+    }
+}
+
+template <typename T, int RA, int B, int GEN>
+__device__ __forceinline__ void brot_bit(T *vr, T *vi, double c, double s) {
+    const bool neg = c < 0.0;
+    // multipliers for +s and for -s
+    const T Pp = T(neg ? s / (1.0 - c) : -s / (1.0 + c)), sp = T(s);
+    const T Pm = -Pp, sm = -sp;
+    if (neg)
+        brot_bit_lift<T, RA, B, GEN, true>(vr, vi, Pp, sp, Pm, sm);
+    else
+        brot_bit_lift<T, RA, B, GEN, false>(vr, vi, Pp, sp, Pm, sm);
+}
+
+// Whether the one bit an op names outside the registers (a thread bit in
+// tb[0] or an out-of-tile qubit in gp) is 1 for this thread and tile.
+__device__ __forceinline__ bool outer_bit(CRegOp &op, uint64_t base, uint32_t t) {
+    const uint64_t gmask = uint64_t(uint32_t(op.gp[0])) | (uint64_t(uint32_t(op.gp[1])) << 32);
+    return ((base & gmask) != 0) || ((t & uint32_t(op.tb[0])) != 0u);
+}
+
+// exp(-i theta Z / 2) = diag(c - is, c + is) on the bit the op names: a
+// register bit (rmask), a thread bit or an out-of-tile bit.  Amplitude
+// (re, im) turns by [[c, -s'], [s', c]] with s' = s where the bit is 1 and
+// -s where it is 0.
+template <typename T, int RA, bool NEG>
+__device__ __forceinline__ void brot_z_lift(T *vr, T *vi, CRegOp &op, T Pp, T sp, uint64_t base, uint32_t t) {
+    const int rm = op.rmask;
+    if (rm) {
+#pragma unroll
+        for (int i = 0; i < (1 << RA); ++i) {
+            const bool one = (i & rm) != 0;
+            lift3(vr[i], vi[i], one ? Pp : -Pp, one ? sp : -sp, NEG);
+        }
+    } else {
+        const bool up = outer_bit(op, base, t);
+        const T P = up ? Pp : -Pp, s = up ? sp : -sp;
+#pragma unroll
+        for (int i = 0; i < (1 << RA); ++i) lift3(vr[i], vi[i], P, s, NEG);
+    }
+}
+
+template <typename T, int RA>
+__device__ __forceinline__ void brot_z(T *vr, T *vi, CRegOp &op, double c, double s, uint64_t base, uint32_t t) {
+    const bool neg = c < 0.0;
+    const T Pp = T(neg ? s / (1.0 - c) : -s / (1.0 + c)), sp = T(s);
+    if (neg)
+        brot_z_lift<T, RA, true>(vr, vi, op, Pp, sp, base, t);
+    else
+        brot_z_lift<T, RA, false>(vr, vi, op, Pp, sp, base, t);
+}
+
+// Batched-circuit codes: rotation exp(-i theta G / 2) with (cos, sin) of the
+// half angle from trig[2 * moff] (negated sine when jmatch is 1): X on bit b
+// -> 220 + b, Y on bit b -> 228 + b, Z anywhere -> 236.
+template <int C, int R>
+__host__ __device__ constexpr bool ext_code_valid() {
+    if (C >= 220 && C < 228) return C - 220 < R;
+    if (C >= 228 && C < 236) return C - 228 < R;
+    return C == 236;
+}
+
+// Op `code` (valid for R register bits) on an amplitude array of RA >= R
+// register bits; with EXT, the batched-circuit codes too (trig: the
+// circuit's half-angle table).  One flat compare chain on the uniform code.
+template <typename T, int R, int C, int RA = R, bool EXT = false>
+__device__ __forceinline__ void run_op(int code, T *vr, T *vi, CRegOp &op, CT<T> *U, uint64_t base, uint32_t t,
+                                       const QSIM_CONST double *trig = nullptr) {
+    if constexpr (C <= (EXT ? 236 : 217)) {
+        if constexpr (code_valid<C, R>() || (EXT && ext_code_valid<C, R>())) {
             if (code == C) {
-                if constexpr (C < 32) {
+                if constexpr (C >= 220) {
+                    const double cs = trig[2 * op.moff];
+                    const double sn = op.jmatch ? -trig[2 * op.moff + 1] : trig[2 * op.moff + 1];
+                    if constexpr (C < 228)
+                        brot_bit<T, RA, C - 220, 1>(vr, vi, cs, sn);
+                    else if constexpr (C < 236)
+                        brot_bit<T, RA, C - 228, 2>(vr, vi, cs, sn);
+                    else
+                        brot_z<T, RA>(vr, vi, op, cs, sn, base, t);
+                } else if constexpr (C < 32) {
                     if constexpr (RA > R && popcount_c(C) >= 3) {
                         // row by row keeps all outputs aside: one copy at a time
 #pragma unroll
@@ -350,16 +461,24 @@ __device__ __forceinline__ void run_op(int code, T *vr, T *vi, CRegOp &op, CT<T>
                 return;
             }
         }
-        run_op<T, R, C + 1, RA>(code, vr, vi, op, U, base, t);
+        run_op<T, R, C + 1, RA, EXT>(code, vr, vi, op, U, base, t, trig);
+    } else {
+        // the host emits valid codes only; telling the compiler so keeps the
+        // amplitudes from being carried through a no-op path
+        __builtin_unreachable();
     }
 }
 
+// LDS address part of thread t: the XOR of vec[b] over its set bits (the
+// eight entries read first, then combined without branches).
 template <typename T>
 __device__ __forceinline__ uint32_t thread_part(uint32_t t, const QSIM_CONST uint32_t *vec) {
+    uint32_t v[8];
+#pragma unroll
+    for (int b = 0; b < 8; ++b) v[b] = vec[b];
     uint32_t a = 0;
 #pragma unroll
-    for (int b = 0; b < 8; ++b)
-        if ((t >> b) & 1u) a ^= vec[b];
+    for (int b = 0; b < 8; ++b) a ^= (0u - ((t >> b) & 1u)) & v[b];
     return a;
 }
 
