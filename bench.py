@@ -286,16 +286,10 @@ def batch_bench(torch, q, W, dtype: str = "c64", reps: int = 3, loop_sample: int
         b.run_device(p_dev, e_dev, g_dev)
     torch.cuda.synchronize()
     t_batch = (time.perf_counter() - t0) / reps
-    # LDS traffic of the kernel's op-by-op tile updates (each op reads and
-    # writes its state's tile once; the reverse sweep does it for psi and
-    # lambda and each probe reads both): the bound of a persistent kernel
-    # that applies one op per barrier
-    amp = 8 if dtype == "c64" else 16
-    lds_bytes = 0.0
-    for c in circs:
-        nops, nprobe = len(c.ops), c.nparams
-        lds_bytes += (2.0 * nops + 2.0 * 2.0 * nops + 2.0 * nprobe) * (1 << c.n) * amp
-    lds_peak = 256 * 128 * 2.4e9 / 1e9
+    # device-memory bytes of the layered passes (each pass moves every tile
+    # of its circuits in and out once; psi and lambda in reverse passes)
+    pass_bytes = b.pass_bytes()
+    layered, persistent = b.layout()
     grid, programs, _ = b.info()
     b.close()
     offs = np.concatenate([[0], np.cumsum([c.nparams for c in circs])])
@@ -319,11 +313,12 @@ def batch_bench(torch, q, W, dtype: str = "c64", reps: int = 3, loop_sample: int
     return {"workload": f"{len(circs)} ansatz circuits, 10-20 qubits, 4-12 layers, {int(offs[-1])} parameters, "
                         f"{dtype}, forward + adjoint gradient",
             "circuits_per_s": round(len(circs) / t_batch, 1), "ms_per_batch": round(t_batch * 1e3, 2),
+            "layered_circuits": layered, "persistent_circuits": persistent,
             "persistent_workgroups": grid, "programs": programs,
-            "lds_bytes_per_batch": lds_bytes, "lds_gbs": round(lds_bytes / t_batch / 1e9, 1),
-            "roofline": {"bound": "lds", "achieved": round(lds_bytes / t_batch / 1e9, 1), "peak": round(lds_peak, 1),
-                         "unit": "GB/s", "frac": round(lds_bytes / t_batch / 1e9 / lds_peak, 4),
-                         "note": "256 CUs x 128 B/clock x 2.4 GHz of LDS bandwidth"},
+            "pass_bytes_per_batch": pass_bytes,
+            "roofline": {"bound": "hbm", "achieved": round(pass_bytes / t_batch / 1e9, 1), "peak": HBM_PEAK_GBS,
+                         "unit": "GB/s", "frac": round(pass_bytes / t_batch / 1e9 / HBM_PEAK_GBS, 4),
+                         "note": "bytes of the layered tile passes over the whole batch time"},
             "loop_ms_same_gpu": round(t_loop * 1e3, 1), "speedup_vs_loop": round(t_loop / t_batch, 1),
             "loop_sample": len(sample)}
 

@@ -287,8 +287,11 @@ qsim_status qsim_adjoint_grad(qsim_state s, const qsim_circuit *c, const double 
  * serialised on one stream.  qsim_batch_info reports the persistent grid
  * size, the number of distinct programs and the widest circuit;
  * qsim_batch_layout how many circuits run layered and how many in the
- * persistent kernel; qsim_batch_free waits for the batch's work and releases
- * it. */
+ * persistent kernel, and the device-memory bytes one run's layered passes
+ * read and write (every tile in and out once per pass: psi in forward
+ * passes, psi and lambda in reverse passes, plus psi read and lambda written
+ * for the energies; any pointer may be NULL); qsim_batch_free waits for the
+ * batch's work and releases it. */
 typedef struct qsim_batch_s *qsim_batch;
 
 qsim_status qsim_batch_create(int ncirc, const qsim_circuit *circs, const int64_t *param_offsets,
@@ -297,7 +300,7 @@ qsim_status qsim_batch_create(int ncirc, const qsim_circuit *circs, const int64_
 qsim_status qsim_batch_run(qsim_batch b, const double *params_dev, double *energies_dev, double *grads_dev,
                            void *hip_stream);
 qsim_status qsim_batch_info(qsim_batch b, int *grid, int *programs, int *max_n);
-qsim_status qsim_batch_layout(qsim_batch b, int *layered, int *persistent);
+qsim_status qsim_batch_layout(qsim_batch b, int *layered, int *persistent, double *pass_bytes);
 qsim_status qsim_batch_free(qsim_batch b);
 
 /* Autotuner (Sec. IV: the paper leaves kernel-level tuning to future work):

@@ -129,7 +129,7 @@ def _load() -> ctypes.CDLL:
                                i32, i32, ctypes.POINTER(QsimOptions), ctypes.POINTER(P)], S),
         "qsim_batch_run": ([P, P, P, P, P], S),
         "qsim_batch_info": ([P, ctypes.POINTER(i32), ctypes.POINTER(i32), ctypes.POINTER(i32)], S),
-        "qsim_batch_layout": ([P, ctypes.POINTER(i32), ctypes.POINTER(i32)], S),
+        "qsim_batch_layout": ([P, ctypes.POINTER(i32), ctypes.POINTER(i32), ctypes.POINTER(ctypes.c_double)], S),
         "qsim_batch_free": ([P], S),
         "qsim_autotune": ([P, ctypes.POINTER(QsimCircuit), ctypes.POINTER(ctypes.c_double), i64, i32,
                            ctypes.POINTER(QsimOptions), ctypes.POINTER(ctypes.c_double)], S),
@@ -444,8 +444,14 @@ class Batch:
     def layout(self) -> Tuple[int, int]:
         """(circuits run layered, circuits run in the persistent kernel)."""
         lay, per = ctypes.c_int(), ctypes.c_int()
-        _check(_lib.qsim_batch_layout(ctypes.c_void_p(self.handle), ctypes.byref(lay), ctypes.byref(per)))
+        _check(_lib.qsim_batch_layout(ctypes.c_void_p(self.handle), ctypes.byref(lay), ctypes.byref(per), None))
         return lay.value, per.value
+
+    def pass_bytes(self) -> float:
+        """Device-memory bytes one run's layered passes read and write."""
+        v = ctypes.c_double()
+        _check(_lib.qsim_batch_layout(ctypes.c_void_p(self.handle), None, None, ctypes.byref(v)))
+        return v.value
 
     def run_device(self, params, energies=None, grads=None):
         """Queues one batch run on torch's current stream: `params` is a

@@ -30,6 +30,7 @@ struct qsim_batch_s {
     void *arena = nullptr;        // per-workgroup psi / lambda slots (persistent kernel)
     void *larena = nullptr;       // per-circuit psi / lambda slots (layered circuits)
     int nlayered = 0;
+    double pass_bytes = 0;        // device-memory bytes of one run's layered passes
     double *d_params = nullptr, *d_energy = nullptr, *d_grads = nullptr;   // inside dev
     hipStream_t last_stream = nullptr;   // stream of the last run
     bool ran = false;
@@ -253,8 +254,9 @@ qsim_status qsim_batch_create(int ncirc, const qsim_circuit *circs, const int64_
                     for (int o = p.rop_begin; o < p.rop_end; ++o) {
                         RegOp r = plan.reg_ops[size_t(o)];
                         // rotations and probes name a parameter, not a pool
-                        // entry; a probe's jmatch is its index in the sweep
-                        if (r.type == 9)
+                        // entry; a probe's jmatch becomes its index in the
+                        // sweep (a fused probe's rotation is the inverse)
+                        if (r.type == 9 || r.type == 10)
                             r.jmatch = bp.nprobes++;
                         else if (r.type != 8)
                             r.moff += pool_base + p.pool_begin;
@@ -296,7 +298,8 @@ qsim_status qsim_batch_create(int ncirc, const qsim_circuit *circs, const int64_
             for (int pi2 = bp.rev_begin; pi2 < bp.rev_end; ++pi2)
                 for (int si = passes[size_t(pi2)].stage_begin; si < passes[size_t(pi2)].stage_end; ++si)
                     for (int o = stages[size_t(si)].op_begin; o < stages[size_t(si)].op_end; ++o)
-                        if (rops[size_t(o)].type == 9) of[size_t(rops[size_t(o)].moff)].push_back(rops[size_t(o)].jmatch);
+                        if (rops[size_t(o)].type == 9 || rops[size_t(o)].type == 10)
+                            of[size_t(rops[size_t(o)].moff)].push_back(rops[size_t(o)].jmatch);
             int32_t at = int32_t(probe_idx.size());
             for (int64_t j = 0; j < np; ++j) {
                 probe_row.push_back(at);
@@ -453,6 +456,21 @@ qsim_status qsim_batch_create(int ncirc, const qsim_circuit *circs, const int64_
             steps.push_back(gr);
         }
         g0 = g1;
+    }
+
+    // bytes the layered passes move per run: tiles in and out per pass
+    // (twice in reverse passes: psi and lambda); the energies read psi and
+    // write lambda
+    for (const BatchStep &st : steps) {
+        const double tile = double(s) * std::ldexp(1.0, batch_tile_max(dtype));
+        if (st.kind == 0) b->pass_bytes += 2.0 * tile * st.wgs;
+        if (st.kind == 1) b->pass_bytes += 4.0 * tile * st.wgs;
+        if (st.kind == 2)
+            for (int w = st.wbegin; w < st.wend; ++w) {
+                const BatchLCirc &l = lcircs[size_t(works[size_t(w)].lc)];
+                b->pass_bytes += (b->want_grad ? 2.0 : 1.0) * double(s) *
+                                 std::ldexp(1.0, progs[size_t(l.prog)].n);
+            }
     }
 
     // device layout
@@ -635,10 +653,11 @@ qsim_status qsim_batch_info(qsim_batch b, int *grid, int *programs, int *max_n) 
     return QSIM_OK;
 }
 
-qsim_status qsim_batch_layout(qsim_batch b, int *layered, int *persistent) {
+qsim_status qsim_batch_layout(qsim_batch b, int *layered, int *persistent, double *pass_bytes) {
     if (!b) return fail(QSIM_ERR_ARG, "batch handle is NULL");
     if (layered) *layered = b->nlayered;
     if (persistent) *persistent = b->ncirc - b->nlayered;
+    if (pass_bytes) *pass_bytes = b->pass_bytes;
     return QSIM_OK;
 }
 

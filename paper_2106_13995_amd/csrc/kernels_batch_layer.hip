@@ -67,6 +67,22 @@ __device__ __forceinline__ uint64_t layer_tile_base(CBatchPass &ps, uint32_t t) 
     return base;
 }
 
+// X / Y rotation on the register bit of code 220 + b / 228 + b.
+template <typename T, int R, int RA, int B>
+__device__ __forceinline__ void brot_dispatch(int code, T *vr, T *vi, double c, double s) {
+    if constexpr (B < R) {
+        if (code == 220 + B) {
+            brot_bit<T, RA, B, 1>(vr, vi, c, s);
+            return;
+        }
+        if (code == 228 + B) {
+            brot_bit<T, RA, B, 2>(vr, vi, c, s);
+            return;
+        }
+        brot_dispatch<T, R, RA, B + 1>(code, vr, vi, c, s);
+    }
+}
+
 // Probe Im <lambda|G|psi> over the thread's amplitudes (psi at [0, 2^R),
 // lambda at [2^R, 2^(R+1))), G = X (GEN 1) or Y (GEN 2) on register bit B:
 // each pair's terms in the state precision, the pairs summed in double.
@@ -221,7 +237,16 @@ __global__ void __launch_bounds__(kLayerThreads) k_batch_layer(const LayerArgs<T
             } else if constexpr (!BOTH) {
                 __builtin_unreachable();   // forward passes hold no probes
             } else {
-                double v = code == 256 ? bprobe_z<T, R>(vr, vi, op, base, t) : bprobe_dispatch<T, R, 0>(code, vr, vi);
+                // probe (240 + ..), or probe and inverse rotation (264 + ..)
+                const int pc = code >= 264 ? code - 24 : code;
+                double v = pc == 256 ? bprobe_z<T, R>(vr, vi, op, base, t) : bprobe_dispatch<T, R, 0>(pc, vr, vi);
+                if (code >= 264) {
+                    const double cs = trig[2 * op.moff], sn = -trig[2 * op.moff + 1];
+                    if (pc == 256)
+                        brot_z<T, RA>(vr, vi, op, cs, sn, base, t);
+                    else
+                        brot_dispatch<T, R, RA, 0>(pc - 20, vr, vi, cs, sn);
+                }
                 for (int sft = 32; sft > 0; sft >>= 1) v += __shfl_xor(v, sft, 64);
                 if (t % 64 == 0) probe[np][t / 64] = v;
                 if (t == 0) probe_k[np] = op.jmatch;

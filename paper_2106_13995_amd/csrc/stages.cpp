@@ -513,6 +513,29 @@ bool build_reg_program(Plan &plan, Pass &p, uint64_t q, const int *local_of,
             plan.tile_pool.insert(plan.tile_pool.end(), table.begin(), table.end());
             plan.reg_ops.push_back(t);
         }
+        // a probe followed by the inverse rotation it belongs to (same
+        // generator, parameter and bit) becomes one op: one pass over the
+        // registers, one dispatch
+        {
+            std::vector<RegOp> fused;
+            for (size_t i = 0; i < sops.size(); ++i) {
+                const RegOp &a = sops[i];
+                if (a.type == 9 && i + 1 < sops.size()) {
+                    const RegOp &b = sops[i + 1];
+                    if (b.type == 8 && b.jmatch == 1 && b.moff == a.moff && b.rj[0] == a.rj[0] &&
+                        b.rmask == a.rmask && b.rb[0] == a.rb[0] && b.tb[0] == a.tb[0] && b.gp[0] == a.gp[0] &&
+                        b.gp[1] == a.gp[1]) {
+                        RegOp f = a;
+                        f.type = 10;
+                        fused.push_back(f);
+                        ++i;
+                        continue;
+                    }
+                }
+                fused.push_back(a);
+            }
+            sops.swap(fused);
+        }
         plan.reg_ops.insert(plan.reg_ops.end(), sops.begin(), sops.end());
         st.op_end = int(plan.reg_ops.size()) - p.rop_begin;
         plan.reg_stages.push_back(st);
@@ -530,6 +553,7 @@ bool build_reg_program(Plan &plan, Pass &p, uint64_t q, const int *local_of,
             case 7: op.code = (op.jmatch ? 160 : 210) + op.rb[0]; break;
             case 8: op.code = op.rj[0] == 3 ? 236 : (op.rj[0] == 1 ? 220 : 228) + op.rb[0]; break;
             case 9: op.code = op.rj[0] == 3 ? 256 : (op.rj[0] == 1 ? 240 : 248) + op.rb[0]; break;
+            case 10: op.code = op.rj[0] == 3 ? 280 : (op.rj[0] == 1 ? 264 : 272) + op.rb[0]; break;
             default: op.code = 201; break;
         }
     }
