@@ -478,13 +478,13 @@ def calib_copy(torch, n: int, dtype: str):
 
 
 def batch_circuit(q, W, n, layers, dtype):
-    """One ansatz circuit alone in the batched kernel: a single workgroup runs
-    it, so this is the time that bounds a batch holding it."""
+    """One ansatz circuit alone through the batched path (layered launches
+    when it fills whole tiles, else one workgroup of the persistent kernel)."""
     c = W.ansatz_circuit(n, layers)
     H = W.chain_observable(n)
     p = W.ansatz_params(n, layers, seed=7)
     out = {"workload": f"one ansatz circuit, {n} qubits, {layers} layers, {c.nparams} parameters, {dtype}, "
-                       "batched persistent kernel"}
+                       "batched run (layered when it fills whole tiles)"}
     for grad, key in ((False, "forward_ms"), (True, "forward_gradient_ms")):
         b = q.Batch([c], [H], dtype, want_grad=grad)
         b.run(p)
