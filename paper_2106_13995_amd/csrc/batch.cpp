@@ -499,7 +499,7 @@ qsim_status qsim_batch_create(int ncirc, const qsim_circuit *circs, const int64_
     const size_t o_energy = place(sizeof(double) * size_t(ncirc));
     const size_t o_grads = place(sizeof(double) * size_t(b->nparams));
     const size_t o_counter = place(sizeof(int));
-    const size_t o_trig = place(2 * sizeof(double) * size_t(b->nparams));
+    const size_t o_trig = place(4 * sizeof(double) * size_t(b->nparams));
     const size_t o_ppart = place(sizeof(double) * size_t(pp_total));
     const size_t o_epart = place(sizeof(double) * size_t(ep_total));
     b->dev_bytes = off;

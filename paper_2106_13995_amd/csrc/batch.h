@@ -140,7 +140,7 @@ struct BatchLayerDevice {
     const BatchHTerm *hterms;
     const int32_t *probe_row, *probe_idx;
     const double *params;
-    double *trig;            // (cos, sin) of each parameter's half angle
+    double *trig;            // lifting form (P, s, c, 0) of each parameter's rotation
     int64_t nparams;
     double *energies, *grads;
     void *arena;

@@ -7,8 +7,8 @@
 // its register bits and the tile is re-laid out through LDS between stages.
 // In the reverse sweep a thread holds psi and lambda side by side (register
 // bit R selects lambda), so every op applies to both alike and the probes
-// Im <lambda|G|psi> read the two halves.  Rotations take cos and sin of
-// their half angle from a table formed once per run; probes leave one
+// Im <lambda|G|psi> read the two halves.  Rotations read their lifting
+// multiplier and sine from a table formed once per run; probes leave one
 // partial per (probe, tile), the energy one per chunk, and fixed-order
 // reductions give the gradient and the energies (bitwise reproducible).
 #include <hip/hip_runtime.h>
@@ -69,17 +69,17 @@ __device__ __forceinline__ uint64_t layer_tile_base(CBatchPass &ps, uint32_t t) 
 
 // X / Y rotation on the register bit of code 220 + b / 228 + b.
 template <typename T, int R, int RA, int B>
-__device__ __forceinline__ void brot_dispatch(int code, T *vr, T *vi, double c, double s) {
+__device__ __forceinline__ void brot_dispatch(int code, T *vr, T *vi, double P, double s, bool neg) {
     if constexpr (B < R) {
         if (code == 220 + B) {
-            brot_bit<T, RA, B, 1>(vr, vi, c, s);
+            brot_bit<T, RA, B, 1>(vr, vi, P, s, neg);
             return;
         }
         if (code == 228 + B) {
-            brot_bit<T, RA, B, 2>(vr, vi, c, s);
+            brot_bit<T, RA, B, 2>(vr, vi, P, s, neg);
             return;
         }
-        brot_dispatch<T, R, RA, B + 1>(code, vr, vi, c, s);
+        brot_dispatch<T, R, RA, B + 1>(code, vr, vi, P, s, neg);
     }
 }
 
@@ -168,7 +168,7 @@ __global__ void __launch_bounds__(kLayerThreads) k_batch_layer(const LayerArgs<T
     CRegStage *sst = (CRegStage *)(a.stages);
     CRegOp *sop = (CRegOp *)(a.rops);
     CT<T> *spool = (CT<T> *)(a.pool);
-    const QSIM_CONST double *trig = (const QSIM_CONST double *)(a.trig) + 2 * c.param_off;
+    const QSIM_CONST double *trig = (const QSIM_CONST double *)(a.trig) + 4 * c.param_off;
     c2_t<T> *psi = a.arena + c.psi_off;
     c2_t<T> *lam = a.arena + c.lam_off;
     const uint64_t base = layer_tile_base(ps, tile);
@@ -241,11 +241,13 @@ __global__ void __launch_bounds__(kLayerThreads) k_batch_layer(const LayerArgs<T
                 const int pc = code >= 264 ? code - 24 : code;
                 double v = pc == 256 ? bprobe_z<T, R>(vr, vi, op, base, t) : bprobe_dispatch<T, R, 0>(pc, vr, vi);
                 if (code >= 264) {
-                    const double cs = trig[2 * op.moff], sn = -trig[2 * op.moff + 1];
+                    // the inverse rotation: P and s negated
+                    const double P = -trig[4 * op.moff], sn = -trig[4 * op.moff + 1];
+                    const bool neg = trig[4 * op.moff + 2] < 0.0;
                     if (pc == 256)
-                        brot_z<T, RA>(vr, vi, op, cs, sn, base, t);
+                        brot_z<T, RA>(vr, vi, op, P, sn, neg, base, t);
                     else
-                        brot_dispatch<T, R, RA, 0>(pc - 20, vr, vi, cs, sn);
+                        brot_dispatch<T, R, RA, 0>(pc - 20, vr, vi, P, sn, neg);
                 }
                 for (int sft = 32; sft > 0; sft >>= 1) v += __shfl_xor(v, sft, 64);
                 if (t % 64 == 0) probe[np][t / 64] = v;
@@ -289,14 +291,18 @@ __global__ void __launch_bounds__(kLayerThreads) k_batch_layer(const LayerArgs<T
     }
 }
 
-// cos and sin of half of every parameter.
+// Lifting form of every parameter's rotation: with c, s the cosine and
+// sine of half its angle, (P, s, c, 0) where P = -s / (1 + c) for c >= 0 and
+// s / (1 - c) otherwise (the forms lift3 takes).
 __global__ void k_batch_trig(const double *params, double *trig, int64_t n) {
     const int64_t j = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
     if (j < n) {
         double s, c;
         sincos(0.5 * params[j], &s, &c);
-        trig[2 * j] = c;
-        trig[2 * j + 1] = s;
+        trig[4 * j] = c >= 0.0 ? -s / (1.0 + c) : s / (1.0 - c);
+        trig[4 * j + 1] = s;
+        trig[4 * j + 2] = c;
+        trig[4 * j + 3] = 0.0;
     }
 }
 

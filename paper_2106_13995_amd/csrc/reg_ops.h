@@ -345,12 +345,11 @@ __device__ __forceinline__ void brot_bit_lift(T *vr, T *vi, T Pp, T sp, T Pm, T 
     }
 }
 
+// The rotation's lifting multiplier P (as lift3: -s / (1 + c), or
+// s / (1 - c) with `neg` when c < 0) and its sine, in double.
 template <typename T, int RA, int B, int GEN>
-__device__ __forceinline__ void brot_bit(T *vr, T *vi, double c, double s) {
-    const bool neg = c < 0.0;
-    // multipliers for +s and for -s
-    const T Pp = T(neg ? s / (1.0 - c) : -s / (1.0 + c)), sp = T(s);
-    const T Pm = -Pp, sm = -sp;
+__device__ __forceinline__ void brot_bit(T *vr, T *vi, double P, double s, bool neg) {
+    const T Pp = T(P), sp = T(s), Pm = -Pp, sm = -sp;
     if (neg)
         brot_bit_lift<T, RA, B, GEN, true>(vr, vi, Pp, sp, Pm, sm);
     else
@@ -386,18 +385,18 @@ __device__ __forceinline__ void brot_z_lift(T *vr, T *vi, CRegOp &op, T Pp, T sp
 }
 
 template <typename T, int RA>
-__device__ __forceinline__ void brot_z(T *vr, T *vi, CRegOp &op, double c, double s, uint64_t base, uint32_t t) {
-    const bool neg = c < 0.0;
-    const T Pp = T(neg ? s / (1.0 - c) : -s / (1.0 + c)), sp = T(s);
+__device__ __forceinline__ void brot_z(T *vr, T *vi, CRegOp &op, double P, double s, bool neg, uint64_t base,
+                                       uint32_t t) {
     if (neg)
-        brot_z_lift<T, RA, true>(vr, vi, op, Pp, sp, base, t);
+        brot_z_lift<T, RA, true>(vr, vi, op, T(P), T(s), base, t);
     else
-        brot_z_lift<T, RA, false>(vr, vi, op, Pp, sp, base, t);
+        brot_z_lift<T, RA, false>(vr, vi, op, T(P), T(s), base, t);
 }
 
-// Batched-circuit codes: rotation exp(-i theta G / 2) with (cos, sin) of the
-// half angle from trig[2 * moff] (negated sine when jmatch is 1): X on bit b
-// -> 220 + b, Y on bit b -> 228 + b, Z anywhere -> 236.
+// Batched-circuit codes: rotation exp(-i theta G / 2) of parameter moff,
+// whose lifting form (P, s, cos) of the half angle is at trig[4 * moff]
+// (inverse when jmatch is 1: P and s negated): X on bit b -> 220 + b, Y on
+// bit b -> 228 + b, Z anywhere -> 236.
 template <int C, int R>
 __host__ __device__ constexpr bool ext_code_valid() {
     if (C >= 220 && C < 228) return C - 220 < R;
@@ -407,7 +406,7 @@ __host__ __device__ constexpr bool ext_code_valid() {
 
 // Op `code` (valid for R register bits) on an amplitude array of RA >= R
 // register bits; with EXT, the batched-circuit codes too (trig: the
-// circuit's half-angle table).  One flat compare chain on the uniform code.
+// circuit's rotation table).  One flat compare chain on the uniform code.
 template <typename T, int R, int C, int RA = R, bool EXT = false>
 __device__ __forceinline__ void run_op(int code, T *vr, T *vi, CRegOp &op, CT<T> *U, uint64_t base, uint32_t t,
                                        const QSIM_CONST double *trig = nullptr) {
@@ -415,14 +414,15 @@ __device__ __forceinline__ void run_op(int code, T *vr, T *vi, CRegOp &op, CT<T>
         if constexpr (code_valid<C, R>() || (EXT && ext_code_valid<C, R>())) {
             if (code == C) {
                 if constexpr (C >= 220) {
-                    const double cs = trig[2 * op.moff];
-                    const double sn = op.jmatch ? -trig[2 * op.moff + 1] : trig[2 * op.moff + 1];
+                    const double P = op.jmatch ? -trig[4 * op.moff] : trig[4 * op.moff];
+                    const double sn = op.jmatch ? -trig[4 * op.moff + 1] : trig[4 * op.moff + 1];
+                    const bool neg = trig[4 * op.moff + 2] < 0.0;
                     if constexpr (C < 228)
-                        brot_bit<T, RA, C - 220, 1>(vr, vi, cs, sn);
+                        brot_bit<T, RA, C - 220, 1>(vr, vi, P, sn, neg);
                     else if constexpr (C < 236)
-                        brot_bit<T, RA, C - 228, 2>(vr, vi, cs, sn);
+                        brot_bit<T, RA, C - 228, 2>(vr, vi, P, sn, neg);
                     else
-                        brot_z<T, RA>(vr, vi, op, cs, sn, base, t);
+                        brot_z<T, RA>(vr, vi, op, P, sn, neg, base, t);
                 } else if constexpr (C < 32) {
                     if constexpr (RA > R && popcount_c(C) >= 3) {
                         // row by row keeps all outputs aside: one copy at a time
