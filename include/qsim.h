@@ -138,13 +138,23 @@ typedef struct {
  *            (whose entries come from timing), so the passes, and with them
  *            the rounding of every result, depend on the inputs alone; every
  *            reduction already runs in a fixed order, so repeated calls give
- *            bitwise identical results.  0 = the table is used when present. */
+ *            bitwise identical results.  0 = the table is used when present.
+ *   checkpoints: qsim_adjoint_grad only.  0 = none: the reverse sweep
+ *            recovers each earlier state by applying the inverse gates to
+ *            the later one.  c in [1, 64] = the circuit is cut into c + 1
+ *            runs of about equal gate counts; the forward sweep keeps a copy
+ *            of the state at each cut (c extra state-sized device buffers,
+ *            allocated on first use and kept with the state), and the
+ *            reverse sweep restores the state from that copy when it gets
+ *            there, so the rounding of the inverse gates accumulates over
+ *            one run instead of the whole circuit.  Other calls ignore it. */
 typedef struct {
     int32_t fuse_k;
     int32_t tile_m;
     int32_t use_mfma;
     int32_t split_1q;
     int32_t deterministic;
+    int32_t checkpoints;
 } qsim_options;
 
 typedef struct qsim_state_s *qsim_state;

@@ -80,7 +80,7 @@ class QsimPauliSum(ctypes.Structure):
 
 class QsimOptions(ctypes.Structure):
     _fields_ = [("fuse_k", ctypes.c_int32), ("tile_m", ctypes.c_int32), ("use_mfma", ctypes.c_int32),
-                ("split_1q", ctypes.c_int32), ("deterministic", ctypes.c_int32)]
+                ("split_1q", ctypes.c_int32), ("deterministic", ctypes.c_int32), ("checkpoints", ctypes.c_int32)]
 
 
 def _hip_runtimes() -> set:
@@ -234,8 +234,8 @@ class PackedCircuit:
 
 
 def make_options(fuse_k: int = 0, tile_m: int = 0, use_mfma: int = 0, split_1q: int = 0,
-                 deterministic: int = 0) -> QsimOptions:
-    return QsimOptions(fuse_k, tile_m, use_mfma, split_1q, deterministic)
+                 deterministic: int = 0, checkpoints: int = 0) -> QsimOptions:
+    return QsimOptions(fuse_k, tile_m, use_mfma, split_1q, deterministic, checkpoints)
 
 
 def qsim_apply_circuit(h: int, packed: PackedCircuit, params: Optional[np.ndarray] = None,
@@ -363,26 +363,27 @@ class State:
     def expectation(self, H) -> float:
         return qsim_expectation(self.handle, PackedPauliSum(H))
 
-    def adjoint_grad_device(self, circ, params, H, tile_m: int = 0):
+    def adjoint_grad_device(self, circ, params, H, tile_m: int = 0, checkpoints: int = 0):
         """Energy (a one-element tensor) and gradient of <psi|C^dag H C|psi>
         for the state's current content psi, as float64 tensors on the
         state's device, queued on its stream without waiting; `params` is a
         float64 device tensor.  The state is returned to psi (up to
-        rounding)."""
+        rounding); `checkpoints` forward states are kept for the reverse
+        sweep."""
         import torch
         dev = self.tensor.device
         energy = torch.empty(1, dtype=torch.float64, device=dev)
         grad = torch.empty(params.numel(), dtype=torch.float64, device=dev)
         qsim_adjoint_grad(self.handle, self.packed(circ), params, PackedPauliSum(H),
-                          make_options(tile_m=tile_m), energy, grad)
+                          make_options(tile_m=tile_m, checkpoints=checkpoints), energy, grad)
         return energy, grad
 
-    def adjoint_grad(self, circ, params, H, tile_m: int = 0):
+    def adjoint_grad(self, circ, params, H, tile_m: int = 0, checkpoints: int = 0):
         """(energy, gradient) as a float and a numpy array: the parameters
         are copied to the device, the gradient back after the call."""
         import torch
         p = torch.as_tensor(np.ascontiguousarray(params, dtype=np.float64)).to(self.tensor.device)
-        e, g = self.adjoint_grad_device(circ, p, H, tile_m=tile_m)
+        e, g = self.adjoint_grad_device(circ, p, H, tile_m=tile_m, checkpoints=checkpoints)
         return float(e.cpu()[0]), g.cpu().numpy()
 
     def autotune(self, circ, params: Optional[np.ndarray] = None, reps: int = 2):

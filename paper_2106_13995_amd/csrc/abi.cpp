@@ -473,6 +473,7 @@ qsim_status qsim_free(qsim_state s) {
     s->transient.reset();
     if (s->adj_h) (void)hipFree(s->adj_h);
     if (s->adj_lam) (void)hipFree(s->adj_lam);
+    if (s->adj_ck) (void)hipFree(s->adj_ck);
     prof_clear(s);
     for (hipEvent_t e : s->prof.pool) (void)hipEventDestroy(e);
     if (s->pinned_ev) (void)hipEventDestroy(s->pinned_ev);
@@ -574,6 +575,7 @@ static qsim_status check_options(const qsim_options *opts) {
     if (opts->use_mfma < -1 || opts->use_mfma > 1) return set_error(QSIM_ERR_ARG, "use_mfma outside [-1, 1]");
     if (opts->deterministic < 0 || opts->deterministic > 1)
         return set_error(QSIM_ERR_ARG, "deterministic must be 0 or 1");
+    if (opts->checkpoints < 0 || opts->checkpoints > 64) return set_error(QSIM_ERR_ARG, "checkpoints outside [0, 64]");
     return QSIM_OK;
 }
 
@@ -998,10 +1000,13 @@ static int rotation_kind_generator(int kind) {
 static qsim_status get_adjoint_plan(qsim_state s, const qsim_circuit *c, int64_t nparams, const qsim_options *opts,
                                     AdjointPlan **out) {
     const int fwd_m = (opts && opts->tile_m > 0) ? opts->tile_m : (s->dtype == QSIM_C128 ? 11 : 12);
+    // checkpoints: at most one per gap between gates
+    const int nck = std::max(0, std::min(opts ? opts->checkpoints : 0, c->nops - 1));
     std::string key;
     auto put = [&key](const void *p, size_t n) { key.append(static_cast<const char *>(p), n); };
     put(&nparams, sizeof nparams);
     put(&fwd_m, sizeof fwd_m);
+    put(&nck, sizeof nck);
     for (int i = 0; i < c->nops; ++i) {
         qsim_op op = c->ops[i];
         if (op.param >= 0) op.angles[0] = op.angles[1] = op.angles[2] = 0.0;
@@ -1031,11 +1036,13 @@ static qsim_status get_adjoint_plan(qsim_state s, const qsim_circuit *c, int64_t
             gates[size_t(i)].rot_param = c->ops[i].param;
         }
     }
-    // reverse sweep, last op first: its probe (if parametric), then its inverse
+    // reverse sweep, last op first: its probe (if parametric), then its
+    // inverse; first_item[i]: where op i's items start
     std::vector<HostGate> items;
-    std::vector<int> slot_param;
+    std::vector<int> slot_param, first_item(size_t(c->nops) + 1, 0);
     items.reserve(2 * gates.size());
     for (int i = c->nops - 1; i >= 0; --i) {
+        first_item[size_t(i)] = int(items.size());
         const HostGate &g = gates[size_t(i)];
         if (g.rot_gen) {
             HostGate pr;
@@ -1058,13 +1065,48 @@ static qsim_status get_adjoint_plan(qsim_state s, const qsim_circuit *c, int64_t
     }
     ap->fwd.n = ap->rev.n = s->n;
     ap->fwd.dtype = ap->rev.dtype = s->dtype;
-    if (build_tile_plan(ap->fwd, gates, std::min(s->n, fwd_m)) < 0)
-        return set_error(QSIM_ERR_UNSUPPORTED, "the planner could not place every op");
     // reverse tiles of 2^10 amplitudes per state (wider when a gate needs
     // it): measured on the 20-qubit ansatz, smaller tiles put more
     // workgroups on the chip
-    ap->mtile = build_adjoint_plan(ap->rev, items, 10);
-    if (ap->mtile < 0) return set_error(QSIM_ERR_UNSUPPORTED, "the planner could not place every op");
+    if (nck == 0) {
+        if (build_tile_plan(ap->fwd, gates, std::min(s->n, fwd_m)) < 0)
+            return set_error(QSIM_ERR_UNSUPPORTED, "the planner could not place every op");
+        ap->mtile = build_adjoint_plan(ap->rev, items, 10);
+        if (ap->mtile < 0) return set_error(QSIM_ERR_UNSUPPORTED, "the planner could not place every op");
+    } else {
+        // runs of about equal gate counts, planned one by one so that every
+        // cut is a pass boundary of both sweeps; one reverse tile width
+        Plan trial;
+        trial.n = s->n;
+        trial.dtype = s->dtype;
+        ap->mtile = build_adjoint_plan(trial, items, 10);
+        if (ap->mtile < 0) return set_error(QSIM_ERR_UNSUPPORTED, "the planner could not place every op");
+        std::vector<int> cut(size_t(nck) + 2, 0);
+        for (int j = 0; j < nck; ++j) cut[size_t(j) + 1] = int((int64_t(j) + 1) * c->nops / (nck + 1));
+        cut[size_t(nck) + 1] = c->nops;
+        for (int j = 0; j <= nck; ++j) {
+            const std::vector<HostGate> seg(gates.begin() + cut[size_t(j)], gates.begin() + cut[size_t(j) + 1]);
+            if (build_tile_plan(ap->fwd, seg, std::min(s->n, fwd_m)) < 0)
+                return set_error(QSIM_ERR_UNSUPPORTED, "the planner could not place every op");
+            if (j < nck) ap->fwd_cut.push_back(int(ap->fwd.passes.size()));
+        }
+        for (int j = nck; j >= 0; --j) {
+            // items of ops cut[j] .. cut[j+1]-1 (last op first)
+            const int i0 = first_item[size_t(cut[size_t(j) + 1] - 1)];
+            const int i1 = cut[size_t(j)] > 0 ? first_item[size_t(cut[size_t(j)] - 1)] : int(items.size());
+            const std::vector<HostGate> seg(items.begin() + i0, items.begin() + i1);
+            if (build_tile_plan(ap->rev, seg, ap->mtile, 2) != ap->mtile)
+                return set_error(QSIM_ERR_UNSUPPORTED, "the planner could not place every op");
+            if (j > 0) {
+                ap->rev_cut.push_back(int(ap->rev.passes.size()));
+                ap->rev_ck.push_back(j - 1);
+            }
+        }
+        for (Pass &p : ap->rev.passes) p.bytes *= 2.0;   // two states per pass
+        ap->fwd.items = int(gates.size());
+        ap->rev.items = int(items.size());
+        ap->nck = nck;
+    }
     ap->nprobes = int(slot_param.size());
     ap->nparams = nparams;
     qsim_status st = upload_plan(s, ap->fwd);
@@ -1147,6 +1189,21 @@ qsim_status qsim_adjoint_grad(qsim_state s, const qsim_circuit *c, const double 
             return set_error(QSIM_ERR_OOM, "cannot allocate the adjoint state");
         }
     }
+    if (ap->nck > s->adj_ck_count) {
+        if (s->adj_ck) {
+            (void)hipStreamSynchronize(s->stream);
+            (void)hipFree(s->adj_ck);
+        }
+        s->adj_ck = nullptr;
+        s->adj_ck_count = 0;
+        if (hipMalloc(&s->adj_ck, sbytes * size_t(ap->nck)) != hipSuccess) {
+            (void)hipGetLastError();
+            s->adj_ck = nullptr;
+            return set_error(QSIM_ERR_OOM, "cannot allocate the adjoint checkpoints");
+        }
+        s->adj_ck_count = ap->nck;
+    }
+    char *ck = static_cast<char *>(s->adj_ck);
     // the Pauli sum on the device, grouped by X mask (kept while it is unchanged)
     struct DevGroup {
         uint64_t x;
@@ -1218,12 +1275,19 @@ qsim_status qsim_adjoint_grad(qsim_state s, const qsim_circuit *c, const double 
     double *sums = reinterpret_cast<double *>(scr + off_sums);
     QSIM_HIP(s, injected_fault(), "injected fault (QSIM_FAULT)");
     QSIM_HIP(s, launch_half_angle_trig(s, params_dev, nparams, trig), "trig launch");
-    // forward: psi <- C(theta) psi
-    for (const Pass &p : ap->fwd.passes) {
+    // forward: psi <- C(theta) psi, with a copy of psi at every cut
+    size_t next_cut = 0;
+    for (size_t pi = 0; pi < ap->fwd.passes.size(); ++pi) {
+        const Pass &p = ap->fwd.passes[pi];
         prof_begin(s, QSIM_KCLASS_TILE, p.bytes, p.flops);
         hipError_t e = launch_tile_pass(s, ap->fwd, p, trig);
         prof_end(s);
         if (e != hipSuccess) return device_error(s, e, "forward pass");
+        if (next_cut < ap->fwd_cut.size() && int(pi) + 1 == ap->fwd_cut[next_cut]) {
+            QSIM_HIP(s, hipMemcpyAsync(ck + sbytes * next_cut, s->data, sbytes, hipMemcpyDeviceToDevice, s->stream),
+                     "checkpoint copy");
+            ++next_cut;
+        }
     }
     // lambda <- H psi, energy partials
     prof_begin(s, QSIM_KCLASS_EXPECT, 2.0 * double(sbytes) * double(std::max(1, ng)));
@@ -1231,12 +1295,22 @@ qsim_status qsim_adjoint_grad(qsim_state s, const qsim_circuit *c, const double 
              "pauli apply");
     prof_end(s);
     QSIM_HIP(s, launch_reduce(s, epart, egrid, sums + nprobes), "reduce");
-    // reverse sweep over (psi, lambda)
-    for (const Pass &p : ap->rev.passes) {
+    // reverse sweep over (psi, lambda); psi restored from its checkpoint at
+    // every cut
+    next_cut = 0;
+    for (size_t pi = 0; pi < ap->rev.passes.size(); ++pi) {
+        const Pass &p = ap->rev.passes[pi];
         prof_begin(s, QSIM_KCLASS_ADJOINT, p.bytes, 2.0 * p.flops);
         hipError_t e = launch_adjoint_pass(s, ap->rev, p, s->adj_lam, pp, trig);
         prof_end(s);
         if (e != hipSuccess) return device_error(s, e, "adjoint pass");
+        if (next_cut < ap->rev_cut.size() && int(pi) + 1 == ap->rev_cut[next_cut]) {
+            QSIM_HIP(s,
+                     hipMemcpyAsync(s->data, ck + sbytes * size_t(ap->rev_ck[next_cut]), sbytes,
+                                    hipMemcpyDeviceToDevice, s->stream),
+                     "checkpoint restore");
+            ++next_cut;
+        }
     }
     QSIM_HIP(s, launch_reduce_rows(s, pp, nprobes, ntiles, sums), "reduce rows");
     const int32_t *row = static_cast<const int32_t *>(ap->dev);

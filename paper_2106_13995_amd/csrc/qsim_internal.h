@@ -288,6 +288,11 @@ struct AdjointPlan {
     Plan fwd, rev;
     int mtile = 0;        // reverse tile width
     int nprobes = 0;
+    // forward-state checkpoints: the forward copies the state after pass
+    // fwd_cut[j] - 1 into checkpoint j; the reverse restores checkpoint j
+    // after pass rev_cut[j] - 1 (reverse runs end there, last run first)
+    int nck = 0;
+    std::vector<int> fwd_cut, rev_cut, rev_ck;
     int64_t nparams = 0;
     void *dev = nullptr;
     size_t idx_off = 0;
@@ -319,6 +324,8 @@ struct qsim_state_s {
     std::vector<qsim::CachedPlan> plans;
     std::unique_ptr<qsim::Plan> transient;   // last uncached plan (single gates)
     void *adj_lam = nullptr;                 // second state of the adjoint method
+    void *adj_ck = nullptr;                  // forward-state checkpoints of the adjoint method
+    int adj_ck_count = 0;
     std::vector<std::unique_ptr<qsim::AdjointPlan>> adj_plans;
     void *adj_h = nullptr;                   // the adjoint's Pauli sum on the device
     size_t adj_h_bytes = 0;

@@ -42,12 +42,12 @@ def test_struct_layouts_match_header_sizes(tmp_path):
     src.write_text('#include <stdio.h>\n#include <stddef.h>\n#include "qsim.h"\n'
                    'int main(void) { printf("%zu %zu %zu %zu %zu %zu\\n", sizeof(qsim_op), sizeof(qsim_circuit), '
                    'sizeof(qsim_pauli_term), sizeof(qsim_pauli_sum), sizeof(qsim_options), '
-                   'offsetof(qsim_options, deterministic)); return 0; }\n')
+                   'offsetof(qsim_options, checkpoints)); return 0; }\n')
     exe = tmp_path / "sizes"
     subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
     got = [int(v) for v in subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.split()]
     assert got == [ctypes.sizeof(q.QsimOp), ctypes.sizeof(q.QsimCircuit), ctypes.sizeof(q.QsimPauliTerm),
-                   ctypes.sizeof(q.QsimPauliSum), ctypes.sizeof(q.QsimOptions), q.QsimOptions.deterministic.offset]
+                   ctypes.sizeof(q.QsimPauliSum), ctypes.sizeof(q.QsimOptions), q.QsimOptions.checkpoints.offset]
 
 
 def test_wrap_validation():
