@@ -277,7 +277,12 @@ def batch_bench(torch, q, W, dtype: str = "c64", reps: int = 3, loop_sample: int
     circs = [W.ansatz_circuit(int(n), int(L)) for n, L in zip(spec.ns, spec.layers)]
     obs = [W.chain_observable(int(n)) for n in spec.ns]
     params = np.concatenate(spec.params)
-    b = q.Batch(circs, obs, dtype)
+    # layered tile width and fixed-gate fusion picked by the batch autotuner
+    # (untimed: each candidate batch is built and replayed)
+    t0 = time.perf_counter()
+    options, tuned_ms = q.Batch.autotune(circs, obs, params, dtype, reps=2)
+    tuning_s = time.perf_counter() - t0
+    b = q.Batch(circs, obs, dtype, options=options)
     p_dev = torch.as_tensor(params, dtype=torch.float64, device="cuda")
     e_dev, g_dev = b.run_device(p_dev)
     torch.cuda.synchronize()
@@ -313,6 +318,7 @@ def batch_bench(torch, q, W, dtype: str = "c64", reps: int = 3, loop_sample: int
     return {"workload": f"{len(circs)} ansatz circuits, 10-20 qubits, 4-12 layers, {int(offs[-1])} parameters, "
                         f"{dtype}, forward + adjoint gradient",
             "circuits_per_s": round(len(circs) / t_batch, 1), "ms_per_batch": round(t_batch * 1e3, 2),
+            "options": options, "tuned_ms": round(tuned_ms, 2), "tuning_s": round(tuning_s, 1),
             "layered_circuits": layered, "persistent_circuits": persistent,
             "persistent_workgroups": grid, "programs": programs,
             "pass_bytes_per_batch": pass_bytes,

@@ -277,7 +277,7 @@ qsim_status qsim_adjoint_grad(qsim_state s, const qsim_circuit *c, const double 
  * must be RX, RY or RZ), builds one device program per distinct structure
  * (circuit ops, fixed angles and matrices, observable), allocates device
  * memory and captures the whole run in a HIP graph.  Circuits that fill
- * whole tiles (n >= 12 complex64, n >= 11 complex128) and whose ops all fit
+ * whole tiles (n >= 11 by default) and whose ops all fit
  * register-staged passes run layered: one launch per pass index applies
  * that pass of every such circuit to all of its tiles at once, each circuit
  * with psi/lambda slots of its own (2 x 2^n amplitudes, in groups that fit
@@ -286,8 +286,11 @@ qsim_status qsim_adjoint_grad(qsim_state s, const qsim_circuit *c, const double 
  * circuits wider than one tile).  Circuit i reads its parameters from params[param_offsets[i]
  * .. param_offsets[i+1]) (param indices in its ops are relative to that
  * block), is applied to |0...0>, and yields energies[i] = <psi|Hs[i]|psi>
- * and, when want_grad, grads over the same block.  `opts` is reserved (may
- * be NULL).
+ * and, when want_grad, grads over the same block.  `opts` (may be NULL):
+ * fuse_k 0 or 1 = no fusion, 2 or 3 = runs of fixed (non-parametric) gates
+ * merged into dense blocks of at most that many qubits; tile_m 0 =
+ * automatic, 11 or 12 (complex64) / 11 (complex128) = tile width of the
+ * layered circuits; the other fields are ignored.
  *
  * qsim_batch_run: params_dev (device, nparams doubles), energies_dev (device,
  * ncirc doubles) and grads_dev (device, nparams doubles; may be NULL when the
@@ -311,6 +314,18 @@ qsim_status qsim_batch_run(qsim_batch b, const double *params_dev, double *energ
                            void *hip_stream);
 qsim_status qsim_batch_info(qsim_batch b, int *grid, int *programs, int *max_n);
 qsim_status qsim_batch_layout(qsim_batch b, int *layered, int *persistent, double *pass_bytes);
+
+/* Batch autotuner (Sec. IV leaves tuning to future work): creates the batch
+ * with each candidate option set (layered tile width 11 and 12 for
+ * complex64, 11 for complex128; fixed-gate fusion 1, 2 and 3), replays it
+ * once to warm up and `reps` times timed with HIP events on a stream of its
+ * own, releases it, and writes the fastest set to *best and its mean time
+ * per run in milliseconds to *best_ms (may be NULL).  Arguments as for
+ * qsim_batch_create; params_dev as for qsim_batch_run.  Allocates and frees
+ * each candidate's device memory in turn; synchronises. */
+qsim_status qsim_batch_autotune(int ncirc, const qsim_circuit *circs, const int64_t *param_offsets,
+                                const qsim_pauli_sum *Hs, qsim_dtype dtype, int want_grad, const double *params_dev,
+                                int reps, qsim_options *best, double *best_ms);
 qsim_status qsim_batch_free(qsim_batch b);
 
 /* Autotuner (Sec. IV: the paper leaves kernel-level tuning to future work):

@@ -49,7 +49,8 @@ EXPORTS = (
     "qsim_set_basis", "qsim_copy_to_host", "qsim_copy_from_host", "qsim_apply_gate",
     "qsim_apply_circuit", "qsim_expectation", "qsim_last_error", "qsim_profile_enable",
     "qsim_profile_read", "qsim_plan_summary", "qsim_adjoint_grad", "qsim_batch_create", "qsim_batch_run",
-    "qsim_batch_info", "qsim_batch_layout", "qsim_batch_free", "qsim_autotune", "qsim_expectation_noalloc",
+    "qsim_batch_info", "qsim_batch_layout", "qsim_batch_autotune", "qsim_batch_free", "qsim_autotune",
+    "qsim_expectation_noalloc",
 )
 
 
@@ -130,6 +131,8 @@ def _load() -> ctypes.CDLL:
         "qsim_batch_run": ([P, P, P, P, P], S),
         "qsim_batch_info": ([P, ctypes.POINTER(i32), ctypes.POINTER(i32), ctypes.POINTER(i32)], S),
         "qsim_batch_layout": ([P, ctypes.POINTER(i32), ctypes.POINTER(i32), ctypes.POINTER(ctypes.c_double)], S),
+        "qsim_batch_autotune": ([i32, ctypes.POINTER(QsimCircuit), ctypes.POINTER(i64), ctypes.POINTER(QsimPauliSum),
+                                 i32, i32, P, i32, ctypes.POINTER(QsimOptions), ctypes.POINTER(ctypes.c_double)], S),
         "qsim_batch_free": ([P], S),
         "qsim_autotune": ([P, ctypes.POINTER(QsimCircuit), ctypes.POINTER(ctypes.c_double), i64, i32,
                            ctypes.POINTER(QsimOptions), ctypes.POINTER(ctypes.c_double)], S),
@@ -415,27 +418,54 @@ class State:
 
 # ------------------------------------------------------------ batches
 
+def _pack_batch(circuits, observables):
+    """ctypes arrays of a batch's circuits and Pauli sums, its parameter
+    offsets, and the objects that must stay alive while they are used."""
+    packed = [PackedCircuit(c) for c in circuits]
+    Hp = [PackedPauliSum(H) for H in observables]
+    offs = [0]
+    for c in circuits:
+        offs.append(offs[-1] + int(c.nparams))
+    n = len(circuits)
+    carr = (QsimCircuit * n)(*[p.c for p in packed])
+    harr = (QsimPauliSum * n)(*[h.h for h in Hp])
+    return n, carr, harr, np.asarray(offs, dtype=np.int64), (packed, Hp, carr, harr)
+
+
 class Batch:
     """Many independent circuits (each on |0...0>, each with its own parameter
     block and observable) run forward (+ adjoint) in one replayed graph."""
 
-    def __init__(self, circuits, observables, dtype: str = "c64", want_grad: bool = True):
-        self.ncirc = len(circuits)
-        self.packed = [PackedCircuit(c) for c in circuits]
-        self.Hp = [PackedPauliSum(H) for H in observables]
-        offs = [0]
-        for c in circuits:
-            offs.append(offs[-1] + int(c.nparams))
-        self.offsets = np.asarray(offs, dtype=np.int64)
-        self.nparams = int(offs[-1])
-        carr = (QsimCircuit * self.ncirc)(*[p.c for p in self.packed])
-        harr = (QsimPauliSum * self.ncirc)(*[h.h for h in self.Hp])
-        self._keep = (carr, harr)
+    def __init__(self, circuits, observables, dtype: str = "c64", want_grad: bool = True,
+                 options: Optional[dict] = None):
+        """`options`: {"fuse_k": 1..3, "tile_m": 11 or 12} (see
+        qsim_batch_create), e.g. what Batch.autotune returns."""
+        self.ncirc, carr, harr, self.offsets, keep = _pack_batch(circuits, observables)
+        self.nparams = int(self.offsets[-1])
+        self._keep = keep
+        opts = make_options(**options) if options else None
         h = ctypes.c_void_p()
         _check(_lib.qsim_batch_create(self.ncirc, carr, self.offsets.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
-                                      harr, DTYPES[dtype], 1 if want_grad else 0, None, ctypes.byref(h)))
+                                      harr, DTYPES[dtype], 1 if want_grad else 0,
+                                      ctypes.byref(opts) if opts is not None else None, ctypes.byref(h)))
         self.handle = h.value
         self.want_grad = want_grad
+
+    @staticmethod
+    def autotune(circuits, observables, params, dtype: str = "c64", want_grad: bool = True, reps: int = 2):
+        """Times the batch under each candidate option set (qsim_batch_autotune)
+        and returns (options dict, ms per run) of the fastest; `params` as
+        for run()."""
+        import torch
+        n, carr, harr, offsets, keep = _pack_batch(circuits, observables)
+        p = torch.as_tensor(np.ascontiguousarray(params, dtype=np.float64)).to("cuda")
+        best = QsimOptions()
+        ms = ctypes.c_double()
+        _check(_lib.qsim_batch_autotune(n, carr, offsets.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), harr,
+                                        DTYPES[dtype], 1 if want_grad else 0, _device_f64(p, "params"), reps,
+                                        ctypes.byref(best), ctypes.byref(ms)))
+        del keep
+        return {"fuse_k": best.fuse_k, "tile_m": best.tile_m}, ms.value
 
     def info(self) -> Tuple[int, int, int]:
         g, p, m = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()

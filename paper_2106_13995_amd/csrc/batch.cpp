@@ -86,12 +86,18 @@ extern "C" {
 qsim_status qsim_batch_create(int ncirc, const qsim_circuit *circs, const int64_t *param_offsets,
                               const qsim_pauli_sum *Hs, qsim_dtype dtype, int want_grad, const qsim_options *opts,
                               qsim_batch *out) {
-    (void)opts;
     if (!out) return fail(QSIM_ERR_ARG, "out is NULL");
     *out = nullptr;
     if (ncirc < 1 || !circs || !param_offsets || !Hs) return fail(QSIM_ERR_ARG, "empty batch or NULL array");
     if (dtype != QSIM_C64 && dtype != QSIM_C128) return fail(QSIM_ERR_ARG, "dtype must be QSIM_C64 or QSIM_C128");
     if (param_offsets[0] != 0) return fail(QSIM_ERR_ARG, "param_offsets[0] must be 0");
+    // options: fusion of the fixed gates between parametric ones, and the
+    // tile width of layered circuits
+    const int fuse_k = opts && opts->fuse_k > 0 ? opts->fuse_k : 1;
+    if (opts && (opts->fuse_k < 0 || opts->fuse_k > 3)) return fail(QSIM_ERR_ARG, "batch fuse_k must be 0..3");
+    const int mL = opts && opts->tile_m > 0 ? opts->tile_m : batch_layer_default(dtype);
+    if (opts && opts->tile_m != 0 && !batch_layer_width_ok(dtype, opts->tile_m))
+        return fail(QSIM_ERR_ARG, "batch tile_m must be 0, 11 or 12 (complex64) or 0 or 11 (complex128)");
     const int nmax_batch = 26;
     std::map<std::string, int> prog_of;
     std::vector<const qsim_circuit *> prog_circ;
@@ -164,7 +170,23 @@ qsim_status qsim_batch_create(int ncirc, const qsim_circuit *circs, const int64_
                 fwd[size_t(o)].rot_param = c.ops[o].param;
             }
         }
-        for (int o = c.nops - 1; o >= 0; --o) {
+        if (fuse_k > 1) {
+            // runs of fixed gates merged into blocks of at most fuse_k qubits
+            // (the parametric rotations between them stay as they are)
+            std::vector<HostGate> merged, run;
+            for (HostGate &g : fwd) {
+                if (g.rot_gen) {
+                    for (HostGate &f : fuse_gates(run, fuse_k)) merged.push_back(std::move(f));
+                    run.clear();
+                    merged.push_back(std::move(g));
+                } else {
+                    run.push_back(std::move(g));
+                }
+            }
+            for (HostGate &f : fuse_gates(run, fuse_k)) merged.push_back(std::move(f));
+            fwd.swap(merged);
+        }
+        for (int o = int(fwd.size()) - 1; o >= 0; --o) {
             const HostGate &g = fwd[size_t(o)];
             if (g.rot_gen) {
                 HostGate pr;
@@ -187,12 +209,13 @@ qsim_status qsim_batch_create(int ncirc, const qsim_circuit *circs, const int64_
         BatchProgram bp{};
         bp.n = c.n;
         bp.m = std::min(c.n, batch_tile_max(dtype));
+        if (c.n >= mL) bp.m = mL;
         b->max_n = std::max(b->max_n, c.n);
         // Circuits that fill whole tiles run layered, register-staged
         // throughout; a program with a pass that cannot be staged (a dense
         // block on more than three qubits) and smaller circuits run in the
         // persistent kernel, from LDS.
-        bool layered = bp.m == batch_tile_max(dtype);
+        bool layered = bp.m == mL;
         Plan plans[2];
         for (int attempt = 0; attempt < 2; ++attempt) {
             bool ok = true;
@@ -215,7 +238,7 @@ qsim_status qsim_batch_create(int ncirc, const qsim_circuit *circs, const int64_
                     return fail(QSIM_ERR_UNSUPPORTED, "a batch program: the planner could not place every op");
                 }
                 if (layered)
-                    for (const Pass &p : plans[dir].passes) ok = ok && p.reg_r == batch_reg_bits(dtype);
+                    for (const Pass &p : plans[dir].passes) ok = ok && p.reg_r == mL - 8;
             }
             if (ok) break;
             layered = false;
@@ -462,7 +485,7 @@ qsim_status qsim_batch_create(int ncirc, const qsim_circuit *circs, const int64_
     // (twice in reverse passes: psi and lambda); the energies read psi and
     // write lambda
     for (const BatchStep &st : steps) {
-        const double tile = double(s) * std::ldexp(1.0, batch_tile_max(dtype));
+        const double tile = double(s) * std::ldexp(1.0, mL);
         if (st.kind == 0) b->pass_bytes += 2.0 * tile * st.wgs;
         if (st.kind == 1) b->pass_bytes += 4.0 * tile * st.wgs;
         if (st.kind == 2)
@@ -593,7 +616,8 @@ qsim_status qsim_batch_create(int ncirc, const qsim_circuit *circs, const int64_
     ld.epart = reinterpret_cast<double *>(d + o_epart);
     ld.want_grad = b->want_grad;
     ld.steps = steps;
-    hipError_t e = lcircs.empty() ? hipSuccess : batch_layer_setup(dtype);
+    ld.R = mL - 8;
+    hipError_t e = lcircs.empty() ? hipSuccess : batch_layer_setup(dtype, ld.R);
     if (e == hipSuccess) e = hipStreamCreateWithFlags(&b->cap_stream, hipStreamNonBlocking);
     if (e == hipSuccess) e = hipStreamBeginCapture(b->cap_stream, hipStreamCaptureModeThreadLocal);
     if (e == hipSuccess && !lcircs.empty()) e = launch_batch_layered(b->cap_stream, dtype, ld);
@@ -658,6 +682,77 @@ qsim_status qsim_batch_layout(qsim_batch b, int *layered, int *persistent, doubl
     if (layered) *layered = b->nlayered;
     if (persistent) *persistent = b->ncirc - b->nlayered;
     if (pass_bytes) *pass_bytes = b->pass_bytes;
+    return QSIM_OK;
+}
+
+qsim_status qsim_batch_autotune(int ncirc, const qsim_circuit *circs, const int64_t *param_offsets,
+                                const qsim_pauli_sum *Hs, qsim_dtype dtype, int want_grad, const double *params_dev,
+                                int reps, qsim_options *best, double *best_ms) {
+    if (!best) return fail(QSIM_ERR_ARG, "best is NULL");
+    if (reps < 1) return fail(QSIM_ERR_ARG, "reps must be at least 1");
+    if (ncirc < 1 || !param_offsets) return fail(QSIM_ERR_ARG, "empty batch or NULL array");
+    const int64_t np = param_offsets[ncirc];
+    if (np > 0 && (!params_dev || !device_memory(params_dev)))
+        return fail(QSIM_ERR_ARG, "params must be device memory");
+    std::vector<qsim_options> cands;
+    for (int m : {12, 11})
+        if (batch_layer_width_ok(dtype, m))
+            for (int f = 1; f <= 3; ++f) {
+                qsim_options o{};
+                o.fuse_k = f;
+                o.tile_m = m;
+                cands.push_back(o);
+            }
+    double *energies = nullptr, *grads = nullptr;
+    hipStream_t st = nullptr;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    auto release = [&]() {
+        if (energies) (void)hipFree(energies);
+        if (grads) (void)hipFree(grads);
+        if (e0) (void)hipEventDestroy(e0);
+        if (e1) (void)hipEventDestroy(e1);
+        if (st) (void)hipStreamDestroy(st);
+    };
+    if (hipMalloc(&energies, sizeof(double) * size_t(ncirc)) != hipSuccess ||
+        (want_grad && np > 0 && hipMalloc(&grads, sizeof(double) * size_t(np)) != hipSuccess)) {
+        (void)hipGetLastError();
+        release();
+        return fail(QSIM_ERR_OOM, "cannot allocate the autotuner's outputs");
+    }
+    if (hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess || hipEventCreate(&e0) != hipSuccess ||
+        hipEventCreate(&e1) != hipSuccess) {
+        (void)hipGetLastError();
+        release();
+        return fail(QSIM_ERR_DEVICE, "cannot create the autotuner's stream and events");
+    }
+    double best_t = -1.0;
+    for (const qsim_options &o : cands) {
+        qsim_batch b = nullptr;
+        qsim_status s = qsim_batch_create(ncirc, circs, param_offsets, Hs, dtype, want_grad, &o, &b);
+        if (s != QSIM_OK) {
+            release();
+            return s;
+        }
+        s = qsim_batch_run(b, params_dev, energies, grads, st);
+        if (s == QSIM_OK && hipEventRecord(e0, st) != hipSuccess) s = fail(QSIM_ERR_DEVICE, "event record failed");
+        for (int r = 0; r < reps && s == QSIM_OK; ++r) s = qsim_batch_run(b, params_dev, energies, grads, st);
+        float ms = 0.0f;
+        if (s == QSIM_OK && (hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+                             hipEventElapsedTime(&ms, e0, e1) != hipSuccess))
+            s = fail(QSIM_ERR_DEVICE, "timing the batch failed");
+        (void)qsim_batch_free(b);
+        if (s != QSIM_OK) {
+            release();
+            return s;
+        }
+        const double t = double(ms) / reps;
+        if (best_t < 0.0 || t < best_t) {
+            best_t = t;
+            *best = o;
+        }
+    }
+    release();
+    if (best_ms) *best_ms = best_t;
     return QSIM_OK;
 }
 

@@ -33,9 +33,13 @@ struct BatchProgram {
     int32_t layered, nprobes, nparams, row_off;
 };
 
-// Register bits of a batch thread in register-staged passes (256 threads,
-// full tiles of batch_tile_max qubits).
-inline int batch_reg_bits(int dtype) { return batch_tile_max(dtype) - 8; }
+// Tile widths layered circuits may run with (256 threads, 2^(m - 8)
+// amplitudes per thread in registers), and the default: 2^11 amplitudes in
+// both precisions (measured on the 4096-circuit mix in complex64: 356 ms
+// against 391 ms with 2^12 tiles, whose reverse kernel holds two waves per
+// SIMD instead of four).
+inline bool batch_layer_width_ok(int dtype, int m) { return m == 11 || (m == 12 && dtype == QSIM_C64); }
+inline int batch_layer_default(int) { return 11; }
 
 struct BatchPass {
     int32_t L, H;
@@ -146,11 +150,12 @@ struct BatchLayerDevice {
     void *arena;
     double *ppart, *epart;
     int want_grad;
+    int R;                   // register bits per thread (tile width - 8)
     std::vector<BatchStep> steps;
 };
 
 // Raises the layered kernels' LDS limits (before any capture).
-hipError_t batch_layer_setup(int dtype);
+hipError_t batch_layer_setup(int dtype, int R);
 hipError_t launch_batch_layered(hipStream_t stream, int dtype, const BatchLayerDevice &d);
 
 }  // namespace qsim

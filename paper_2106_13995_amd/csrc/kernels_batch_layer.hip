@@ -457,9 +457,10 @@ static hipError_t layer_lds(size_t &fwd, size_t &rev) {
     return e;
 }
 
-hipError_t batch_layer_setup(int dtype) {
+hipError_t batch_layer_setup(int dtype, int R) {
     size_t f, r;
-    return dtype == QSIM_C64 ? layer_lds<float, 4>(f, r) : layer_lds<double, 3>(f, r);
+    if (dtype == QSIM_C64) return R == 4 ? layer_lds<float, 4>(f, r) : layer_lds<float, 3>(f, r);
+    return layer_lds<double, 3>(f, r);
 }
 
 template <typename T, int R>
@@ -517,7 +518,9 @@ static hipError_t launch_layered_t(hipStream_t stream, const BatchLayerDevice &d
 }
 
 hipError_t launch_batch_layered(hipStream_t stream, int dtype, const BatchLayerDevice &d) {
-    return dtype == QSIM_C64 ? launch_layered_t<float, 4>(stream, d) : launch_layered_t<double, 3>(stream, d);
+    if (dtype == QSIM_C64) return d.R == 4 ? launch_layered_t<float, 4>(stream, d) : launch_layered_t<float, 3>(stream, d);
+    if (d.R != 3) return hipErrorInvalidValue;
+    return launch_layered_t<double, 3>(stream, d);
 }
 
 }  // namespace qsim

@@ -26,7 +26,7 @@ hipError_t launch_gather_gradient(qsim_state, const double *, const int32_t *, c
 }
 hipError_t launch_batch(hipStream_t, int, const BatchDevice &, int) { no_device("batch"); }
 hipError_t launch_batch_layered(hipStream_t, int, const BatchLayerDevice &) { no_device("batch"); }
-hipError_t batch_layer_setup(int) { no_device("batch"); }
+hipError_t batch_layer_setup(int, int) { no_device("batch"); }
 hipError_t launch_dense_sweep(qsim_state, const Pass &) { no_device("dense"); }
 hipError_t launch_diag_sweep(qsim_state, const Pass &) { no_device("diag"); }
 hipError_t launch_expect_group(qsim_state, uint64_t, const void *, int, double *, int *) { no_device("expect"); }

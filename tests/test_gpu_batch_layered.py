@@ -64,12 +64,12 @@ def observable(n, seed):
                       list(H.zmasks) + list(ch.zmasks))
 
 
-def run_checks(q, dtype, ns, nops, seed0, tol_e, tol_g, expect_layered):
+def run_checks(q, dtype, ns, nops, seed0, tol_e, tol_g, expect_layered, options=None):
     circs = [param_circuit(n, nops, 9, seed0 + i) for i, n in enumerate(ns)]
     obs = [observable(n, seed0 + 100 + i) for i, n in enumerate(ns)]
     rng = np.random.default_rng(seed0 + 7)
     params = rng.uniform(0, TWO_PI, size=sum(c.nparams for c in circs))
-    b = q.Batch(circs, obs, dtype)
+    b = q.Batch(circs, obs, dtype, options=options)
     lay, per = b.layout()
     assert (lay, per) == expect_layered, (lay, per)
     e, g = b.run(params)
@@ -92,8 +92,8 @@ def test_layered_c128_one_and_several_tiles(q):
 
 
 def test_layered_c64_one_and_several_tiles(q):
-    # complex64 tiles hold 12 qubits
-    run_checks(q, "c64", [12, 13, 14, 10], 60, 400, 2e-5, 1e-4, (3, 1))
+    # complex64 tiles hold 11 qubits by default: n = 11 is one tile
+    run_checks(q, "c64", [12, 11, 13, 14, 10], 60, 400, 2e-5, 1e-4, (4, 1))
 
 
 def test_layered_groups_and_replay(q, monkeypatch):
@@ -157,3 +157,34 @@ def test_layered_edge_circuits(q):
                 assert rel(g[off:off + c.nparams], ref_g) < tol_g, (dtype, i)
             off += c.nparams
         b.close()
+
+
+@pytest.mark.parametrize("dtype,options,layout,tol", [
+    # 2^11-amplitude tiles in complex64 (eight amplitudes a thread): n = 11
+    # is one tile and runs layered too
+    ("c64", {"fuse_k": 1, "tile_m": 11}, (4, 1), (2e-5, 1e-4)),
+    # fixed-gate runs fused into dense blocks of up to three qubits
+    ("c64", {"fuse_k": 3, "tile_m": 12}, (3, 2), (2e-5, 1e-4)),
+    ("c128", {"fuse_k": 2, "tile_m": 11}, (4, 1), (1e-11, 1e-10)),
+], ids=["c64_tile11", "c64_fuse3", "c128_fuse2"])
+def test_layered_options_against_oracle(q, dtype, options, layout, tol):
+    run_checks(q, dtype, [11, 12, 13, 14, 9], 60, 700, tol[0], tol[1], layout, options=options)
+
+
+def test_batch_autotune_choice_is_a_candidate_and_correct(q):
+    ns = [12, 13, 11, 14, 10, 12]
+    circs = [param_circuit(n, 50, 7, 800 + i) for i, n in enumerate(ns)]
+    obs = [observable(n, 900 + i) for i, n in enumerate(ns)]
+    params = np.random.default_rng(81).uniform(0, TWO_PI, size=sum(c.nparams for c in circs))
+    best, ms = q.Batch.autotune(circs, obs, params, "c64", reps=2)
+    assert best["fuse_k"] in (1, 2, 3) and best["tile_m"] in (11, 12) and ms > 0.0
+    b = q.Batch(circs, obs, "c64", options=best)
+    e, g = b.run(params)
+    b.close()
+    off = 0
+    for i, (c, H) in enumerate(zip(circs, obs)):
+        p = params[off:off + c.nparams]
+        ref_e = O.energy(c, p, H, threaded=True)
+        assert abs(e[i] - ref_e) < 2e-5 * max(1.0, abs(ref_e))
+        assert rel(g[off:off + c.nparams], O.param_shift_grad(c, p, H, threaded=True)) < 1e-4
+        off += c.nparams
