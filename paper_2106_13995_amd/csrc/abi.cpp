@@ -7,6 +7,7 @@
 #include <map>
 #include <new>
 
+#include "batch.h"
 #include "qsim_internal.h"
 
 namespace qsim {
@@ -470,6 +471,7 @@ qsim_status qsim_free(qsim_state s) {
     (void)hipStreamSynchronize(s->stream);
     s->plans.clear();
     s->adj_plans.clear();
+    s->adj_lplans.clear();
     s->transient.reset();
     if (s->adj_h) (void)hipFree(s->adj_h);
     if (s->adj_lam) (void)hipFree(s->adj_lam);
@@ -496,6 +498,7 @@ qsim_status qsim_set_stream(qsim_state s, void *hip_stream) {
         ap->fwd.dev_stream = ap->rev.dev_stream = s->stream;
         ap->dev_stream = s->stream;
     }
+    for (auto &lp : s->adj_lplans) lp->dev_stream = s->stream;
     if (s->transient) s->transient->dev_stream = s->stream;
     return QSIM_OK;
 }
@@ -1150,6 +1153,63 @@ static qsim_status get_adjoint_plan(qsim_state s, const qsim_circuit *c, int64_t
     return QSIM_OK;
 }
 
+// The layered adjoint plan of (circuit structure, parameter count,
+// observable) on this state, planned and uploaded on first use; *out is
+// null when the circuit cannot run layered.
+static qsim_status get_layered_adjoint(qsim_state s, const qsim_circuit *c, int64_t nparams, const qsim_pauli_sum *H,
+                                       LayeredAdjointPlan **out) {
+    *out = nullptr;
+    std::string key;
+    auto put = [&key](const void *p, size_t n) { key.append(static_cast<const char *>(p), n); };
+    put(&nparams, sizeof nparams);
+    for (int i = 0; i < c->nops; ++i) {
+        qsim_op op = c->ops[i];
+        if (op.param >= 0) op.angles[0] = op.angles[1] = op.angles[2] = 0.0;
+        put(&op, sizeof op);
+    }
+    if (c->mats && c->nmats > 0) put(c->mats, sizeof(double) * 2 * size_t(c->nmats));
+    put(&H->nterms, sizeof H->nterms);
+    if (H->nterms > 0) put(H->terms, sizeof(qsim_pauli_term) * size_t(H->nterms));
+    for (auto &lp : s->adj_lplans)
+        if (lp->key == key) {
+            lp->last_use = ++s->use_clock;
+            if (lp->ok) *out = lp.get();
+            return QSIM_OK;
+        }
+    std::unique_ptr<LayeredAdjointPlan> lp(new (std::nothrow) LayeredAdjointPlan());
+    if (!lp) return set_error(QSIM_ERR_OOM, "host allocation failed");
+    qsim_status st = plan_layered_adjoint(c, nparams, H, s->dtype, lp->la, &lp->ok);
+    if (st != QSIM_OK) return st;
+    if (lp->ok) {
+        const size_t bytes = lp->la.host.size();
+        if (hipMallocAsync(&lp->dev, bytes, s->stream) != hipSuccess) {
+            (void)hipGetLastError();
+            lp->dev = nullptr;
+            return set_error(QSIM_ERR_OOM, "cannot allocate device memory for the adjoint plan");
+        }
+        lp->dev_stream = s->stream;
+        st = ensure_pinned(s, bytes);
+        if (st != QSIM_OK) return st;
+        std::memcpy(s->pinned, lp->la.host.data(), bytes);
+        st = upload_staged(s, lp->dev, bytes);
+        if (st != QSIM_OK) return st;
+        QSIM_HIP(s, batch_layer_setup(s->dtype, lp->la.ld.R), "layered kernel set-up");
+    }
+    if (s->adj_lplans.size() >= kMaxAdjointPlans) {
+        auto lru = std::min_element(
+            s->adj_lplans.begin(), s->adj_lplans.end(),
+            [](const std::unique_ptr<LayeredAdjointPlan> &a, const std::unique_ptr<LayeredAdjointPlan> &b) {
+                return a->last_use < b->last_use;
+            });
+        s->adj_lplans.erase(lru);   // released in stream order
+    }
+    lp->key = std::move(key);
+    lp->last_use = ++s->use_clock;
+    if (lp->ok) *out = lp.get();
+    s->adj_lplans.push_back(std::move(lp));
+    return QSIM_OK;
+}
+
 static bool on_device(const void *p) {
     hipPointerAttribute_t attr;
     if (hipPointerGetAttributes(&attr, p) != hipSuccess) {
@@ -1178,10 +1238,35 @@ qsim_status qsim_adjoint_grad(qsim_state s, const qsim_circuit *c, const double 
             return set_error(QSIM_ERR_ARG, "Pauli mask has a bit at or above n");
     if (!on_device(energy_dev) || (nparams > 0 && (!on_device(params_dev) || !on_device(grad_dev))))
         return set_error(QSIM_ERR_ARG, "params, energy and grad must be device memory");
+    const size_t sbytes = amp_bytes(s->dtype) << s->n;
+    // states of 2^11 amplitudes and more without checkpoints: the
+    // register-staged layered passes of the batch, one circuit
+    if (!(opts && opts->checkpoints > 0) && !(opts && opts->tile_m > 0)) {
+        LayeredAdjointPlan *lp = nullptr;
+        st = get_layered_adjoint(s, c, nparams, H, &lp);
+        if (st != QSIM_OK) return st;
+        if (lp) {
+            if (!s->adj_lam) {
+                if (hipMalloc(&s->adj_lam, sbytes) != hipSuccess) {
+                    (void)hipGetLastError();
+                    s->adj_lam = nullptr;
+                    return set_error(QSIM_ERR_OOM, "cannot allocate the adjoint state");
+                }
+            }
+            st = ensure_scratch(s, lp->la.scratch_bytes);
+            if (st != QSIM_OK) return st;
+            bind_layered_adjoint(lp->la, lp->dev, s->data, s->adj_lam, s->scratch, params_dev, energy_dev, grad_dev);
+            QSIM_HIP(s, injected_fault(), "injected fault (QSIM_FAULT)");
+            prof_begin(s, QSIM_KCLASS_ADJOINT, lp->la.pass_bytes, 0.0);
+            const hipError_t e = launch_batch_layered(s->stream, s->dtype, lp->la.ld);
+            prof_end(s);
+            if (e != hipSuccess) return device_error(s, e, "layered adjoint");
+            return QSIM_OK;
+        }
+    }
     AdjointPlan *ap = nullptr;
     st = get_adjoint_plan(s, c, nparams, opts, &ap);
     if (st != QSIM_OK) return st;
-    const size_t sbytes = amp_bytes(s->dtype) << s->n;
     if (!s->adj_lam) {
         if (hipMalloc(&s->adj_lam, sbytes) != hipSuccess) {
             (void)hipGetLastError();

@@ -81,6 +81,367 @@ void pack_pool(const std::vector<cd> &pool, char *dst) {
 
 }  // namespace
 
+namespace qsim {
+
+// Plans circuit c with observable H as one batch program and appends it to
+// t: layered (register-staged passes, tiles of mL qubits) when c fills whole
+// tiles and every pass can be staged, else for the persistent kernel, unless
+// layered_only (then *is_layered is false and nothing is appended).
+qsim_status add_batch_program(BatchTables &t, const qsim_circuit &c, const qsim_pauli_sum &H, int dtype, int mL,
+                              int fuse_k, bool layered_only, bool *is_layered) {
+    std::vector<BatchProgram> &progs = t.progs;
+    std::vector<BatchPass> &passes = t.passes;
+    std::vector<TileOp> &ops = t.ops;
+    std::vector<RegStage> &stages = t.stages;
+    std::vector<RegOp> &rops = t.rops;
+    std::vector<cd> &pool = t.pool;
+    std::vector<BatchHGroup> &hgroups = t.hgroups;
+    std::vector<BatchHTerm> &hterms = t.hterms;
+    std::vector<int32_t> &probe_row = t.probe_row, &probe_idx = t.probe_idx;
+    std::vector<HostGate> fwd(size_t(c.nops)), rev;
+    int64_t np = 0;
+    for (int o = 0; o < c.nops; ++o)
+        if (c.ops[o].param >= 0) np = std::max<int64_t>(np, c.ops[o].param + 1);
+    std::vector<double> zeros(size_t(std::max<int64_t>(np, 1)), 0.0);
+    for (int o = 0; o < c.nops; ++o) {
+        make_gate(&c, o, zeros.data(), np, fwd[size_t(o)]);
+        if (c.ops[o].param >= 0) {
+            fwd[size_t(o)].rot_gen = rotation_generator(c.ops[o].kind);
+            fwd[size_t(o)].rot_param = c.ops[o].param;
+        }
+    }
+    if (fuse_k > 1) {
+        // runs of fixed gates merged into blocks of at most fuse_k qubits
+        // (the parametric rotations between them stay as they are)
+        std::vector<HostGate> merged, run;
+        for (HostGate &g : fwd) {
+            if (g.rot_gen) {
+                for (HostGate &f : fuse_gates(run, fuse_k)) merged.push_back(std::move(f));
+                run.clear();
+                merged.push_back(std::move(g));
+            } else {
+                run.push_back(std::move(g));
+            }
+        }
+        for (HostGate &f : fuse_gates(run, fuse_k)) merged.push_back(std::move(f));
+        fwd.swap(merged);
+    }
+    for (int o = int(fwd.size()) - 1; o >= 0; --o) {
+        const HostGate &g = fwd[size_t(o)];
+        if (g.rot_gen) {
+            HostGate pr;
+            pr.k = 1;
+            pr.targets[0] = g.targets[0];
+            pr.probe_gen = g.rot_gen;
+            pr.probe_slot = g.rot_param;
+            rev.push_back(pr);
+            HostGate inv = g;
+            inv.rot_inv = 1;
+            rev.push_back(inv);
+        } else {
+            HostGate inv = g;
+            const int d = 1 << g.k;
+            for (int r = 0; r < d; ++r)
+                for (int cc = 0; cc < d; ++cc) inv.M[size_t(r) * d + cc] = std::conj(g.M[size_t(cc) * d + r]);
+            rev.push_back(std::move(inv));
+        }
+    }
+    BatchProgram bp{};
+    bp.n = c.n;
+    bp.m = std::min(c.n, batch_tile_max(dtype));
+    if (c.n >= mL) bp.m = mL;
+    // Circuits that fill whole tiles run layered, register-staged
+    // throughout; a program with a pass that cannot be staged (a dense
+    // block on more than three qubits) and smaller circuits run in the
+    // persistent kernel, from LDS.
+    bool layered = bp.m == mL;
+    Plan plans[2];
+    for (int attempt = 0; attempt < 2; ++attempt) {
+        bool ok = true;
+        for (int dir = 0; dir < 2; ++dir) {
+            plans[dir] = Plan();
+            plans[dir].n = c.n;
+            plans[dir].dtype = dtype;
+            std::vector<HostGate> items = dir == 0 ? fwd : rev;
+            if (dir == 0 && items.empty() && layered) {
+                // an identity on qubit 0 gives the forward sweep the pass
+                // that starts psi at |0...0>
+                HostGate id;
+                id.k = 1;
+                id.M = {cd(1.0), cd(0.0), cd(0.0), cd(1.0)};
+                items.push_back(id);
+            }
+            // batch tiles hold L + 6 qubits, so the planner never widens them
+            if (build_tile_plan(plans[dir], items, bp.m, 1, layered) != bp.m)
+                return fail(QSIM_ERR_UNSUPPORTED, "a batch program: the planner could not place every op");
+            if (layered)
+                for (const Pass &p : plans[dir].passes) ok = ok && p.reg_r == mL - 8;
+        }
+        if (ok) break;
+        if (layered_only) {
+            *is_layered = false;
+            return QSIM_OK;
+        }
+        layered = false;
+    }
+    if (!layered && bp.m < c.n) t.nonsingle_max_n = std::max(t.nonsingle_max_n, c.n);
+    bp.layered = layered ? 1 : 0;
+    for (int dir = 0; dir < 2; ++dir) {
+        Plan &plan = plans[dir];
+        if (dir == 0 && plan.passes.empty()) {
+            // one empty forward pass initialises psi
+            Pass p;
+            p.kind = PASS_TILE;
+            p.m = bp.m;
+            p.L = std::min(bp.m, dtype == QSIM_C128 ? 4 : 5);
+            for (int q = p.L; q < c.n && int(p.hpos.size()) < bp.m - p.L; ++q) p.hpos.push_back(q);
+            plan.passes.push_back(p);
+        }
+        const int first = int(passes.size());
+        const int op_base = int(ops.size());
+        const int pool_base = int(pool.size());
+        for (const Pass &p : plan.passes) {
+            BatchPass bps{};
+            bps.L = p.L;
+            bps.H = int(p.hpos.size());
+            for (int i = 0; i < bps.H; ++i) bps.hpos[i] = p.hpos[size_t(i)];
+            bps.op_begin = op_base + p.op_begin;
+            bps.op_end = op_base + p.op_end;
+            for (int o = p.op_begin; o < p.op_end; ++o) {
+                TileOp t = plan.tile_ops[size_t(o)];
+                if (t.type == 0 || t.type == 1 || t.type == 5) t.moff += pool_base + p.pool_begin;
+                ops.push_back(t);
+            }
+            if (layered) {
+                bps.reg_r = p.reg_r;
+                const int rop0 = int(rops.size());
+                for (int o = p.rop_begin; o < p.rop_end; ++o) {
+                    RegOp r = plan.reg_ops[size_t(o)];
+                    // rotations and probes name a parameter, not a pool
+                    // entry; a probe's jmatch becomes its index in the
+                    // sweep (a fused probe's rotation is the inverse)
+                    if (r.type == 9 || r.type == 10)
+                        r.jmatch = bp.nprobes++;
+                    else if (r.type != 8)
+                        r.moff += pool_base + p.pool_begin;
+                    rops.push_back(r);
+                }
+                bps.stage_begin = int(stages.size());
+                for (int si = p.stage_begin; si < p.stage_end; ++si) {
+                    RegStage st = plan.reg_stages[size_t(si)];
+                    st.op_begin += rop0;
+                    st.op_end += rop0;
+                    stages.push_back(st);
+                }
+                bps.stage_end = int(stages.size());
+                for (int i = 0; i < 8; ++i) {
+                    bps.ld_t[i] = p.ld_t[i];
+                    bps.st_t[i] = p.st_t[i];
+                }
+                for (int i = 0; i < kRegBitsMax; ++i) {
+                    bps.ld_r[i] = p.ld_r[i];
+                    bps.st_r[i] = p.st_r[i];
+                }
+            }
+            passes.push_back(bps);
+        }
+        pool.insert(pool.end(), plan.tile_pool.begin(), plan.tile_pool.end());
+        if (dir == 0) {
+            bp.fwd_begin = first;
+            bp.fwd_end = int(passes.size());
+        } else {
+            bp.rev_begin = first;
+            bp.rev_end = int(passes.size());
+        }
+    }
+    if (layered) {
+        // parameter -> its probes (CSR), in sweep order
+        bp.nparams = int(np);
+        bp.row_off = int(probe_row.size());
+        std::vector<std::vector<int32_t>> of(static_cast<size_t>(np));
+        for (int pi2 = bp.rev_begin; pi2 < bp.rev_end; ++pi2)
+            for (int si = passes[size_t(pi2)].stage_begin; si < passes[size_t(pi2)].stage_end; ++si)
+                for (int o = stages[size_t(si)].op_begin; o < stages[size_t(si)].op_end; ++o)
+                    if (rops[size_t(o)].type == 9 || rops[size_t(o)].type == 10)
+                        of[size_t(rops[size_t(o)].moff)].push_back(rops[size_t(o)].jmatch);
+        int32_t at = int32_t(probe_idx.size());
+        for (int64_t j = 0; j < np; ++j) {
+            probe_row.push_back(at);
+            for (int32_t k : of[size_t(j)]) probe_idx.push_back(k);
+            at = int32_t(probe_idx.size());
+        }
+        probe_row.push_back(at);
+    }
+    std::map<uint64_t, std::vector<int>> byx;
+    for (int t = 0; t < H.nterms; ++t) byx[H.terms[t].xmask].push_back(t);
+    bp.hg_begin = int(hgroups.size());
+    for (auto &kv : byx) {
+        BatchHGroup g{};
+        g.x = kv.first;
+        g.first = int(hterms.size());
+        g.count = int(kv.second.size());
+        hgroups.push_back(g);
+        for (int t : kv.second) {
+            const qsim_pauli_term &pt = H.terms[t];
+            const int ny = __builtin_popcountll(pt.xmask & pt.zmask) & 3;
+            const double re[4] = {1, 0, -1, 0}, im[4] = {0, 1, 0, -1};
+            BatchHTerm ht{};
+            ht.wr = pt.coeff * re[ny];
+            ht.wi = pt.coeff * im[ny];
+            ht.z = pt.zmask;
+            hterms.push_back(ht);
+        }
+    }
+    bp.hg_end = int(hgroups.size());
+    progs.push_back(bp);
+    *is_layered = layered;
+    return QSIM_OK;
+}
+
+qsim_status plan_layered_adjoint(const qsim_circuit *c, int64_t nparams, const qsim_pauli_sum *H, int dtype,
+                                 LayeredAdjoint &out, bool *ok) {
+    *ok = false;
+    const int mL = batch_layer_default(dtype);
+    if (c->n < mL || c->nops < 1) return QSIM_OK;
+    // parameters in range and on RX, RY, RZ only (the LDS path reports the
+    // error otherwise)
+    for (int o = 0; o < c->nops; ++o)
+        if (c->ops[o].param >= nparams || (c->ops[o].param >= 0 && !rotation_generator(c->ops[o].kind)))
+            return QSIM_OK;
+    BatchTables t;
+    bool lay = false;
+    qsim_status st = add_batch_program(t, *c, *H, dtype, mL, 1, true, &lay);
+    if (st != QSIM_OK || !lay) return st;
+    const BatchProgram &pg = t.progs[0];
+    BatchLCirc l{};
+    l.circ = 0;
+    l.prog = 0;
+    l.ntiles = 1 << (pg.n - pg.m);
+    l.nchunks = int(std::max<int64_t>(1, (int64_t(1) << pg.n) / kBatchChunk));
+    l.param_off = 0;
+    l.nparams = int(nparams);
+    l.gfirst = 0;
+    l.psi_off = l.lam_off = 0;   // the state and the second state, each its own base
+    l.pp_off = l.ep_off = 0;
+    std::vector<BatchWork> works;
+    std::vector<BatchStep> steps;
+    auto layer = [&](int kind, int pass) {
+        BatchStep s{};
+        s.kind = kind;
+        s.init = 0;   // the forward sweep starts from the state's content
+        s.wbegin = int(works.size());
+        BatchWork w{};
+        w.lc = 0;
+        w.pass = pass;
+        w.first = 0;
+        w.count = uint32_t(kind == 2 ? l.nchunks : l.ntiles);
+        works.push_back(w);
+        s.wend = int(works.size());
+        s.wgs = w.count;
+        s.lc_begin = 0;
+        s.lc_end = 1;
+        steps.push_back(s);
+    };
+    for (int p = pg.fwd_begin; p < pg.fwd_end; ++p) layer(0, p);
+    layer(2, -1);
+    for (int p = pg.rev_begin; p < pg.rev_end; ++p) layer(1, p);
+    BatchStep gr{};
+    gr.kind = 3;
+    gr.lc_begin = 0;
+    gr.lc_end = 1;
+    gr.gw_begin = 0;
+    gr.gw_end = nparams;
+    steps.push_back(gr);
+    const double tile = double(amp_bytes(dtype)) * std::ldexp(1.0, mL);
+    out.pass_bytes = (2.0 * double(pg.fwd_end - pg.fwd_begin) + 4.0 * double(pg.rev_end - pg.rev_begin)) * tile *
+                         double(l.ntiles) +
+                     2.0 * double(amp_bytes(dtype)) * std::ldexp(1.0, pg.n);
+    // packed tables
+    const size_t s = amp_bytes(dtype);
+    auto al = [](size_t v) { return (v + 255) & ~size_t(255); };
+    size_t off = 0;
+    auto place = [&](size_t bytes) {
+        const size_t o = off;
+        off = al(off + std::max<size_t>(bytes, 8));
+        return o;
+    };
+    out.o_progs = place(sizeof(BatchProgram) * t.progs.size());
+    out.o_passes = place(sizeof(BatchPass) * t.passes.size());
+    out.o_stages = place(sizeof(RegStage) * t.stages.size());
+    out.o_rops = place(sizeof(RegOp) * t.rops.size());
+    out.o_pool = place(s * t.pool.size());
+    out.o_hg = place(sizeof(BatchHGroup) * t.hgroups.size());
+    out.o_ht = place(sizeof(BatchHTerm) * t.hterms.size());
+    out.o_lc = place(sizeof(BatchLCirc));
+    out.o_works = place(sizeof(BatchWork) * works.size());
+    out.o_prow = place(sizeof(int32_t) * t.probe_row.size());
+    out.o_pidx = place(sizeof(int32_t) * t.probe_idx.size());
+    out.host.assign(off, 0);
+    char *h = out.host.data();
+    std::memcpy(h + out.o_progs, t.progs.data(), sizeof(BatchProgram) * t.progs.size());
+    std::memcpy(h + out.o_passes, t.passes.data(), sizeof(BatchPass) * t.passes.size());
+    if (!t.stages.empty()) std::memcpy(h + out.o_stages, t.stages.data(), sizeof(RegStage) * t.stages.size());
+    if (!t.rops.empty()) std::memcpy(h + out.o_rops, t.rops.data(), sizeof(RegOp) * t.rops.size());
+    if (dtype == QSIM_C64)
+        pack_pool<float>(t.pool, h + out.o_pool);
+    else
+        pack_pool<double>(t.pool, h + out.o_pool);
+    if (!t.hgroups.empty()) std::memcpy(h + out.o_hg, t.hgroups.data(), sizeof(BatchHGroup) * t.hgroups.size());
+    if (!t.hterms.empty()) std::memcpy(h + out.o_ht, t.hterms.data(), sizeof(BatchHTerm) * t.hterms.size());
+    std::memcpy(h + out.o_lc, &l, sizeof(BatchLCirc));
+    std::memcpy(h + out.o_works, works.data(), sizeof(BatchWork) * works.size());
+    if (!t.probe_row.empty()) std::memcpy(h + out.o_prow, t.probe_row.data(), sizeof(int32_t) * t.probe_row.size());
+    if (!t.probe_idx.empty()) std::memcpy(h + out.o_pidx, t.probe_idx.data(), sizeof(int32_t) * t.probe_idx.size());
+    // the call's scratch: rotation table, probe partials, energy partials
+    size_t so = 0;
+    auto splace = [&](size_t bytes) {
+        const size_t o = so;
+        so = al(so + std::max<size_t>(bytes, 8));
+        return o;
+    };
+    out.o_trig = splace(4 * sizeof(double) * size_t(std::max<int64_t>(nparams, 1)));
+    out.o_ppart = splace(sizeof(double) * size_t(pg.nprobes) * size_t(l.ntiles));
+    out.o_epart = splace(sizeof(double) * size_t(l.nchunks));
+    out.scratch_bytes = so;
+    BatchLayerDevice &ld = out.ld;
+    ld = BatchLayerDevice{};
+    ld.nlc = 1;
+    ld.nparams = nparams;
+    ld.want_grad = 1;
+    ld.R = mL - 8;
+    ld.steps = std::move(steps);
+    *ok = true;
+    return QSIM_OK;
+}
+
+void bind_layered_adjoint(LayeredAdjoint &la, void *dev, void *psi, void *lam, void *scratch,
+                          const double *params_dev, double *energy_dev, double *grad_dev) {
+    char *d = static_cast<char *>(dev);
+    char *sc = static_cast<char *>(scratch);
+    BatchLayerDevice &ld = la.ld;
+    ld.lc = reinterpret_cast<const BatchLCirc *>(d + la.o_lc);
+    ld.works = reinterpret_cast<const BatchWork *>(d + la.o_works);
+    ld.progs = reinterpret_cast<const BatchProgram *>(d + la.o_progs);
+    ld.passes = reinterpret_cast<const BatchPass *>(d + la.o_passes);
+    ld.stages = reinterpret_cast<const RegStage *>(d + la.o_stages);
+    ld.rops = reinterpret_cast<const RegOp *>(d + la.o_rops);
+    ld.pool = d + la.o_pool;
+    ld.hgroups = reinterpret_cast<const BatchHGroup *>(d + la.o_hg);
+    ld.hterms = reinterpret_cast<const BatchHTerm *>(d + la.o_ht);
+    ld.probe_row = reinterpret_cast<const int32_t *>(d + la.o_prow);
+    ld.probe_idx = reinterpret_cast<const int32_t *>(d + la.o_pidx);
+    ld.params = params_dev;
+    ld.trig = reinterpret_cast<double *>(sc + la.o_trig);
+    ld.ppart = reinterpret_cast<double *>(sc + la.o_ppart);
+    ld.epart = reinterpret_cast<double *>(sc + la.o_epart);
+    ld.energies = energy_dev;
+    ld.grads = grad_dev;
+    ld.arena = psi;
+    ld.lam_arena = lam;
+}
+
+}  // namespace qsim
+
 extern "C" {
 
 qsim_status qsim_batch_create(int ncirc, const qsim_circuit *circs, const int64_t *param_offsets,
@@ -145,215 +506,26 @@ qsim_status qsim_batch_create(int ncirc, const qsim_circuit *circs, const int64_
     b->programs = int(prog_circ.size());
 
     // programs
-    std::vector<BatchProgram> progs;
-    std::vector<BatchPass> passes;
-    std::vector<TileOp> ops;
-    std::vector<RegStage> stages;
-    std::vector<RegOp> rops;
-    std::vector<cd> pool;
-    std::vector<BatchHGroup> hgroups;
-    std::vector<BatchHTerm> hterms;
-    std::vector<int32_t> probe_row, probe_idx;
-    int nonsingle_max_n = 0;
+    BatchTables tabs;
     for (size_t pi = 0; pi < prog_circ.size(); ++pi) {
-        const qsim_circuit &c = *prog_circ[pi];
-        const qsim_pauli_sum &H = *prog_H[pi];
-        std::vector<HostGate> fwd(size_t(c.nops)), rev;
-        int64_t np = 0;
-        for (int o = 0; o < c.nops; ++o)
-            if (c.ops[o].param >= 0) np = std::max<int64_t>(np, c.ops[o].param + 1);
-        std::vector<double> zeros(size_t(std::max<int64_t>(np, 1)), 0.0);
-        for (int o = 0; o < c.nops; ++o) {
-            make_gate(&c, o, zeros.data(), np, fwd[size_t(o)]);
-            if (c.ops[o].param >= 0) {
-                fwd[size_t(o)].rot_gen = rotation_generator(c.ops[o].kind);
-                fwd[size_t(o)].rot_param = c.ops[o].param;
-            }
+        b->max_n = std::max(b->max_n, prog_circ[pi]->n);
+        bool lay = false;
+        const qsim_status st = add_batch_program(tabs, *prog_circ[pi], *prog_H[pi], dtype, mL, fuse_k, false, &lay);
+        if (st != QSIM_OK) {
+            delete b;
+            return st;
         }
-        if (fuse_k > 1) {
-            // runs of fixed gates merged into blocks of at most fuse_k qubits
-            // (the parametric rotations between them stay as they are)
-            std::vector<HostGate> merged, run;
-            for (HostGate &g : fwd) {
-                if (g.rot_gen) {
-                    for (HostGate &f : fuse_gates(run, fuse_k)) merged.push_back(std::move(f));
-                    run.clear();
-                    merged.push_back(std::move(g));
-                } else {
-                    run.push_back(std::move(g));
-                }
-            }
-            for (HostGate &f : fuse_gates(run, fuse_k)) merged.push_back(std::move(f));
-            fwd.swap(merged);
-        }
-        for (int o = int(fwd.size()) - 1; o >= 0; --o) {
-            const HostGate &g = fwd[size_t(o)];
-            if (g.rot_gen) {
-                HostGate pr;
-                pr.k = 1;
-                pr.targets[0] = g.targets[0];
-                pr.probe_gen = g.rot_gen;
-                pr.probe_slot = g.rot_param;
-                rev.push_back(pr);
-                HostGate inv = g;
-                inv.rot_inv = 1;
-                rev.push_back(inv);
-            } else {
-                HostGate inv = g;
-                const int d = 1 << g.k;
-                for (int r = 0; r < d; ++r)
-                    for (int cc = 0; cc < d; ++cc) inv.M[size_t(r) * d + cc] = std::conj(g.M[size_t(cc) * d + r]);
-                rev.push_back(std::move(inv));
-            }
-        }
-        BatchProgram bp{};
-        bp.n = c.n;
-        bp.m = std::min(c.n, batch_tile_max(dtype));
-        if (c.n >= mL) bp.m = mL;
-        b->max_n = std::max(b->max_n, c.n);
-        // Circuits that fill whole tiles run layered, register-staged
-        // throughout; a program with a pass that cannot be staged (a dense
-        // block on more than three qubits) and smaller circuits run in the
-        // persistent kernel, from LDS.
-        bool layered = bp.m == mL;
-        Plan plans[2];
-        for (int attempt = 0; attempt < 2; ++attempt) {
-            bool ok = true;
-            for (int dir = 0; dir < 2; ++dir) {
-                plans[dir] = Plan();
-                plans[dir].n = c.n;
-                plans[dir].dtype = dtype;
-                std::vector<HostGate> items = dir == 0 ? fwd : rev;
-                if (dir == 0 && items.empty() && layered) {
-                    // an identity on qubit 0 gives the forward sweep the pass
-                    // that starts psi at |0...0>
-                    HostGate id;
-                    id.k = 1;
-                    id.M = {cd(1.0), cd(0.0), cd(0.0), cd(1.0)};
-                    items.push_back(id);
-                }
-                // batch tiles hold L + 6 qubits, so the planner never widens them
-                if (build_tile_plan(plans[dir], items, bp.m, 1, layered) != bp.m) {
-                    delete b;
-                    return fail(QSIM_ERR_UNSUPPORTED, "a batch program: the planner could not place every op");
-                }
-                if (layered)
-                    for (const Pass &p : plans[dir].passes) ok = ok && p.reg_r == mL - 8;
-            }
-            if (ok) break;
-            layered = false;
-        }
-        if (!layered && bp.m < c.n) nonsingle_max_n = std::max(nonsingle_max_n, c.n);
-        bp.layered = layered ? 1 : 0;
-        for (int dir = 0; dir < 2; ++dir) {
-            Plan &plan = plans[dir];
-            if (dir == 0 && plan.passes.empty()) {
-                // one empty forward pass initialises psi
-                Pass p;
-                p.kind = PASS_TILE;
-                p.m = bp.m;
-                p.L = std::min(bp.m, dtype == QSIM_C128 ? 4 : 5);
-                for (int q = p.L; q < c.n && int(p.hpos.size()) < bp.m - p.L; ++q) p.hpos.push_back(q);
-                plan.passes.push_back(p);
-            }
-            const int first = int(passes.size());
-            const int op_base = int(ops.size());
-            const int pool_base = int(pool.size());
-            for (const Pass &p : plan.passes) {
-                BatchPass bps{};
-                bps.L = p.L;
-                bps.H = int(p.hpos.size());
-                for (int i = 0; i < bps.H; ++i) bps.hpos[i] = p.hpos[size_t(i)];
-                bps.op_begin = op_base + p.op_begin;
-                bps.op_end = op_base + p.op_end;
-                for (int o = p.op_begin; o < p.op_end; ++o) {
-                    TileOp t = plan.tile_ops[size_t(o)];
-                    if (t.type == 0 || t.type == 1 || t.type == 5) t.moff += pool_base + p.pool_begin;
-                    ops.push_back(t);
-                }
-                if (layered) {
-                    bps.reg_r = p.reg_r;
-                    const int rop0 = int(rops.size());
-                    for (int o = p.rop_begin; o < p.rop_end; ++o) {
-                        RegOp r = plan.reg_ops[size_t(o)];
-                        // rotations and probes name a parameter, not a pool
-                        // entry; a probe's jmatch becomes its index in the
-                        // sweep (a fused probe's rotation is the inverse)
-                        if (r.type == 9 || r.type == 10)
-                            r.jmatch = bp.nprobes++;
-                        else if (r.type != 8)
-                            r.moff += pool_base + p.pool_begin;
-                        rops.push_back(r);
-                    }
-                    bps.stage_begin = int(stages.size());
-                    for (int si = p.stage_begin; si < p.stage_end; ++si) {
-                        RegStage st = plan.reg_stages[size_t(si)];
-                        st.op_begin += rop0;
-                        st.op_end += rop0;
-                        stages.push_back(st);
-                    }
-                    bps.stage_end = int(stages.size());
-                    for (int i = 0; i < 8; ++i) {
-                        bps.ld_t[i] = p.ld_t[i];
-                        bps.st_t[i] = p.st_t[i];
-                    }
-                    for (int i = 0; i < kRegBitsMax; ++i) {
-                        bps.ld_r[i] = p.ld_r[i];
-                        bps.st_r[i] = p.st_r[i];
-                    }
-                }
-                passes.push_back(bps);
-            }
-            pool.insert(pool.end(), plan.tile_pool.begin(), plan.tile_pool.end());
-            if (dir == 0) {
-                bp.fwd_begin = first;
-                bp.fwd_end = int(passes.size());
-            } else {
-                bp.rev_begin = first;
-                bp.rev_end = int(passes.size());
-            }
-        }
-        if (layered) {
-            // parameter -> its probes (CSR), in sweep order
-            bp.nparams = int(np);
-            bp.row_off = int(probe_row.size());
-            std::vector<std::vector<int32_t>> of(static_cast<size_t>(np));
-            for (int pi2 = bp.rev_begin; pi2 < bp.rev_end; ++pi2)
-                for (int si = passes[size_t(pi2)].stage_begin; si < passes[size_t(pi2)].stage_end; ++si)
-                    for (int o = stages[size_t(si)].op_begin; o < stages[size_t(si)].op_end; ++o)
-                        if (rops[size_t(o)].type == 9 || rops[size_t(o)].type == 10)
-                            of[size_t(rops[size_t(o)].moff)].push_back(rops[size_t(o)].jmatch);
-            int32_t at = int32_t(probe_idx.size());
-            for (int64_t j = 0; j < np; ++j) {
-                probe_row.push_back(at);
-                for (int32_t k : of[size_t(j)]) probe_idx.push_back(k);
-                at = int32_t(probe_idx.size());
-            }
-            probe_row.push_back(at);
-        }
-        std::map<uint64_t, std::vector<int>> byx;
-        for (int t = 0; t < H.nterms; ++t) byx[H.terms[t].xmask].push_back(t);
-        bp.hg_begin = int(hgroups.size());
-        for (auto &kv : byx) {
-            BatchHGroup g{};
-            g.x = kv.first;
-            g.first = int(hterms.size());
-            g.count = int(kv.second.size());
-            hgroups.push_back(g);
-            for (int t : kv.second) {
-                const qsim_pauli_term &pt = H.terms[t];
-                const int ny = __builtin_popcountll(pt.xmask & pt.zmask) & 3;
-                const double re[4] = {1, 0, -1, 0}, im[4] = {0, 1, 0, -1};
-                BatchHTerm ht{};
-                ht.wr = pt.coeff * re[ny];
-                ht.wi = pt.coeff * im[ny];
-                ht.z = pt.zmask;
-                hterms.push_back(ht);
-            }
-        }
-        bp.hg_end = int(hgroups.size());
-        progs.push_back(bp);
     }
+    std::vector<BatchProgram> &progs = tabs.progs;
+    std::vector<BatchPass> &passes = tabs.passes;
+    std::vector<TileOp> &ops = tabs.ops;
+    std::vector<RegStage> &stages = tabs.stages;
+    std::vector<RegOp> &rops = tabs.rops;
+    std::vector<cd> &pool = tabs.pool;
+    std::vector<BatchHGroup> &hgroups = tabs.hgroups;
+    std::vector<BatchHTerm> &hterms = tabs.hterms;
+    std::vector<int32_t> &probe_row = tabs.probe_row, &probe_idx = tabs.probe_idx;
+    const int nonsingle_max_n = tabs.nonsingle_max_n;
     // circuits, largest (2^n x ops) first; persistent ones in `order`, the
     // layered ones in `lcircs`
     std::vector<BatchCircuit> bc(static_cast<size_t>(ncirc));
@@ -617,6 +789,7 @@ qsim_status qsim_batch_create(int ncirc, const qsim_circuit *circs, const int64_
     ld.want_grad = b->want_grad;
     ld.steps = steps;
     ld.R = mL - 8;
+    ld.lam_arena = nullptr;
     hipError_t e = lcircs.empty() ? hipSuccess : batch_layer_setup(dtype, ld.R);
     if (e == hipSuccess) e = hipStreamCreateWithFlags(&b->cap_stream, hipStreamNonBlocking);
     if (e == hipSuccess) e = hipStreamBeginCapture(b->cap_stream, hipStreamCaptureModeThreadLocal);

@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <string>
 #include <vector>
 
 #include "qsim_internal.h"
@@ -132,6 +133,7 @@ struct BatchStep {
 };
 
 struct BatchLayerDevice {
+    void *lam_arena;         // base of lambda slots (null: the arena)
     const BatchLCirc *lc;
     int nlc;
     const BatchWork *works;
@@ -152,6 +154,62 @@ struct BatchLayerDevice {
     int want_grad;
     int R;                   // register bits per thread (tile width - 8)
     std::vector<BatchStep> steps;
+};
+
+// Host tables of batch programs (appended to by add_batch_program).
+struct BatchTables {
+    std::vector<BatchProgram> progs;
+    std::vector<BatchPass> passes;
+    std::vector<TileOp> ops;
+    std::vector<RegStage> stages;
+    std::vector<RegOp> rops;
+    std::vector<cd> pool;
+    std::vector<BatchHGroup> hgroups;
+    std::vector<BatchHTerm> hterms;
+    std::vector<int32_t> probe_row, probe_idx;
+    int nonsingle_max_n = 0;
+};
+
+// Plans circuit c with observable H as one batch program and appends it to
+// t: layered (register-staged passes, tiles of mL qubits) when c fills whole
+// tiles and every pass can be staged, else for the persistent kernel, unless
+// layered_only (then *is_layered is false and nothing is appended).
+qsim_status add_batch_program(BatchTables &t, const qsim_circuit &c, const qsim_pauli_sum &H, int dtype, int mL,
+                              int fuse_k, bool layered_only, bool *is_layered);
+
+// One circuit's adjoint gradient run layered (qsim_adjoint_grad on states of
+// 2^11 amplitudes and more): its tables packed for one upload, the launch
+// description, and the per-call scratch it needs (rotation table, probe and
+// energy partials).
+struct LayeredAdjoint {
+    std::vector<char> host;
+    size_t o_progs = 0, o_passes = 0, o_stages = 0, o_rops = 0, o_pool = 0, o_hg = 0, o_ht = 0, o_lc = 0,
+           o_works = 0, o_prow = 0, o_pidx = 0;
+    size_t o_trig = 0, o_ppart = 0, o_epart = 0, scratch_bytes = 0;   // offsets in the call's scratch
+    double pass_bytes = 0;
+    BatchLayerDevice ld{};
+};
+
+// Plans the layered adjoint of c (nparams parameters, observable H) on an
+// n-qubit state; *ok is false when some pass cannot be register-staged (the
+// caller then takes the LDS path).
+qsim_status plan_layered_adjoint(const qsim_circuit *c, int64_t nparams, const qsim_pauli_sum *H, int dtype,
+                                 LayeredAdjoint &out, bool *ok);
+// Points la.ld at the uploaded tables (dev), the state (psi), the second
+// state (lam), the call's scratch and the caller's parameters and outputs.
+void bind_layered_adjoint(LayeredAdjoint &la, void *dev, void *psi, void *lam, void *scratch,
+                          const double *params_dev, double *energy_dev, double *grad_dev);
+
+struct LayeredAdjointPlan {
+    std::string key;
+    bool ok = false;              // false: some pass cannot be staged (the LDS path runs it)
+    LayeredAdjoint la;
+    void *dev = nullptr;          // the uploaded tables
+    hipStream_t dev_stream = nullptr;
+    uint64_t last_use = 0;
+    ~LayeredAdjointPlan() {
+        if (dev) (void)hipFreeAsync(dev, dev_stream);
+    }
 };
 
 // Raises the layered kernels' LDS limits (before any capture).

@@ -38,6 +38,7 @@ struct LayerArgs {
     const c2_t<T> *pool;
     const double *trig;
     c2_t<T> *arena;
+    c2_t<T> *lam_arena;
     double *ppart;
     int wbegin, wend;
     int init;
@@ -170,7 +171,7 @@ __global__ void __launch_bounds__(kLayerThreads) k_batch_layer(const LayerArgs<T
     CT<T> *spool = (CT<T> *)(a.pool);
     const QSIM_CONST double *trig = (const QSIM_CONST double *)(a.trig) + 4 * c.param_off;
     c2_t<T> *psi = a.arena + c.psi_off;
-    c2_t<T> *lam = a.arena + c.lam_off;
+    c2_t<T> *lam = a.lam_arena + c.lam_off;
     const uint64_t base = layer_tile_base(ps, tile);
     const uint32_t t = threadIdx.x;
     T vr[NV], vi[NV];
@@ -314,6 +315,7 @@ struct EnergyArgs {
     const BatchHGroup *hgroups;
     const BatchHTerm *hterms;
     c2_t<T> *arena;
+    c2_t<T> *lam_arena;
     double *epart;
     int wbegin, wend;
     int want_grad;
@@ -338,7 +340,7 @@ __global__ void __launch_bounds__(kLayerThreads) k_batch_energy(const EnergyArgs
     const QSIM_CONST BatchHGroup *hg = (const QSIM_CONST BatchHGroup *)(a.hgroups);
     const QSIM_CONST BatchHTerm *ht = (const QSIM_CONST BatchHTerm *)(a.hterms);
     const c2_t<T> *src = a.arena + c.psi_off;
-    c2_t<T> *dst = a.arena + c.lam_off;
+    c2_t<T> *dst = a.lam_arena + c.lam_off;
     const uint64_t N = 1ull << pg.n;
     const uint64_t cbase = uint64_t(chunk) * kBatchChunk;
     double e = 0.0;
@@ -475,6 +477,7 @@ static hipError_t launch_layered_t(hipStream_t stream, const BatchLayerDevice &d
     la.pool = static_cast<const c2_t<T> *>(d.pool);
     la.trig = d.trig;
     la.arena = static_cast<c2_t<T> *>(d.arena);
+    la.lam_arena = static_cast<c2_t<T> *>(d.lam_arena ? d.lam_arena : d.arena);
     la.ppart = d.ppart;
     EnergyArgs<T> ea{};
     ea.lc = d.lc;
@@ -483,6 +486,7 @@ static hipError_t launch_layered_t(hipStream_t stream, const BatchLayerDevice &d
     ea.hgroups = d.hgroups;
     ea.hterms = d.hterms;
     ea.arena = static_cast<c2_t<T> *>(d.arena);
+    ea.lam_arena = la.lam_arena;
     ea.epart = d.epart;
     ea.want_grad = d.want_grad;
     if (d.nparams > 0)

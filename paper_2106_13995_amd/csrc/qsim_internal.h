@@ -303,6 +303,10 @@ struct AdjointPlan {
     }
 };
 
+// The adjoint of one circuit structure and observable run layered
+// (register-staged passes; defined with the batch tables).
+struct LayeredAdjointPlan;
+
 }  // namespace qsim
 
 struct qsim_state_s {
@@ -327,6 +331,7 @@ struct qsim_state_s {
     void *adj_ck = nullptr;                  // forward-state checkpoints of the adjoint method
     int adj_ck_count = 0;
     std::vector<std::unique_ptr<qsim::AdjointPlan>> adj_plans;
+    std::vector<std::unique_ptr<qsim::LayeredAdjointPlan>> adj_lplans;
     void *adj_h = nullptr;                   // the adjoint's Pauli sum on the device
     size_t adj_h_bytes = 0;
     std::string adj_h_key;                   // ... and the terms it was written from
