@@ -222,7 +222,7 @@ qsim_status add_batch_program(BatchTables &t, const qsim_circuit &c, const qsim_
                     // sweep (a fused probe's rotation is the inverse)
                     if (r.type == 9 || r.type == 10)
                         r.jmatch = bp.nprobes++;
-                    else if (r.type != 8)
+                    else if (r.type != 8 && r.type != 11)
                         r.moff += pool_base + p.pool_begin;
                     rops.push_back(r);
                 }

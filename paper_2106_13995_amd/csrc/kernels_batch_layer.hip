@@ -233,7 +233,7 @@ __global__ void __launch_bounds__(kLayerThreads) k_batch_layer(const LayerArgs<T
         for (int o = st.op_begin; o < st.op_end; ++o) {
             CRegOp &op = sop[o];
             const int code = op.code;
-            if (code < 240) {
+            if (code < 240 || code >= 288) {
                 run_op<T, R, 0, RA, true>(code, vr, vi, op, spool + 2 * op.moff, base, t, trig);
             } else if constexpr (!BOTH) {
                 __builtin_unreachable();   // forward passes hold no probes

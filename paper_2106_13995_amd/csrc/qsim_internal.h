@@ -129,7 +129,9 @@ struct RegOp {
     // 8 batched rotation exp(-i theta G / 2), theta the circuit's parameter
     // moff, G = X, Y, Z for rj[0] = 1, 2, 3, inverse when jmatch is 1,
     // 9 batched probe Im <lambda|G|psi> into gradient slot moff (G as in 8),
-    // 10 that probe followed by the inverse rotation of parameter moff;
+    // 10 that probe followed by the inverse rotation of parameter moff,
+    // 11 two rotations on register bit rb[0]: G = rj[0] (X or Y) of
+    // parameter moff, then G = rj[1] of parameter gj[0];
     // X and Y act on register bit rb[0], Z on the bit that rmask, tb[0] or
     // gp[0..1] names
     int32_t type;

@@ -393,14 +393,32 @@ __device__ __forceinline__ void brot_z(T *vr, T *vi, CRegOp &op, double P, doubl
         brot_z_lift<T, RA, false>(vr, vi, op, T(P), T(s), base, t);
 }
 
+// exp(-i theta Z / 2) on register bit B (lift3 multipliers as brot_bit).
+template <typename T, int RA, int B>
+__device__ __forceinline__ void brot_z_bit(T *vr, T *vi, double P, double s, bool neg) {
+    const T Pp = T(P), sp = T(s);
+#pragma unroll
+    for (int i = 0; i < (1 << RA); ++i) {
+        const bool one = (i >> B) & 1;
+        if (neg)
+            lift3(vr[i], vi[i], one ? Pp : -Pp, one ? sp : -sp, true);
+        else
+            lift3(vr[i], vi[i], one ? Pp : -Pp, one ? sp : -sp, false);
+    }
+}
+
 // Batched-circuit codes: rotation exp(-i theta G / 2) of parameter moff,
 // whose lifting form (P, s, cos) of the half angle is at trig[4 * moff]
 // (inverse when jmatch is 1: P and s negated): X on bit b -> 220 + b, Y on
 // bit b -> 228 + b, Z anywhere -> 236.
+// Two rotations on one register bit b, the first (G1 = X or Y, parameter
+// moff) then the second (G2 = X, Y or Z, parameter gj[0]), both forward:
+// 288 + 8 ((G1 - 1) 3 + G2 - 1) + b.
 template <int C, int R>
 __host__ __device__ constexpr bool ext_code_valid() {
     if (C >= 220 && C < 228) return C - 220 < R;
     if (C >= 228 && C < 236) return C - 228 < R;
+    if (C >= 288 && C < 336) return (C - 288) % 8 < R;
     return C == 236;
 }
 
@@ -410,10 +428,18 @@ __host__ __device__ constexpr bool ext_code_valid() {
 template <typename T, int R, int C, int RA = R, bool EXT = false>
 __device__ __forceinline__ void run_op(int code, T *vr, T *vi, CRegOp &op, CT<T> *U, uint64_t base, uint32_t t,
                                        const QSIM_CONST double *trig = nullptr) {
-    if constexpr (C <= (EXT ? 236 : 217)) {
+    if constexpr (C <= (EXT ? 335 : 217)) {
         if constexpr (code_valid<C, R>() || (EXT && ext_code_valid<C, R>())) {
             if (code == C) {
-                if constexpr (C >= 220) {
+                if constexpr (C >= 288) {
+                    constexpr int B = (C - 288) % 8, G1 = (C - 288) / 24 + 1, G2 = ((C - 288) / 8) % 3 + 1;
+                    const int m2 = op.gj[0];
+                    brot_bit<T, RA, B, G1>(vr, vi, trig[4 * op.moff], trig[4 * op.moff + 1], trig[4 * op.moff + 2] < 0.0);
+                    if constexpr (G2 == 3)
+                        brot_z_bit<T, RA, B>(vr, vi, trig[4 * m2], trig[4 * m2 + 1], trig[4 * m2 + 2] < 0.0);
+                    else
+                        brot_bit<T, RA, B, G2>(vr, vi, trig[4 * m2], trig[4 * m2 + 1], trig[4 * m2 + 2] < 0.0);
+                } else if constexpr (C >= 220) {
                     const double P = op.jmatch ? -trig[4 * op.moff] : trig[4 * op.moff];
                     const double sn = op.jmatch ? -trig[4 * op.moff + 1] : trig[4 * op.moff + 1];
                     const bool neg = trig[4 * op.moff + 2] < 0.0;
