@@ -73,6 +73,49 @@ k_dense_sweep(c2_t<T> *__restrict__ psi, const DenseArgs<T, K> a, uint64_t nthre
     }
 }
 
+// One-qubit gate on a low target t = B + 1 (t = 1..6, complex64, no
+// controls): lane l of a wave loads amplitudes 2l and 2l + 1 of the wave's
+// 128 with one 16-byte access, so every load and store instruction covers
+// 1 KiB contiguously; the target bit is lane bit B, and the partner
+// amplitudes come from lane l ^ 2^B by a cross-lane exchange.  Each lane
+// writes back its own two.  The grid is a whole number of waves.
+template <int B>
+__global__ void __launch_bounds__(kSweepThreads)
+k_lane_sweep1(float2 *__restrict__ psi, const DenseArgs<float, 1> a, uint64_t nthreads) {
+    const uint64_t tid = uint64_t(blockIdx.x) * kSweepThreads + threadIdx.x;
+    if (tid >= nthreads) return;
+    const f32x4 w = ld<true, f32x4>(psi + 2 * tid);
+    const float p0 = __shfl_xor(w.x, 1 << B, 64), p1 = __shfl_xor(w.y, 1 << B, 64);
+    const float p2 = __shfl_xor(w.z, 1 << B, 64), p3 = __shfl_xor(w.w, 1 << B, 64);
+    // this lane's half of the pair: row 0 (M00 self + M01 partner) or
+    // row 1 (M10 partner + M11 self)
+    const bool hi = (threadIdx.x >> B) & 1u;
+    const float sr = hi ? a.re[3] : a.re[0], si = hi ? a.im[3] : a.im[0];
+    const float orr = hi ? a.re[2] : a.re[1], oi = hi ? a.im[2] : a.im[1];
+    f32x4 o;
+    o.x = sr * w.x - si * w.y + orr * p0 - oi * p1;
+    o.y = sr * w.y + si * w.x + orr * p1 + oi * p0;
+    o.z = sr * w.z - si * w.w + orr * p2 - oi * p3;
+    o.w = sr * w.w + si * w.z + orr * p3 + oi * p2;
+    st<true, f32x4>(psi + 2 * tid, o);
+}
+
+static hipError_t lane_sweep1(qsim_state s, const DenseArgs<float, 1> &a, int t) {
+    auto *psi = static_cast<float2 *>(s->data);
+    // a multiple of 64 (n >= 7): lanes past the end leave as whole waves
+    const uint64_t nthr = 1ull << (s->n - 1);
+    const dim3 grid(unsigned((nthr + kSweepThreads - 1) / kSweepThreads));
+    switch (t) {
+        case 1: hipLaunchKernelGGL((k_lane_sweep1<0>), grid, dim3(kSweepThreads), 0, s->stream, psi, a, nthr); break;
+        case 2: hipLaunchKernelGGL((k_lane_sweep1<1>), grid, dim3(kSweepThreads), 0, s->stream, psi, a, nthr); break;
+        case 3: hipLaunchKernelGGL((k_lane_sweep1<2>), grid, dim3(kSweepThreads), 0, s->stream, psi, a, nthr); break;
+        case 4: hipLaunchKernelGGL((k_lane_sweep1<3>), grid, dim3(kSweepThreads), 0, s->stream, psi, a, nthr); break;
+        case 5: hipLaunchKernelGGL((k_lane_sweep1<4>), grid, dim3(kSweepThreads), 0, s->stream, psi, a, nthr); break;
+        default: hipLaunchKernelGGL((k_lane_sweep1<5>), grid, dim3(kSweepThreads), 0, s->stream, psi, a, nthr); break;
+    }
+    return hipGetLastError();
+}
+
 template <typename T, int K>
 static hipError_t dense_sweep_t(qsim_state s, const Pass &p) {
     DenseArgs<T, K> a{};
@@ -101,6 +144,10 @@ static hipError_t dense_sweep_t(qsim_state s, const Pass &p) {
     const uint64_t groups = 1ull << (s->n - np);
     auto *psi = static_cast<c2_t<T> *>(s->data);
     const bool nt = all[0] >= 4;
+    if constexpr (std::is_same<T, float>::value && K == 1) {
+        // low targets: whole-wave contiguous accesses and a lane exchange
+        if (p.nctrl == 0 && p.targets[0] >= 1 && p.targets[0] <= 6 && s->n >= 7) return lane_sweep1(s, a, p.targets[0]);
+    }
     if constexpr (std::is_same<T, float>::value) {
         if (all[0] >= 1 && groups >= 2) {
             const uint64_t nthr = groups / 2;
