@@ -116,6 +116,97 @@ static hipError_t lane_sweep1(qsim_state s, const DenseArgs<float, 1> &a, int t)
     return hipGetLastError();
 }
 
+// Dense K-qubit gate (K = 2, 3) with every target below qubit 7
+// (complex64, no controls): as k_lane_sweep1, lane l holds amplitudes 2l
+// and 2l + 1 of its wave's 128 (one 16-byte access; the wave moves 1 KiB
+// contiguously).  Target bits 1..6 are lane bits; Z0: qubit 0 is a target
+// too (both of a lane's amplitudes are in one group), else each belongs to
+// its own group.  The lane takes the group's other amplitudes from the
+// lanes that differ in the target lane bits (l ^ dl[e]) and forms
+// out(j) = sum over d of M[j][j ^ d] amp(j ^ d), the coefficients read by
+// local index from a table in LDS.
+struct LaneArgs {
+    float re[64], im[64];   // M, row-major, on the targets in ascending order
+    uint32_t dl[8];         // lane offset of partner e: e's bits on the target lane bits
+    int32_t lbit[3];        // lane bits of the targets above qubit 0, ascending
+};
+
+template <int K, bool Z0>
+__global__ void __launch_bounds__(kSweepThreads)
+k_lane_sweep(float2 *__restrict__ psi, const LaneArgs a, uint64_t nthreads) {
+    constexpr int KL = Z0 ? K - 1 : K;
+    constexpr int D = 1 << K;
+    __shared__ float2 coef[D * D];   // coef[j D + d] = M[j][j ^ d]
+    if (threadIdx.x < D * D) {
+        const int j = int(threadIdx.x) / D, d = int(threadIdx.x) % D;
+        coef[threadIdx.x] = float2{a.re[j * D + (j ^ d)], a.im[j * D + (j ^ d)]};
+    }
+    __syncthreads();
+    const uint64_t tid = uint64_t(blockIdx.x) * kSweepThreads + threadIdx.x;
+    if (tid >= nthreads) return;
+    const f32x4 w = ld<true, f32x4>(psi + 2 * tid);
+    float P[1 << KL][4];
+    P[0][0] = w.x; P[0][1] = w.y; P[0][2] = w.z; P[0][3] = w.w;
+#pragma unroll
+    for (int e = 1; e < (1 << KL); ++e) {
+        const int d = int(a.dl[e]);
+        P[e][0] = __shfl_xor(w.x, d, 64);
+        P[e][1] = __shfl_xor(w.y, d, 64);
+        P[e][2] = __shfl_xor(w.z, d, 64);
+        P[e][3] = __shfl_xor(w.w, d, 64);
+    }
+    const uint32_t lane = threadIdx.x & 63u;
+    uint32_t jl = 0;
+#pragma unroll
+    for (int b = 0; b < KL; ++b) jl |= ((lane >> a.lbit[b]) & 1u) << b;
+    float out[4];
+#pragma unroll
+    for (int s = 0; s < 2; ++s) {
+        const uint32_t jA = Z0 ? (uint32_t(s) | (jl << 1)) : jl;
+        float ar = 0.0f, ai = 0.0f;
+#pragma unroll
+        for (int dd = 0; dd < D; ++dd) {
+            const int e = Z0 ? (dd >> 1) : dd;
+            const int sub = Z0 ? (s ^ (dd & 1)) : s;
+            const float2 c = coef[jA * D + dd];
+            const float xr = P[e][2 * sub], xi = P[e][2 * sub + 1];
+            ar = fma(c.x, xr, fma(-c.y, xi, ar));
+            ai = fma(c.x, xi, fma(c.y, xr, ai));
+        }
+        out[2 * s] = ar;
+        out[2 * s + 1] = ai;
+    }
+    st<true, f32x4>(psi + 2 * tid, f32x4{out[0], out[1], out[2], out[3]});
+}
+
+template <int K>
+static hipError_t lane_sweep(qsim_state s, const Pass &p) {
+    LaneArgs a{};
+    constexpr int D = 1 << K;
+    for (int i = 0; i < D * D; ++i) {
+        a.re[i] = float(p.M[i].real());
+        a.im[i] = float(p.M[i].imag());
+    }
+    // targets are ascending (sweep passes hold the sorted form)
+    const bool z0 = p.targets[0] == 0;
+    int nl = 0;
+    for (int b = z0 ? 1 : 0; b < K; ++b) a.lbit[nl++] = p.targets[b] - 1;
+    for (int e = 0; e < (1 << nl); ++e) {
+        uint32_t d = 0;
+        for (int b = 0; b < nl; ++b)
+            if ((e >> b) & 1) d |= 1u << a.lbit[b];
+        a.dl[e] = d;
+    }
+    auto *psi = static_cast<float2 *>(s->data);
+    const uint64_t nthr = 1ull << (s->n - 1);   // a multiple of 64 (n >= 7)
+    const dim3 grid(unsigned((nthr + kSweepThreads - 1) / kSweepThreads));
+    if (z0)
+        hipLaunchKernelGGL((k_lane_sweep<K, true>), grid, dim3(kSweepThreads), 0, s->stream, psi, a, nthr);
+    else
+        hipLaunchKernelGGL((k_lane_sweep<K, false>), grid, dim3(kSweepThreads), 0, s->stream, psi, a, nthr);
+    return hipGetLastError();
+}
+
 template <typename T, int K>
 static hipError_t dense_sweep_t(qsim_state s, const Pass &p) {
     DenseArgs<T, K> a{};
@@ -144,9 +235,12 @@ static hipError_t dense_sweep_t(qsim_state s, const Pass &p) {
     const uint64_t groups = 1ull << (s->n - np);
     auto *psi = static_cast<c2_t<T> *>(s->data);
     const bool nt = all[0] >= 4;
-    if constexpr (std::is_same<T, float>::value && K == 1) {
-        // low targets: whole-wave contiguous accesses and a lane exchange
-        if (p.nctrl == 0 && p.targets[0] >= 1 && p.targets[0] <= 6 && s->n >= 7) return lane_sweep1(s, a, p.targets[0]);
+    if constexpr (std::is_same<T, float>::value) {
+        // low targets: whole-wave contiguous accesses and lane exchanges
+        if (lane_sweep_ok(s->dtype, s->n, p)) {
+            if constexpr (K == 1) return lane_sweep1(s, a, p.targets[0]);
+            else return lane_sweep<K>(s, p);
+        }
     }
     if constexpr (std::is_same<T, float>::value) {
         if (all[0] >= 1 && groups >= 2) {

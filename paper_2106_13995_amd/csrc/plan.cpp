@@ -96,6 +96,16 @@ static double diag_bytes(const HostGate &g, int n, int dtype) {
     return 2.0 * double(nonunit) * std::ldexp(1.0, n - g.k) * double(amp_bytes(dtype));
 }
 
+// Whether a sweep pass runs as a lane-exchange kernel: complex64, one to
+// three targets all below qubit 7 (qubit 0 only with another target), no
+// controls, at least 7 qubits.
+bool lane_sweep_ok(int dtype, int n, const Pass &p) {
+    if (dtype != QSIM_C64 || n < 7 || p.kind != PASS_DENSE || p.nctrl != 0 || p.k < 1 || p.k > 3) return false;
+    for (int b = 0; b < p.k; ++b)
+        if (p.targets[b] > 6) return false;
+    return p.k > 1 || p.targets[0] >= 1;
+}
+
 static Pass sweep_pass(const HostGate &g, int n, int dtype) {
     Pass p;
     if (is_diagonal(g)) {
@@ -455,7 +465,13 @@ bool build_plan(Plan &plan, const std::vector<HostGate> &gates_in, const PlanOpt
             const int nc = diag ? 0 : extract_controls(g, red, ctrls);
             int tlow = 64;
             for (int b = 0; b < red.k && !diag; ++b) tlow = std::min(tlow, red.targets[b]);
-            if (!diag && po.reg_tiles && g.k <= 3 && g.k - nc >= 2 && tlow <= 2 && n >= default_tile_m(dtype)) {
+            // targets all below qubit 7 and no controls (complex64): a sweep
+            // whose waves exchange partner amplitudes between lanes
+            Pass lane;
+            if (!diag) lane = sweep_pass(g, n, dtype);
+            if (!diag && lane_sweep_ok(dtype, n, lane)) {
+                plan.passes.push_back(std::move(lane));
+            } else if (!diag && po.reg_tiles && g.k <= 3 && g.k - nc >= 2 && tlow <= 2 && n >= default_tile_m(dtype)) {
                 // two or more targets among the lowest qubits: a sweep's
                 // threads would each gather a few adjacent amplitudes with
                 // strided accesses; a one-gate register tile reads whole

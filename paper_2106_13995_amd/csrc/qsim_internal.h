@@ -345,6 +345,9 @@ namespace qsim {
 size_t amp_bytes(int dtype);
 
 // Launchers (kernels_*.hip).  All return hipSuccess or the launch error.
+// Whether a sweep pass runs as a lane-exchange kernel (complex64, targets
+// below qubit 7, no controls).
+bool lane_sweep_ok(int dtype, int n, const Pass &p);
 hipError_t launch_dense_sweep(qsim_state s, const Pass &p);
 hipError_t launch_diag_sweep(qsim_state s, const Pass &p);
 // trig: (cos, sin) of each parameter's half angle, for passes with

@@ -93,6 +93,25 @@ def test_two_qubit_gate_all_ordered_pairs(qs, dtype):
     assert O.rel_l2(s.to_numpy(), ref) <= TOL[dtype]
 
 
+@pytest.mark.parametrize("n", [7, 13])
+def test_low_target_gates_lane_exchange(qs, n):
+    """Complex64 dense gates with every target among qubits 0..6 and no
+    controls run as lane-exchange sweeps (qubit 0 with or without others,
+    targets in any order, two and three of them, and one-qubit gates on
+    1..6); at n = 7 the grid is one partly filled workgroup."""
+    rng = np.random.default_rng(107 + n)
+    psi0 = _rounded(W.random_state(n, rng), "c64")
+    s = _state(qs, n, "c64", psi0)
+    ref = psi0.copy()
+    cases = [[0, 1], [1, 0], [0, 6], [5, 2], [6, 3], [0, 1, 2], [2, 0, 1], [1, 4, 6], [6, 5, 0], [3, 1, 5]]
+    cases += [[int(t) for t in rng.choice(7, size=int(k), replace=False)] for k in rng.integers(1, 4, size=12)]
+    for tg in cases:
+        U = W.random_unitary(len(tg), rng)
+        s.apply_gate(tg, U)
+        O.apply_matrix(ref, tg, U)
+    assert O.rel_l2(s.to_numpy(), ref) <= TOL["c64"]
+
+
 @pytest.mark.parametrize("dtype", ["c64", "c128"])
 @pytest.mark.parametrize("k", [3, 4, 5, 6])
 def test_dense_k_qubit_gates_sampled_targets(qs, dtype, k):
