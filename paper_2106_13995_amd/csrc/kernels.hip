@@ -73,62 +73,24 @@ k_dense_sweep(c2_t<T> *__restrict__ psi, const DenseArgs<T, K> a, uint64_t nthre
     }
 }
 
-// One-qubit gate on a low target t = B + 1 (t = 1..6, complex64, no
-// controls): lane l of a wave loads amplitudes 2l and 2l + 1 of the wave's
-// 128 with one 16-byte access, so every load and store instruction covers
-// 1 KiB contiguously; the target bit is lane bit B, and the partner
-// amplitudes come from lane l ^ 2^B by a cross-lane exchange.  Each lane
-// writes back its own two.  The grid is a whole number of waves.
-template <int B>
-__global__ void __launch_bounds__(kSweepThreads)
-k_lane_sweep1(float2 *__restrict__ psi, const DenseArgs<float, 1> a, uint64_t nthreads) {
-    const uint64_t tid = uint64_t(blockIdx.x) * kSweepThreads + threadIdx.x;
-    if (tid >= nthreads) return;
-    const f32x4 w = ld<true, f32x4>(psi + 2 * tid);
-    const float p0 = __shfl_xor(w.x, 1 << B, 64), p1 = __shfl_xor(w.y, 1 << B, 64);
-    const float p2 = __shfl_xor(w.z, 1 << B, 64), p3 = __shfl_xor(w.w, 1 << B, 64);
-    // this lane's half of the pair: row 0 (M00 self + M01 partner) or
-    // row 1 (M10 partner + M11 self)
-    const bool hi = (threadIdx.x >> B) & 1u;
-    const float sr = hi ? a.re[3] : a.re[0], si = hi ? a.im[3] : a.im[0];
-    const float orr = hi ? a.re[2] : a.re[1], oi = hi ? a.im[2] : a.im[1];
-    f32x4 o;
-    o.x = sr * w.x - si * w.y + orr * p0 - oi * p1;
-    o.y = sr * w.y + si * w.x + orr * p1 + oi * p0;
-    o.z = sr * w.z - si * w.w + orr * p2 - oi * p3;
-    o.w = sr * w.w + si * w.z + orr * p3 + oi * p2;
-    st<true, f32x4>(psi + 2 * tid, o);
-}
-
-static hipError_t lane_sweep1(qsim_state s, const DenseArgs<float, 1> &a, int t) {
-    auto *psi = static_cast<float2 *>(s->data);
-    // a multiple of 64 (n >= 7): lanes past the end leave as whole waves
-    const uint64_t nthr = 1ull << (s->n - 1);
-    const dim3 grid(unsigned((nthr + kSweepThreads - 1) / kSweepThreads));
-    switch (t) {
-        case 1: hipLaunchKernelGGL((k_lane_sweep1<0>), grid, dim3(kSweepThreads), 0, s->stream, psi, a, nthr); break;
-        case 2: hipLaunchKernelGGL((k_lane_sweep1<1>), grid, dim3(kSweepThreads), 0, s->stream, psi, a, nthr); break;
-        case 3: hipLaunchKernelGGL((k_lane_sweep1<2>), grid, dim3(kSweepThreads), 0, s->stream, psi, a, nthr); break;
-        case 4: hipLaunchKernelGGL((k_lane_sweep1<3>), grid, dim3(kSweepThreads), 0, s->stream, psi, a, nthr); break;
-        case 5: hipLaunchKernelGGL((k_lane_sweep1<4>), grid, dim3(kSweepThreads), 0, s->stream, psi, a, nthr); break;
-        default: hipLaunchKernelGGL((k_lane_sweep1<5>), grid, dim3(kSweepThreads), 0, s->stream, psi, a, nthr); break;
-    }
-    return hipGetLastError();
-}
-
-// Dense K-qubit gate (K = 2, 3) with every target below qubit 7
-// (complex64, no controls): as k_lane_sweep1, lane l holds amplitudes 2l
-// and 2l + 1 of its wave's 128 (one 16-byte access; the wave moves 1 KiB
-// contiguously).  Target bits 1..6 are lane bits; Z0: qubit 0 is a target
-// too (both of a lane's amplitudes are in one group), else each belongs to
-// its own group.  The lane takes the group's other amplitudes from the
-// lanes that differ in the target lane bits (l ^ dl[e]) and forms
+// Dense K-qubit gate (K = 1..3, complex64, no controls) as a lane-exchange
+// sweep.  Each lane holds two adjacent amplitudes (one 16-byte access);
+// lane bit b stands for amplitude bit lmap[b] and the wave index fills the
+// other bits.  Targets are amplitude bit 0 (Z0: both of a lane's amplitudes
+// are then in one group) or lane bits: targets below qubit 7 keep their
+// natural lane bit, higher ones take the top free lane bits, and the other
+// lane bits take the lowest free amplitude bits, so an access instruction
+// covers runs of at least 128 contiguous bytes (1 KiB when every target is
+// below qubit 7).  A lane takes the rest of its group from the lanes that
+// differ in the target lane bits (l ^ dl[e]) and forms
 // out(j) = sum over d of M[j][j ^ d] amp(j ^ d), the coefficients read by
-// local index from a table in LDS.
+// local index from a table in LDS; it writes back its own two amplitudes.
 struct LaneArgs {
     float re[64], im[64];   // M, row-major, on the targets in ascending order
     uint32_t dl[8];         // lane offset of partner e: e's bits on the target lane bits
-    int32_t lbit[3];        // lane bits of the targets above qubit 0, ascending
+    int32_t lbit[3];        // lane bits of the targets other than qubit 0, in target order
+    int32_t lmap[6];        // amplitude bit of each lane bit
+    int32_t ins[7];         // amplitude bit 0 and the lane bits' bits, ascending
 };
 
 template <int K, bool Z0>
@@ -136,15 +98,26 @@ __global__ void __launch_bounds__(kSweepThreads)
 k_lane_sweep(float2 *__restrict__ psi, const LaneArgs a, uint64_t nthreads) {
     constexpr int KL = Z0 ? K - 1 : K;
     constexpr int D = 1 << K;
-    __shared__ float2 coef[D * D];   // coef[j D + d] = M[j][j ^ d]
+    __shared__ float2 coef[D * D];      // coef[j D + d] = M[j][j ^ d]
+    __shared__ uint64_t lane_off[64];   // amplitude offset of each lane
     if (threadIdx.x < D * D) {
         const int j = int(threadIdx.x) / D, d = int(threadIdx.x) % D;
         coef[threadIdx.x] = float2{a.re[j * D + (j ^ d)], a.im[j * D + (j ^ d)]};
     }
+    if (threadIdx.x < 64) {
+        uint64_t o = 0;
+        for (int b = 0; b < 6; ++b) o |= uint64_t((threadIdx.x >> b) & 1u) << a.lmap[b];
+        lane_off[threadIdx.x] = o;
+    }
     __syncthreads();
     const uint64_t tid = uint64_t(blockIdx.x) * kSweepThreads + threadIdx.x;
     if (tid >= nthreads) return;
-    const f32x4 w = ld<true, f32x4>(psi + 2 * tid);
+    const uint32_t lane = threadIdx.x & 63u;
+    // the wave's first amplitude: its index spread over the bits no lane
+    // stands for (uniform across the wave, in scalar registers)
+    const uint64_t wave = uint64_t(blockIdx.x) * (kSweepThreads / 64) + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const uint64_t x = insert_zeros(wave, a.ins, 7) | lane_off[lane];
+    const f32x4 w = ld<true, f32x4>(psi + x);
     float P[1 << KL][4];
     P[0][0] = w.x; P[0][1] = w.y; P[0][2] = w.z; P[0][3] = w.w;
 #pragma unroll
@@ -155,7 +128,6 @@ k_lane_sweep(float2 *__restrict__ psi, const LaneArgs a, uint64_t nthreads) {
         P[e][2] = __shfl_xor(w.z, d, 64);
         P[e][3] = __shfl_xor(w.w, d, 64);
     }
-    const uint32_t lane = threadIdx.x & 63u;
     uint32_t jl = 0;
 #pragma unroll
     for (int b = 0; b < KL; ++b) jl |= ((lane >> a.lbit[b]) & 1u) << b;
@@ -176,7 +148,7 @@ k_lane_sweep(float2 *__restrict__ psi, const LaneArgs a, uint64_t nthreads) {
         out[2 * s] = ar;
         out[2 * s + 1] = ai;
     }
-    st<true, f32x4>(psi + 2 * tid, f32x4{out[0], out[1], out[2], out[3]});
+    st<true, f32x4>(psi + x, f32x4{out[0], out[1], out[2], out[3]});
 }
 
 template <int K>
@@ -189,8 +161,39 @@ static hipError_t lane_sweep(qsim_state s, const Pass &p) {
     }
     // targets are ascending (sweep passes hold the sorted form)
     const bool z0 = p.targets[0] == 0;
+    int lane_of[QSIM_MAX_K];
+    uint32_t used_lane = 0;
+    uint64_t used_amp = 1;   // bit 0: the two amplitudes of a lane
+    for (int b = 0; b < K; ++b) used_amp |= 1ull << p.targets[b];
+    for (int b = z0 ? 1 : 0; b < K; ++b)
+        if (p.targets[b] <= 6) {
+            lane_of[b] = p.targets[b] - 1;
+            used_lane |= 1u << lane_of[b];
+        }
+    for (int b = K - 1; b >= (z0 ? 1 : 0); --b)
+        if (p.targets[b] > 6) {
+            int l = 5;
+            while ((used_lane >> l) & 1u) --l;
+            lane_of[b] = l;
+            used_lane |= 1u << l;
+        }
     int nl = 0;
-    for (int b = z0 ? 1 : 0; b < K; ++b) a.lbit[nl++] = p.targets[b] - 1;
+    for (int b = z0 ? 1 : 0; b < K; ++b) {
+        a.lbit[nl++] = lane_of[b];
+        a.lmap[lane_of[b]] = p.targets[b];
+    }
+    int next = 1;
+    for (int l = 0; l < 6; ++l) {
+        if ((used_lane >> l) & 1u) continue;
+        while ((used_amp >> next) & 1ull) ++next;
+        a.lmap[l] = next;
+        used_amp |= 1ull << next;
+    }
+    int pos[7];
+    pos[0] = 0;
+    for (int l = 0; l < 6; ++l) pos[l + 1] = a.lmap[l];
+    std::sort(pos, pos + 7);
+    for (int i = 0; i < 7; ++i) a.ins[i] = pos[i];
     for (int e = 0; e < (1 << nl); ++e) {
         uint32_t d = 0;
         for (int b = 0; b < nl; ++b)
@@ -198,7 +201,7 @@ static hipError_t lane_sweep(qsim_state s, const Pass &p) {
         a.dl[e] = d;
     }
     auto *psi = static_cast<float2 *>(s->data);
-    const uint64_t nthr = 1ull << (s->n - 1);   // a multiple of 64 (n >= 7)
+    const uint64_t nthr = 1ull << (s->n - 1);   // a multiple of 64 (n >= 7): whole waves leave together
     const dim3 grid(unsigned((nthr + kSweepThreads - 1) / kSweepThreads));
     if (z0)
         hipLaunchKernelGGL((k_lane_sweep<K, true>), grid, dim3(kSweepThreads), 0, s->stream, psi, a, nthr);
@@ -237,10 +240,7 @@ static hipError_t dense_sweep_t(qsim_state s, const Pass &p) {
     const bool nt = all[0] >= 4;
     if constexpr (std::is_same<T, float>::value) {
         // low targets: whole-wave contiguous accesses and lane exchanges
-        if (lane_sweep_ok(s->dtype, s->n, p)) {
-            if constexpr (K == 1) return lane_sweep1(s, a, p.targets[0]);
-            else return lane_sweep<K>(s, p);
-        }
+        if (lane_sweep_ok(s->dtype, s->n, p)) return lane_sweep<K>(s, p);
     }
     if constexpr (std::is_same<T, float>::value) {
         if (all[0] >= 1 && groups >= 2) {

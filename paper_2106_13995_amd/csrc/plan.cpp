@@ -10,6 +10,7 @@
 //               diagonal gates may act anywhere (bits outside the tile are
 //               constant across a tile).
 #include <algorithm>
+#include <cstdlib>
 #include <cstring>
 #include <set>
 
@@ -96,14 +97,16 @@ static double diag_bytes(const HostGate &g, int n, int dtype) {
     return 2.0 * double(nonunit) * std::ldexp(1.0, n - g.k) * double(amp_bytes(dtype));
 }
 
-// Whether a sweep pass runs as a lane-exchange kernel: complex64, one to
-// three targets all below qubit 7 (qubit 0 only with another target), no
-// controls, at least 7 qubits.
+// Whether a sweep pass runs as a lane-exchange kernel: complex64, no
+// controls, at least 7 qubits, one or two targets anywhere or three with at
+// most one above qubit 6 (measured on 30 qubits: three high targets split a
+// wave's accesses into eight 128-byte runs and take 0.65 of HBM, against
+// 0.70 for the two-stream sweep).
 bool lane_sweep_ok(int dtype, int n, const Pass &p) {
     if (dtype != QSIM_C64 || n < 7 || p.kind != PASS_DENSE || p.nctrl != 0 || p.k < 1 || p.k > 3) return false;
-    for (int b = 0; b < p.k; ++b)
-        if (p.targets[b] > 6) return false;
-    return p.k > 1 || p.targets[0] >= 1;
+    int high = 0;
+    for (int b = 0; b < p.k; ++b) high += p.targets[b] > 6;
+    return p.k < 3 || high <= 1;
 }
 
 static Pass sweep_pass(const HostGate &g, int n, int dtype) {
@@ -465,8 +468,8 @@ bool build_plan(Plan &plan, const std::vector<HostGate> &gates_in, const PlanOpt
             const int nc = diag ? 0 : extract_controls(g, red, ctrls);
             int tlow = 64;
             for (int b = 0; b < red.k && !diag; ++b) tlow = std::min(tlow, red.targets[b]);
-            // targets all below qubit 7 and no controls (complex64): a sweep
-            // whose waves exchange partner amplitudes between lanes
+            // up to three targets and no controls (complex64): a sweep whose
+            // waves exchange partner amplitudes between lanes
             Pass lane;
             if (!diag) lane = sweep_pass(g, n, dtype);
             if (!diag && lane_sweep_ok(dtype, n, lane)) {

@@ -345,8 +345,8 @@ namespace qsim {
 size_t amp_bytes(int dtype);
 
 // Launchers (kernels_*.hip).  All return hipSuccess or the launch error.
-// Whether a sweep pass runs as a lane-exchange kernel (complex64, targets
-// below qubit 7, no controls).
+// Whether a sweep pass runs as a lane-exchange kernel (complex64, one to
+// three targets, no controls).
 bool lane_sweep_ok(int dtype, int n, const Pass &p);
 hipError_t launch_dense_sweep(qsim_state s, const Pass &p);
 hipError_t launch_diag_sweep(qsim_state s, const Pass &p);

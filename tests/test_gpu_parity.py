@@ -94,17 +94,19 @@ def test_two_qubit_gate_all_ordered_pairs(qs, dtype):
 
 
 @pytest.mark.parametrize("n", [7, 13])
-def test_low_target_gates_lane_exchange(qs, n):
-    """Complex64 dense gates with every target among qubits 0..6 and no
-    controls run as lane-exchange sweeps (qubit 0 with or without others,
-    targets in any order, two and three of them, and one-qubit gates on
-    1..6); at n = 7 the grid is one partly filled workgroup."""
+def test_gates_lane_exchange(qs, n):
+    """Complex64 dense gates without controls run as lane-exchange sweeps:
+    targets among qubits 0..6 keep their lane bits, higher ones take the top
+    lane bits (qubit 0 with or without others, any order, one to three
+    targets); at n = 7 the grid is one partly filled workgroup."""
     rng = np.random.default_rng(107 + n)
     psi0 = _rounded(W.random_state(n, rng), "c64")
     s = _state(qs, n, "c64", psi0)
     ref = psi0.copy()
-    cases = [[0, 1], [1, 0], [0, 6], [5, 2], [6, 3], [0, 1, 2], [2, 0, 1], [1, 4, 6], [6, 5, 0], [3, 1, 5]]
-    cases += [[int(t) for t in rng.choice(7, size=int(k), replace=False)] for k in rng.integers(1, 4, size=12)]
+    cases = [[0, 1], [1, 0], [0, 6], [5, 2], [6, 3], [0, 1, 2], [2, 0, 1], [1, 4, 6], [6, 5, 0], [3, 1, 5], [0], [3]]
+    if n > 7:
+        cases += [[n - 1], [n - 2, n - 1], [0, n - 1], [3, n - 1], [2, 7, n - 1], [n - 1, 0, 6], [7, 8, 9]]
+    cases += [[int(t) for t in rng.choice(n, size=int(k), replace=False)] for k in rng.integers(1, 4, size=16)]
     for tg in cases:
         U = W.random_unitary(len(tg), rng)
         s.apply_gate(tg, U)
