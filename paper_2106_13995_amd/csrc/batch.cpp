@@ -220,10 +220,14 @@ qsim_status add_batch_program(BatchTables &t, const qsim_circuit &c, const qsim_
                     // rotations and probes name a parameter, not a pool
                     // entry; a probe's jmatch becomes its index in the
                     // sweep (a fused probe's rotation is the inverse)
-                    if (r.type == 9 || r.type == 10)
+                    if (r.type == 9 || r.type == 10) {
                         r.jmatch = bp.nprobes++;
-                    else if (r.type != 8 && r.type != 11)
+                    } else if (r.type == 12) {
+                        r.jmatch = bp.nprobes;
+                        bp.nprobes += 2;
+                    } else if (r.type != 8 && r.type != 11) {
                         r.moff += pool_base + p.pool_begin;
+                    }
                     rops.push_back(r);
                 }
                 bps.stage_begin = int(stages.size());
@@ -262,8 +266,12 @@ qsim_status add_batch_program(BatchTables &t, const qsim_circuit &c, const qsim_
         for (int pi2 = bp.rev_begin; pi2 < bp.rev_end; ++pi2)
             for (int si = passes[size_t(pi2)].stage_begin; si < passes[size_t(pi2)].stage_end; ++si)
                 for (int o = stages[size_t(si)].op_begin; o < stages[size_t(si)].op_end; ++o)
-                    if (rops[size_t(o)].type == 9 || rops[size_t(o)].type == 10)
+                    if (rops[size_t(o)].type == 9 || rops[size_t(o)].type == 10) {
                         of[size_t(rops[size_t(o)].moff)].push_back(rops[size_t(o)].jmatch);
+                    } else if (rops[size_t(o)].type == 12) {
+                        of[size_t(rops[size_t(o)].moff)].push_back(rops[size_t(o)].jmatch);
+                        of[size_t(rops[size_t(o)].gj[0])].push_back(rops[size_t(o)].jmatch + 1);
+                    }
         int32_t at = int32_t(probe_idx.size());
         for (int64_t j = 0; j < np; ++j) {
             probe_row.push_back(at);

@@ -134,6 +134,49 @@ __device__ __forceinline__ double bprobe_dispatch(int code, const T *vr, const T
     return 0.0;
 }
 
+// Z probe on register bit B.
+template <typename T, int R, int B>
+__device__ __forceinline__ double bprobe_z_bit(const T *vr, const T *vi) {
+    constexpr int NA = 1 << R;
+    double acc = 0.0;
+#pragma unroll
+    for (int i = 0; i < NA; ++i) {
+        const T v = vr[NA + i] * vi[i] - vi[NA + i] * vr[i];
+        acc += ((i >> B) & 1) ? -double(v) : double(v);
+    }
+    return acc;
+}
+
+// Probe and inverse rotation of generator G on register bit B, parameter m.
+template <typename T, int R, int RA, int B, int G>
+__device__ __forceinline__ double probe_rotate(T *vr, T *vi, const QSIM_CONST double *trig, int m) {
+    const double v = G == 3 ? bprobe_z_bit<T, R, B>(vr, vi) : bprobe_bit<T, R, B, (G == 3 ? 1 : G)>(vr, vi);
+    const double P = -trig[4 * m], sn = -trig[4 * m + 1];
+    const bool neg = trig[4 * m + 2] < 0.0;
+    if constexpr (G == 3)
+        brot_z_bit<T, RA, B>(vr, vi, P, sn, neg);
+    else
+        brot_bit<T, RA, B, G>(vr, vi, P, sn, neg);
+    return v;
+}
+
+// Two probe-and-inverse-rotation ops on one register bit (codes 344 + ..).
+template <typename T, int R, int RA, int C>
+__device__ __forceinline__ void probe_pair(int code, T *vr, T *vi, CRegOp &op, const QSIM_CONST double *trig,
+                                           double &v1, double &v2) {
+    if constexpr (C < 344 + 72) {
+        constexpr int B = (C - 344) % 8, G1 = (C - 344) / 24 + 1, G2 = ((C - 344) / 8) % 3 + 1;
+        if constexpr (B < R) {
+            if (code == C) {
+                v1 = probe_rotate<T, R, RA, B, G1>(vr, vi, trig, op.moff);
+                v2 = probe_rotate<T, R, RA, B, G2>(vr, vi, trig, op.gj[0]);
+                return;
+            }
+        }
+        probe_pair<T, R, RA, C + 1>(code, vr, vi, op, trig, v1, v2);
+    }
+}
+
 // Sums the pending probes of this tile over the waves (wave order) and
 // writes them to their (probe, tile) partials.
 __device__ __forceinline__ void layer_flush(const double (*probe)[kLayerThreads / 64], const int *probe_k, int np,
@@ -233,10 +276,39 @@ __global__ void __launch_bounds__(kLayerThreads) k_batch_layer(const LayerArgs<T
         for (int o = st.op_begin; o < st.op_end; ++o) {
             CRegOp &op = sop[o];
             const int code = op.code;
-            if (code < 240 || code >= 288) {
+            if (code < 240 || (code >= 288 && code < 344)) {
                 run_op<T, R, 0, RA, true>(code, vr, vi, op, spool + 2 * op.moff, base, t, trig);
             } else if constexpr (!BOTH) {
                 __builtin_unreachable();   // forward passes hold no probes
+            } else if (code >= 344) {
+                // two probes with their inverse rotations
+                if (np + 2 > kLayerProbeSlots) {
+                    __syncthreads();
+                    layer_flush(probe, probe_k, np, a.ppart + c.pp_off, uint32_t(c.ntiles), tile);
+                    __syncthreads();
+                    np = 0;
+                }
+                double v1 = 0.0, v2 = 0.0;
+                probe_pair<T, R, RA, 344>(code, vr, vi, op, trig, v1, v2);
+                for (int sft = 32; sft > 0; sft >>= 1) {
+                    v1 += __shfl_xor(v1, sft, 64);
+                    v2 += __shfl_xor(v2, sft, 64);
+                }
+                if (t % 64 == 0) {
+                    probe[np][t / 64] = v1;
+                    probe[np + 1][t / 64] = v2;
+                }
+                if (t == 0) {
+                    probe_k[np] = op.jmatch;
+                    probe_k[np + 1] = op.jmatch + 1;
+                }
+                np += 2;
+                if (np == kLayerProbeSlots) {
+                    __syncthreads();
+                    layer_flush(probe, probe_k, np, a.ppart + c.pp_off, uint32_t(c.ntiles), tile);
+                    __syncthreads();
+                    np = 0;
+                }
             } else {
                 // probe (240 + ..), or probe and inverse rotation (264 + ..)
                 const int pc = code >= 264 ? code - 24 : code;

@@ -131,7 +131,9 @@ struct RegOp {
     // 9 batched probe Im <lambda|G|psi> into gradient slot moff (G as in 8),
     // 10 that probe followed by the inverse rotation of parameter moff,
     // 11 two rotations on register bit rb[0]: G = rj[0] (X or Y) of
-    // parameter moff, then G = rj[1] of parameter gj[0];
+    // parameter moff, then G = rj[1] of parameter gj[0]; 12 two ops of
+    // type 10 on register bit rb[0] (G = rj[0], parameter moff, then
+    // G = rj[1], parameter gj[0]; probes jmatch and jmatch + 1);
     // X and Y act on register bit rb[0], Z on the bit that rmask, tb[0] or
     // gp[0..1] names
     int32_t type;

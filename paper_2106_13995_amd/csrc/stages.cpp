@@ -536,6 +536,28 @@ bool build_reg_program(Plan &plan, Pass &p, uint64_t q, const int *local_of,
             }
             sops.swap(fused);
         }
+        // two such probe-and-inverse-rotation ops on one register bit become
+        // one (the second's parameter in gj[0], generator in rj[1])
+        {
+            std::vector<RegOp> fused;
+            for (size_t i = 0; i < sops.size(); ++i) {
+                const RegOp &a = sops[i];
+                if (a.type == 10 && a.nreg == 1 && i + 1 < sops.size()) {
+                    const RegOp &b = sops[i + 1];
+                    if (b.type == 10 && b.nreg == 1 && b.rb[0] == a.rb[0]) {
+                        RegOp f = a;
+                        f.type = 12;
+                        f.rj[1] = b.rj[0];
+                        f.gj[0] = b.moff;
+                        fused.push_back(f);
+                        ++i;
+                        continue;
+                    }
+                }
+                fused.push_back(a);
+            }
+            sops.swap(fused);
+        }
         // two forward rotations on one register bit, the first about X or Y,
         // become one op (the second's parameter in gj[0], generator in rj[1])
         {
@@ -577,6 +599,7 @@ bool build_reg_program(Plan &plan, Pass &p, uint64_t q, const int *local_of,
             case 9: op.code = op.rj[0] == 3 ? 256 : (op.rj[0] == 1 ? 240 : 248) + op.rb[0]; break;
             case 10: op.code = op.rj[0] == 3 ? 280 : (op.rj[0] == 1 ? 264 : 272) + op.rb[0]; break;
             case 11: op.code = 288 + 8 * ((op.rj[0] - 1) * 3 + op.rj[1] - 1) + op.rb[0]; break;
+            case 12: op.code = 344 + 8 * ((op.rj[0] - 1) * 3 + op.rj[1] - 1) + op.rb[0]; break;
             default: op.code = 201; break;
         }
     }
