@@ -9,6 +9,7 @@ which stays resident in HBM.  Prints one JSON line.
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--fuse-k F] [--tile-m M]
     python bench.py --calib-copy      # plain 8 GiB device copy (counter calibration)
     python bench.py --width-sweep     # both circuit families, 13 to 30 qubits
+    python bench.py --batch-once 2,12 # the 4096-circuit batch, one replay (for profilers)
 """
 from __future__ import annotations
 
@@ -26,7 +27,7 @@ sys.path.insert(0, ROOT)
 
 METRIC = "gate-apps/s + HBM GB/s (30q c64); adjoint grads/s and batched circuits/s"
 HBM_PEAK_GBS = 8000.0
-# Vector ALU ceiling without packed-FP32 instructions (this build keeps them
+# Vector ALU ceiling without packed-FP32 instructions (the library is compiled with them
 # off): 256 CUs x 4 SIMDs x 16 lanes x 2 flop per FMA x 2.4 GHz.  The same
 # figure is the FP64 vector peak.
 ALU_PEAK_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
@@ -65,6 +66,9 @@ def parse():
     ap.add_argument("--batch-circuit", default="",
                     help="n,layers: time one ansatz circuit through the batched persistent kernel "
                          "(forward alone, then forward + gradient) and print that line instead")
+    ap.add_argument("--batch-once", default="",
+                    help="fuse_k,tile_m (or 'default'): build the 4096-circuit batch of the batch figure with "
+                         "these options, replay it once and print its layout (a short run for profilers)")
     return ap.parse_args()
 
 
@@ -268,15 +272,43 @@ def adjoint_bench(torch, q, W, dtype: str, reps: int = 10, shift_sample: int = 1
             "speedup_vs_param_shift": round(shift / adj, 1)}
 
 
-def batch_bench(torch, q, W, dtype: str = "c64", reps: int = 3, loop_sample: int = 128):
+def batch_workload(W):
     """4096 independent ansatz circuits (10-20 qubits, 4-12 layers, own
-    parameters, sum Z_iZ_{i+1} + 0.5 sum X_i), forward + adjoint gradient in
-    one replayed graph, against a loop of per-circuit adjoint calls on the
-    same GPU (timed on a stratified sample, scaled to 4096)."""
+    parameters, sum Z_iZ_{i+1} + 0.5 sum X_i)."""
     spec = W.batch_spec(count=4096, seed=5)
     circs = [W.ansatz_circuit(int(n), int(L)) for n, L in zip(spec.ns, spec.layers)]
     obs = [W.chain_observable(int(n)) for n in spec.ns]
-    params = np.concatenate(spec.params)
+    return circs, obs, np.concatenate(spec.params)
+
+
+def batch_once(torch, q, W, opts: str, dtype: str):
+    """The batch of `batch_workload`, built with the given options and
+    replayed once (forward + gradient); prints the time of that replay."""
+    circs, obs, params = batch_workload(W)
+    options = None
+    if opts != "default":
+        fk, tm = (int(v) for v in opts.split(","))
+        options = {"fuse_k": fk, "tile_m": tm}
+    b = q.Batch(circs, obs, dtype, options=options)
+    p_dev = torch.as_tensor(params, dtype=torch.float64, device="cuda")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    e_dev, g_dev = b.run_device(p_dev)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3
+    layered, persistent = b.layout()
+    out = {"batch_once": opts, "dtype": dtype, "ms_first_replay": round(ms, 2), "layered_circuits": layered,
+           "persistent_circuits": persistent, "pass_bytes": b.pass_bytes(),
+           "energy_sum": float(e_dev.sum().item())}
+    b.close()
+    return out
+
+
+def batch_bench(torch, q, W, dtype: str = "c64", reps: int = 3, loop_sample: int = 128):
+    """The 4096 circuits of `batch_workload`, forward + adjoint gradient in
+    one replayed graph, against a loop of per-circuit adjoint calls on the
+    same GPU (timed on a stratified sample, scaled to 4096)."""
+    circs, obs, params = batch_workload(W)
     # layered tile width and fixed-gate fusion picked by the batch autotuner
     # (untimed: each candidate batch is built and replayed)
     t0 = time.perf_counter()
@@ -507,7 +539,7 @@ def batch_circuit(q, W, n, layers, dtype):
 def main():
     a = parse()
     if a.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
+        print(json.dumps({"error": "the library runs on one GPU only; --gpus must be 1"}))
         sys.exit(2)
     import torch
     if a.calib_copy:
@@ -521,6 +553,9 @@ def main():
     if a.batch_circuit:
         n, layers = (int(v) for v in a.batch_circuit.split(","))
         print(json.dumps(batch_circuit(q, W, n, layers, a.dtype)))
+        return
+    if a.batch_once:
+        print(json.dumps(batch_once(torch, q, W, a.batch_once, a.dtype)))
         return
 
     rows = 5
@@ -570,7 +605,7 @@ def main():
                         "frac_of_78.6": round(alu_tfs / ALU_PEAK_TFLOPS, 4),
                         "frac_of_157.3": round(alu_tfs / 157.3, 4),
                         "note": "flops of the arithmetic the compiled passes perform; 78.6 TFLOP/s is the "
-                                "vector FP32 rate without packed instructions (kept off in this build), "
+                                "vector FP32 rate without packed instructions (kept off in the library build), "
                                 "157.3 the published FP32 vector peak"}}
     total_bytes = sum(v[2] for v in stats.values())
 

@@ -49,7 +49,7 @@ typedef enum {
     QSIM_ERR_ARG = -1,          /* invalid argument; nothing was done */
     QSIM_ERR_OOM = -2,          /* device memory could not be allocated */
     QSIM_ERR_DEVICE = -3,       /* a HIP call failed; the state is now invalid */
-    QSIM_ERR_UNSUPPORTED = -4,  /* valid request this build does not support */
+    QSIM_ERR_UNSUPPORTED = -4,  /* valid request the library does not support */
     QSIM_ERR_STATE = -5         /* the state handle is invalid */
 } qsim_status;
 

@@ -9,7 +9,7 @@
     python -m paper_2106_13995_amd.profiling stats <kernel_stats.csv>
     python -m paper_2106_13995_amd.profiling traffic --fetch F.csv --write W.csv \
         --calib-fetch CF.csv --calib-write CW.csv --calib-bytes B --kernel SUBSTR \
-        --cls tile --config KEY --out profiles/pmc_traffic.json
+        --cls tile --config KEY --out profiles/pmc_traffic.json [--skip S --take T]
 """
 from __future__ import annotations
 
@@ -46,29 +46,34 @@ def kernel_stats(path: str):
     return out
 
 
-def counter_per_dispatch(path: str, kernel_substr: str):
+def counter_per_dispatch(path: str, kernel_substr: str, skip: int = 0, take: int = 0):
     """Mean counter value per dispatch of kernels whose name contains
-    `kernel_substr` (values of one dispatch are summed over instances)."""
+    `kernel_substr` (values of one dispatch are summed over instances).
+    `skip` and `take` select, in dispatch order, the dispatches that count:
+    the first `skip` are left out, then `take` are kept (0: all the rest)."""
     per = defaultdict(float)
     with open(path) as f:
         for r in csv.DictReader(f):
             if kernel_substr not in r.get("Kernel_Name", ""):
                 continue
-            per[r.get("Dispatch_Id") or r.get("Correlation_Id")] += float(r["Counter_Value"])
-    if not per:
-        raise ValueError(f"no dispatch of {kernel_substr!r} in {path}")
-    return sum(per.values()) / len(per), len(per)
+            per[int(r.get("Dispatch_Id") or r.get("Correlation_Id"))] += float(r["Counter_Value"])
+    ids = sorted(per)[skip:]
+    if take:
+        ids = ids[:take]
+    if not ids or (take and len(ids) < take):
+        raise ValueError(f"too few dispatches of {kernel_substr!r} in {path}: {len(per)}, skip {skip}, take {take}")
+    return sum(per[i] for i in ids) / len(ids), len(ids)
 
 
 def pmc_traffic(a):
-    fetch, nf = counter_per_dispatch(a.fetch, a.kernel)
-    write, nw = counter_per_dispatch(a.write, a.kernel)
+    fetch, nf = counter_per_dispatch(a.fetch, a.kernel, a.skip, a.take)
+    write, nw = counter_per_dispatch(a.write, a.kernel, a.skip, a.take)
     cf, _ = counter_per_dispatch(a.calib_fetch, a.calib_kernel)
     cw, _ = counter_per_dispatch(a.calib_write, a.calib_kernel)
     kib = float(a.calib_bytes) / 1024.0
     sf, sw = kib / cf, kib / cw
     rec = {
-        "kernel": a.kernel, "dispatches": nf,
+        "kernel": a.kernel, "dispatches": nf, "skipped_dispatches": a.skip,
         "fetch_kib_raw": fetch, "write_kib_raw": write,
         "calib_fetch_kib_raw": cf, "calib_write_kib_raw": cw, "calib_bytes_each_way": int(a.calib_bytes),
         "fetch_scale": sf, "write_scale": sw,
@@ -97,6 +102,8 @@ def main():
     t.add_argument("--calib-bytes", required=True, type=int)
     t.add_argument("--calib-kernel", default="copy")
     t.add_argument("--commands", default="")
+    t.add_argument("--skip", type=int, default=0, help="dispatches of the kernel left out at the start")
+    t.add_argument("--take", type=int, default=0, help="dispatches counted after those (0: all the rest)")
     a = ap.parse_args()
     if a.cmd == "stats":
         for r in kernel_stats(a.csv):
