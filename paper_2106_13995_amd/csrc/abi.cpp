@@ -749,10 +749,16 @@ qsim_status expectation_with(qsim_state s, const qsim_pauli_sum *H, double *out_
                         if ((ht[size_t(t)].z >> sp.lane_q[b]) & 1) zl |= 1u << b;
                     ht[size_t(t)].pad = uint64_t(mu) | (uint64_t(zl) << 8);
                 }
+                auto key = [](const DevTerm &d) { return ((d.pad & 0xffu) << 8) | (d.pad >> 8); };
                 std::stable_sort(ht.begin() + first, ht.begin() + first + cnt,
-                                 [](const DevTerm &a, const DevTerm &b) { return a.pad < b.pad; });
+                                 [&](const DevTerm &a, const DevTerm &b) { return key(a) < key(b); });
                 sp.diag_first = first;
                 sp.diag_end = first + cnt;
+                int t = first;
+                for (int mu = 0; mu <= (1 << R); ++mu) {
+                    while (t < first + cnt && int(ht[size_t(t)].pad & 0xffu) < mu) ++t;
+                    sp.diag_mu[mu] = t;
+                }
             }
         }
     }

@@ -13,8 +13,8 @@
 // w_t (-1)^{|y & z_t|} |psi_y|^2: the sign splits into the lane/block part of
 // z_t (one parity per term and tile) and its register part mu_t, and
 // sum_k (-1)^{|mu & k|} |a_k|^2 over a lane's registers is the Walsh-Hadamard
-// transform of |a|^2, computed in place; terms sharing mu and their lane part
-// share one multiply by it.  Everything after the amplitudes'
+// transform of |a|^2, computed in place; terms sharing mu share one
+// multiply by its entry.  Everything after the amplitudes'
 // conversion is double precision; each lane accumulates its tiles in order,
 // and a fixed-order wave sum gives one partial per workgroup.
 #include <hip/hip_runtime.h>
@@ -129,29 +129,12 @@ __device__ __forceinline__ void lane_group(const f64x2 (&a)[NA], int b, double &
     }
 }
 
-// acc += c w[mu] for a mu that is the same on every lane: a uniform branch
-// per value, so the register array is never indexed at run time (which
-// would place it in scratch memory).
-template <int NA>
-__device__ __forceinline__ void add_at(const double (&w)[NA], int mu, double c, double &acc) {
-    switch (mu) {
-#define QSIM_CASE(K) \
-    case K:          \
-        if constexpr (K < NA) acc = fma(c, w[K], acc); \
-        break;
-        QSIM_CASE(0) QSIM_CASE(1) QSIM_CASE(2) QSIM_CASE(3) QSIM_CASE(4) QSIM_CASE(5) QSIM_CASE(6) QSIM_CASE(7)
-        QSIM_CASE(8) QSIM_CASE(9) QSIM_CASE(10) QSIM_CASE(11) QSIM_CASE(12) QSIM_CASE(13) QSIM_CASE(14)
-        QSIM_CASE(15)
-#undef QSIM_CASE
-        default: break;
-    }
-}
-
 template <typename T, int R>
 __global__ void __launch_bounds__(64)
 k_expect_simple(const c2_t<T> *__restrict__ psi, const ExpSimplePass p, const SimpleTerm *__restrict__ terms,
                 uint64_t ntiles, double *__restrict__ partials) {
     constexpr int NA = 1 << R;
+    static_assert(R == kExpSimpleR, "diag_mu holds 2^kExpSimpleR + 1 offsets");
     const unsigned lane = threadIdx.x;
     uint64_t toff = 0;
     for (int b = 0; b < 6; ++b) toff |= uint64_t((lane >> b) & 1u) << p.lane_q[b];
@@ -215,18 +198,23 @@ k_expect_simple(const c2_t<T> *__restrict__ psi, const ExpSimplePass p, const Si
                 }
             }
             // Each term's sign is the parity of its Z mask over the block bits
-            // (the same on every lane: a scalar choice of +-1), its lane part
-            // zl and its register part mu (pad_ holds mu | zl << 8); the
-            // register part selects the transform entry.  The trip count is
-            // known at the loop's start, so unrolled iterations issue their
-            // term loads together.
-#pragma unroll 8
-            for (int t = p.diag_first; t < p.diag_end; ++t) {
-                const SimpleTerm e = terms[t];
-                const double sg = (__popcll(e.z & base) & 1) ? -1.0 : 1.0;
-                const uint32_t zl = uint32_t(e.pad_ >> 8);
-                const double c = (__popc(zl & lane) & 1) ? -sg * e.wr : sg * e.wr;
-                add_at<NA>(w, int(e.pad_ & 0xffu), c, acc);
+            // (the same on every lane: a scalar choice), its lane part zl
+            // (pad_ holds mu | zl << 8) and its register part mu, which
+            // selects the transform entry.  The terms come grouped by mu:
+            // each group's signed weights are summed, then one product with
+            // its entry, so no entry is chosen at run time.
+#pragma unroll
+            for (int mu = 0; mu < NA; ++mu) {
+                const int t0 = p.diag_mu[mu], t1 = p.diag_mu[mu + 1];
+                if (t0 == t1) continue;
+                double c = 0.0;
+                for (int t = t0; t < t1; ++t) {
+                    const SimpleTerm e = terms[t];
+                    const uint32_t zl = uint32_t(e.pad_ >> 8);
+                    const bool neg = ((__popcll(e.z & base) + __popc(zl & lane)) & 1) != 0;
+                    c += neg ? -e.wr : e.wr;
+                }
+                acc = fma(c, w[mu], acc);
             }
         }
     }

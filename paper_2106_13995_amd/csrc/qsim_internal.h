@@ -408,7 +408,9 @@ hipError_t launch_expect_tiles(qsim_state s, const ExpTilePass &p, const void *d
 // groups on lane qubits exchange across lanes (lane_bit).  With diag set the
 // pass also evaluates the diagonal group: terms diag_first .. diag_end - 1,
 // ordered by the register part mu of their Z mask and then its lane part zl
-// (each term's pad field holds mu | zl << 8).  Each launch writes one partial per workgroup.
+// (each term's pad field holds mu | zl << 8); the terms with register part
+// mu are diag_mu[mu] .. diag_mu[mu + 1] - 1.  Each launch writes one partial
+// per workgroup.
 constexpr int kExpSimpleMaxR = 6;
 constexpr int kExpSimpleR = 4;
 struct ExpSimplePass {
@@ -419,6 +421,7 @@ struct ExpSimplePass {
     int32_t reg_bit[kExpSimpleMaxR], lane_bit[6];
     double reg_A[kExpSimpleMaxR], reg_B[kExpSimpleMaxR], lane_A[6], lane_B[6];
     int32_t diag_first, diag_end;
+    int32_t diag_mu[(1 << kExpSimpleR) + 1];
 };
 int expect_simple_grid(uint64_t ntiles);
 hipError_t launch_expect_simple(qsim_state s, const ExpSimplePass &p, const void *dev_terms, double *partials,
